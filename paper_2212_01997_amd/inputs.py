@@ -1,0 +1,441 @@
+"""Seeded synthetic systems for the graph-based density / response path.
+
+This module only builds inputs: geometries, the orthogonal tight-binding
+Hamiltonian H (CSR), diagonal perturbations H1, core partitions and electron
+counts.  It contains none of the method's arithmetic (no eigensolve, no Fermi
+function, no graph construction) and is shared by the oracle-side tests and
+the GPU-side tests and benchmark.
+
+The paper's own workloads are SCC-DFTB water, ammonium-hydroxide and solvated
+Trp-cage structures (Sec. VI); those structures and parameter sets are not
+available, so seeded synthetic stand-ins with the same shape are generated
+here:
+
+* water boxes: rigid molecules (O-H 0.96 A, H-O-H 104.5 deg), random
+  orientation, random sequential addition with O-O >= 2.5 A and every
+  intermolecular atom pair >= 1.5 A (minimum image);
+* a chain of C/N/O/S heavy atoms (1.5 A steps, self-avoiding random walk)
+  embedded in such water at 0.1 atoms / A^3.
+
+Hamiltonian (Hartree, Angstrom): on-site energies are diagonal per orbital;
+every orbital pair on two distinct atoms closer than 4 A (minimum image)
+couples with -0.5 exp(-r/1.2).  There is no angular dependence.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+# orbitals per element and their on-site energies (Ha): s first, then p
+ORBITALS = {
+    "H": (-0.24,),
+    "O": (-0.87, -0.33, -0.33, -0.33),
+    "C": (-0.50, -0.19, -0.19, -0.19),
+    "N": (-0.68, -0.26, -0.26, -0.26),
+    "S": (-0.63, -0.26, -0.26, -0.26),
+}
+VALENCE = {"H": 1, "O": 6, "C": 4, "N": 5, "S": 6}
+
+HOP_PREFACTOR = -0.5
+HOP_DECAY = 1.2
+HOP_CUTOFF = 4.0
+
+OH_BOND = 0.96
+HOH_ANGLE = math.radians(104.5)
+
+
+@dataclass
+class System:
+    """A synthetic orthogonal tight-binding system.
+
+    H is stored as CSR with ascending column indices in every row; the
+    pattern is symmetric and contains the diagonal.
+    """
+    name: str
+    box: float
+    pos: np.ndarray            # [n_atoms, 3] float64
+    species: list              # [n_atoms] element symbols
+    atom_orb_ptr: np.ndarray   # [n_atoms + 1] int32
+    h_row_ptr: np.ndarray      # [N + 1] int32
+    h_col: np.ndarray          # [nnz] int32
+    h_val: np.ndarray          # [nnz] float64
+    n_elec: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_atoms(self) -> int:
+        return len(self.species)
+
+    @property
+    def n_orb(self) -> int:
+        return int(self.atom_orb_ptr[-1])
+
+    def dense_h(self) -> np.ndarray:
+        n = self.n_orb
+        out = np.zeros((n, n))
+        rows = np.repeat(np.arange(n), np.diff(self.h_row_ptr))
+        out[rows, self.h_col] = self.h_val
+        return out
+
+
+# ---------------------------------------------------------------- geometry
+
+def _random_rotations(rng, count):
+    """Uniform random rotation matrices from unit quaternions."""
+    q = rng.normal(size=(count, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    r = np.empty((count, 3, 3))
+    r[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    r[:, 0, 1] = 2 * (x * y - z * w)
+    r[:, 0, 2] = 2 * (x * z + y * w)
+    r[:, 1, 0] = 2 * (x * y + z * w)
+    r[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    r[:, 1, 2] = 2 * (y * z - x * w)
+    r[:, 2, 0] = 2 * (x * z - y * w)
+    r[:, 2, 1] = 2 * (y * z + x * w)
+    r[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return r
+
+
+def _water_template():
+    half = HOH_ANGLE / 2
+    return np.array([
+        [0.0, 0.0, 0.0],
+        [OH_BOND * math.sin(half), OH_BOND * math.cos(half), 0.0],
+        [-OH_BOND * math.sin(half), OH_BOND * math.cos(half), 0.0],
+    ])
+
+
+class _Grid:
+    """Cell list under periodic boundaries for incremental insertion."""
+
+    def __init__(self, box, cell):
+        self.box = box
+        self.nc = max(1, int(box // cell))
+        self.cell = box / self.nc
+        self.cells = {}
+        self.pos = []
+        self.tag = []
+
+    def _key(self, p):
+        c = np.floor(np.mod(p, self.box) / self.cell).astype(int) % self.nc
+        return tuple(c)
+
+    def add(self, p, tag):
+        idx = len(self.pos)
+        self.pos.append(np.asarray(p, dtype=float))
+        self.tag.append(tag)
+        self.cells.setdefault(self._key(p), []).append(idx)
+
+    def near(self, p):
+        """Indices of stored points in the 27 cells around p."""
+        cx, cy, cz = self._key(p)
+        out = []
+        rng = (-1, 0, 1) if self.nc >= 3 else range(-(self.nc // 2), self.nc - self.nc // 2)
+        seen = set()
+        for dx in rng:
+            for dy in rng:
+                for dz in rng:
+                    k = ((cx + dx) % self.nc, (cy + dy) % self.nc, (cz + dz) % self.nc)
+                    if k in seen:
+                        continue
+                    seen.add(k)
+                    out.extend(self.cells.get(k, ()))
+        return out
+
+    def min_dist(self, p, idx, tag_filter=None):
+        if not idx:
+            return np.inf
+        pts = np.array([self.pos[i] for i in idx])
+        d = pts - p
+        d -= self.box * np.round(d / self.box)
+        r = np.sqrt((d * d).sum(axis=1))
+        if tag_filter is not None:
+            mask = np.array([tag_filter(self.tag[i]) for i in idx])
+            if not mask.any():
+                return np.inf
+            r = r[mask]
+        return r.min()
+
+
+def place_waters(rng, n_mol, box, grid=None, max_tries=200000,
+                 oo_min=2.5, inter_min=1.5, heavy_min=2.5):
+    """Random sequential addition of rigid waters into a periodic box.
+
+    `grid` may already hold other atoms (tag 'X' = foreign heavy atom); new
+    oxygens keep `heavy_min` from them.  Returns an [n_mol*3, 3] array in
+    O, H, H order per molecule.
+    """
+    if grid is None:
+        grid = _Grid(box, 2.5)
+    tmpl = _water_template()
+    out = []
+    tries = 0
+    batch = 256
+    while len(out) < n_mol:
+        centers = rng.uniform(0.0, box, size=(batch, 3))
+        rots = _random_rotations(rng, batch)
+        for c, rot in zip(centers, rots):
+            tries += 1
+            if tries > max_tries:
+                raise RuntimeError(f"water placement failed after {tries} tries "
+                                   f"({len(out)}/{n_mol} placed)")
+            atoms = c + tmpl @ rot.T
+            ok = True
+            for j, a in enumerate(atoms):
+                idx = grid.near(a)
+                if not idx:
+                    continue
+                pts = np.array([grid.pos[i] for i in idx])
+                d = pts - a
+                d -= box * np.round(d / box)
+                r = np.sqrt((d * d).sum(axis=1))
+                tags = [grid.tag[i] for i in idx]
+                for rr, t in zip(r, tags):
+                    if rr < inter_min:
+                        ok = False
+                        break
+                    if j == 0 and t == "O" and rr < oo_min:
+                        ok = False
+                        break
+                    if t == "X" and rr < heavy_min:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
+                continue
+            grid.add(atoms[0], "O")
+            grid.add(atoms[1], "H")
+            grid.add(atoms[2], "H")
+            out.append(np.mod(atoms, box))
+            if len(out) == n_mol:
+                break
+    return np.concatenate(out, axis=0) if out else np.zeros((0, 3))
+
+
+def chain_walk(rng, n_chain, box, step=1.5, min_sep=2.4, retries=100):
+    """Self-avoiding random walk of heavy atoms under periodic boundaries.
+
+    Every new atom keeps `min_sep` from all chain atoms except its
+    predecessor; after `retries` failed directions the walk backtracks.
+    """
+    grid = _Grid(box, min_sep)
+    pts = [rng.uniform(0.0, box, size=3)]
+    grid.add(pts[0], 0)
+    fails = [0]
+    while len(pts) < n_chain:
+        prev = pts[-1]
+        placed = False
+        for _ in range(retries):
+            d = rng.normal(size=3)
+            d *= step / np.linalg.norm(d)
+            cand = np.mod(prev + d, box)
+            idx = [i for i in grid.near(cand) if grid.tag[i] != len(pts) - 1]
+            if grid.min_dist(cand, idx) >= min_sep:
+                pts.append(cand)
+                grid.add(cand, len(pts) - 1)
+                fails.append(0)
+                placed = True
+                break
+        if not placed:
+            # backtrack one atom
+            if len(pts) <= 1:
+                raise RuntimeError("chain walk stuck at the first atom")
+            last = len(pts) - 1
+            key = grid._key(pts[last])
+            grid.cells[key].remove(last)
+            grid.pos.pop()
+            grid.tag.pop()
+            pts.pop()
+            fails.pop()
+            fails[-1] += 1
+    return np.array(pts)
+
+
+# ------------------------------------------------------------- Hamiltonian
+
+def build_hamiltonian(pos, species, box, cutoff=HOP_CUTOFF):
+    """Orthogonal tight-binding H as CSR (sorted columns, symmetric pattern)."""
+    n_atoms = len(species)
+    norb = np.array([len(ORBITALS[s]) for s in species], dtype=np.int64)
+    atom_orb_ptr = np.zeros(n_atoms + 1, dtype=np.int64)
+    np.cumsum(norb, out=atom_orb_ptr[1:])
+    n = int(atom_orb_ptr[-1])
+    if box < 2 * cutoff:
+        raise ValueError("box must be at least twice the hopping cutoff")
+
+    tree = cKDTree(np.mod(pos, box), boxsize=box)
+    pairs = tree.query_pairs(cutoff, output_type="ndarray")
+    ii, jj = pairs[:, 0], pairs[:, 1]
+    d = pos[ii] - pos[jj]
+    d -= box * np.round(d / box)
+    r = np.sqrt((d * d).sum(axis=1))
+    hop = HOP_PREFACTOR * np.exp(-r / HOP_DECAY)
+
+    rows, cols, vals = [], [], []
+    # off-diagonal blocks, both orientations
+    for a_idx, b_idx in ((ii, jj), (jj, ii)):
+        na = norb[a_idx]
+        nb = norb[b_idx]
+        cnt = na * nb
+        pair_of = np.repeat(np.arange(len(a_idx)), cnt)
+        start = np.zeros(len(a_idx) + 1, dtype=np.int64)
+        np.cumsum(cnt, out=start[1:])
+        local = np.arange(int(start[-1])) - start[pair_of]
+        nb_rep = nb[pair_of]
+        rows.append(atom_orb_ptr[a_idx][pair_of] + local // nb_rep)
+        cols.append(atom_orb_ptr[b_idx][pair_of] + local % nb_rep)
+        vals.append(hop[pair_of])
+    onsite = np.concatenate([np.array(ORBITALS[s]) for s in species])
+    rows.append(np.arange(n))
+    cols.append(np.arange(n))
+    vals.append(onsite)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    np.cumsum(row_ptr, out=row_ptr)
+    return (atom_orb_ptr.astype(np.int32), row_ptr.astype(np.int32),
+            cols.astype(np.int32), vals.astype(np.float64))
+
+
+def electron_count(species, n_water=None):
+    """Valence electrons; one more is added if the total is odd."""
+    ne = sum(VALENCE[s] for s in species)
+    if ne % 2:
+        ne += 1
+    return float(ne)
+
+
+def make_system(name, box, pos, species, meta):
+    aop, rp, col, val = build_hamiltonian(pos, species, box)
+    return System(name=name, box=float(box), pos=np.asarray(pos, dtype=np.float64),
+                  species=list(species), atom_orb_ptr=aop, h_row_ptr=rp,
+                  h_col=col, h_val=val, n_elec=electron_count(species), meta=meta)
+
+
+def water_system(n_mol, box, seed, name=None):
+    rng = np.random.default_rng(seed)
+    pos = place_waters(rng, n_mol, box)
+    species = ["O", "H", "H"] * n_mol
+    return make_system(name or f"water{n_mol}", box, pos, species,
+                        {"kind": "water", "n_mol": n_mol, "seed": seed})
+
+
+CHAIN_MIX = (("C", 0.62), ("N", 0.17), ("O", 0.20), ("S", 0.01))
+
+
+def chain_water_system(n_atoms, n_chain, seed, density=0.1, name=None):
+    """Heavy-atom chain embedded in water at `density` atoms / A^3."""
+    rng = np.random.default_rng(seed)
+    box = (n_atoms / density) ** (1.0 / 3.0)
+    chain = chain_walk(rng, n_chain, box)
+    elems = [e for e, _ in CHAIN_MIX]
+    probs = np.array([p for _, p in CHAIN_MIX])
+    chain_species = list(rng.choice(elems, size=n_chain, p=probs / probs.sum()))
+    grid = _Grid(box, 2.5)
+    for p in chain:
+        grid.add(p, "X")
+    n_mol = (n_atoms - n_chain) // 3
+    water = place_waters(rng, n_mol, box, grid=grid)
+    pos = np.concatenate([chain, water], axis=0)
+    species = chain_species + ["O", "H", "H"] * n_mol
+    return make_system(name or f"chain{n_chain}_water{n_mol}", box, pos, species,
+                        {"kind": "chain+water", "n_chain": n_chain, "n_mol": n_mol,
+                         "seed": seed})
+
+
+def isolated_molecules_system(n_mol, spacing, seed):
+    """Waters on a cubic lattice `spacing` apart: H is block diagonal when
+    spacing - 2 A > 4 A (used to check the disconnected case)."""
+    rng = np.random.default_rng(seed)
+    m = int(math.ceil(n_mol ** (1.0 / 3.0)))
+    box = m * spacing
+    tmpl = _water_template()
+    rots = _random_rotations(rng, n_mol)
+    pos = []
+    k = 0
+    for ix in range(m):
+        for iy in range(m):
+            for iz in range(m):
+                if k == n_mol:
+                    break
+                c = np.array([ix, iy, iz], dtype=float) * spacing + spacing / 2
+                pos.append(c + tmpl @ rots[k].T)
+                k += 1
+    pos = np.mod(np.concatenate(pos, axis=0), box)
+    species = ["O", "H", "H"] * n_mol
+    return make_system(f"isolated{n_mol}", box, pos, species,
+                        {"kind": "isolated", "n_mol": n_mol, "seed": seed})
+
+
+# ---------------------------------------------------------- perturbations
+
+def h1_diagonal(system, k, seed, sigma=0.05):
+    """K diagonal perturbations: one N(0, sigma) shift per atom, applied to
+    every orbital of that atom.  Returns float64 [K, N]."""
+    rng = np.random.default_rng(seed)
+    shifts = rng.normal(0.0, sigma, size=(k, system.n_atoms))
+    norb = np.diff(system.atom_orb_ptr)
+    return np.repeat(shifts, norb, axis=1).astype(np.float64)
+
+
+# -------------------------------------------------------------- partitions
+
+def single_atom_cores(system):
+    return np.arange(system.n_atoms, dtype=np.int32)
+
+
+def _spread_bits(v):
+    v = v.astype(np.uint64) & np.uint64(0x3FF)
+    out = np.zeros_like(v)
+    for b in range(10):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
+    return out
+
+
+def spatial_cores(system, core_size):
+    """Morton (Z-order) sort of positions quantised to box/1024, ties broken
+    by atom index, cut into consecutive chunks of `core_size` atoms."""
+    q = np.floor(np.mod(system.pos, system.box) / system.box * 1024.0).astype(np.int64)
+    q = np.clip(q, 0, 1023)
+    key = (_spread_bits(q[:, 0]) | (_spread_bits(q[:, 1]) << np.uint64(1))
+           | (_spread_bits(q[:, 2]) << np.uint64(2)))
+    order = np.lexsort((np.arange(system.n_atoms), key))
+    core = np.empty(system.n_atoms, dtype=np.int32)
+    core[order] = (np.arange(system.n_atoms) // core_size).astype(np.int32)
+    return core
+
+
+# ------------------------------------------------------------ the configs
+
+def config_system(k, seed=None):
+    """The seeded systems of the benchmark configurations.
+
+    1: 32 waters in a 10 A box (96 atoms, 192 orbitals, N_e = 256)
+    2: 1,000 waters in a 31 A box (3,000 atoms, 6,000 orbitals)
+    3: 6,000-atom C/N/O/S chain in water, 30,000 atoms at 0.1 atoms / A^3
+    """
+    s = (1000 * k + 1) if seed is None else seed
+    if k == 1:
+        return water_system(32, 10.0, s, name="config1_water32")
+    if k == 2:
+        return water_system(1000, 31.0, s, name="config2_water1000")
+    if k == 3:
+        return chain_water_system(30000, 6000, s, name="config3_chain6000")
+    raise ValueError(f"unknown config {k}")
+
+
+def csr_to_dense(row_ptr, col, val, n):
+    out = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    out[rows, col] = val
+    return out
