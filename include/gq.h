@@ -1,0 +1,205 @@
+/*
+ * gq — graph-based density matrix and canonical first-order response on
+ * AMD Instinct MI355X (gfx950).  C ABI of libgq.so.
+ *
+ * Method: Negre, Wall, Niklasson, "Graph-based quantum response theory and
+ * shadow Born-Oppenheimer molecular dynamics", arXiv:2212.01997.
+ *
+ *   graph_build      Sec. II.E (graph estimate from a previous density and the
+ *                    Hamiltonian, optional paths of length two), Sec. II.C and
+ *                    Fig. 1 (core + halo subgraphs, principal submatrices)
+ *   submatrix_solve  Fig. 1 (principal submatrix h of each subgraph) and
+ *                    Eq. (SmallKS) (h = Q diag(eps) Q^T)
+ *   density          Sec. II.G, Eq. (NewtonRaphson) (one chemical potential
+ *                    shared by all subgraphs) and Eqs. (DD0), (DD) (core rows)
+ *   response         Sec. IV.A, Eqs. (D1_a), (D1_b), (ddlambda), (dddmu),
+ *                    (dmu_1) (canonical first-order response in the eigenbasis)
+ *   assemble         Eqs. (sub_f), (dCollect), (D1) (collect core rows)
+ *
+ * Conventions
+ *   - Orthogonal basis; energies in Hartree.  Densities carry the closed-shell
+ *     spin factor 2: Tr rho = N_e.  beta = 1/kT.
+ *   - A "subgraph" i has n_i orbitals, of which the first c_i are its core.
+ *   - "Blocks" are ragged per-subgraph arrays of c_i x n_i doubles, row-major,
+ *     subgraph after subgraph (offsets from gq_graph_block_offsets); the
+ *     collected CSR pattern of rho and rho1 has the same nnz = sum c_i n_i.
+ *   - Host pointers are borrowed for the call; the library copies what it
+ *     keeps.  Device pointers named *_dev point to memory on the context's
+ *     device; output buffers are allocated by the caller.
+ *   - All device work is enqueued on the context's stream (a hipStream_t
+ *     given at gq_ctx_create).  A call blocks the host only where it returns
+ *     a host scalar (noted per call).
+ *   - Errors: every call returns gq_status; on error the outputs are
+ *     unspecified, handles stay valid, and gq_last_error() gives a message
+ *     (thread-local).  No exception crosses the ABI.
+ */
+#ifndef GQ_H
+#define GQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gq_status;
+#define GQ_OK 0
+#define GQ_EINVAL (-1)   /* bad argument or input structure */
+#define GQ_ENOMEM (-2)   /* device or host allocation failed, or size limit */
+#define GQ_ENOCONV (-3)  /* eigensolver or chemical-potential bracket failed */
+#define GQ_EDEVICE (-4)  /* HIP runtime error */
+#define GQ_EBUSY (-5)    /* resource busy (serving admission) */
+
+/* graph_build flags */
+#define GQ_PATHS2 1u     /* extend the estimated graph by paths of length two */
+#define GQ_COMPLETE 2u   /* every halo is the whole system (dense limit) */
+
+/* submatrix_solve flags */
+#define GQ_SOLVE_DEFAULT 0u
+
+/* response precision */
+#define GQ_PREC_FP64 0u       /* congruences in FP64 */
+#define GQ_PREC_SPLIT32 1u    /* split-FP32 congruences + one FP64 refinement */
+
+typedef struct gq_ctx gq_ctx;
+typedef struct gq_graph gq_graph;
+typedef struct gq_eigs gq_eigs;
+
+/* CSR matrix, 0-based, ascending columns in every row.  Host or device
+ * memory as stated by the call that takes it. */
+typedef struct {
+  int32_t n_rows;
+  int32_t nnz;
+  const int32_t* row_ptr; /* [n_rows + 1] */
+  const int32_t* col;     /* [nnz] */
+  const double* val;      /* [nnz] */
+} gq_csr;
+
+typedef struct {
+  int32_t n_atoms;
+  int32_t n_orb;        /* N */
+  int32_t n_sub;        /* number of subgraphs (= number of cores) */
+  int32_t max_n;        /* largest subgraph, orbitals */
+  int32_t min_n;
+  int32_t max_c;        /* largest core, orbitals */
+  int64_t nnz;          /* collected pattern = sum c_i n_i */
+  int64_t sum_n;        /* sum n_i */
+  int64_t sum_n2;       /* sum n_i^2 */
+  int64_t sub_atoms_len;/* sum of subgraph vertex counts */
+} gq_graph_info;
+
+/* Message for the last non-OK status returned on this thread. */
+const char* gq_last_error(void);
+/* Library version string. */
+const char* gq_version(void);
+
+/* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  The stream is borrowed and must outlive the context. */
+gq_status gq_ctx_create(int32_t device, void* hip_stream, gq_ctx** out);
+void gq_ctx_destroy(gq_ctx* ctx);
+
+/* ---------------------------------------------------------- graph_build
+ * Host, integer work, deterministic.  Atom graph: I != J are joined when some
+ * orbital pair (a in I, b in J) has |H_ab| >= tau, or |rho_prev_ab| >= tau or
+ * |rho_prev_ba| >= tau (Sec. II.E); GQ_PATHS2 adds every pair joined by a path
+ * of length two.  Subgraph i: its core atoms (core_of_atom[I] == i) ascending,
+ * then its halo (atoms joined to a core atom, not in the core) ascending
+ * (Sec. II.C, Fig. 1); GQ_COMPLETE makes every halo the rest of the system.
+ * Orbitals follow their atoms in native order.  The collected pattern holds,
+ * for every orbital a, the ascending orbitals of a's subgraph.
+ *
+ * All pointers are host memory.  atom_orb_ptr[n_atoms+1] strictly increasing
+ * from 0; H: N x N with a symmetric pattern; rho_prev: N x N or NULL;
+ * core_of_atom[n_atoms]: ids 0..n_sub-1, each used.  GQ_EINVAL on any
+ * violation or tau < 0; GQ_ENOMEM if a count exceeds int32.  *out is owned by
+ * the caller (gq_graph_destroy). */
+gq_status gq_graph_build(int32_t n_atoms, const int32_t* atom_orb_ptr, const gq_csr* H,
+                         const gq_csr* rho_prev, const int32_t* core_of_atom, double tau,
+                         uint32_t flags, gq_graph** out);
+gq_status gq_graph_query(const gq_graph* g, gq_graph_info* info);
+/* Copies the graph into caller arrays sized from gq_graph_info (any may be
+ * NULL): sub_ptr[n_sub+1], sub_atoms[sub_atoms_len], n_core_atoms[n_sub],
+ * sub_orb_ptr[n_sub+1], sub_orbs[sum_n], n_core_orbs[n_sub],
+ * rho_row_ptr[N+1], rho_col[nnz]. */
+gq_status gq_graph_export(const gq_graph* g, int32_t* sub_ptr, int32_t* sub_atoms,
+                          int32_t* n_core_atoms, int32_t* sub_orb_ptr, int32_t* sub_orbs,
+                          int32_t* n_core_orbs, int32_t* rho_row_ptr, int32_t* rho_col);
+/* Block offsets: off[i] = sum_{j<i} c_j n_j, off[n_sub] = nnz (host array). */
+gq_status gq_graph_block_offsets(const gq_graph* g, int64_t* off);
+void gq_graph_destroy(gq_graph* g);
+
+/* ------------------------------------------------------- eigen workspace
+ * Device-resident state of one graph: eigenpairs, core weights, the mu
+ * response rows and the divided differences, sized for up to `max_k`
+ * perturbations per response call.  Allocates device memory (GQ_ENOMEM). */
+gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs** out);
+/* Device bytes held by an eigen workspace for graph g and max_k (for
+ * admission control); no allocation. */
+gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, int64_t* bytes);
+void gq_eigs_destroy(gq_eigs* e);
+
+/* ------------------------------------------------------ submatrix_solve
+ * Gathers every principal submatrix h_i = H[orbs_i, orbs_i] from the device
+ * CSR H (same N and a pattern containing the one given to graph_build) and
+ * solves h_i = Q_i diag(eps_i) Q_i^T in FP64 (eps ascending), all on the
+ * context stream.  Asynchronous; a later call that syncs reports GQ_ENOCONV
+ * if an eigensolve hit its iteration cap. */
+gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev,
+                             uint32_t flags, gq_eigs* e);
+
+/* -------------------------------------------------------------- density
+ * Shared chemical potential: the root of 2 sum_{i,k} w_ik f(eps_ik; mu) = n_elec
+ * with core weights w_ik = sum_{j<c_i} Q_i[j,k]^2 (Sec. II.G), found by
+ * multisection on the device to the last representable interval.  Then the
+ * core rows rho_i = 2 Q_i[0:c_i,:] diag(f) Q_i^T into rho_blocks_dev (device,
+ * nnz doubles; may be NULL), and the mu-response rows
+ * 2 beta Q_c diag(f(1-f)) Q^T kept in the workspace.  kT > 0 and
+ * 0 < n_elec < 2N (GQ_EINVAL).  *mu_out (host, may be NULL) makes the call
+ * wait for the stream. */
+gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* mu_out,
+                     double* rho_blocks_dev);
+
+/* ------------------------------------------------------------- response
+ * K perturbations H1_q given as diagonals h1_dev[K][N] (device).  For each
+ * subgraph: X = Q^T diag(h1) Q, Y = X o dF with dF_kl = (f_k - f_l)/(e_k - e_l)
+ * (f'(e_k) when equal), P = 2 Q_c Y Q^T, and the canonical
+ * mu1_q = -sum_i Tr_c P_i / sum_i Tr_c M_i (Sec. IV.A).  Writes
+ * p_blocks_dev[K][nnz] = P + mu1_q M (the collected rho1 rows in block layout)
+ * and mu1_dev[K] (device; may be NULL).  `precision` is GQ_PREC_FP64 or
+ * GQ_PREC_SPLIT32.  Requires gq_density on the same workspace first; K <= max_k.
+ * mu1_host (may be NULL) makes the call wait for the stream. */
+gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const double* h1_dev, int32_t K,
+                      uint32_t precision, double* p_blocks_dev, double* mu1_dev,
+                      double* mu1_host);
+
+/* ------------------------------------------------------------- assemble
+ * Scatters K block arrays (device, [K][nnz], block layout) into CSR value
+ * arrays vals_dev[K][nnz] in the collected pattern of g (device). */
+gq_status gq_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks_dev, int32_t K,
+                      double* vals_dev);
+
+/* ---------------------------------------------------------- profiling
+ * Diagnostics, not part of the method.  While enabled, every kernel launch
+ * of the context is bracketed by a hipEvent pair on its stream.
+ * gq_ctx_kernel_times waits for the stream and reports per kernel name the
+ * launch count and total milliseconds since profiling was last enabled
+ * (arrays of `cap` entries, host; *count = entries filled; the name strings
+ * are static).  Enabling resets the totals. */
+gq_status gq_ctx_set_profiling(gq_ctx* ctx, int32_t enable);
+gq_status gq_ctx_kernel_times(gq_ctx* ctx, const char** names, int64_t* launches,
+                              double* total_ms, int32_t cap, int32_t* count);
+
+/* ---------------------------------------------------------- diagnostics
+ * Copies eigenvalues eps[sum_n] (subgraph by subgraph, ascending) and core
+ * weights w[sum_n] to host arrays (either may be NULL); waits for the stream.
+ * Returns GQ_ENOCONV if any eigensolve failed to converge. */
+gq_status gq_eigs_export(gq_ctx* ctx, const gq_eigs* e, double* eps, double* w);
+/* Device pointer to subgraph i's eigenvectors (n_i x n_i, column-major). */
+gq_status gq_eigs_vectors(const gq_eigs* e, int32_t i, const double** q_dev, int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

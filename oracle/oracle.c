@@ -713,8 +713,8 @@ int orc_solve(const orc_graph* g, const orc_csr* H, double kT, double n_elec, in
   if (!(kT > 0.0)) return fail(ORC_EINVAL, "kT must be > 0");
   const int32_t ns = g->n_sub;
   int64_t tot = g->sub_orb_ptr[ns];
-  double* eps = malloc(sizeof(double) * (size_t)tot);
-  double* wts = malloc(sizeof(double) * (size_t)tot);
+  double* eps = calloc((size_t)(tot > 0 ? tot : 1), sizeof(double));
+  double* wts = calloc((size_t)(tot > 0 ? tot : 1), sizeof(double));
   double** Z = calloc((size_t)ns, sizeof(double*));
   int rc = ORC_OK;
   for (int32_t s = 0; s < ns && rc == ORC_OK; ++s) {

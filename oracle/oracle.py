@@ -392,7 +392,7 @@ def solve_pool(system, graph: Graph, kT, h1_diag=None, n_elec=None, fn=FN_FERMI,
     chunks = [list(map(int, order[w::workers])) for w in range(workers)]
     chunks = [c for c in chunks if c]
     h1 = None if h1_diag is None else np.atleast_2d(np.asarray(h1_diag, dtype=np.float64))
-    ctx = mp.get_context("fork")
+    ctx = mp.get_context("spawn")  # safe after a GPU runtime is initialised
     sa = (system.h_row_ptr, system.h_col, system.h_val)
     eps_l, wts_l = [None] * ns, [None] * ns
     items = [None] * ns

@@ -1,0 +1,273 @@
+// Graph estimate and core/halo partition (host, integer work).
+//
+// Sec. II.E: the data-dependency graph is estimated from the thresholded
+// density of a previous step together with the thresholded Hamiltonian, and
+// optionally widened by paths of length two.  Sec. II.C / Fig. 1: each core
+// (a set of atoms) with every atom joined to it forms a subgraph, whose
+// orbitals select a principal submatrix.  Eq. (sub_f): the collected result
+// keeps the core rows of each subgraph, so the collected pattern of orbital a
+// is the orbital set of the subgraph owning a.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "gq_internal.hpp"
+
+namespace gq {
+
+namespace {
+
+gq_status check_csr(const gq_csr* X, int32_t n, const char* name) {
+  if (!X || X->n_rows != n || !X->row_ptr || (X->nnz > 0 && (!X->col || !X->val))) {
+    set_error("%s: CSR header does not match N = %d", name, n);
+    return GQ_EINVAL;
+  }
+  if (X->row_ptr[0] != 0 || X->row_ptr[n] != X->nnz) {
+    set_error("%s: row_ptr must run from 0 to nnz", name);
+    return GQ_EINVAL;
+  }
+  for (int32_t a = 0; a < n; ++a) {
+    const int32_t b0 = X->row_ptr[a], b1 = X->row_ptr[a + 1];
+    if (b1 < b0) {
+      set_error("%s: row_ptr decreases at row %d", name, a);
+      return GQ_EINVAL;
+    }
+    for (int32_t p = b0; p < b1; ++p) {
+      const int32_t c = X->col[p];
+      if (c < 0 || c >= n || (p > b0 && c <= X->col[p - 1])) {
+        set_error("%s: row %d has columns out of range or not ascending", name, a);
+        return GQ_EINVAL;
+      }
+    }
+  }
+  return GQ_OK;
+}
+
+bool pattern_symmetric(const gq_csr* X) {
+  const int32_t n = X->n_rows;
+  for (int32_t a = 0; a < n; ++a) {
+    for (int32_t p = X->row_ptr[a]; p < X->row_ptr[a + 1]; ++p) {
+      const int32_t b = X->col[p];
+      const int32_t* first = X->col + X->row_ptr[b];
+      const int32_t* last = X->col + X->row_ptr[b + 1];
+      if (!std::binary_search(first, last, a)) return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const gq_csr* H,
+                           const gq_csr* rho_prev, const int32_t* core_of_atom, double tau,
+                           uint32_t flags, gq_graph* g) {
+  if (n_atoms <= 0 || !atom_orb_ptr || !core_of_atom || !H) {
+    set_error("graph_build: empty system or NULL input");
+    return GQ_EINVAL;
+  }
+  if (!(tau >= 0.0)) {
+    set_error("graph_build: tau must be >= 0 (got %g)", tau);
+    return GQ_EINVAL;
+  }
+  if (atom_orb_ptr[0] != 0) {
+    set_error("graph_build: atom_orb_ptr[0] must be 0");
+    return GQ_EINVAL;
+  }
+  for (int32_t I = 0; I < n_atoms; ++I) {
+    if (atom_orb_ptr[I + 1] <= atom_orb_ptr[I]) {
+      set_error("graph_build: atom_orb_ptr must be strictly increasing (atom %d)", I);
+      return GQ_EINVAL;
+    }
+  }
+  const int32_t N = atom_orb_ptr[n_atoms];
+  if (gq_status st = check_csr(H, N, "H")) return st;
+  if (rho_prev)
+    if (gq_status st = check_csr(rho_prev, N, "rho_prev")) return st;
+  if (!pattern_symmetric(H)) {
+    set_error("graph_build: the pattern of H is not symmetric");
+    return GQ_EINVAL;
+  }
+
+  int32_t n_sub = 0;
+  for (int32_t I = 0; I < n_atoms; ++I) {
+    if (core_of_atom[I] < 0) {
+      set_error("graph_build: negative core id at atom %d", I);
+      return GQ_EINVAL;
+    }
+    n_sub = std::max(n_sub, core_of_atom[I] + 1);
+  }
+  std::vector<std::vector<int32_t>> cores(n_sub);
+  for (int32_t I = 0; I < n_atoms; ++I) cores[core_of_atom[I]].push_back(I);
+  for (int32_t s = 0; s < n_sub; ++s) {
+    if (cores[s].empty()) {
+      set_error("graph_build: core ids must be dense; core %d is empty", s);
+      return GQ_EINVAL;
+    }
+  }
+
+  std::vector<int32_t> atom_of(N);
+  for (int32_t I = 0; I < n_atoms; ++I)
+    std::fill(atom_of.begin() + atom_orb_ptr[I], atom_of.begin() + atom_orb_ptr[I + 1], I);
+
+  // atom adjacency: every thresholded element joins its two atoms (both ways)
+  std::vector<std::vector<int32_t>> nbr(n_atoms);
+  auto scan = [&](const gq_csr* X) {
+    for (int32_t a = 0; a < N; ++a) {
+      const int32_t I = atom_of[a];
+      for (int32_t p = X->row_ptr[a]; p < X->row_ptr[a + 1]; ++p) {
+        if (!(std::fabs(X->val[p]) >= tau)) continue;
+        const int32_t J = atom_of[X->col[p]];
+        if (I == J) continue;
+        nbr[I].push_back(J);
+        nbr[J].push_back(I);
+      }
+    }
+  };
+  scan(H);
+  if (rho_prev) scan(rho_prev);
+  for (auto& v : nbr) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+
+  if (flags & GQ_PATHS2) {
+    std::vector<std::vector<int32_t>> two(n_atoms);
+    std::vector<int32_t> stamp(n_atoms, -1);
+    for (int32_t I = 0; I < n_atoms; ++I) {
+      stamp[I] = I;
+      auto& out = two[I];
+      for (int32_t J : nbr[I]) {
+        if (stamp[J] != I) { stamp[J] = I; out.push_back(J); }
+        for (int32_t L : nbr[J])
+          if (stamp[L] != I) { stamp[L] = I; out.push_back(L); }
+      }
+      std::sort(out.begin(), out.end());
+    }
+    nbr.swap(two);
+  }
+
+  // subgraphs: core ascending (already, atoms were visited in order) ++ halo ascending
+  g->n_atoms = n_atoms;
+  g->N = N;
+  g->n_sub = n_sub;
+  g->sub_ptr.assign(n_sub + 1, 0);
+  g->n_core_atoms.resize(n_sub);
+  g->sub_atoms.clear();
+  std::vector<int32_t> owner_mark(n_atoms, -1);
+  std::vector<int32_t> halo;
+  for (int32_t s = 0; s < n_sub; ++s) {
+    for (int32_t I : cores[s]) owner_mark[I] = s;
+    halo.clear();
+    if (flags & GQ_COMPLETE) {
+      for (int32_t I = 0; I < n_atoms; ++I)
+        if (core_of_atom[I] != s) halo.push_back(I);
+    } else {
+      for (int32_t I : cores[s])
+        for (int32_t J : nbr[I])
+          if (owner_mark[J] != s) { owner_mark[J] = s; halo.push_back(J); }
+      std::sort(halo.begin(), halo.end());
+    }
+    g->sub_atoms.insert(g->sub_atoms.end(), cores[s].begin(), cores[s].end());
+    g->sub_atoms.insert(g->sub_atoms.end(), halo.begin(), halo.end());
+    g->n_core_atoms[s] = (int32_t)cores[s].size();
+    if (g->sub_atoms.size() > (size_t)INT32_MAX) {
+      set_error("graph_build: subgraph vertex lists exceed int32");
+      return GQ_ENOMEM;
+    }
+    g->sub_ptr[s + 1] = (int32_t)g->sub_atoms.size();
+  }
+
+  // orbital maps
+  g->sub_orb_ptr.assign(n_sub + 1, 0);
+  g->n_core_orbs.resize(n_sub);
+  g->sub_orbs.clear();
+  for (int32_t s = 0; s < n_sub; ++s) {
+    int32_t c = 0;
+    for (int32_t q = g->sub_ptr[s]; q < g->sub_ptr[s + 1]; ++q) {
+      const int32_t I = g->sub_atoms[q];
+      for (int32_t a = atom_orb_ptr[I]; a < atom_orb_ptr[I + 1]; ++a) g->sub_orbs.push_back(a);
+      if (q - g->sub_ptr[s] < g->n_core_atoms[s]) c += atom_orb_ptr[I + 1] - atom_orb_ptr[I];
+    }
+    if (g->sub_orbs.size() > (size_t)INT32_MAX) {
+      set_error("graph_build: orbital lists exceed int32");
+      return GQ_ENOMEM;
+    }
+    g->n_core_orbs[s] = c;
+    g->sub_orb_ptr[s + 1] = (int32_t)g->sub_orbs.size();
+  }
+
+  // sorted orbital lists, their local indices, and the column slot of every local orbital
+  const size_t sum_n = g->sub_orbs.size();
+  g->sorted_orbs.resize(sum_n);
+  g->sorted_local.resize(sum_n);
+  g->slot.resize(sum_n);
+  for (int32_t s = 0; s < n_sub; ++s) {
+    const int32_t b = g->sub_orb_ptr[s], n = g->sub_orb_ptr[s + 1] - b;
+    int32_t* loc = g->sorted_local.data() + b;
+    std::iota(loc, loc + n, 0);
+    const int32_t* orbs = g->sub_orbs.data() + b;
+    std::sort(loc, loc + n, [&](int32_t x, int32_t y) { return orbs[x] < orbs[y]; });
+    for (int32_t r = 0; r < n; ++r) {
+      g->sorted_orbs[b + r] = orbs[loc[r]];
+      g->slot[b + loc[r]] = r;
+    }
+  }
+
+  // collected pattern
+  g->rho_row_ptr.assign(N + 1, 0);
+  int64_t nnz = 0;
+  for (int32_t a = 0; a < N; ++a) {
+    const int32_t s = core_of_atom[atom_of[a]];
+    nnz += g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
+    if (nnz > INT32_MAX) {
+      set_error("graph_build: collected pattern exceeds int32 nonzeros");
+      return GQ_ENOMEM;
+    }
+    g->rho_row_ptr[a + 1] = (int32_t)nnz;
+  }
+  g->rho_col.resize(nnz);
+  for (int32_t s = 0; s < n_sub; ++s) {
+    const int32_t b = g->sub_orb_ptr[s], n = g->sub_orb_ptr[s + 1] - b;
+    for (int32_t j = 0; j < g->n_core_orbs[s]; ++j) {
+      const int32_t a = g->sub_orbs[b + j];
+      std::copy(g->sorted_orbs.begin() + b, g->sorted_orbs.begin() + b + n,
+                g->rho_col.begin() + g->rho_row_ptr[a]);
+    }
+  }
+
+  // per-subgraph offsets and a largest-first order
+  g->off2.assign(n_sub + 1, 0);
+  g->offc.assign(n_sub + 1, 0);
+  g->offcd.assign(n_sub + 1, 0);
+  int32_t max_n = 0, min_n = INT32_MAX, max_c = 0;
+  for (int32_t s = 0; s < n_sub; ++s) {
+    const int64_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
+    const int64_t c = g->n_core_orbs[s];
+    g->off2[s + 1] = g->off2[s] + n * n;
+    g->offc[s + 1] = g->offc[s] + c * n;
+    g->offcd[s + 1] = g->offcd[s] + (int32_t)c;
+    max_n = std::max<int32_t>(max_n, (int32_t)n);
+    min_n = std::min<int32_t>(min_n, (int32_t)n);
+    max_c = std::max<int32_t>(max_c, (int32_t)c);
+  }
+  g->order.resize(n_sub);
+  std::iota(g->order.begin(), g->order.end(), 0);
+  std::stable_sort(g->order.begin(), g->order.end(), [&](int32_t x, int32_t y) {
+    return (g->sub_orb_ptr[x + 1] - g->sub_orb_ptr[x]) > (g->sub_orb_ptr[y + 1] - g->sub_orb_ptr[y]);
+  });
+
+  gq_graph_info& in = g->info;
+  in.n_atoms = n_atoms;
+  in.n_orb = N;
+  in.n_sub = n_sub;
+  in.max_n = max_n;
+  in.min_n = min_n;
+  in.max_c = max_c;
+  in.nnz = nnz;
+  in.sum_n = (int64_t)sum_n;
+  in.sum_n2 = g->off2[n_sub];
+  in.sub_atoms_len = (int64_t)g->sub_atoms.size();
+  return GQ_OK;
+}
+
+}  // namespace gq

@@ -1,0 +1,136 @@
+// Internal declarations of libgq (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gq.h"
+
+namespace gq {
+
+// Largest subgraph the kernels accept (orbitals).  The eigensolver keeps four
+// wave-private copies of the tridiagonal and its rotations in LDS.
+constexpr int kMaxN = 1024;
+// Core rows handled per workgroup in the core-row products.
+constexpr int kRowChunk = 16;
+// Points per multisection pass of the chemical-potential search.
+constexpr int kMuPoints = 128;
+constexpr int kMuPasses = 9;
+
+void set_error(const char* fmt, ...);
+
+#define GQ_HIP(call)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::gq::set_error("%s failed: %s", #call, hipGetErrorString(e_));            \
+      return GQ_EDEVICE;                                                         \
+    }                                                                            \
+  } while (0)
+
+}  // namespace gq
+
+// Per-kernel timing on the context stream (hipEvent pairs), enabled on demand.
+struct gq_prof_rec {
+  const char* name;
+  hipEvent_t start, stop;
+};
+struct gq_prof_stat {
+  const char* name;
+  int64_t count;
+  double total_ms;
+};
+
+struct gq_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool profiling = false;
+  std::vector<gq_prof_rec> pending;
+  std::vector<gq_prof_stat> stats;
+};
+
+// Device copy of the index maps of a graph.
+struct gq_graph_dev {
+  int device = -1;
+  int32_t* sub_orb_ptr = nullptr;  // [n_sub+1]
+  int32_t* sub_orbs = nullptr;     // [sum_n]
+  int32_t* n_core = nullptr;       // [n_sub]
+  int32_t* sorted_orbs = nullptr;  // [sum_n] ascending orbitals per subgraph
+  int32_t* sorted_local = nullptr; // [sum_n] local index of each sorted entry
+  int32_t* slot = nullptr;         // [sum_n] column slot of each local orbital
+  int64_t* off2 = nullptr;         // [n_sub+1] offsets of n_i^2 arrays
+  int64_t* offc = nullptr;         // [n_sub+1] offsets of c_i n_i blocks
+  int32_t* offcd = nullptr;        // [n_sub+1] offsets of c_i arrays
+  int32_t* order = nullptr;        // subgraphs by decreasing n
+  int32_t* rho_row_ptr = nullptr;  // [N+1]
+  int32_t* tiles = nullptr;        // [n_tiles*3] (subgraph, tile row, tile col), lower triangle
+  int32_t n_tiles = 0;
+};
+
+struct gq_graph {
+  int32_t n_atoms = 0, N = 0, n_sub = 0;
+  std::vector<int32_t> sub_ptr, sub_atoms, n_core_atoms;
+  std::vector<int32_t> sub_orb_ptr, sub_orbs, n_core_orbs;
+  std::vector<int32_t> rho_row_ptr, rho_col;
+  std::vector<int32_t> sorted_orbs, sorted_local, slot;
+  std::vector<int64_t> off2, offc;
+  std::vector<int32_t> offcd;
+  std::vector<int32_t> order;
+  gq_graph_info info{};
+  mutable gq_graph_dev dev;
+};
+
+struct gq_eigs {
+  gq_ctx* ctx = nullptr;
+  const gq_graph* g = nullptr;
+  int32_t max_k = 0;
+  double* A = nullptr;      // [sum n^2] gathered matrix / tridiagonal work, then dF
+  double* Q = nullptr;      // [sum n^2] eigenvectors, column-major per subgraph
+  double* Y = nullptr;      // [sum n^2] response scratch (X o dF)
+  double* T = nullptr;      // [sum c n] response scratch (Q_c Y)
+  double* eps = nullptr;    // [sum n]
+  double* wts = nullptr;    // [sum n]
+  double* dd = nullptr;     // [sum n] tridiagonal diagonal
+  double* ee = nullptr;     // [sum n] tridiagonal off-diagonal
+  double* tau = nullptr;    // [sum n] reflector scalars
+  double* M = nullptr;      // [sum c n] mu-response rows 2 beta Q_c diag(f(1-f)) Q^T
+  double* tmu = nullptr;    // [n_sub]
+  double* pdiag = nullptr;  // [max_k][sum c] diagonal of P (for the core traces)
+  double* mu1 = nullptr;    // [max_k]
+  double* mu_state = nullptr;  // lo, hi, mu, kT, n_elec, ...
+  double* mu_part = nullptr;   // [blocks][kMuPoints]
+  int32_t mu_blocks = 0;
+  int32_t* status = nullptr;   // [n_sub] eigensolver status (0 ok)
+  bool have_density = false;
+  double kT = 0, n_elec = 0;
+};
+
+namespace gq {
+
+gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const gq_csr* H,
+                           const gq_csr* rho_prev, const int32_t* core_of_atom, double tau,
+                           uint32_t flags, gq_graph* g);
+gq_status graph_upload(const gq_graph* g, int device);
+void graph_free_dev(const gq_graph* g);
+
+// Marks the start / end of a timed launch on ctx->stream (no-ops unless profiling).
+void prof_begin(gq_ctx* ctx, const char* name);
+void prof_end(gq_ctx* ctx);
+
+// kernel launchers (all asynchronous on ctx->stream)
+void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status);
+void eig_set_attributes();
+int mu_blocks_for(int64_t count);
+void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_blocks);
+void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h1, int32_t K,
+                     uint32_t precision, double* p_blocks);
+void launch_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks, int32_t K,
+                     double* vals);
+
+}  // namespace gq

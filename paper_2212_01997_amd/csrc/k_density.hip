@@ -1,0 +1,290 @@
+// Shared chemical potential, density core rows, mu-response rows and the
+// divided-difference matrix of the Fermi function (gfx950, FP64).
+//
+// Sec. II.G: one mu for all subgraphs solves 2 sum_{i,k} w_ik f(eps_ik; mu) =
+// N_e with w_ik the squared core part of eigenvector k.  Found here by
+// multisection: every pass evaluates the occupation at kMuPoints chemical
+// potentials inside the current bracket (block partial sums, then one
+// fixed-order reduction), keeping the bracket on the device.
+// Eq. (DD): core rows 2 Q_c diag(f) Q^T.  Eq. (dddmu): 2 beta Q_c diag(f(1-f)) Q^T.
+// Divided differences dF_kl = (f_k - f_l)/(e_k - e_l) use the exact form
+//   -(beta/4) sinhc(x) / (cosh(y_k) cosh(y_l)),  y = beta (e - mu)/2,  x = y_k - y_l,
+// with each cosh written as e^{|y|}(1 + e^{-2|y|})/2, so that nothing overflows
+// and equal eigenvalues give f'(e) without a special case.
+#include <cfloat>
+
+#include "gq_internal.hpp"
+
+namespace gq {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMuChunk = 1024;  // (eps, w) pairs per block of the occupation pass
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ double block_sum(double x, double* red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = x;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kThreads / 64; ++i) t += red[i];
+  return t;
+}
+
+// Fermi occupation and f(1-f) from t = exp(-|x|), x = (e - mu)/kT
+__device__ __forceinline__ void fermi2(double e, double mu, double beta, double& f, double& f1f) {
+  const double x = (e - mu) * beta;
+  const double t = exp(-fabs(x));
+  const double inv = 1.0 / (1.0 + t);
+  f = x > 0.0 ? t * inv : inv;
+  f1f = t * inv * inv;
+}
+
+// state: [0] lo, [1] hi, [2] mu, [3] kT, [4] n_elec
+__global__ __launch_bounds__(kThreads) void k_mu_init(const double* __restrict__ eps, int64_t count,
+                                                      double* __restrict__ state, double kT,
+                                                      double n_elec) {
+  __shared__ double rmin[kThreads], rmax[kThreads];
+  double lo = DBL_MAX, hi = -DBL_MAX;
+  for (int64_t i = threadIdx.x; i < count; i += kThreads) {
+    lo = fmin(lo, eps[i]);
+    hi = fmax(hi, eps[i]);
+  }
+  rmin[threadIdx.x] = lo;
+  rmax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      rmin[threadIdx.x] = fmin(rmin[threadIdx.x], rmin[threadIdx.x + o]);
+      rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    state[0] = rmin[0] - 50.0 * kT;
+    state[1] = rmax[0] + 50.0 * kT;
+    state[2] = 0.5 * (state[0] + state[1]);
+    state[3] = kT;
+    state[4] = n_elec;
+  }
+}
+
+__device__ __forceinline__ double mu_point(double lo, double hi, int j) {
+  return lo + (hi - lo) * ((double)(j + 1) / (double)(kMuPoints + 1));
+}
+
+__global__ __launch_bounds__(kThreads) void k_mu_eval(const double* __restrict__ eps,
+                                                      const double* __restrict__ wts, int64_t count,
+                                                      const double* __restrict__ state,
+                                                      double* __restrict__ part) {
+  __shared__ double se[kMuChunk], sw[kMuChunk];
+  __shared__ double half[kMuPoints];
+  const int64_t base = (int64_t)blockIdx.x * kMuChunk;
+  const int cnt = (int)min<int64_t>(kMuChunk, count - base);
+  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+    se[i] = eps[base + i];
+    sw[i] = wts[base + i];
+  }
+  __syncthreads();
+  const double lo = state[0], hi = state[1], beta = 1.0 / state[3];
+  const int j = threadIdx.x % kMuPoints;
+  const int h = threadIdx.x / kMuPoints;  // 0 or 1
+  const double mu = mu_point(lo, hi, j);
+  double acc = 0.0;
+  for (int p = h; p < cnt; p += kThreads / kMuPoints) {
+    double f, f1f;
+    fermi2(se[p], mu, beta, f, f1f);
+    acc += sw[p] * f;
+  }
+  if (h == 1) half[j] = acc;
+  __syncthreads();
+  if (h == 0) part[(size_t)blockIdx.x * kMuPoints + j] = acc + half[j];
+}
+
+__global__ __launch_bounds__(kMuPoints) void k_mu_update(const double* __restrict__ part, int nblk,
+                                                         double* __restrict__ state) {
+  __shared__ double F[kMuPoints];
+  const int j = threadIdx.x;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * kMuPoints + j];
+  F[j] = 2.0 * acc - state[4];
+  __syncthreads();
+  if (j == 0) {
+    const double lo = state[0], hi = state[1];
+    int first = kMuPoints;
+    for (int q = 0; q < kMuPoints; ++q)
+      if (F[q] >= 0.0) {
+        first = q;
+        break;
+      }
+    const double nlo = first == 0 ? lo : mu_point(lo, hi, first - 1);
+    const double nhi = first == kMuPoints ? hi : mu_point(lo, hi, first);
+    state[0] = nlo;
+    state[1] = nhi;
+    state[2] = 0.5 * (nlo + nhi);
+  }
+}
+
+// Core-row products out[j, l] = sum_k L[j, k] R[l + n k] for a chunk of
+// kRowChunk core rows j and kThreads columns l of one subgraph.  The density
+// form has L = Q_c diag(g) for two weight vectors g at once.
+__global__ __launch_bounds__(kThreads) void k_density_rows(
+    const double* __restrict__ qbuf, const double* __restrict__ eps,
+    const double* __restrict__ wts, const int64_t* __restrict__ off2,
+    const int64_t* __restrict__ offc, const int32_t* __restrict__ sub_orb_ptr,
+    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order,
+    const double* __restrict__ state, double* __restrict__ rho, double* __restrict__ mrows,
+    double* __restrict__ tmu) {
+  __shared__ double gf[64], gm[64];
+  __shared__ double Lr[kRowChunk][64 + 1], Lm[kRowChunk][64 + 1];
+  __shared__ double red[8];
+  const int s = order[blockIdx.x];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const int c = n_core[s];
+  const int l = blockIdx.y * kThreads + threadIdx.x;
+  const int j0 = blockIdx.z * kRowChunk;
+  if (blockIdx.y * kThreads >= n || j0 >= c) return;
+  const double mu = state[2], beta = 1.0 / state[3];
+  const double* Q = qbuf + off2[s];
+  const double* e = eps + b;
+
+  if (blockIdx.y == 0 && blockIdx.z == 0) {
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n; k += kThreads) {
+      double f, f1f;
+      fermi2(e[k], mu, beta, f, f1f);
+      acc += f1f * wts[b + k];
+    }
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) tmu[s] = 2.0 * beta * t;
+  }
+
+  double ar[kRowChunk], am[kRowChunk];
+#pragma unroll
+  for (int jj = 0; jj < kRowChunk; ++jj) ar[jj] = am[jj] = 0.0;
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int k = k0 + threadIdx.x;
+      double f = 0.0, f1f = 0.0;
+      if (k < n) fermi2(e[k], mu, beta, f, f1f);
+      gf[threadIdx.x] = 2.0 * f;
+      gm[threadIdx.x] = 2.0 * beta * f1f;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kRowChunk * 64; idx += kThreads) {
+      const int jj = idx % kRowChunk, kk = idx / kRowChunk;
+      const int j = j0 + jj, k = k0 + kk;
+      const double q = (j < c && k < n) ? Q[j + (size_t)n * k] : 0.0;
+      Lr[jj][kk] = q * gf[kk];
+      Lm[jj][kk] = q * gm[kk];
+    }
+    __syncthreads();
+    if (l < n) {
+      const int kend = min(64, n - k0);
+      for (int kk = 0; kk < kend; ++kk) {
+        const double r = Q[l + (size_t)n * (k0 + kk)];
+#pragma unroll
+        for (int jj = 0; jj < kRowChunk; ++jj) {
+          ar[jj] += Lr[jj][kk] * r;
+          am[jj] += Lm[jj][kk] * r;
+        }
+      }
+    }
+  }
+  if (l < n) {
+    const size_t base = offc[s];
+#pragma unroll
+    for (int jj = 0; jj < kRowChunk; ++jj) {
+      const int j = j0 + jj;
+      if (j < c) {
+        if (rho) rho[base + (size_t)j * n + l] = ar[jj];
+        mrows[base + (size_t)j * n + l] = am[jj];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_divided_differences(
+    const double* __restrict__ eps, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
+    const double* __restrict__ state, double* __restrict__ dfbuf) {
+  const int s = order[blockIdx.x];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const size_t nn = (size_t)n * n;
+  const size_t start = (size_t)blockIdx.y * kThreads * 16;
+  if (start >= nn) return;
+  const double mu = state[2], beta = 1.0 / state[3];
+  double* dF = dfbuf + off2[s];
+  const size_t end = min(nn, start + (size_t)kThreads * 16);
+  for (size_t idx = start + threadIdx.x; idx < end; idx += kThreads) {
+    const int k = (int)(idx % n), l = (int)(idx / n);
+    const double ek = eps[b + k], el = eps[b + l];
+    const double ak = fabs(0.5 * beta * (ek - mu)), al = fabs(0.5 * beta * (el - mu));
+    const double den = (1.0 + exp(-2.0 * ak)) * (1.0 + exp(-2.0 * al));
+    const double x = fabs(0.5 * beta * (ek - el));
+    double val;
+    if (x < 0.5) {
+      const double shc = x == 0.0 ? 1.0 : sinh(x) / x;
+      val = -beta * shc * exp(-(ak + al)) / den;
+    } else {
+      val = -beta * (exp(x - ak - al) - exp(-x - ak - al)) / (2.0 * x * den);
+    }
+    dF[idx] = val;
+  }
+}
+
+}  // namespace
+
+void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
+  const int64_t count = g->info.sum_n;
+  hipStream_t st = ctx->stream;
+  prof_begin(ctx, "k_mu");
+  hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(kThreads), 0, st, e->eps, count, e->mu_state, e->kT,
+                     e->n_elec);
+  const int nblk = (int)((count + kMuChunk - 1) / kMuChunk);
+  for (int pass = 0; pass < kMuPasses; ++pass) {
+    hipLaunchKernelGGL(k_mu_eval, dim3(nblk), dim3(kThreads), 0, st, e->eps, e->wts, count,
+                       e->mu_state, e->mu_part);
+    hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(kMuPoints), 0, st, e->mu_part, nblk, e->mu_state);
+  }
+  prof_end(ctx);
+}
+
+int mu_blocks_for(int64_t count) { return (int)((count + kMuChunk - 1) / kMuChunk); }
+
+void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_blocks) {
+  const gq_graph_dev& dv = g->dev;
+  hipStream_t st = ctx->stream;
+  prof_begin(ctx, "k_density_rows");
+  dim3 grid(g->n_sub, (g->info.max_n + kThreads - 1) / kThreads,
+            (g->info.max_c + kRowChunk - 1) / kRowChunk);
+  hipLaunchKernelGGL(k_density_rows, grid, dim3(kThreads), 0, st, e->Q, e->eps, e->wts, dv.off2,
+                     dv.offc, dv.sub_orb_ptr, dv.n_core, dv.order, e->mu_state, rho_blocks, e->M,
+                     e->tmu);
+  prof_end(ctx);
+}
+
+void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
+  const gq_graph_dev& dv = g->dev;
+  hipStream_t st = ctx->stream;
+  prof_begin(ctx, "k_divided_differences");
+  const size_t maxnn = (size_t)g->info.max_n * g->info.max_n;
+  dim3 grid(g->n_sub, (unsigned)((maxnn + kThreads * 16 - 1) / (kThreads * 16)));
+  hipLaunchKernelGGL(k_divided_differences, grid, dim3(kThreads), 0, st, e->eps, dv.off2,
+                     dv.sub_orb_ptr, dv.order, e->mu_state, e->A);
+  prof_end(ctx);
+}
+
+}  // namespace gq

@@ -1,0 +1,71 @@
+"""The whole path on one GPU through the C ABI (marshalling only).
+
+    graph_build -> submatrix_solve -> density -> response -> assemble
+
+Buffers are torch tensors on the context's device; every arithmetic step runs
+in libgq's HIP kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import gq
+
+
+class GraphPath:
+    """Device state of one system on one graph, reusable across perturbations."""
+
+    def __init__(self, ctx: gq.Context, system, core_of_atom, tau, rho_prev=None, flags=0,
+                 max_k=1, graph: gq.Graph | None = None, H: gq.DeviceCsr | None = None):
+        import torch
+        self.ctx = ctx
+        self.system = system
+        self.graph = graph or gq.Graph.for_system(system, core_of_atom, tau, rho_prev, flags)
+        self.H = H or gq.DeviceCsr(system.h_row_ptr, system.h_col, system.h_val, ctx.device)
+        self.eigs = gq.Eigs(ctx, self.graph, max_k)
+        nnz = self.graph.info.nnz
+        dev = torch.device("cuda", ctx.device)
+        self.max_k = max_k
+        self.rho_blocks = torch.empty(nnz, dtype=torch.float64, device=dev)
+        self.rho = torch.empty(nnz, dtype=torch.float64, device=dev)
+        self.p_blocks = torch.empty(max_k * nnz, dtype=torch.float64, device=dev)
+        self.rho1 = torch.empty(max_k * nnz, dtype=torch.float64, device=dev)
+        self.mu1_dev = torch.empty(max_k, dtype=torch.float64, device=dev)
+
+    @property
+    def nnz(self):
+        return self.graph.info.nnz
+
+    def ground_state(self, kT, n_elec=None, want_mu=True):
+        """submatrix_solve + density + assemble(rho)."""
+        ne = self.system.n_elec if n_elec is None else n_elec
+        self.eigs.solve(self.H)
+        mu = self.eigs.density(kT, ne, self.rho_blocks, want_mu=want_mu)
+        gq.assemble(self.ctx, self.graph, self.rho_blocks, self.rho, 1)
+        return mu
+
+    def respond(self, h1, precision=gq.PREC_FP64, want_mu1=True):
+        """response + assemble(rho1) for K = h1.shape[0] perturbations."""
+        K = int(h1.shape[0])
+        mu1 = self.eigs.response(h1, self.p_blocks[:K * self.nnz], precision,
+                                 mu1_dev=self.mu1_dev[:K], want_mu1=want_mu1)
+        gq.assemble(self.ctx, self.graph, self.p_blocks[:K * self.nnz], self.rho1[:K * self.nnz], K)
+        return mu1
+
+    def rho1_view(self, K):
+        return self.rho1[:K * self.nnz].view(K, self.nnz)
+
+
+def bootstrap_prev(ctx, system, core_of_atom, kT):
+    """Previous-step density for the graph estimate: one pass of the path on
+    the graph of every nonzero of H.  Returns the host CSR triple."""
+    p = GraphPath(ctx, system, core_of_atom, 0.0)
+    p.ground_state(kT, want_mu=False)
+    ex = p.graph.export()
+    vals = p.rho.cpu().numpy()
+    return ex["rho_row_ptr"], ex["rho_col"], vals
+
+
+def collected_rows(graph_export):
+    rp = graph_export["rho_row_ptr"]
+    return np.repeat(np.arange(len(rp) - 1), np.diff(rp))

@@ -1,0 +1,218 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, element by element.
+
+Bar (FP64 path): rho, rho1 and mu1 within 1e-10 max-abs, mu within 1e-12,
+eigenvalues within 1e-12; graph maps bit-exact.  The oracle's inputs come from
+the seeded generator only (its bootstrap density included); the GPU gets the
+same inputs.  Large oracle runs use the oracle's process pool (spawned workers,
+identical results to its serial path).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2212_01997_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+KT = 0.01
+TOL = 1e-10
+TOL_MU = 1e-12
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2212_01997_amd import gq
+    return gq.Context(0)
+
+
+def run_gpu(ctx, system, core, tau, prev, flags, kT, h1):
+    import torch
+    from paper_2212_01997_amd.path import GraphPath
+    K = h1.shape[0]
+    p = GraphPath(ctx, system, core, tau, prev, flags, max_k=K)
+    mu = p.ground_state(kT)
+    mu1 = p.respond(torch.as_tensor(h1, device="cuda"))
+    torch.cuda.synchronize()
+    eps, w = p.eigs.export()
+    return {"mu": mu, "mu1": mu1, "rho": p.rho.cpu().numpy(),
+            "rho1": p.rho1_view(K).cpu().numpy(), "eps": eps, "w": w,
+            "graph": p.graph.export(), "path": p}
+
+
+def run_oracle(O, system, core, tau, prev, flags, kT, h1, pool=False):
+    g = O.graph_build(system, core, tau, rho_prev=prev, flags=flags)
+    if pool:
+        r = O.solve_pool(system, g, kT, h1, workers=min(16, os.cpu_count() or 1))
+    else:
+        r = O.solve(system, g, kT, h1)
+    return g, r
+
+
+def compare(gpu, g, r, tol=TOL, tol_mu=TOL_MU):
+    ex = gpu["graph"]
+    for name in ("sub_orb_ptr", "sub_orbs", "n_core_orbs", "rho_row_ptr", "rho_col"):
+        assert np.array_equal(ex[name], getattr(g, name)), name
+    assert abs(gpu["mu"] - r.mu) <= tol_mu, (gpu["mu"], r.mu)
+    assert np.abs(gpu["eps"] - r.eps).max() <= 1e-12
+    assert np.abs(gpu["rho"] - r.rho).max() <= tol
+    assert np.abs(gpu["mu1"] - r.mu1).max() <= tol
+    assert np.abs(gpu["rho1"] - r.rho1).max() <= tol
+
+
+def case_config1(O, tau, flags, kT=KT, K=2):
+    s = I.config_system(1)
+    core = I.single_atom_cores(s)
+    prev = O.bootstrap_prev(s, core, KT)
+    return s, core, prev, I.h1_diagonal(s, K, seed=1002)
+
+
+@pytest.mark.parametrize("tau,flags", [(1e-5, 0), (0.07, 1), (1e-5, 2)],
+                         ids=["tau1e-5", "paths2_tau0.07", "complete"])
+def test_config1(ctx, oracle_lib, tau, flags):
+    O = oracle_lib
+    s, core, prev, h1 = case_config1(O, tau, flags)
+    _say(f"config1 tau={tau} flags={flags}")
+    g, r = run_oracle(O, s, core, tau, prev, flags, KT, h1)
+    gpu = run_gpu(ctx, s, core, tau, prev, flags, KT, h1)
+    compare(gpu, g, r)
+
+
+@pytest.mark.parametrize("kT", [0.003, 0.03])
+def test_config1_temperatures(ctx, oracle_lib, kT):
+    O = oracle_lib
+    s, core, prev, h1 = case_config1(O, 0.07, 1)
+    _say(f"config1 kT={kT}")
+    g, r = run_oracle(O, s, core, 0.07, prev, 1, kT, h1)
+    gpu = run_gpu(ctx, s, core, 0.07, prev, 1, kT, h1)
+    compare(gpu, g, r)
+
+
+def test_water60_spatial_cores(ctx, oracle_lib):
+    """8-atom spatial cores, paths of two: several 64-wide tiles and ragged tails."""
+    O = oracle_lib
+    s = I.water_system(60, 12.2, seed=61)
+    core = I.spatial_cores(s, 8)
+    prev = O.bootstrap_prev(s, core, KT)
+    h1 = I.h1_diagonal(s, 3, seed=62)
+    g, r = run_oracle(O, s, core, 0.07, prev, 1, KT, h1, pool=True)
+    _say(f"water60 sizes {g.sizes().min()}..{g.sizes().max()}")
+    gpu = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
+    compare(gpu, g, r)
+
+
+def test_chain_in_water(ctx, oracle_lib):
+    O = oracle_lib
+    s = I.chain_water_system(900, 180, seed=3001)
+    core = I.spatial_cores(s, 8)
+    prev = O.bootstrap_prev(s, core, KT, pool=True)
+    h1 = I.h1_diagonal(s, 2, seed=3002)
+    g, r = run_oracle(O, s, core, 0.07, prev, 1, KT, h1, pool=True)
+    _say(f"chain900 sizes {g.sizes().min()}..{g.sizes().max()}")
+    gpu = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
+    compare(gpu, g, r)
+
+
+def _h_line(n_atoms, spacing=1.0):
+    pos = np.zeros((n_atoms, 3))
+    pos[:, 0] = np.arange(n_atoms) * spacing + 0.5
+    box = max(n_atoms * spacing + 9.0, 10.0)
+    return I.make_system(f"hline{n_atoms}", box, pos, ["H"] * n_atoms, {})
+
+
+@pytest.mark.parametrize("n_atoms", [63, 64, 65, 130])
+def test_tile_edges_complete(ctx, oracle_lib, n_atoms):
+    """Subgraphs of exactly 63/64/65/130 orbitals (tile boundaries)."""
+    O = oracle_lib
+    s = _h_line(n_atoms)
+    core = (np.arange(n_atoms) // 9).astype(np.int32)
+    h1 = I.h1_diagonal(s, 1, seed=5)
+    g, r = run_oracle(O, s, core, 0.0, None, 2, KT, h1)
+    assert (g.sizes() == n_atoms).all()
+    gpu = run_gpu(ctx, s, core, 0.0, None, 2, KT, h1)
+    compare(gpu, g, r)
+
+
+def test_tiny_subgraphs(ctx, oracle_lib):
+    """Isolated molecules and a lone atom: subgraphs of 1, 3 and 6 orbitals."""
+    O = oracle_lib
+    w = I.isolated_molecules_system(7, 8.0, seed=9)
+    pos = np.concatenate([w.pos, [[w.box - 0.5, w.box - 0.5, w.box - 0.5]]])
+    s = I.make_system("iso+H", w.box, pos, w.species + ["H"], {})
+    core = I.single_atom_cores(s)
+    h1 = I.h1_diagonal(s, 1, seed=10)
+    g, r = run_oracle(O, s, core, 1e-6, None, 0, KT, h1)
+    assert g.sizes().min() == 1
+    gpu = run_gpu(ctx, s, core, 1e-6, None, 0, KT, h1)
+    compare(gpu, g, r)
+
+
+def test_deterministic(ctx, oracle_lib):
+    O = oracle_lib
+    s, core, prev, h1 = case_config1(O, 0.07, 1)
+    a = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
+    b = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
+    assert a["mu"] == b["mu"]
+    assert np.array_equal(a["rho"], b["rho"]) and np.array_equal(a["rho1"], b["rho1"])
+    assert np.array_equal(a["mu1"], b["mu1"])
+
+
+@pytest.fixture(scope="module")
+def config2(oracle_lib):
+    """The benchmark workload: 1,000 waters, 8-atom cores, paths of two at
+    tau = 0.07 on the bootstrap density; one perturbation."""
+    O = oracle_lib
+    s = I.config_system(2)
+    core = I.spatial_cores(s, 8)
+    _say("config2 oracle bootstrap")
+    prev = O.bootstrap_prev(s, core, KT, pool=True)
+    h1 = I.h1_diagonal(s, 1, seed=2002)
+    _say("config2 oracle solve")
+    g, r = run_oracle(O, s, core, 0.07, prev, 1, KT, h1, pool=True)
+    return s, core, prev, h1, g, r
+
+
+def test_config2_full_size(ctx, config2):
+    s, core, prev, h1, g, r = config2
+    _say(f"config2 gpu: sizes {g.sizes().min()}..{g.sizes().max()}")
+    gpu = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
+    compare(gpu, g, r)
+
+
+def test_config2_invariants(ctx, config2):
+    """Properties that hold at any size: Tr rho = N_e, Tr rho1 = 0, and
+    H1 = I gives mu1 = 1 with rho1 = 0."""
+    s, core, prev, h1, g, r = config2
+    h = np.vstack([h1, np.ones((1, s.n_orb))])
+    gpu = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h)
+    rows = np.repeat(np.arange(s.n_orb), np.diff(gpu["graph"]["rho_row_ptr"]))
+    diag = rows == gpu["graph"]["rho_col"]
+    assert abs(gpu["rho"][diag].sum() - s.n_elec) <= 1e-11 * s.n_elec
+    assert abs(gpu["rho1"][0][diag].sum()) <= 1e-10
+    assert abs(gpu["mu1"][1] - 1.0) <= 1e-12
+    assert np.abs(gpu["rho1"][1]).max() <= 1e-10
+
+
+def test_error_paths(ctx):
+    import torch
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath
+    s = I.config_system(1)
+    p = GraphPath(ctx, s, I.single_atom_cores(s), 1e-3, max_k=1)
+    h1 = torch.zeros((1, s.n_orb), dtype=torch.float64, device="cuda")
+    with pytest.raises(gq.GQError, match="gq_density first"):
+        p.eigs.response(h1, p.p_blocks)
+    p.eigs.solve(p.H)
+    with pytest.raises(gq.GQError, match="kT"):
+        p.eigs.density(0.0, s.n_elec)
+    with pytest.raises(gq.GQError, match="N_e"):
+        p.eigs.density(0.01, 2.0 * s.n_orb)
+    p.eigs.density(0.01, s.n_elec)
+    with pytest.raises(gq.GQError, match="max_k"):
+        p.eigs.response(torch.zeros((2, s.n_orb), dtype=torch.float64, device="cuda"), p.p_blocks)
