@@ -162,59 +162,65 @@ class _Grid:
         return r.min()
 
 
-def place_waters(rng, n_mol, box, grid=None, max_tries=200000,
-                 oo_min=2.5, inter_min=1.5, heavy_min=2.5):
-    """Random sequential addition of rigid waters into a periodic box.
-
-    `grid` may already hold other atoms (tag 'X' = foreign heavy atom); new
-    oxygens keep `heavy_min` from them.  Returns an [n_mol*3, 3] array in
-    O, H, H order per molecule.
-    """
-    if grid is None:
-        grid = _Grid(box, 2.5)
+def place_waters(rng, n_mol, box, fixed=None, oo_min=2.5, inter_min=1.5, batch=2048,
+                 max_rounds=4000):
+    """Random sequential addition of rigid waters into a periodic box, in
+    batches: every candidate keeps `inter_min` from all placed atoms (waters
+    and the `fixed` foreign atoms) and its O keeps `oo_min` from placed
+    oxygens; conflicts inside a batch are resolved greedily in candidate
+    order.  Returns an [n_mol*3, 3] array in O, H, H order per molecule."""
     tmpl = _water_template()
+    placed = np.zeros((0, 3)) if fixed is None else np.mod(np.asarray(fixed, float), box)
+    oxy = np.zeros((0, 3))
     out = []
-    tries = 0
-    batch = 256
-    while len(out) < n_mol:
+    n_done = 0
+    rounds = 0
+    while n_done < n_mol:
+        rounds += 1
+        if rounds > max_rounds:
+            raise RuntimeError(f"water placement stalled ({n_done}/{n_mol} placed)")
         centers = rng.uniform(0.0, box, size=(batch, 3))
         rots = _random_rotations(rng, batch)
-        for c, rot in zip(centers, rots):
-            tries += 1
-            if tries > max_tries:
-                raise RuntimeError(f"water placement failed after {tries} tries "
-                                   f"({len(out)}/{n_mol} placed)")
-            atoms = c + tmpl @ rot.T
-            ok = True
-            for j, a in enumerate(atoms):
-                idx = grid.near(a)
-                if not idx:
-                    continue
-                pts = np.array([grid.pos[i] for i in idx])
-                d = pts - a
-                d -= box * np.round(d / box)
-                r = np.sqrt((d * d).sum(axis=1))
-                tags = [grid.tag[i] for i in idx]
-                for rr, t in zip(r, tags):
-                    if rr < inter_min:
-                        ok = False
-                        break
-                    if j == 0 and t == "O" and rr < oo_min:
-                        ok = False
-                        break
-                    if t == "X" and rr < heavy_min:
-                        ok = False
-                        break
-                if not ok:
-                    break
-            if not ok:
-                continue
-            grid.add(atoms[0], "O")
-            grid.add(atoms[1], "H")
-            grid.add(atoms[2], "H")
-            out.append(np.mod(atoms, box))
-            if len(out) == n_mol:
+        mol = np.mod(centers[:, None, :] + np.einsum("aj,bij->bai", tmpl, rots), box)  # [B,3,3]
+        ok = np.ones(batch, bool)
+        if len(placed):
+            t_all = cKDTree(placed, boxsize=box)
+            d, _ = t_all.query(mol.reshape(-1, 3), k=1)
+            ok &= (d.reshape(batch, 3) >= inter_min).all(axis=1)
+        if len(oxy):
+            t_o = cKDTree(oxy, boxsize=box)
+            d, _ = t_o.query(mol[:, 0, :], k=1)
+            ok &= d >= oo_min
+        idx = np.nonzero(ok)[0]
+        if len(idx) == 0:
+            continue
+        cand = mol[idx]
+        flat = cand.reshape(-1, 3)
+        tree = cKDTree(flat, boxsize=box)
+        pairs = tree.query_pairs(max(oo_min, inter_min), output_type="ndarray")
+        conflict = [[] for _ in range(len(idx))]
+        if len(pairs):
+            a, b = pairs[:, 0], pairs[:, 1]
+            ma, mb = a // 3, b // 3
+            dv = flat[a] - flat[b]
+            dv -= box * np.round(dv / box)
+            r = np.sqrt((dv * dv).sum(axis=1))
+            both_o = (a % 3 == 0) & (b % 3 == 0)
+            bad = (ma != mb) & ((r < inter_min) | (both_o & (r < oo_min)))
+            for x, y in zip(ma[bad], mb[bad]):
+                conflict[max(x, y)].append(min(x, y))
+        taken = np.zeros(len(idx), bool)
+        for m in range(len(idx)):
+            if n_done >= n_mol:
                 break
+            if any(taken[o] for o in conflict[m]):
+                continue
+            taken[m] = True
+            out.append(cand[m])
+            n_done += 1
+        acc = cand[taken]
+        placed = np.concatenate([placed, acc.reshape(-1, 3)])
+        oxy = np.concatenate([oxy, acc[:, 0, :]])
     return np.concatenate(out, axis=0) if out else np.zeros((0, 3))
 
 
@@ -341,11 +347,8 @@ def chain_water_system(n_atoms, n_chain, seed, density=0.1, name=None):
     elems = [e for e, _ in CHAIN_MIX]
     probs = np.array([p for _, p in CHAIN_MIX])
     chain_species = list(rng.choice(elems, size=n_chain, p=probs / probs.sum()))
-    grid = _Grid(box, 2.5)
-    for p in chain:
-        grid.add(p, "X")
     n_mol = (n_atoms - n_chain) // 3
-    water = place_waters(rng, n_mol, box, grid=grid)
+    water = place_waters(rng, n_mol, box, fixed=chain)
     pos = np.concatenate([chain, water], axis=0)
     species = chain_species + ["O", "H", "H"] * n_mol
     return make_system(name or f"chain{n_chain}_water{n_mol}", box, pos, species,
