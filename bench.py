@@ -159,14 +159,14 @@ def main():
     flops = work.get(dominant, 0.0)
     launches_per_step = kt[dominant][0] / nprof
     achieved = flops / (per_launch[dominant] * 1e-3) if flops else 0.0
-    bound = "alu" if dominant in ("k_ql", "k_tridiag", "k_formq") else "mfma"
+    bound = "alu" if dominant in ("k_tridiag", "k_dc_prep", "k_dc_leaves") else "mfma"
     roofline = {"bound": bound, "kernel": dominant, "achieved": achieved / 1e12,
                 "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
                 "traffic": None,
                 "algorithmic_flops_per_launch": flops, "launch_ms": per_launch[dominant],
                 "launches_per_step": launches_per_step}
     phases = {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda x: -x[1])}
-    eig_ms = sum(per_step.get(k, 0) for k in ("k_gather", "k_tridiag", "k_formq", "k_ql"))
+    eig_ms = sum(v for k, v in per_step.items() if k in ("k_gather", "k_tridiag") or k.startswith(("k_dc", "k_back")))
     resp_ms = sum(per_step.get(k, 0) for k in ("k_xy", "k_rows", "k_mu1_combine"))
     dens_ms = sum(per_step.get(k, 0) for k in ("k_mu", "k_density_rows", "k_divided_differences"))
     line = {

@@ -33,7 +33,8 @@ static gq_status dev_upload(T** dst, const std::vector<T>& src) {
 void graph_free_dev(const gq_graph* g) {
   gq_graph_dev& d = g->dev;
   void* ptrs[] = {d.sub_orb_ptr, d.sub_orbs, d.n_core, d.sorted_orbs, d.sorted_local, d.slot,
-                  d.off2, d.offc, d.offcd, d.order, d.rho_row_ptr, d.tiles};
+                  d.off2, d.offc, d.offcd, d.order, d.rho_row_ptr, d.tiles,
+                  d.dc_leaves, d.dc_merges, d.dc_tiles};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = gq_graph_dev{};
@@ -63,11 +64,14 @@ gq_status graph_upload(const gq_graph* g, int device) {
       (st = dev_upload(&d.sorted_local, g->sorted_local)) || (st = dev_upload(&d.slot, g->slot)) ||
       (st = dev_upload(&d.off2, g->off2)) || (st = dev_upload(&d.offc, g->offc)) ||
       (st = dev_upload(&d.offcd, g->offcd)) || (st = dev_upload(&d.order, g->order)) ||
-      (st = dev_upload(&d.rho_row_ptr, g->rho_row_ptr)) || (st = dev_upload(&d.tiles, tiles))) {
+      (st = dev_upload(&d.rho_row_ptr, g->rho_row_ptr)) || (st = dev_upload(&d.tiles, tiles)) ||
+      (st = dev_upload(&d.dc_leaves, g->dc_leaves)) || (st = dev_upload(&d.dc_merges, g->dc_merges)) ||
+      (st = dev_upload(&d.dc_tiles, g->dc_tiles))) {
     graph_free_dev(g);
     return st;
   }
   d.n_tiles = (int32_t)(tiles.size() / 3);
+  d.n_leaves = (int32_t)(g->dc_leaves.size() / 3);
   d.device = device;
   return GQ_OK;
 }
@@ -101,6 +105,7 @@ gq_status gq_ctx_create(int32_t device, void* hip_stream, gq_ctx** out) {
     return GQ_EDEVICE;
   }
   eig_set_attributes();
+  dc_set_attributes();
   gq_ctx* c = new (std::nothrow) gq_ctx;
   if (!c) {
     set_error("gq_ctx_create: out of host memory");
@@ -200,6 +205,7 @@ static int64_t footprint(const gq_graph* g, int32_t max_k) {
   b += (int64_t)g->n_sub * (8 + 4);  // tmu, status
   b += (int64_t)std::max(max_k, 1) * (sum_c + 1) * 8;  // pdiag, mu1
   b += (int64_t)mu_blocks_for(in.sum_n) * kMuPoints * 8 + 16 * 8;
+  b += in.sum_n * (4 * 8 + 5 * 4) + (int64_t)(g->dc_merges.size() / 4 + 1) * 4;  // merge metadata
   return b;
 }
 
@@ -215,7 +221,9 @@ gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, int64_t* bytes) {
 void gq_eigs_destroy(gq_eigs* e) {
   if (!e) return;
   void* ptrs[] = {e->A, e->Q, e->Y, e->T, e->eps, e->wts, e->dd, e->ee, e->tau, e->M,
-                  e->tmu, e->pdiag, e->mu1, e->mu_state, e->mu_part, e->status};
+                  e->tmu, e->pdiag, e->mu1, e->mu_state, e->mu_part, e->status,
+                  e->md_k, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
+                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete e;
@@ -251,7 +259,9 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
               {&e->ee, in.sum_n}, {&e->tau, in.sum_n}, {&e->tmu, g->n_sub},
               {&e->pdiag, (int64_t)std::max(max_k, 1) * std::max<int64_t>(sum_c, 1)},
               {&e->mu1, std::max(max_k, 1)}, {&e->mu_state, 16},
-              {&e->mu_part, (int64_t)e->mu_blocks * kMuPoints}};
+              {&e->mu_part, (int64_t)e->mu_blocks * kMuPoints},
+              {&e->md_delta, in.sum_n}, {&e->md_tau, in.sum_n}, {&e->md_zhat, in.sum_n},
+              {&e->md_inv, in.sum_n}};
   for (auto& r : reqs) {
     if (hipMalloc((void**)r.p, std::max<int64_t>(1, r.count) * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
@@ -261,11 +271,19 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
       return GQ_ENOMEM;
     }
   }
-  if (hipMalloc((void**)&e->status, std::max(1, g->n_sub) * sizeof(int32_t)) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("gq_eigs_create: device allocation failed");
-    gq_eigs_destroy(e);
-    return GQ_ENOMEM;
+  struct ReqI {
+    int32_t** p;
+    int64_t count;
+  } reqi[] = {{&e->status, g->n_sub}, {&e->md_k, (int64_t)(g->dc_merges.size() / 4)},
+              {&e->md_cols, in.sum_n}, {&e->md_org, in.sum_n}, {&e->md_pos, in.sum_n},
+              {&e->md_dsrc, in.sum_n}, {&e->md_dpos, in.sum_n}};
+  for (auto& r : reqi) {
+    if (hipMalloc((void**)r.p, std::max<int64_t>(1, r.count) * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("gq_eigs_create: device allocation failed");
+      gq_eigs_destroy(e);
+      return GQ_ENOMEM;
+    }
   }
   *out = e;
   return GQ_OK;

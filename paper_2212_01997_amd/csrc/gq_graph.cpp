@@ -267,7 +267,63 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   in.sum_n = (int64_t)sum_n;
   in.sum_n2 = g->off2[n_sub];
   in.sub_atoms_len = (int64_t)g->sub_atoms.size();
+  build_dc_plan(g);
   return GQ_OK;
+}
+
+}  // namespace gq
+
+namespace gq {
+
+// Halving tree of every subgraph's tridiagonal down to blocks of at most
+// kLeaf rows.  Merges are grouped by depth, deepest first, so each level only
+// needs the results of the levels before it; every level carries its list of
+// 64x64 output tiles.
+void build_dc_plan(gq_graph* g) {
+  struct Node {
+    int32_t lo, m, depth;
+  };
+  std::vector<std::vector<int32_t>> by_depth;
+  g->dc_leaves.clear();
+  for (int32_t s = 0; s < g->n_sub; ++s) {
+    const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
+    std::vector<Node> stack{{0, n, 0}};
+    while (!stack.empty()) {
+      const Node nd = stack.back();
+      stack.pop_back();
+      if (nd.m > kLeaf) {
+        const int32_t m1 = nd.m / 2;
+        if ((int32_t)by_depth.size() <= nd.depth) by_depth.resize(nd.depth + 1);
+        auto& v = by_depth[nd.depth];
+        v.insert(v.end(), {s, nd.lo, m1, nd.m - m1});
+        stack.push_back({nd.lo, m1, nd.depth + 1});
+        stack.push_back({nd.lo + m1, nd.m - m1, nd.depth + 1});
+      } else {
+        g->dc_leaves.insert(g->dc_leaves.end(), {s, nd.lo, nd.m});
+      }
+    }
+  }
+  g->dc_merges.clear();
+  g->dc_tiles.clear();
+  g->dc_level_merge_off.assign(1, 0);
+  g->dc_level_tile_off.assign(1, 0);
+  g->dc_level_maxm.clear();
+  for (int d = (int)by_depth.size() - 1; d >= 0; --d) {
+    const auto& v = by_depth[d];
+    int32_t maxm = 0;
+    for (size_t q = 0; q < v.size(); q += 4) {
+      const int32_t li = (int32_t)(q / 4);
+      const int32_t m = v[q + 2] + v[q + 3];
+      maxm = std::max(maxm, m);
+      const int32_t nt = (m + 63) / 64;
+      for (int32_t tr = 0; tr < nt; ++tr)
+        for (int32_t tc = 0; tc < nt; ++tc) g->dc_tiles.insert(g->dc_tiles.end(), {li, tr, tc});
+    }
+    g->dc_merges.insert(g->dc_merges.end(), v.begin(), v.end());
+    g->dc_level_merge_off.push_back((int32_t)(g->dc_merges.size() / 4));
+    g->dc_level_tile_off.push_back((int32_t)(g->dc_tiles.size() / 3));
+    g->dc_level_maxm.push_back(maxm);
+  }
 }
 
 }  // namespace gq

@@ -14,6 +14,8 @@ namespace gq {
 // Largest subgraph the kernels accept (orbitals).  The eigensolver keeps four
 // wave-private copies of the tridiagonal and its rotations in LDS.
 constexpr int kMaxN = 1024;
+// Largest tridiagonal block solved directly in the divide-and-conquer tree.
+constexpr int kLeaf = 32;
 // Core rows handled per workgroup in the core-row products.
 constexpr int kRowChunk = 16;
 // Points per multisection pass of the chemical-potential search.
@@ -68,6 +70,10 @@ struct gq_graph_dev {
   int32_t* rho_row_ptr = nullptr;  // [N+1]
   int32_t* tiles = nullptr;        // [n_tiles*3] (subgraph, tile row, tile col), lower triangle
   int32_t n_tiles = 0;
+  int32_t* dc_leaves = nullptr;    // [n_leaves*3] (subgraph, lo, m)
+  int32_t* dc_merges = nullptr;    // [n_merges*4] (subgraph, lo, m1, m2), deepest level first
+  int32_t* dc_tiles = nullptr;     // [*3] (merge index within its level, tile row, tile col)
+  int32_t n_leaves = 0;
 };
 
 struct gq_graph {
@@ -79,6 +85,9 @@ struct gq_graph {
   std::vector<int64_t> off2, offc;
   std::vector<int32_t> offcd;
   std::vector<int32_t> order;
+  // divide-and-conquer plan of the tridiagonal eigensolves
+  std::vector<int32_t> dc_leaves, dc_merges, dc_tiles;
+  std::vector<int32_t> dc_level_merge_off, dc_level_tile_off, dc_level_maxm;
   gq_graph_info info{};
   mutable gq_graph_dev dev;
 };
@@ -104,6 +113,10 @@ struct gq_eigs {
   double* mu_part = nullptr;   // [blocks][kMuPoints]
   int32_t mu_blocks = 0;
   int32_t* status = nullptr;   // [n_sub] eigensolver status (0 ok)
+  // merge metadata of the divide-and-conquer levels
+  int32_t *md_k = nullptr, *md_cols = nullptr, *md_org = nullptr, *md_pos = nullptr;
+  int32_t *md_dsrc = nullptr, *md_dpos = nullptr;
+  double *md_delta = nullptr, *md_tau = nullptr, *md_zhat = nullptr, *md_inv = nullptr;
   bool have_density = false;
   double kT = 0, n_elec = 0;
 };
@@ -123,6 +136,9 @@ void prof_end(gq_ctx* ctx);
 // kernel launchers (all asynchronous on ctx->stream)
 void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status);
 void eig_set_attributes();
+void dc_set_attributes();
+void build_dc_plan(gq_graph* g);
+void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
 int mu_blocks_for(int64_t count);
 void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
 void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);

@@ -206,7 +206,7 @@ def test_error_paths(ctx):
     s = I.config_system(1)
     p = GraphPath(ctx, s, I.single_atom_cores(s), 1e-3, max_k=1)
     h1 = torch.zeros((1, s.n_orb), dtype=torch.float64, device="cuda")
-    with pytest.raises(gq.GQError, match="gq_density first"):
+    with pytest.raises(gq.GQError, match="call gq_density"):
         p.eigs.response(h1, p.p_blocks)
     p.eigs.solve(p.H)
     with pytest.raises(gq.GQError, match="kT"):
