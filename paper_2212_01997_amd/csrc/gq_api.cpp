@@ -34,7 +34,7 @@ void graph_free_dev(const gq_graph* g) {
   gq_graph_dev& d = g->dev;
   void* ptrs[] = {d.sub_orb_ptr, d.sub_orbs, d.n_core, d.sorted_orbs, d.sorted_local, d.slot,
                   d.off2, d.offc, d.offcd, d.order, d.rho_row_ptr, d.tiles,
-                  d.dc_leaves, d.dc_merges, d.dc_tiles};
+                  d.dc_leaves, d.dc_merges, d.dc_tiles, d.bt_toff};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = gq_graph_dev{};
@@ -66,7 +66,7 @@ gq_status graph_upload(const gq_graph* g, int device) {
       (st = dev_upload(&d.offcd, g->offcd)) || (st = dev_upload(&d.order, g->order)) ||
       (st = dev_upload(&d.rho_row_ptr, g->rho_row_ptr)) || (st = dev_upload(&d.tiles, tiles)) ||
       (st = dev_upload(&d.dc_leaves, g->dc_leaves)) || (st = dev_upload(&d.dc_merges, g->dc_merges)) ||
-      (st = dev_upload(&d.dc_tiles, g->dc_tiles))) {
+      (st = dev_upload(&d.dc_tiles, g->dc_tiles)) || (st = dev_upload(&d.bt_toff, g->bt_toff))) {
     graph_free_dev(g);
     return st;
   }
@@ -206,6 +206,7 @@ static int64_t footprint(const gq_graph* g, int32_t max_k) {
   b += (int64_t)std::max(max_k, 1) * (sum_c + 1) * 8;  // pdiag, mu1
   b += (int64_t)mu_blocks_for(in.sum_n) * kMuPoints * 8 + 16 * 8;
   b += in.sum_n * (4 * 8 + 5 * 4) + (int64_t)(g->dc_merges.size() / 4 + 1) * 4;  // merge metadata
+  b += (int64_t)g->bt_nblocks * 256 * 8;                                          // WY factors
   return b;
 }
 
@@ -223,7 +224,7 @@ void gq_eigs_destroy(gq_eigs* e) {
   void* ptrs[] = {e->A, e->Q, e->Y, e->T, e->eps, e->wts, e->dd, e->ee, e->tau, e->M,
                   e->tmu, e->pdiag, e->mu1, e->mu_state, e->mu_part, e->status,
                   e->md_k, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
-                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv};
+                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete e;
@@ -261,7 +262,7 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
               {&e->mu1, std::max(max_k, 1)}, {&e->mu_state, 16},
               {&e->mu_part, (int64_t)e->mu_blocks * kMuPoints},
               {&e->md_delta, in.sum_n}, {&e->md_tau, in.sum_n}, {&e->md_zhat, in.sum_n},
-              {&e->md_inv, in.sum_n}};
+              {&e->md_inv, in.sum_n}, {&e->tfac, (int64_t)g->bt_nblocks * 256}};
   for (auto& r : reqs) {
     if (hipMalloc((void**)r.p, std::max<int64_t>(1, r.count) * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();

@@ -324,6 +324,14 @@ void build_dc_plan(gq_graph* g) {
     g->dc_level_tile_off.push_back((int32_t)(g->dc_tiles.size() / 3));
     g->dc_level_maxm.push_back(maxm);
   }
+  g->bt_toff.assign(g->n_sub, 0);
+  int32_t nb = 0;
+  for (int32_t s = 0; s < g->n_sub; ++s) {
+    const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
+    g->bt_toff[s] = nb;
+    nb += n > 2 ? (n - 2 + 15) / 16 : 0;
+  }
+  g->bt_nblocks = nb;
 }
 
 }  // namespace gq

@@ -74,6 +74,7 @@ struct gq_graph_dev {
   int32_t* dc_merges = nullptr;    // [n_merges*4] (subgraph, lo, m1, m2), deepest level first
   int32_t* dc_tiles = nullptr;     // [*3] (merge index within its level, tile row, tile col)
   int32_t n_leaves = 0;
+  int32_t* bt_toff = nullptr;      // [n_sub] first compact-WY block of each subgraph
 };
 
 struct gq_graph {
@@ -88,6 +89,8 @@ struct gq_graph {
   // divide-and-conquer plan of the tridiagonal eigensolves
   std::vector<int32_t> dc_leaves, dc_merges, dc_tiles;
   std::vector<int32_t> dc_level_merge_off, dc_level_tile_off, dc_level_maxm;
+  std::vector<int32_t> bt_toff;  // compact-WY block offsets (16 reflectors per block)
+  int32_t bt_nblocks = 0;
   gq_graph_info info{};
   mutable gq_graph_dev dev;
 };
@@ -117,6 +120,7 @@ struct gq_eigs {
   int32_t *md_k = nullptr, *md_cols = nullptr, *md_org = nullptr, *md_pos = nullptr;
   int32_t *md_dsrc = nullptr, *md_dpos = nullptr;
   double *md_delta = nullptr, *md_tau = nullptr, *md_zhat = nullptr, *md_inv = nullptr;
+  double* tfac = nullptr;  // [bt_nblocks][16*16] compact-WY T factors
   bool have_density = false;
   double kT = 0, n_elec = 0;
 };

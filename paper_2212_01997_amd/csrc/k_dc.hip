@@ -18,6 +18,7 @@
 // k_backtransform applies H_0 ... H_{n-3} to the eigenvectors of T in blocks
 // of 16 reflectors (compact WY, I - V T V^T) on 16-column panels held in LDS,
 // and forms the core weights of each eigenvector.
+#include <algorithm>
 #include <cfloat>
 
 #include "gq_internal.hpp"
@@ -684,6 +685,149 @@ __global__ __launch_bounds__(kThreads) void k_backtransform(
   }
 }
 
+// T factors of the compact-WY blocks: H_kb ... H_{kb+nb-1} = I - V T V^T with
+// T upper triangular (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V^T v_i).
+// One workgroup per (subgraph, block); T stored as kNb x kNb row-major.
+__device__ __forceinline__ double refl(const double* A, int n, int kb, int nb, int r, int q) {
+  const int top = kb + q + 1;
+  if (q >= nb || r < top) return 0.0;
+  if (r == top) return 1.0;
+  return A[r + (size_t)n * (kb + q)];
+}
+
+__global__ __launch_bounds__(kThreads) void k_bt_tfactors(
+    const double* __restrict__ abuf, const double* __restrict__ TAU, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ toff,
+    double* __restrict__ tfac) {
+  __shared__ double G[kNb][kNb + 1];
+  __shared__ double T[kNb][kNb + 1];
+  const int s = blockIdx.x;
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const int kbi = blockIdx.y;
+  const int kb = kbi * kNb;
+  if (kb >= n - 2) return;
+  const int nb = min(kNb, n - 2 - kb);
+  const double* A = abuf + off2[s];
+  const int q = threadIdx.x % kNb, p = threadIdx.x / kNb;  // G[p][q]
+  double acc = 0.0;
+  for (int r = kb + 1; r < n; ++r) acc += refl(A, n, kb, nb, r, p) * refl(A, n, kb, nb, r, q);
+  G[p][q] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kNb; ++i)
+      for (int j = 0; j < kNb; ++j) T[i][j] = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      const double ti = TAU[b + kb + i];
+      for (int rr = 0; rr < i; ++rr) {
+        double a = 0.0;
+        for (int qq = rr; qq < i; ++qq) a += T[rr][qq] * G[qq][i];
+        T[rr][i] = -ti * a;
+      }
+      T[i][i] = ti;
+    }
+    double* out = tfac + (size_t)(toff[s] + kbi) * kNb * kNb;
+    for (int i = 0; i < kNb; ++i)
+      for (int j = 0; j < kNb; ++j) out[i * kNb + j] = T[i][j];
+  }
+}
+
+// Back-transformation of a 16-column panel with the reflector block staged in
+// LDS (subgraphs of at most kBtSmall orbitals).
+constexpr int kBtSmall = 512;
+
+__global__ __launch_bounds__(kThreads) void k_backtransform_lds(
+    const double* __restrict__ abuf, const double* __restrict__ tfac,
+    const int32_t* __restrict__ toff, double* __restrict__ zbuf, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core,
+    const int32_t* __restrict__ order, double* __restrict__ wts) {
+  extern __shared__ double sm[];
+  __shared__ double part[kThreads / 64][kNb][kCb + 1];
+  __shared__ double Wm[kNb][kCb + 1], Tm[kNb][kNb + 1], W2[kNb][kCb + 1];
+  const int s = order[blockIdx.x];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const int c0 = blockIdx.y * kCb;
+  if (c0 >= n) return;
+  const int ncol = min(kCb, n - c0);
+  double* zc = sm;                       // [n][kCb]
+  double* vb = sm + (size_t)n * kCb;     // [n][kNb] (rows kb+1.. used)
+  const double* A = abuf + off2[s];
+  double* Z = zbuf + off2[s];
+  const int tid = threadIdx.x;
+  const int cl = tid % kCb, rg = tid / kCb;
+  const int wv = tid >> 6, lane = tid & 63;
+  for (int idx = tid; idx < n * kCb; idx += kThreads) {
+    const int r = idx % n, c = idx / n;
+    zc[r * kCb + c] = c < ncol ? Z[r + (size_t)n * (c0 + c)] : 0.0;
+  }
+  const int nref = n - 2;
+  for (int kbi = (nref - 1) / kNb; nref > 0 && kbi >= 0; --kbi) {
+    const int kb = kbi * kNb;
+    const int nb = min(kNb, nref - kb);
+    const int nr = n - (kb + 1);
+    __syncthreads();
+    for (int idx = tid; idx < nr * kNb; idx += kThreads) {
+      const int rr = idx % nr, q = idx / nr;
+      vb[(kb + 1 + rr) * kNb + q] = refl(A, n, kb, nb, kb + 1 + rr, q);
+    }
+    if (tid < kNb * kNb) Tm[tid / kNb][tid % kNb] = tfac[(size_t)(toff[s] + kbi) * kNb * kNb + tid];
+    __syncthreads();
+    double w[kNb];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) w[q] = 0.0;
+    for (int r = kb + 1 + rg; r < n; r += 16) {
+      const double zr = zc[r * kCb + cl];
+      const double* vr = vb + r * kNb;
+#pragma unroll
+      for (int q = 0; q < kNb; ++q) w[q] += vr[q] * zr;
+    }
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) {
+      w[q] += __shfl_xor(w[q], 16, 64);
+      w[q] += __shfl_xor(w[q], 32, 64);
+    }
+    if (lane < kCb) {
+#pragma unroll
+      for (int q = 0; q < kNb; ++q) part[wv][q][cl] = w[q];
+    }
+    __syncthreads();
+    {
+      const int q = tid / kCb, c = tid % kCb;
+      Wm[q][c] = part[0][q][c] + part[1][q][c] + part[2][q][c] + part[3][q][c];
+    }
+    __syncthreads();
+    {
+      const int q = tid / kCb, c = tid % kCb;
+      double acc = 0.0;
+      for (int p = q; p < kNb; ++p) acc += Tm[q][p] * Wm[p][c];
+      W2[q][c] = acc;
+    }
+    __syncthreads();
+    double w2[kNb];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) w2[q] = W2[q][cl];
+    for (int r = kb + 1 + rg; r < n; r += 16) {
+      const double* vr = vb + r * kNb;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < kNb; ++q) acc += vr[q] * w2[q];
+      zc[r * kCb + cl] -= acc;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * kCb; idx += kThreads) {
+    const int r = idx % n, c = idx / n;
+    if (c < ncol) Z[r + (size_t)n * (c0 + c)] = zc[r * kCb + c];
+  }
+  if (tid < ncol) {
+    const int c = n_core[s];
+    double acc = 0.0;
+    for (int r = 0; r < c; ++r) acc += zc[r * kCb + tid] * zc[r * kCb + tid];
+    wts[b + c0 + tid] = acc;
+  }
+}
+
 }  // namespace
 
 size_t dc_prep_lds(int m) { return (size_t)m * (12 * sizeof(double) + 7 * sizeof(int)); }
@@ -694,6 +838,9 @@ void dc_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_backtransform,
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(kMaxN * kCb * sizeof(double)));
+  (void)hipFuncSetAttribute((const void*)k_backtransform_lds,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kBtSmall * (kCb + kNb) * sizeof(double)));
 }
 
 void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
@@ -726,11 +873,26 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
                        dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->Q, e->Y);
     prof_end(ctx);
   }
-  prof_begin(ctx, "k_backtransform");
   const int maxn = g->info.max_n;
-  hipLaunchKernelGGL(k_backtransform, dim3(g->n_sub, (maxn + kCb - 1) / kCb), dim3(kThreads),
-                     (size_t)maxn * kCb * sizeof(double), st, e->A, e->tau, e->Y, dv.off2,
-                     dv.sub_orb_ptr, dv.n_core, dv.order, e->wts);
+  // subgraphs are ordered by decreasing size: the first n_big exceed kBtSmall
+  int n_big = 0;
+  while (n_big < g->n_sub && g->sub_orb_ptr[g->order[n_big] + 1] - g->sub_orb_ptr[g->order[n_big]] > kBtSmall) ++n_big;
+  prof_begin(ctx, "k_bt_tfactors");
+  hipLaunchKernelGGL(k_bt_tfactors, dim3(g->n_sub, (maxn + kNb - 1) / kNb), dim3(kThreads), 0, st,
+                     e->A, e->tau, dv.off2, dv.sub_orb_ptr, dv.bt_toff, e->tfac);
+  prof_end(ctx);
+  prof_begin(ctx, "k_backtransform");
+  if (n_big > 0)
+    hipLaunchKernelGGL(k_backtransform, dim3(n_big, (maxn + kCb - 1) / kCb), dim3(kThreads),
+                       (size_t)maxn * kCb * sizeof(double), st, e->A, e->tau, e->Y, dv.off2,
+                       dv.sub_orb_ptr, dv.n_core, dv.order, e->wts);
+  if (n_big < g->n_sub) {
+    const int nsm = std::min(maxn, kBtSmall);
+    hipLaunchKernelGGL(k_backtransform_lds, dim3(g->n_sub - n_big, (nsm + kCb - 1) / kCb),
+                       dim3(kThreads), (size_t)nsm * (kCb + kNb) * sizeof(double), st, e->A,
+                       e->tfac, dv.bt_toff, e->Y, dv.off2, dv.sub_orb_ptr, dv.n_core,
+                       dv.order + n_big, e->wts);
+  }
   prof_end(ctx);
 }
 

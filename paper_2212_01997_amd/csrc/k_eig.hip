@@ -4,8 +4,8 @@
 // Eq. (SmallKS): h = Q diag(eps) Q^T.  One workgroup (4 waves) per subgraph:
 //   k_gather    CSR rows of H -> dense column-major h (binary search of each
 //               column index in the subgraph's sorted orbital list, in LDS)
-//   k_tridiag   Householder reduction to tridiagonal form, reflectors kept in
-//               the lower triangle (symv + rank-2 update streamed from L2)
+//   k_tridiag   blocked Householder reduction to tridiagonal form, reflectors
+//               kept in the lower triangle
 //   then the tridiagonal eigenproblem by divide and conquer and the
 //   back-transformation (k_dc.hip).
 #include <cfloat>
@@ -76,61 +76,181 @@ __global__ __launch_bounds__(kThreads) void k_gather(
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_tridiag(
+// Blocked Householder tridiagonalisation, one 1024-thread workgroup per
+// subgraph.  Rows are owned by threads (H = 1024/next_pow2(n) threads share a
+// row and split its columns).  A panel of kPanel reflectors is formed before
+// the trailing matrix is touched: inside the panel the current column and the
+// symmetric product use the stale trailing matrix plus the panel corrections
+//   A_cur = A - sum_q (v_q w_q^T + w_q v_q^T),
+// whose per-row factors V[r][q], W[r][q] live in registers; at the end of the
+// panel one pass applies the rank-2*kPanel update.  Reflector k is stored as
+// v (v[0] = 1 at row k+1) in A[k+1.., k]; d, e and tau go to D, E, TAU.
+constexpr int kTdThreads = 1024;
+constexpr int kPanel = 16;
+constexpr int kStage = 128;
+
+__device__ double tsum(double x, double* red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = x;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kTdThreads / 64; ++i) t += red[i];
+  return t;
+}
+
+__global__ __launch_bounds__(kTdThreads) void k_tridiag(
     double* __restrict__ abuf, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
-  extern __shared__ double sm[];
+  __shared__ double vl[kMaxN], wl[kMaxN], part[kTdThreads];
+  __shared__ double red[kTdThreads / 64];
+  __shared__ double ysh[2 * kPanel][kTdThreads / 64];
+  __shared__ double rowc[2 * kPanel];
+  __shared__ double stage[kStage][2 * kPanel + 1];
+  __shared__ double alpha_sh;
   const int s = order[blockIdx.x];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   double* A = abuf + off2[s];
-  double* v = sm;
-  double* w = sm + n;
-  double* red = sm + 2 * n;
   const int tid = threadIdx.x;
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    double* x = A + (k + 1) + (size_t)n * k;
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += kThreads) part += x[i] * x[i];
-    const double sigma = block_sum(part, red);
-    const double alpha = x[0];
-    if (tid == 0) D[b + k] = A[k + (size_t)n * k];
-    if (sigma == 0.0) {
-      if (tid == 0) {
-        TAU[b + k] = 0.0;
-        E[b + k] = alpha;
+  const int H = n <= 128 ? 8 : n <= 256 ? 4 : n <= 512 ? 2 : 1;
+  const int P = kTdThreads / H;
+  const int r = tid % P, h = tid / P;
+  const bool own = (h == 0) && (r < n);  // the thread that owns row r's scalar work
+  const int lane = tid & 63, wv = tid >> 6;
+
+  double Vr[kPanel], Wr[kPanel];
+  for (int k0 = 0; k0 + 2 < n; k0 += kPanel) {
+    const int nb = min(kPanel, n - 2 - k0);
+#pragma unroll
+    for (int q = 0; q < kPanel; ++q) Vr[q] = Wr[q] = 0.0;
+    for (int j = 0; j < nb; ++j) {
+      const int c = k0 + j;
+      if (own && r == c) {
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q) {
+          rowc[q] = Vr[q];
+          rowc[kPanel + q] = Wr[q];
+        }
       }
       __syncthreads();
-      continue;
-    }
-    const double nrm = sqrt(alpha * alpha + sigma);
-    const double beta = alpha >= 0.0 ? -nrm : nrm;
-    const double t = (beta - alpha) / beta;
-    const double scale = 1.0 / (alpha - beta);
-    for (int i = tid; i < m; i += kThreads) v[i] = (i == 0) ? 1.0 : x[i] * scale;
-    __syncthreads();
-    double* A22 = A + (k + 1) + (size_t)n * (k + 1);
-    for (int i = tid; i < m; i += kThreads) {
+      // current column c, rows c..n-1
+      double a = 0.0;
+      if (own && r >= c) {
+        a = A[r + (size_t)n * c];
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q) a -= Vr[q] * rowc[kPanel + q] + Wr[q] * rowc[q];
+        if (r == c) D[b + c] = a;
+        if (r == c + 1) alpha_sh = a;
+      }
+      const double sigma = tsum(own && r >= c + 2 ? a * a : 0.0, red);
+      const double alpha = alpha_sh;
+      double tau = 0.0, beta = alpha, scale = 0.0;
+      if (sigma != 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (own) {
+        const double v = r == c + 1 ? 1.0 : (r >= c + 2 ? a * scale : 0.0);
+        vl[r] = v;
+        if (r >= c + 2) A[r + (size_t)n * c] = v;
+        if (r == c) {
+          TAU[b + c] = tau;
+          E[b + c] = beta;
+        }
+      }
+      __syncthreads();
+      if (tau == 0.0) {
+        // H = I: this column contributes nothing to the panel
+        continue;
+      }
+      const double vr = r < n ? vl[r] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q)
+        if (q == j) Vr[q] = vr;
+      // p = A22 v over the stale trailing matrix (this thread: row r, columns = h mod H)
       double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += A22[i + (size_t)n * j] * v[j];
-      w[i] = t * acc;
+      if (r >= c + 1 && r < n) {
+        const double* row = A + r;
+        int col = c + 1 + h;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (; col + 3 * H < n; col += 4 * H) {
+          const double x0 = row[(size_t)n * col];
+          const double x1 = row[(size_t)n * (col + H)];
+          const double x2 = row[(size_t)n * (col + 2 * H)];
+          const double x3 = row[(size_t)n * (col + 3 * H)];
+          a0 += x0 * vl[col];
+          a1 += x1 * vl[col + H];
+          a2 += x2 * vl[col + 2 * H];
+          a3 += x3 * vl[col + 3 * H];
+        }
+        for (; col < n; col += H) a0 += row[(size_t)n * col] * vl[col];
+        acc = (a0 + a1) + (a2 + a3);
+      }
+      part[tid] = acc;
+      // y1 = W^T v, y2 = V^T v over the panel so far
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q) {
+        const double t1 = wave_sum(own ? Wr[q] * vr : 0.0);
+        const double t2 = wave_sum(own ? Vr[q] * vr : 0.0);
+        if (lane == 0) {
+          ysh[q][wv] = t1;
+          ysh[kPanel + q][wv] = t2;
+        }
+      }
+      __syncthreads();
+      double p = 0.0;
+      if (own && r >= c + 1) {
+        for (int hh = 0; hh < H; ++hh) p += part[hh * P + r];
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q) {
+          if (q < j) {
+            double y1 = 0.0, y2 = 0.0;
+            for (int w = 0; w < kTdThreads / 64; ++w) {
+              y1 += ysh[q][w];
+              y2 += ysh[kPanel + q][w];
+            }
+            p -= Vr[q] * y1 + Wr[q] * y2;
+          }
+        }
+        p *= tau;
+      }
+      const double K = 0.5 * tau * tsum(own && r >= c + 1 ? p * vr : 0.0, red);
+      if (own) wl[r] = r >= c + 1 ? p - K * vr : 0.0;
+      __syncthreads();
+      const double wr = r < n ? wl[r] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q)
+        if (q == j) Wr[q] = wr;
     }
-    __syncthreads();
-    double pv = 0.0;
-    for (int i = tid; i < m; i += kThreads) pv += w[i] * v[i];
-    const double K = 0.5 * t * block_sum(pv, red);
-    for (int i = tid; i < m; i += kThreads) w[i] -= K * v[i];
-    __syncthreads();
-    for (int j = 0; j < m; ++j) {
-      const double vj = v[j], wj = w[j];
-      for (int i = tid; i < m; i += kThreads) A22[i + (size_t)n * j] -= v[i] * wj + w[i] * vj;
-    }
-    for (int i = 1 + tid; i < m; i += kThreads) x[i] = v[i];
-    if (tid == 0) {
-      TAU[b + k] = t;
-      E[b + k] = beta;
+    // trailing update of rows/cols >= k0 + nb
+    const int t0 = k0 + nb;
+    for (int cc0 = t0; cc0 < n; cc0 += kStage) {
+      __syncthreads();
+      if (own && r >= cc0 && r < cc0 + kStage) {
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q) {
+          stage[r - cc0][q] = Vr[q];
+          stage[r - cc0][kPanel + q] = Wr[q];
+        }
+      }
+      __syncthreads();
+      if (r >= t0 && r < n) {
+        const int cend = min(n, cc0 + kStage);
+        for (int col = cc0 + h; col < cend; col += H) {
+          double* ap = A + r + (size_t)n * col;
+          double a = *ap;
+          const double* sv = stage[col - cc0];
+#pragma unroll
+          for (int q = 0; q < kPanel; ++q) a -= Vr[q] * sv[kPanel + q] + Wr[q] * sv[q];
+          *ap = a;
+        }
+      }
     }
     __syncthreads();
   }
@@ -164,8 +284,9 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   const int maxn = g->info.max_n;
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_tridiag");
-  hipLaunchKernelGGL(k_tridiag, dim3(g->n_sub), dim3(kThreads), (2 * maxn + 8) * sizeof(double),
-                     st, e->A, dv.off2, dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
+  (void)maxn;
+  hipLaunchKernelGGL(k_tridiag, dim3(g->n_sub), dim3(kTdThreads), 0, st, e->A, dv.off2,
+                     dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
   prof_end(ctx);
   launch_dc(ctx, g, e);
   // the eigenvectors were formed in e->Y; from here on they are e->Q
