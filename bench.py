@@ -48,6 +48,29 @@ def algorithmic_work(sizes, cores):
     }
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factor), or None
+    when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_water1000.txt")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("{"):
+                rec = json.loads(line)
+    if not rec or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    src = os.path.join(ROOT, "paper_2212_01997_amd", "csrc", k["source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != k["sha256_16"]:
+            return None
+    return k["bytes_per_launch"]
+
+
 def cpu_baseline(system, core, h1, budget_s=12.0):
     """The oracle as it stands, single-threaded, on a size-stratified sample of
     subgraphs of its own graph (its own bootstrap density); extrapolated to the
@@ -58,11 +81,12 @@ def cpu_baseline(system, core, h1, budget_s=12.0):
     g = O.graph_build(system, core, TAU, rho_prev=prev, flags=O.PATHS2)
     sizes = g.sizes()
     H = O.Csr(system.h_row_ptr, system.h_col, system.h_val)
+    # size-stratified order: quantiles first, then the rest, until the budget is spent
     order = np.argsort(sizes)
-    picks = []
-    for frac in (0.5, 0.95, 0.05, 0.75, 0.25, 0.99, 0.01, 0.6, 0.4, 0.85, 0.15):
-        picks.append(int(order[min(len(order) - 1, int(frac * len(order)))]))
-    picks = list(dict.fromkeys(picks))
+    first = [int(order[min(len(order) - 1, int(f * len(order)))])
+             for f in (0.5, 0.95, 0.05, 0.75, 0.25, 0.99, 0.01, 0.6, 0.4, 0.85, 0.15)]
+    rest = [int(x) for x in np.random.default_rng(0).permutation(g.n_sub)]
+    picks = list(dict.fromkeys(first + rest))
     t_used, n3_used, done = 0.0, 0.0, 0
     mu = -0.22
     for s in picks:
@@ -85,9 +109,10 @@ def cpu_baseline(system, core, h1, budget_s=12.0):
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"{done} of {g.n_sub} subgraphs (n = {sorted(int(sizes[p]) for p in picks[:done])}),"
-                   f" single thread, {t_used:.1f} s; whole-step time extrapolated by sum n^3"
-                   f" to {total:.1f} s"),
+        "sample": (f"{done} of {g.n_sub} subgraphs (size-stratified, n {int(min(sizes[p] for p in picks[:done]))}"
+                   f"..{int(max(sizes[p] for p in picks[:done]))}), single thread, {t_used:.1f} s of"
+                   f" gather + eigensolve + density rows + response rows; whole-step time"
+                   f" extrapolated by sum n^3 to {total:.1f} s"),
     }
 
 
@@ -97,6 +122,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one device copy of 256 MiB (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -145,6 +172,14 @@ def main():
     ms = dt * 1e3 / args.steps
     log(f"timed {args.steps} steps: {ms:.3f} ms/step")
 
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 268435456 bytes read, 268435456 bytes written")
+
     # per-kernel durations, measured with hipEvents on the library stream
     ctx.set_profiling(True)
     nprof = max(2, min(5, args.steps))
@@ -162,7 +197,7 @@ def main():
     bound = "alu" if dominant in ("k_tridiag", "k_dc_prep", "k_dc_leaves") else "mfma"
     roofline = {"bound": bound, "kernel": dominant, "achieved": achieved / 1e12,
                 "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-                "traffic": None,
+                "traffic": measured_traffic(dominant),
                 "algorithmic_flops_per_launch": flops, "launch_ms": per_launch[dominant],
                 "launches_per_step": launches_per_step}
     phases = {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda x: -x[1])}

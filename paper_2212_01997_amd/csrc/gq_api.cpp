@@ -207,6 +207,7 @@ static int64_t footprint(const gq_graph* g, int32_t max_k) {
   b += (int64_t)mu_blocks_for(in.sum_n) * kMuPoints * 8 + 16 * 8;
   b += in.sum_n * (4 * 8 + 5 * 4) + (int64_t)(g->dc_merges.size() / 4 + 1) * 4;  // merge metadata
   b += (int64_t)g->bt_nblocks * 256 * 8;                                          // WY factors
+  b += in.sum_n * 16 * 8;                                                         // panel scratch
   return b;
 }
 
@@ -224,7 +225,7 @@ void gq_eigs_destroy(gq_eigs* e) {
   void* ptrs[] = {e->A, e->Q, e->Y, e->T, e->eps, e->wts, e->dd, e->ee, e->tau, e->M,
                   e->tmu, e->pdiag, e->mu1, e->mu_state, e->mu_part, e->status,
                   e->md_k, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
-                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac};
+                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac, e->wsc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete e;
@@ -262,7 +263,8 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
               {&e->mu1, std::max(max_k, 1)}, {&e->mu_state, 16},
               {&e->mu_part, (int64_t)e->mu_blocks * kMuPoints},
               {&e->md_delta, in.sum_n}, {&e->md_tau, in.sum_n}, {&e->md_zhat, in.sum_n},
-              {&e->md_inv, in.sum_n}, {&e->tfac, (int64_t)g->bt_nblocks * 256}};
+              {&e->md_inv, in.sum_n}, {&e->tfac, (int64_t)g->bt_nblocks * 256},
+              {&e->wsc, in.sum_n * 16}};
   for (auto& r : reqs) {
     if (hipMalloc((void**)r.p, std::max<int64_t>(1, r.count) * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();

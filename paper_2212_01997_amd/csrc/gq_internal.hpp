@@ -15,7 +15,7 @@ namespace gq {
 // wave-private copies of the tridiagonal and its rotations in LDS.
 constexpr int kMaxN = 1024;
 // Largest tridiagonal block solved directly in the divide-and-conquer tree.
-constexpr int kLeaf = 32;
+constexpr int kLeaf = 16;
 // Core rows handled per workgroup in the core-row products.
 constexpr int kRowChunk = 16;
 // Points per multisection pass of the chemical-potential search.
@@ -121,6 +121,7 @@ struct gq_eigs {
   int32_t *md_dsrc = nullptr, *md_dpos = nullptr;
   double *md_delta = nullptr, *md_tau = nullptr, *md_zhat = nullptr, *md_inv = nullptr;
   double* tfac = nullptr;  // [bt_nblocks][16*16] compact-WY T factors
+  double* wsc = nullptr;   // [sum_n * 16] panel scratch of the tridiagonalisation
   bool have_density = false;
   double kT = 0, n_elec = 0;
 };

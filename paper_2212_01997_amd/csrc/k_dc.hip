@@ -378,14 +378,43 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
   __syncthreads();
   const int k = sh_k, nrot = sh_nrot;
   // apply the deflating rotations to the columns of the children's vectors
+  // Rotation t pairs sorted indices p_t < i_t with i_t strictly increasing in
+  // t, so i_t is untouched before step t and p_t is either untouched or the
+  // i of the previous step (then forwarded from a register).  Operands are
+  // therefore loaded kPre steps ahead.
+  constexpr int kPre = 8;
   for (int r = tid; r < m; r += kThreads) {
     double* row = Z + (lo + r);
-    for (int t = 0; t < nrot; ++t) {
-      const size_t cp = (size_t)n * (lo + L.perm[L.rp[t]]);
-      const size_t ci = (size_t)n * (lo + L.perm[L.ri[t]]);
-      const double a = row[cp], bb = row[ci];
-      row[cp] = L.rc[t] * a + L.rs[t] * bb;
-      row[ci] = L.rc[t] * bb - L.rs[t] * a;
+    double qa[kPre], qb[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      if (u < nrot) {
+        qa[u] = row[(size_t)n * (lo + L.perm[L.rp[u]])];
+        qb[u] = row[(size_t)n * (lo + L.perm[L.ri[u]])];
+      }
+    }
+    double carry = 0.0;
+    int carry_idx = -1;
+    for (int t0 = 0; t0 < nrot; t0 += kPre) {
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int t = t0 + u;
+        if (t < nrot) {
+          const double a = (L.rp[t] == carry_idx) ? carry : qa[u];
+          const double bb = qb[u];
+          const double na = L.rc[t] * a + L.rs[t] * bb;
+          const double nb = L.rc[t] * bb - L.rs[t] * a;
+          row[(size_t)n * (lo + L.perm[L.rp[t]])] = na;
+          row[(size_t)n * (lo + L.perm[L.ri[t]])] = nb;
+          carry = nb;
+          carry_idx = L.ri[t];
+          const int tn = t + kPre;
+          if (tn < nrot) {
+            qa[u] = row[(size_t)n * (lo + L.perm[L.rp[tn]])];
+            qb[u] = row[(size_t)n * (lo + L.perm[L.ri[tn]])];
+          }
+        }
+      }
     }
   }
   for (int j = tid; j < k; j += kThreads) {

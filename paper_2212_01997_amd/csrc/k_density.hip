@@ -20,7 +20,7 @@ namespace gq {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMuChunk = 1024;  // (eps, w) pairs per block of the occupation pass
+constexpr int kMuChunk = 128;  // (eps, w) pairs per block of the occupation pass
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -49,15 +49,17 @@ __device__ __forceinline__ void fermi2(double e, double mu, double beta, double&
   f1f = t * inv * inv;
 }
 
-// state: [0] lo, [1] hi, [2] mu, [3] kT, [4] n_elec
-__global__ __launch_bounds__(kThreads) void k_mu_init(const double* __restrict__ eps, int64_t count,
-                                                      double* __restrict__ state, double kT,
-                                                      double n_elec) {
+// state: [0] lo, [1] hi, [2] mu, [3] kT, [4] n_elec.  Eigenvalues are ascending
+// within each subgraph, so the extremes are the first and last of each.
+__global__ __launch_bounds__(kThreads) void k_mu_init(const double* __restrict__ eps,
+                                                      const int32_t* __restrict__ sub_orb_ptr,
+                                                      int n_sub, double* __restrict__ state,
+                                                      double kT, double n_elec) {
   __shared__ double rmin[kThreads], rmax[kThreads];
   double lo = DBL_MAX, hi = -DBL_MAX;
-  for (int64_t i = threadIdx.x; i < count; i += kThreads) {
-    lo = fmin(lo, eps[i]);
-    hi = fmax(hi, eps[i]);
+  for (int s = threadIdx.x; s < n_sub; s += kThreads) {
+    lo = fmin(lo, eps[sub_orb_ptr[s]]);
+    hi = fmax(hi, eps[sub_orb_ptr[s + 1] - 1]);
   }
   rmin[threadIdx.x] = lo;
   rmax[threadIdx.x] = hi;
@@ -110,15 +112,26 @@ __global__ __launch_bounds__(kThreads) void k_mu_eval(const double* __restrict__
   if (h == 0) part[(size_t)blockIdx.x * kMuPoints + j] = acc + half[j];
 }
 
-__global__ __launch_bounds__(kMuPoints) void k_mu_update(const double* __restrict__ part, int nblk,
-                                                         double* __restrict__ state) {
+// Fixed-order reduction of the block partials: group g of kMuGroups sums the
+// blocks g, g + kMuGroups, ... in order, then the groups are added in order.
+constexpr int kMuGroups = 8;
+
+__global__ __launch_bounds__(kMuPoints * kMuGroups) void k_mu_update(
+    const double* __restrict__ part, int nblk, double* __restrict__ state) {
+  __shared__ double G[kMuGroups][kMuPoints];
   __shared__ double F[kMuPoints];
-  const int j = threadIdx.x;
+  const int j = threadIdx.x % kMuPoints, g = threadIdx.x / kMuPoints;
   double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += part[(size_t)b * kMuPoints + j];
-  F[j] = 2.0 * acc - state[4];
+  for (int b = g; b < nblk; b += kMuGroups) acc += part[(size_t)b * kMuPoints + j];
+  G[g][j] = acc;
   __syncthreads();
-  if (j == 0) {
+  if (g == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kMuGroups; ++q) t += G[q][j];
+    F[j] = 2.0 * t - state[4];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     const double lo = state[0], hi = state[1];
     int first = kMuPoints;
     for (int q = 0; q < kMuPoints; ++q)
@@ -251,13 +264,14 @@ void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   const int64_t count = g->info.sum_n;
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_mu");
-  hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(kThreads), 0, st, e->eps, count, e->mu_state, e->kT,
-                     e->n_elec);
+  hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(kThreads), 0, st, e->eps, g->dev.sub_orb_ptr,
+                     g->n_sub, e->mu_state, e->kT, e->n_elec);
   const int nblk = (int)((count + kMuChunk - 1) / kMuChunk);
   for (int pass = 0; pass < kMuPasses; ++pass) {
     hipLaunchKernelGGL(k_mu_eval, dim3(nblk), dim3(kThreads), 0, st, e->eps, e->wts, count,
                        e->mu_state, e->mu_part);
-    hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(kMuPoints), 0, st, e->mu_part, nblk, e->mu_state);
+    hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(kMuPoints * kMuGroups), 0, st, e->mu_part, nblk,
+                       e->mu_state);
   }
   prof_end(ctx);
 }

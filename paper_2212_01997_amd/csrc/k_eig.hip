@@ -81,13 +81,15 @@ __global__ __launch_bounds__(kThreads) void k_gather(
 // row and split its columns).  A panel of kPanel reflectors is formed before
 // the trailing matrix is touched: inside the panel the current column and the
 // symmetric product use the stale trailing matrix plus the panel corrections
-//   A_cur = A - sum_q (v_q w_q^T + w_q v_q^T),
-// whose per-row factors V[r][q], W[r][q] live in registers; at the end of the
-// panel one pass applies the rank-2*kPanel update.  Reflector k is stored as
-// v (v[0] = 1 at row k+1) in A[k+1.., k]; d, e and tau go to D, E, TAU.
+//   A_cur = A - sum_q (v_q w_q^T + w_q v_q^T);
+// v_q is kept in A's column k0+q (v[0] = 1 stored at row k0+q+1) and w_q in a
+// global panel scratch, so the symmetric product keeps its registers for 16
+// loads in flight.  At the end of the panel one pass applies the rank-2*kPanel
+// update.  d, e and tau go to D, E, TAU.
 constexpr int kTdThreads = 1024;
 constexpr int kPanel = 16;
 constexpr int kStage = 128;
+constexpr int kUnroll = 8;
 
 __device__ double tsum(double x, double* red) {
   x = wave_sum(x);
@@ -102,47 +104,44 @@ __device__ double tsum(double x, double* red) {
 }
 
 __global__ __launch_bounds__(kTdThreads) void k_tridiag(
-    double* __restrict__ abuf, const int64_t* __restrict__ off2,
+    double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
   __shared__ double vl[kMaxN], wl[kMaxN], part[kTdThreads];
   __shared__ double red[kTdThreads / 64];
   __shared__ double ysh[2 * kPanel][kTdThreads / 64];
+  __shared__ double yfin[2 * kPanel];
   __shared__ double rowc[2 * kPanel];
-  __shared__ double stage[kStage][2 * kPanel + 1];
+  __shared__ double stage[kStage][kPanel + 1];
   __shared__ double alpha_sh;
   const int s = order[blockIdx.x];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   double* A = abuf + off2[s];
+  double* W = wsc + (size_t)b * kPanel;  // W[q * n + r]
   const int tid = threadIdx.x;
   const int H = n <= 128 ? 8 : n <= 256 ? 4 : n <= 512 ? 2 : 1;
   const int P = kTdThreads / H;
   const int r = tid % P, h = tid / P;
-  const bool own = (h == 0) && (r < n);  // the thread that owns row r's scalar work
+  const bool own = (h == 0) && (r < n);
   const int lane = tid & 63, wv = tid >> 6;
 
-  double Vr[kPanel], Wr[kPanel];
   for (int k0 = 0; k0 + 2 < n; k0 += kPanel) {
     const int nb = min(kPanel, n - 2 - k0);
-#pragma unroll
-    for (int q = 0; q < kPanel; ++q) Vr[q] = Wr[q] = 0.0;
     for (int j = 0; j < nb; ++j) {
       const int c = k0 + j;
       if (own && r == c) {
-#pragma unroll
-        for (int q = 0; q < kPanel; ++q) {
-          rowc[q] = Vr[q];
-          rowc[kPanel + q] = Wr[q];
+        for (int q = 0; q < j; ++q) {
+          rowc[q] = A[r + (size_t)n * (k0 + q)];
+          rowc[kPanel + q] = W[q * n + r];
         }
       }
       __syncthreads();
-      // current column c, rows c..n-1
       double a = 0.0;
       if (own && r >= c) {
         a = A[r + (size_t)n * c];
-#pragma unroll
-        for (int q = 0; q < kPanel; ++q) a -= Vr[q] * rowc[kPanel + q] + Wr[q] * rowc[q];
+        for (int q = 0; q < j; ++q)
+          a -= A[r + (size_t)n * (k0 + q)] * rowc[kPanel + q] + W[q * n + r] * rowc[q];
         if (r == c) D[b + c] = a;
         if (r == c + 1) alpha_sh = a;
       }
@@ -158,7 +157,7 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
       if (own) {
         const double v = r == c + 1 ? 1.0 : (r >= c + 2 ? a * scale : 0.0);
         vl[r] = v;
-        if (r >= c + 2) A[r + (size_t)n * c] = v;
+        if (r >= c + 1) A[r + (size_t)n * c] = v;
         if (r == c) {
           TAU[b + c] = tau;
           E[b + c] = beta;
@@ -166,89 +165,97 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
       }
       __syncthreads();
       if (tau == 0.0) {
-        // H = I: this column contributes nothing to the panel
+        // H = I (column already reduced): it adds no correction to the panel
+        if (own) W[j * n + r] = 0.0;
+        if (own && r >= c + 1) A[r + (size_t)n * c] = 0.0;
         continue;
       }
       const double vr = r < n ? vl[r] : 0.0;
-#pragma unroll
-      for (int q = 0; q < kPanel; ++q)
-        if (q == j) Vr[q] = vr;
-      // p = A22 v over the stale trailing matrix (this thread: row r, columns = h mod H)
+      // p = A22 v over the stale trailing matrix (row r, columns = h mod H)
       double acc = 0.0;
       if (r >= c + 1 && r < n) {
         const double* row = A + r;
         int col = c + 1 + h;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (; col + 3 * H < n; col += 4 * H) {
-          const double x0 = row[(size_t)n * col];
-          const double x1 = row[(size_t)n * (col + H)];
-          const double x2 = row[(size_t)n * (col + 2 * H)];
-          const double x3 = row[(size_t)n * (col + 3 * H)];
-          a0 += x0 * vl[col];
-          a1 += x1 * vl[col + H];
-          a2 += x2 * vl[col + 2 * H];
-          a3 += x3 * vl[col + 3 * H];
+        double ac[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) ac[u] = 0.0;
+        for (; col + (kUnroll - 1) * H < n; col += kUnroll * H) {
+          double x[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * (col + u * H)];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) ac[u] += x[u] * vl[col + u * H];
         }
-        for (; col < n; col += H) a0 += row[(size_t)n * col] * vl[col];
-        acc = (a0 + a1) + (a2 + a3);
+        for (; col < n; col += H) ac[0] += row[(size_t)n * col] * vl[col];
+#pragma unroll
+        for (int u = 1; u < kUnroll; ++u) ac[0] += ac[u];
+        acc = ac[0];
       }
       part[tid] = acc;
-      // y1 = W^T v, y2 = V^T v over the panel so far
-#pragma unroll
-      for (int q = 0; q < kPanel; ++q) {
-        const double t1 = wave_sum(own ? Wr[q] * vr : 0.0);
-        const double t2 = wave_sum(own ? Vr[q] * vr : 0.0);
+      // y1 = W^T v, y2 = V^T v over the panel so far (rows > c; V, W vanish above)
+      for (int q = 0; q < j; ++q) {
+        double t1 = 0.0, t2 = 0.0;
+        if (own && r > c) {
+          t1 = W[q * n + r] * vr;
+          t2 = A[r + (size_t)n * (k0 + q)] * vr;
+        }
+        t1 = wave_sum(t1);
+        t2 = wave_sum(t2);
         if (lane == 0) {
           ysh[q][wv] = t1;
           ysh[kPanel + q][wv] = t2;
         }
       }
       __syncthreads();
+      if (tid < 2 * kPanel && (tid % kPanel) < j) {
+        double t = 0.0;
+        for (int w = 0; w < kTdThreads / 64; ++w) t += ysh[tid][w];
+        yfin[tid] = t;
+      }
+      __syncthreads();
       double p = 0.0;
       if (own && r >= c + 1) {
         for (int hh = 0; hh < H; ++hh) p += part[hh * P + r];
-#pragma unroll
-        for (int q = 0; q < kPanel; ++q) {
-          if (q < j) {
-            double y1 = 0.0, y2 = 0.0;
-            for (int w = 0; w < kTdThreads / 64; ++w) {
-              y1 += ysh[q][w];
-              y2 += ysh[kPanel + q][w];
-            }
-            p -= Vr[q] * y1 + Wr[q] * y2;
-          }
-        }
+        for (int q = 0; q < j; ++q)
+          p -= A[r + (size_t)n * (k0 + q)] * yfin[q] + W[q * n + r] * yfin[kPanel + q];
         p *= tau;
       }
       const double K = 0.5 * tau * tsum(own && r >= c + 1 ? p * vr : 0.0, red);
-      if (own) wl[r] = r >= c + 1 ? p - K * vr : 0.0;
-      __syncthreads();
-      const double wr = r < n ? wl[r] : 0.0;
-#pragma unroll
-      for (int q = 0; q < kPanel; ++q)
-        if (q == j) Wr[q] = wr;
+      if (own) W[j * n + r] = r >= c + 1 ? p - K * vr : 0.0;
     }
-    // trailing update of rows/cols >= k0 + nb
+    __syncthreads();
+    // trailing update of rows/cols >= k0 + nb, in two halves of the panel so
+    // that a thread's row factors fit in registers
     const int t0 = k0 + nb;
-    for (int cc0 = t0; cc0 < n; cc0 += kStage) {
-      __syncthreads();
-      if (own && r >= cc0 && r < cc0 + kStage) {
+#pragma unroll 1
+    for (int qh = 0; qh < kPanel; qh += kPanel / 2) {
+      double Vr[kPanel / 2], Wr[kPanel / 2];
 #pragma unroll
-        for (int q = 0; q < kPanel; ++q) {
-          stage[r - cc0][q] = Vr[q];
-          stage[r - cc0][kPanel + q] = Wr[q];
-        }
+      for (int q = 0; q < kPanel / 2; ++q) {
+        const bool ok = qh + q < nb && r >= t0 && r < n;
+        Vr[q] = ok ? A[r + (size_t)n * (k0 + qh + q)] : 0.0;
+        Wr[q] = ok ? W[(qh + q) * n + r] : 0.0;
       }
-      __syncthreads();
-      if (r >= t0 && r < n) {
-        const int cend = min(n, cc0 + kStage);
-        for (int col = cc0 + h; col < cend; col += H) {
-          double* ap = A + r + (size_t)n * col;
-          double a = *ap;
-          const double* sv = stage[col - cc0];
+      for (int cc0 = t0; cc0 < n; cc0 += kStage) {
+        __syncthreads();
+        if (own && r >= cc0 && r < cc0 + kStage) {
 #pragma unroll
-          for (int q = 0; q < kPanel; ++q) a -= Vr[q] * sv[kPanel + q] + Wr[q] * sv[q];
-          *ap = a;
+          for (int q = 0; q < kPanel / 2; ++q) {
+            stage[r - cc0][q] = Vr[q];
+            stage[r - cc0][kPanel / 2 + q] = Wr[q];
+          }
+        }
+        __syncthreads();
+        if (r >= t0 && r < n) {
+          const int cend = min(n, cc0 + kStage);
+          for (int col = cc0 + h; col < cend; col += H) {
+            double* ap = A + r + (size_t)n * col;
+            double a = *ap;
+            const double* sv = stage[col - cc0];
+#pragma unroll
+            for (int q = 0; q < kPanel / 2; ++q) a -= Vr[q] * sv[kPanel / 2 + q] + Wr[q] * sv[q];
+            *ap = a;
+          }
         }
       }
     }
@@ -285,7 +292,7 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_tridiag");
   (void)maxn;
-  hipLaunchKernelGGL(k_tridiag, dim3(g->n_sub), dim3(kTdThreads), 0, st, e->A, dv.off2,
+  hipLaunchKernelGGL(k_tridiag, dim3(g->n_sub), dim3(kTdThreads), 0, st, e->A, e->wsc, dv.off2,
                      dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
   prof_end(ctx);
   launch_dc(ctx, g, e);
