@@ -200,14 +200,14 @@ static int64_t footprint(const gq_graph* g, int32_t max_k) {
   const int64_t sum_c = g->offcd[g->n_sub];
   int64_t b = 0;
   b += 3 * in.sum_n2 * 8;          // A, Q, Y
-  b += 2 * in.nnz * 8;             // T, M
+  b += in.nnz * 8 + in.sum_n * 32 * 8;  // M, T
   b += 5 * in.sum_n * 8;           // eps, wts, dd, ee, tau
   b += (int64_t)g->n_sub * (8 + 4);  // tmu, status
   b += (int64_t)std::max(max_k, 1) * (sum_c + 1) * 8;  // pdiag, mu1
   b += (int64_t)mu_blocks_for(in.sum_n) * kMuPoints * 8 + 16 * 8;
   b += in.sum_n * (4 * 8 + 5 * 4) + (int64_t)(g->dc_merges.size() / 4 + 1) * 4;  // merge metadata
   b += (int64_t)g->bt_nblocks * 256 * 8;                                          // WY factors
-  b += in.sum_n * 16 * 8;                                                         // panel scratch
+  b += in.sum_n * 17 * 8;                                                         // panel scratch, h1
   return b;
 }
 
@@ -225,7 +225,7 @@ void gq_eigs_destroy(gq_eigs* e) {
   void* ptrs[] = {e->A, e->Q, e->Y, e->T, e->eps, e->wts, e->dd, e->ee, e->tau, e->M,
                   e->tmu, e->pdiag, e->mu1, e->mu_state, e->mu_part, e->status,
                   e->md_k, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
-                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac, e->wsc};
+                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac, e->wsc, e->hloc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete e;
@@ -238,6 +238,10 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
   }
   if (g->info.max_n > kMaxN) {
     set_error("gq_eigs_create: subgraph of %d orbitals exceeds the limit %d", g->info.max_n, kMaxN);
+    return GQ_EINVAL;
+  }
+  if (g->info.max_c > kMaxCore) {
+    set_error("gq_eigs_create: core of %d orbitals exceeds the limit %d", g->info.max_c, kMaxCore);
     return GQ_EINVAL;
   }
   GQ_HIP(hipSetDevice(ctx->device));
@@ -256,7 +260,7 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
   struct Req {
     double** p;
     int64_t count;
-  } reqs[] = {{&e->A, in.sum_n2}, {&e->Q, in.sum_n2}, {&e->Y, in.sum_n2}, {&e->T, in.nnz},
+  } reqs[] = {{&e->A, in.sum_n2}, {&e->Q, in.sum_n2}, {&e->Y, in.sum_n2}, {&e->T, in.sum_n * 32},
               {&e->M, in.nnz}, {&e->eps, in.sum_n}, {&e->wts, in.sum_n}, {&e->dd, in.sum_n},
               {&e->ee, in.sum_n}, {&e->tau, in.sum_n}, {&e->tmu, g->n_sub},
               {&e->pdiag, (int64_t)std::max(max_k, 1) * std::max<int64_t>(sum_c, 1)},
@@ -264,7 +268,7 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
               {&e->mu_part, (int64_t)e->mu_blocks * kMuPoints},
               {&e->md_delta, in.sum_n}, {&e->md_tau, in.sum_n}, {&e->md_zhat, in.sum_n},
               {&e->md_inv, in.sum_n}, {&e->tfac, (int64_t)g->bt_nblocks * 256},
-              {&e->wsc, in.sum_n * 16}};
+              {&e->wsc, in.sum_n * 16}, {&e->hloc, in.sum_n}};
   for (auto& r : reqs) {
     if (hipMalloc((void**)r.p, std::max<int64_t>(1, r.count) * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();

@@ -16,6 +16,8 @@ namespace gq {
 constexpr int kMaxN = 1024;
 // Largest tridiagonal block solved directly in the divide-and-conquer tree.
 constexpr int kLeaf = 16;
+// Largest core (orbitals): the response products keep two 16-row MFMA blocks.
+constexpr int kMaxCore = 32;
 // Core rows handled per workgroup in the core-row products.
 constexpr int kRowChunk = 16;
 // Points per multisection pass of the chemical-potential search.
@@ -102,7 +104,7 @@ struct gq_eigs {
   double* A = nullptr;      // [sum n^2] gathered matrix / tridiagonal work, then dF
   double* Q = nullptr;      // [sum n^2] eigenvectors, column-major per subgraph
   double* Y = nullptr;      // [sum n^2] response scratch (X o dF)
-  double* T = nullptr;      // [sum c n] response scratch (Q_c Y)
+  double* T = nullptr;      // [sum n][32] response scratch (Q_c Y), column by column
   double* eps = nullptr;    // [sum n]
   double* wts = nullptr;    // [sum n]
   double* dd = nullptr;     // [sum n] tridiagonal diagonal
@@ -122,6 +124,7 @@ struct gq_eigs {
   double *md_delta = nullptr, *md_tau = nullptr, *md_zhat = nullptr, *md_inv = nullptr;
   double* tfac = nullptr;  // [bt_nblocks][16*16] compact-WY T factors
   double* wsc = nullptr;   // [sum_n * 16] panel scratch of the tridiagonalisation
+  double* hloc = nullptr;  // [sum_n] perturbation gathered into subgraph order
   bool have_density = false;
   double kT = 0, n_elec = 0;
 };

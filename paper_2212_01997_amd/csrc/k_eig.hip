@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
     double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
-  __shared__ double vl[kMaxN], wl[kMaxN], part[kTdThreads];
+  __shared__ double vl[kMaxN], part[kTdThreads];
   __shared__ double red[kTdThreads / 64];
   __shared__ double ysh[2 * kPanel][kTdThreads / 64];
   __shared__ double yfin[2 * kPanel];

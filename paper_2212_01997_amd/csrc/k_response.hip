@@ -7,9 +7,9 @@
 //   mu1 = -sum_i Tr_c d1lambda_i / sum_i Tr_c d1mu_i,
 // so that the collected rho1 = 2 (d1lambda + mu1 d1mu) core rows has zero trace
 // (Eq. (D1)).  Kernels per perturbation q:
-//   k_xy       lower-triangular 64x64 tiles of X = Q^T diag(h1) Q, times dF,
-//              written with their mirror into Y (symmetric)
-//   k_rows     T = Q_c Y, then P = 2 T Q^T (c x n core rows), P's diagonal
+//   k_xy_mfma  lower-triangular 64x64 tiles of X = Q^T diag(h1) Q on FP64
+//              MFMA, times dF, into Y (each symmetric pair stored once)
+//   k_t_mfma   T = Q_c Y;  k_p_mfma  P = 2 T Q^T (c x n core rows) and diag(P)
 //   k_mu1      fixed-order traces -> mu1_q
 //   k_combine  P += mu1_q M
 // Eq. (sub_f) / (dCollect): k_assemble scatters block rows into CSR values.
@@ -23,7 +23,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kTile = 64;
-constexpr int kKc = 16;
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -31,125 +30,208 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-__global__ __launch_bounds__(kThreads) void k_xy(
+// ---------------------------------------------------------------- FP64 MFMA
+// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A(l%16, l/16) and
+// B(l/16, l%16); D(i, j) is returned in lane j + 16*(i%4), register i/4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kXK = 32;  // K chunk of the X tiles
+
+// Y = (Q^T diag(h1) Q) o dF on the lower 64x64 tiles (ti >= tj).  A tile's
+// value y(k, l), k in tile ti, l in tile tj, is stored at Y[l + n k]
+// (row l, column k): every value of the symmetric Y sits at the position
+// whose row tile is not above its column tile, written coalesced.
+__global__ __launch_bounds__(kThreads) void k_xy_mfma(
     const double* __restrict__ qbuf, const double* __restrict__ dfbuf, double* __restrict__ ybuf,
-    const double* __restrict__ h1, int N, const int32_t* __restrict__ tiles,
-    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
-    const int32_t* __restrict__ sub_orbs) {
-  __shared__ double As[kKc][kTile + 1];
-  __shared__ double Bs[kKc][kTile + 1];
-  __shared__ double hs[kKc];
+    const double* __restrict__ hloc, const int32_t* __restrict__ tiles,
+    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr) {
+  __shared__ double As[kXK][kTile + 1];
+  __shared__ double Bs[kXK][kTile + 1];
   const int s = tiles[3 * blockIdx.x], ti = tiles[3 * blockIdx.x + 1], tj = tiles[3 * blockIdx.x + 2];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const double* Q = qbuf + off2[s];
   const int k0 = ti * kTile, l0 = tj * kTile;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  constexpr int kPer = kXK * kTile / kThreads;  // values of As (and of Bs) per thread
+  __shared__ double hs[kXK];
+  const double* hl = hloc + b;
+  double pa[kPer], pb[kPer], ph = 0.0;
+  auto fetch = [&](int m0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int m0 = 0; m0 < n; m0 += kKc) {
-    __syncthreads();
-    if (threadIdx.x < kKc) {
-      const int m = m0 + threadIdx.x;
-      hs[threadIdx.x] = m < n ? h1[sub_orbs[b + m]] : 0.0;
-    }
-    for (int idx = threadIdx.x; idx < kKc * kTile; idx += kThreads) {
-      const int mm = idx % kKc, kk = idx / kKc;
+    for (int u = 0; u < kPer; ++u) {
+      const int idx = tid + u * kThreads;
+      const int mm = idx % kXK, kk = idx / kXK;
       const int m = m0 + mm;
-      As[mm][kk] = (m < n && k0 + kk < n) ? Q[m + (size_t)n * (k0 + kk)] : 0.0;
-      Bs[mm][kk] = (m < n && l0 + kk < n) ? Q[m + (size_t)n * (l0 + kk)] : 0.0;
+      const bool okm = m < n;
+      pa[u] = (okm && k0 + kk < n) ? Q[m + (size_t)n * (k0 + kk)] : 0.0;
+      pb[u] = (okm && l0 + kk < n) ? Q[m + (size_t)n * (l0 + kk)] : 0.0;
     }
+    if (tid < kXK) ph = (m0 + tid < n) ? hl[m0 + tid] : 0.0;
+  };
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  for (int m0 = 0; m0 < n; m0 += kXK) {
     __syncthreads();
-#pragma unroll 4
-    for (int mm = 0; mm < kKc; ++mm) {
-      const double h = hs[mm];
-      double a[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[mm][tx + 16 * i];
+    for (int u = 0; u < kPer; ++u) {
+      const int idx = tid + u * kThreads;
+      As[idx % kXK][idx / kXK] = pa[u];
+      Bs[idx % kXK][idx / kXK] = pb[u];
+    }
+    if (tid < kXK) hs[tid] = ph;
+    __syncthreads();
+    if (m0 + kXK < n) fetch(m0 + kXK);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = h * Bs[mm][ty + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * bv[j];
+    for (int ks = 0; ks < kXK / 4; ++ks) {
+      const int row = 4 * ks + lk;
+      const double hr = hs[row];
+      const double a0 = As[row][wr + li], a1 = As[row][wr + 16 + li];
+      const double b0 = hr * Bs[row][wc + li], b1 = hr * Bs[row][wc + 16 + li];
+      acc[0][0] = mfma16(a0, b0, acc[0][0]);
+      acc[0][1] = mfma16(a0, b1, acc[0][1]);
+      acc[1][0] = mfma16(a1, b0, acc[1][0]);
+      acc[1][1] = mfma16(a1, b1, acc[1][1]);
     }
   }
   const double* dF = dfbuf + off2[s];
   double* Y = ybuf + off2[s];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int k = k0 + tx + 16 * i;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int l = l0 + ty + 16 * j;
-      if (k < n && l < n) {
-        const double y = acc[i][j] * dF[k + (size_t)n * l];
-        Y[k + (size_t)n * l] = y;
-        if (ti != tj) Y[l + (size_t)n * k] = y;
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = k0 + wr + 16 * x + lk + 4 * r;
+        const int l = l0 + wc + 16 * y + li;
+        if (k < n && l < n) {
+          const size_t at = (size_t)l + (size_t)n * k;
+          Y[at] = acc[x][y][r] * dF[at];
+        }
       }
-    }
-  }
 }
 
-// out[j, l] = alpha * sum_k L[j, k] R[l + n k] for kRowChunk core rows and
-// kThreads columns.  mode 0: L = Q_c (rows of Q), R = Y.  mode 1: L = T
-// (row-major c x n), R = Q; also writes out's diagonal for the core trace.
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void k_rows(
-    const double* __restrict__ lsrc, const double* __restrict__ rbuf, double* __restrict__ out,
-    double* __restrict__ pdiag, double alpha, const int64_t* __restrict__ off2,
-    const int64_t* __restrict__ offc, const int32_t* __restrict__ offcd,
-    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core,
-    const int32_t* __restrict__ order) {
-  __shared__ double L[kRowChunk][64 + 1];
+// h1 restricted to every subgraph, in subgraph order: hloc[b + m] = h1[orbs[b + m]]
+__global__ __launch_bounds__(kThreads) void k_h1_gather(const double* __restrict__ h1,
+                                                        const int32_t* __restrict__ sub_orbs,
+                                                        int64_t sum_n, double* __restrict__ hloc) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < sum_n;
+       i += (int64_t)gridDim.x * kThreads)
+    hloc[i] = h1[sub_orbs[i]];
+}
+
+// Y(k, l) under the storage rule of k_xy_mfma
+__device__ __forceinline__ size_t ypos(int k, int l, int n) {
+  return (k / kTile >= l / kTile) ? (size_t)l + (size_t)n * k : (size_t)k + (size_t)n * l;
+}
+
+// T = Q_c Y for 64 columns of one subgraph; T stored as tbuf[(b + l) * 32 + j].
+__global__ __launch_bounds__(kThreads) void k_t_mfma(
+    const double* __restrict__ qbuf, const double* __restrict__ ybuf, double* __restrict__ tbuf,
+    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
+    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order) {
+  __shared__ double As[16][33];
+  __shared__ double Bs[16][kTile + 1];
   const int s = order[blockIdx.x];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
-  const int l = blockIdx.y * kThreads + threadIdx.x;
-  const int j0 = blockIdx.z * kRowChunk;
-  if (blockIdx.y * kThreads >= n || j0 >= c) return;
-  const double* R = rbuf + off2[s];
-  double acc[kRowChunk];
-#pragma unroll
-  for (int jj = 0; jj < kRowChunk; ++jj) acc[jj] = 0.0;
-  for (int k0 = 0; k0 < n; k0 += 64) {
+  const int L0 = blockIdx.y * kTile;
+  if (L0 >= n) return;
+  const double* Q = qbuf + off2[s];
+  const double* Y = ybuf + off2[s];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < n; k0 += 16) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kRowChunk * 64; idx += kThreads) {
-      int jj, kk;
-      double v = 0.0;
-      if (MODE == 0) {
-        jj = idx % kRowChunk;
-        kk = idx / kRowChunk;
-        if (j0 + jj < c && k0 + kk < n) v = lsrc[off2[s] + (j0 + jj) + (size_t)n * (k0 + kk)];
+    for (int idx = tid; idx < 16 * 32; idx += kThreads) {
+      const int j = idx % 32, kk = idx / 32;
+      As[kk][j] = (j < c && k0 + kk < n) ? Q[j + (size_t)n * (k0 + kk)] : 0.0;
+    }
+    // Y rows k0..k0+15, columns L0..L0+63; coalesced along the stored direction
+    const bool lower = (k0 / kTile) >= (L0 / kTile);
+    for (int idx = tid; idx < 16 * kTile; idx += kThreads) {
+      int kk, ll;
+      if (lower) {
+        ll = idx % kTile;
+        kk = idx / kTile;
       } else {
-        kk = idx % 64;
-        jj = idx / 64;
-        if (j0 + jj < c && k0 + kk < n) v = lsrc[offc[s] + (size_t)(j0 + jj) * n + (k0 + kk)];
+        kk = idx % 16;
+        ll = idx / 16;
       }
-      L[jj][kk] = v;
+      const int k = k0 + kk, l = L0 + ll;
+      Bs[kk][ll] = (k < n && l < n) ? Y[ypos(k, l, n)] : 0.0;
     }
     __syncthreads();
-    if (l < n) {
-      const int kend = min(64, n - k0);
-      for (int kk = 0; kk < kend; ++kk) {
-        const double r = R[l + (size_t)n * (k0 + kk)];
 #pragma unroll
-        for (int jj = 0; jj < kRowChunk; ++jj) acc[jj] += L[jj][kk] * r;
-      }
+    for (int ks = 0; ks < 4; ++ks) {
+      const int row = 4 * ks + lk;
+      const double bv = Bs[row][16 * w + li];
+      acc0 = mfma16(As[row][li], bv, acc0);
+      acc1 = mfma16(As[row][16 + li], bv, acc1);
     }
   }
+  const int l = L0 + 16 * w + li;
   if (l < n) {
 #pragma unroll
-    for (int jj = 0; jj < kRowChunk; ++jj) {
-      const int j = j0 + jj;
-      if (j < c) {
-        const double v = alpha * acc[jj];
-        out[offc[s] + (size_t)j * n + l] = v;
-        if (MODE == 1 && l == j) pdiag[offcd[s] + j] = v;
+    for (int r = 0; r < 4; ++r) {
+      tbuf[(size_t)(b + l) * 32 + lk + 4 * r] = acc0[r];
+      tbuf[(size_t)(b + l) * 32 + 16 + lk + 4 * r] = acc1[r];
+    }
+  }
+}
+
+// P = 2 T Q^T (c x n core rows, block layout) and its diagonal.
+__global__ __launch_bounds__(kThreads) void k_p_mfma(
+    const double* __restrict__ tbuf, const double* __restrict__ qbuf, double* __restrict__ out,
+    double* __restrict__ pdiag, const int64_t* __restrict__ off2, const int64_t* __restrict__ offc,
+    const int32_t* __restrict__ offcd, const int32_t* __restrict__ sub_orb_ptr,
+    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order) {
+  const int s = order[blockIdx.x];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const int c = n_core[s];
+  const int L0 = blockIdx.y * kTile;
+  if (L0 >= n) return;
+  const double* Q = qbuf + off2[s];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int lcol = L0 + 16 * w + li;
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int q0 = 0; q0 < n; q0 += 4) {
+    const int q = q0 + lk;
+    const bool ok = q < n;
+    const double a0 = ok ? tbuf[(size_t)(b + q) * 32 + li] : 0.0;
+    const double a1 = ok ? tbuf[(size_t)(b + q) * 32 + 16 + li] : 0.0;
+    const double bv = (ok && lcol < n) ? Q[lcol + (size_t)n * q] : 0.0;
+    acc0 = mfma16(a0, bv, acc0);
+    acc1 = mfma16(a1, bv, acc1);
+  }
+  if (lcol < n) {
+    const size_t base = offc[s];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j0 = lk + 4 * r, j1 = 16 + lk + 4 * r;
+      if (j0 < c) {
+        const double v = 2.0 * acc0[r];
+        out[base + (size_t)j0 * n + lcol] = v;
+        if (lcol == j0) pdiag[offcd[s] + j0] = v;
+      }
+      if (j1 < c) {
+        const double v = 2.0 * acc1[r];
+        out[base + (size_t)j1 * n + lcol] = v;
+        if (lcol == j1) pdiag[offcd[s] + j1] = v;
       }
     }
   }
@@ -218,21 +300,21 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h
   const gq_graph_dev& dv = g->dev;
   const int64_t nnz = g->info.nnz;
   const int sum_c = g->offcd[g->n_sub];
-  dim3 grid_rows(g->n_sub, (g->info.max_n + kThreads - 1) / kThreads,
-                 (g->info.max_c + kRowChunk - 1) / kRowChunk);
+  dim3 grid_cols(g->n_sub, (g->info.max_n + kTile - 1) / kTile);
   for (int q = 0; q < K; ++q) {
     prof_begin(ctx, "k_xy");
-    hipLaunchKernelGGL(k_xy, dim3(dv.n_tiles), dim3(kThreads), 0, st, e->Q, e->A, e->Y,
-                       h1 + (size_t)q * g->N, g->N, dv.tiles, dv.off2, dv.sub_orb_ptr,
-                       dv.sub_orbs);
+    const int64_t sum_n = g->info.sum_n;
+    hipLaunchKernelGGL(k_h1_gather, dim3((unsigned)std::min<int64_t>(1024, (sum_n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, h1 + (size_t)q * g->N, dv.sub_orbs, sum_n, e->hloc);
+    hipLaunchKernelGGL(k_xy_mfma, dim3(dv.n_tiles), dim3(kThreads), 0, st, e->Q, e->A, e->Y,
+                       e->hloc, dv.tiles, dv.off2, dv.sub_orb_ptr);
     prof_end(ctx);
     prof_begin(ctx, "k_rows");
-    hipLaunchKernelGGL(k_rows<0>, grid_rows, dim3(kThreads), 0, st, e->Q, e->Y, e->T,
-                       (double*)nullptr, 1.0, dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core,
-                       dv.order);
-    hipLaunchKernelGGL(k_rows<1>, grid_rows, dim3(kThreads), 0, st, e->T, e->Q,
-                       p_blocks + (size_t)q * nnz, e->pdiag + (size_t)q * sum_c, 2.0, dv.off2,
-                       dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core, dv.order);
+    hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, e->Y, e->T, dv.off2,
+                       dv.sub_orb_ptr, dv.n_core, dv.order);
+    hipLaunchKernelGGL(k_p_mfma, grid_cols, dim3(kThreads), 0, st, e->T, e->Q,
+                       p_blocks + (size_t)q * nnz, e->pdiag + (size_t)q * sum_c, dv.off2, dv.offc,
+                       dv.offcd, dv.sub_orb_ptr, dv.n_core, dv.order);
     prof_end(ctx);
   }
   prof_begin(ctx, "k_mu1_combine");
