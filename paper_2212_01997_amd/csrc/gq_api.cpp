@@ -208,6 +208,7 @@ static int64_t footprint(const gq_graph* g, int32_t max_k) {
   b += in.sum_n * (4 * 8 + 5 * 4) + (int64_t)(g->dc_merges.size() / 4 + 1) * 4;  // merge metadata
   b += (int64_t)g->bt_nblocks * 256 * 8;                                          // WY factors
   b += in.sum_n * 17 * 8;                                                         // panel scratch, h1
+  b += in.sum_n2 * 4;                                                             // FP32 part of Q
   return b;
 }
 
@@ -225,7 +226,8 @@ void gq_eigs_destroy(gq_eigs* e) {
   void* ptrs[] = {e->A, e->Q, e->Y, e->T, e->eps, e->wts, e->dd, e->ee, e->tau, e->M,
                   e->tmu, e->pdiag, e->mu1, e->mu_state, e->mu_part, e->status,
                   e->md_k, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
-                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac, e->wsc, e->hloc};
+                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac, e->wsc, e->hloc,
+                  e->Q32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete e;
@@ -292,6 +294,12 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
       return GQ_ENOMEM;
     }
   }
+  if (hipMalloc((void**)&e->Q32, std::max<int64_t>(1, in.sum_n2) * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("gq_eigs_create: device allocation failed");
+    gq_eigs_destroy(e);
+    return GQ_ENOMEM;
+  }
   *out = e;
   return GQ_OK;
 }
@@ -315,6 +323,7 @@ gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev
   launch_eigensolve(ctx, g, e);
   GQ_HIP(hipGetLastError());
   e->have_density = false;
+  e->q32_valid = false;
   return GQ_OK;
 }
 
@@ -375,7 +384,7 @@ gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const double* h1_dev, int32_t K, 
     set_error("gq_response: K = %d outside [1, max_k = %d]", K, e->max_k);
     return GQ_EINVAL;
   }
-  if (precision != GQ_PREC_FP64) {
+  if (precision != GQ_PREC_FP64 && precision != GQ_PREC_SPLIT32) {
     set_error("gq_response: precision %u not available", precision);
     return GQ_EINVAL;
   }

@@ -125,6 +125,8 @@ struct gq_eigs {
   double* tfac = nullptr;  // [bt_nblocks][16*16] compact-WY T factors
   double* wsc = nullptr;   // [sum_n * 16] panel scratch of the tridiagonalisation
   double* hloc = nullptr;  // [sum_n] perturbation gathered into subgraph order
+  float* Q32 = nullptr;    // [sum n^2] FP32 leading part of Q (split-FP32 congruences)
+  bool q32_valid = false;  // Q32 matches the current Q
   bool have_density = false;
   double kT = 0, n_elec = 0;
 };
