@@ -116,12 +116,214 @@ def cpu_baseline(system, core, h1, budget_s=12.0):
     }
 
 
+# ------------------------------------------------------------ the three forms
+def _time_ms(fn, sync, reps=3):
+    """Best of `reps` wall-clock runs of fn, bracketed by `sync`."""
+    best = 1e30
+    for _ in range(reps):
+        sync()
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        best = min(best, time.perf_counter() - t0)
+    return best * 1e3
+
+
+def _golden3():
+    path = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def _digest(a):
+    import hashlib
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(a, np.int32).tobytes()).hexdigest()[:16]
+
+
+def form_batched_and_mixed(ctx, side):
+    """Config 3 (30,000-atom chain in water, K = 6 perturbations per
+    eigenbasis): the plain batched FP64 path against the autotuned,
+    size-binned, graph-captured one; then the split-FP32 congruences at
+    kT = 0.003, 0.01, 0.03 with their errors against the FP64 path (whole
+    system) and against the stored oracle values (sampled positions)."""
+    import numpy as np
+    import torch
+    from paper_2212_01997_amd import gq, inputs as I
+    from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
+    K = 6
+    log("config 3: generating the 30,000-atom system")
+    s = I.config_system(3)
+    core = I.spatial_cores(s, 8)
+    prev = bootstrap_prev(ctx, s, core, KT)
+    graph = gq.Graph.for_system(s, core, TAU, prev, gq.PATHS2)
+    info = graph.info
+    path = GraphPath(ctx, s, core, TAU, graph=graph, max_k=K)
+    h1 = torch.as_tensor(I.h1_diagonal(s, K, seed=3002), device="cuda")
+    torch.cuda.synchronize()
+    sync = side.synchronize
+    out = {"workload": "config 3: 30,000 atoms (6,000-atom C/N/O/S chain in water), 72,000 "
+                       "orbitals, 8-atom cores, paths of two at tau 0.07, K = 6 diagonal H1",
+           "n_sub": info.n_sub, "n_min": info.min_n, "n_max": info.max_n, "nnz": info.nnz}
+    # plain: default launch variant, eager launches
+    for b in range(5):
+        graph.set_launch(0, b, 0)
+        graph.set_launch(1, b, 0)
+    path.ground_state(KT, want_mu=False)
+    g_ms = _time_ms(lambda: path.ground_state(KT, want_mu=False), sync)
+    r_ms = _time_ms(lambda: path.respond(h1, want_mu1=False), sync)
+    out["plain"] = {"ground_state_ms": g_ms, "response_ms_K6": r_ms,
+                    "response_solves_per_s": K * 1e3 / r_ms,
+                    "step_ms": g_ms + r_ms, "step_solves_per_s": K * 1e3 / (g_ms + r_ms)}
+    # batched: autotuned bins + one captured graph per step
+    report = path.eigs.autotune(gq.PREC_FP64)
+    ctx.capture_begin()
+    path.respond(h1, want_mu1=False)
+    x_resp = ctx.capture_end()
+    ctx.capture_begin()
+    path.ground_state(KT, want_mu=False)
+    path.respond(h1, want_mu1=False)
+    x_step = ctx.capture_end()
+    rb_ms = _time_ms(x_resp.launch, sync)
+    sb_ms = _time_ms(x_step.launch, sync)
+    out["batched"] = {"response_ms_K6": rb_ms, "response_solves_per_s": K * 1e3 / rb_ms,
+                      "step_ms": sb_ms, "step_solves_per_s": K * 1e3 / sb_ms,
+                      "speedup_response_vs_plain": r_ms / rb_ms,
+                      "speedup_step_vs_plain": (g_ms + r_ms) / sb_ms,
+                      "autotune": [ln for ln in report.splitlines() if "->" in ln]}
+    del x_resp, x_step
+    # mixed precision at three temperatures
+    gold = _golden3()
+    ex = graph.export()
+    gold_ok = gold is not None and all(
+        gold["graph"][k] == _digest(ex[k]) for k in ("sub_orb_ptr", "sub_orbs", "rho_row_ptr", "rho_col"))
+    path.eigs.autotune(gq.PREC_SPLIT32)
+    mixed = []
+    for kT in (0.003, 0.01, 0.03):
+        mu = path.ground_state(kT)
+        path.sync()
+        mu1_64 = path.respond(h1)
+        path.sync()
+        rho = path.rho.clone()
+        rho1_64 = path.rho1_view(K).clone()
+        t64 = _time_ms(lambda: path.respond(h1, want_mu1=False), sync)
+        mu1_32 = path.respond(h1, precision=gq.PREC_SPLIT32)
+        path.sync()
+        rho1_32 = path.rho1_view(K).clone()
+        t32 = _time_ms(lambda: path.respond(h1, precision=gq.PREC_SPLIT32, want_mu1=False), sync)
+        row = {"kT": kT, "fp64_response_ms_K6": t64, "split32_response_ms_K6": t32,
+               "speedup": t64 / t32,
+               "split32_vs_fp64_path": {"rho1": float((rho1_32 - rho1_64).abs().max()),
+                                        "mu1": float(np.abs(mu1_32 - mu1_64).max())}}
+        if gold_ok:
+            g = gold["kT"][repr(kT)]
+            idx = torch.as_tensor(np.array(gold["idx"]), device="cuda")
+            r_or = np.array(g["rho1"])
+            row["vs_oracle_sampled"] = {
+                "positions": len(gold["idx"]),
+                "mu": abs(mu - g["mu"]),
+                "rho": float(np.abs(rho[idx].cpu().numpy() - np.array(g["rho"])).max()),
+                "fp64": {"rho1": float(np.abs(rho1_64[:, idx].cpu().numpy() - r_or).max()),
+                         "mu1": float(np.abs(mu1_64 - np.array(g["mu1"])).max())},
+                "split32": {"rho1": float(np.abs(rho1_32[:, idx].cpu().numpy() - r_or).max()),
+                            "mu1": float(np.abs(mu1_32 - np.array(g["mu1"])).max())}}
+        mixed.append(row)
+        log(f"mixed kT={kT}: fp64 {t64:.2f} ms, split32 {t32:.2f} ms, "
+            f"|drho1| {row['split32_vs_fp64_path']['rho1']:.2e}")
+    out["mixed"] = mixed
+    out["oracle_values"] = ("stored oracle values at 4,096 sampled positions (tests/golden)"
+                            if gold_ok else "not compared (stored oracle values missing or for another graph)")
+    return out
+
+
+def form_served(ctx, side, n_slots=4):
+    """Config 5: a Poisson trace (20 requests/s, 200 requests, 500..20,000
+    atoms, K = 1..8) served by the runtime, against the same trace run one
+    request after another on the plain path (FIFO, same arrival times)."""
+    import threading
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    from paper_2212_01997_amd import gq, inputs as I
+    from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
+    tr = I.serving_trace()
+    log(f"config 5: generating {len(tr.pool)} pool systems")
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1),
+                             mp_context=mp.get_context("spawn")) as ex:
+        systems = list(ex.map(_pool_system, tr.pool))
+    cores = [I.spatial_cores(s, 8) for s in systems]
+    prevs = [bootstrap_prev(ctx, s, c, KT) for s, c in zip(systems, cores)]
+    h1s = [I.h1_diagonal(systems[i], int(k), seed=int(sd))
+           for i, k, sd in zip(tr.system, tr.K, tr.h1_seed)]
+    n = len(tr.arrival)
+    solves = int(tr.K.sum())
+    # sequential plain path
+    log("config 5: sequential plain path")
+    lat_seq = np.zeros(n)
+    t0 = time.perf_counter()
+    for j in range(n):
+        now = time.perf_counter() - t0
+        if now < tr.arrival[j]:
+            time.sleep(tr.arrival[j] - now)
+        i = int(tr.system[j])
+        p = GraphPath(ctx, systems[i], cores[i], TAU, prevs[i], gq.PATHS2, max_k=int(tr.K[j]))
+        p.ground_state(KT, want_mu=False)
+        p.respond(torch.as_tensor(h1s[j], device="cuda"), want_mu1=False)
+        side.synchronize()
+        rho1 = p.rho1.cpu()  # results to the host, as the server returns them
+        del rho1
+        lat_seq[j] = time.perf_counter() - t0 - tr.arrival[j]
+        del p
+    span_seq = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    # served
+    log("config 5: served")
+    srv = gq.Server(0, n_slots=n_slots, arena_bytes=96 << 30)
+    ids = [None] * n
+    start = srv.clock()
+
+    def feeder():
+        for j in range(n):
+            now = srv.clock() - start
+            if now < tr.arrival[j]:
+                time.sleep(tr.arrival[j] - now)
+            i = int(tr.system[j])
+            ids[j] = srv.submit(systems[i], cores[i], TAU, prevs[i], gq.PATHS2, KT, h1s[j])
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    infos = [srv.wait(rid) for rid in ids]
+    lat_srv = np.array([inf["t_done"] - (start + tr.arrival[j]) for j, inf in enumerate(infos)])
+    span_srv = max(inf["t_done"] for inf in infos) - start
+    srv.close()
+    return {"workload": f"config 5: {n} requests, Poisson 20/s, {len(tr.pool)} seeded pool systems "
+                        f"of 500..20,000 atoms (log-uniform; water or chain-in-water), K = 1..8 "
+                        f"({solves} solves), kT 0.01, paths of two at tau 0.07",
+            "served": {"slots": n_slots, "p50_ms": float(np.percentile(lat_srv, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat_srv, 99) * 1e3),
+                       "solves_per_s": solves / span_srv, "makespan_s": span_srv},
+            "sequential_plain": {"p50_ms": float(np.percentile(lat_seq, 50) * 1e3),
+                                 "p99_ms": float(np.percentile(lat_seq, 99) * 1e3),
+                                 "solves_per_s": solves / span_seq, "makespan_s": span_seq}}
+
+
+def _pool_system(spec):
+    from paper_2212_01997_amd import inputs as I
+    return I.pool_system(*spec)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched (config 3), mixed (config 4) and served (config 5) forms")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 256 MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -139,7 +341,8 @@ def main():
     system = I.config_system(2)
     core = I.spatial_cores(system, 8)
     h1_host = I.h1_diagonal(system, 1, seed=2002)
-    ctx = gq.Context(0)
+    side = torch.cuda.Stream()  # a stream of its own, so that whole steps can be captured
+    ctx = gq.Context(0, stream=side)
     log("previous-step density on the Hamiltonian graph")
     prev = bootstrap_prev(ctx, system, core, KT)
     gb = []
@@ -200,6 +403,15 @@ def main():
                 "traffic": measured_traffic(dominant),
                 "algorithmic_flops_per_launch": flops, "launch_ms": per_launch[dominant],
                 "launches_per_step": launches_per_step}
+    xy_flops = work["k_xy"]
+    xy_ms = per_launch.get("k_xy", 0.0)
+    roofline_congruence = None
+    if xy_ms:
+        a = xy_flops / (xy_ms * 1e-3)
+        roofline_congruence = {"bound": "mfma", "kernel": "k_xy", "achieved": a / 1e12,
+                               "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": a / PEAK_FP64,
+                               "traffic": measured_traffic("k_xy"),
+                               "algorithmic_flops_per_launch": xy_flops, "launch_ms": xy_ms}
     phases = {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda x: -x[1])}
     eig_ms = sum(v for k, v in per_step.items() if k in ("k_gather", "k_tridiag") or k.startswith(("k_dc", "k_back")))
     resp_ms = sum(per_step.get(k, 0) for k in ("k_xy", "k_rows", "k_mu1_combine"))
@@ -232,7 +444,14 @@ def main():
         "elements_per_s": info.nnz * 1000.0 / ms,
         "response_only_solves_per_s": 1000.0 / resp_ms if resp_ms else None,
         "roofline": roofline,
+        "roofline_congruence": roofline_congruence,
     }
+    if not args.no_forms:
+        forms = {}
+        forms["batched_and_mixed"] = form_batched_and_mixed(ctx, side)
+        torch.cuda.empty_cache()
+        forms["served"] = form_served(ctx, side)
+        line["forms"] = forms
     if not args.no_cpu_baseline:
         log("oracle CPU baseline on a sample of subgraphs")
         from oracle import oracle as O

@@ -65,6 +65,7 @@ typedef int32_t gq_status;
 typedef struct gq_ctx gq_ctx;
 typedef struct gq_graph gq_graph;
 typedef struct gq_eigs gq_eigs;
+typedef struct gq_exec gq_exec;
 
 /* CSR matrix, 0-based, ascending columns in every row.  Host or device
  * memory as stated by the call that takes it. */
@@ -137,6 +138,15 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
 /* Device bytes held by an eigen workspace for graph g and max_k (for
  * admission control); no allocation. */
 gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, int64_t* bytes);
+/* As gq_eigs_create, with every device array of the workspace (and the
+ * graph's device maps, if the graph is not bound to a device yet) placed in
+ * caller-owned device memory `mem` of `bytes` >= gq_eigs_footprint(g, max_k),
+ * 256-byte aligned.  For allocators that hand out pieces of one arena (the
+ * serving runtime): neither this call nor gq_eigs_destroy / gq_graph_destroy
+ * allocate or free device memory for such a workspace.  mem must outlive both
+ * handles. */
+gq_status gq_eigs_create_in(gq_ctx* ctx, const gq_graph* g, int32_t max_k, void* mem,
+                            int64_t bytes, gq_eigs** out);
 void gq_eigs_destroy(gq_eigs* e);
 
 /* ------------------------------------------------------ submatrix_solve
@@ -178,6 +188,93 @@ gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const double* h1_dev, int32_t K,
  * arrays vals_dev[K][nnz] in the collected pattern of g (device). */
 gq_status gq_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks_dev, int32_t K,
                       double* vals_dev);
+
+/* ------------------------------------------------------------ batching
+ * Launch tuning and whole-step capture for batches of uneven subgraphs
+ * (Sec. II.G: the subgraph problems are independent and are run as one
+ * batch; the sizes follow from the graph).
+ *
+ * gq_autotune: times, on this workspace and for precision GQ_PREC_FP64 or
+ * GQ_PREC_SPLIT32, each launch variant of the response's X kernel (64x64 or
+ * 32x32 tiles; one workgroup per tile or a persistent grid) on every size bin
+ * of the subgraphs (n <= 128, 256, 384, 512, 1024) and keeps the fastest per
+ * bin in the graph handle, where later gq_response calls on any workspace of
+ * that graph use it.  Requires gq_density first.  Overwrites the workspace's
+ * response scratch; waits for the stream.  report (host, may be NULL)
+ * receives up to report_len bytes of NUL-terminated text, one line per
+ * variant and bin.  GQ_EINVAL while capturing.
+ *
+ * gq_capture_begin / gq_capture_end record every library call made on ctx in
+ * between into one HIP graph instead of running it (the context's stream must
+ * not be the legacy default stream).  Recorded calls must not return host
+ * scalars (mu_out and mu1_host NULL, no gq_eigs_export or kernel times):
+ * such calls fail with GQ_EINVAL while capturing.  Profiling is suspended.
+ * gq_exec_launch replays the recorded work on ctx's stream with the buffers
+ * and arguments of the recording (asynchronous); the handles and device
+ * buffers it names must stay alive.  gq_exec_destroy frees the graph. */
+gq_status gq_autotune(gq_ctx* ctx, gq_eigs* e, uint32_t precision, char* report,
+                      size_t report_len);
+/* Sets the X-kernel launch variant of one size bin by hand (diagnostics and
+ * tests): bin 0..4 as above, variant bit 0 = 32x32 tiles, bit 1 = persistent
+ * grid.  Every variant gives bit-identical results. */
+gq_status gq_graph_set_launch(const gq_graph* g, uint32_t precision, int32_t bin,
+                              int32_t variant);
+gq_status gq_capture_begin(gq_ctx* ctx);
+gq_status gq_capture_end(gq_ctx* ctx, gq_exec** out);
+gq_status gq_exec_launch(gq_ctx* ctx, gq_exec* x);
+void gq_exec_destroy(gq_exec* x);
+
+/* ------------------------------------------------------------- serving
+ * A runtime that admits whole-path requests continuously on one GPU.  One
+ * device arena of arena_bytes is allocated at creation; n_slots executor
+ * threads, each with a HIP stream and context of its own, take the oldest
+ * waiting request, build its graph on the host, size its footprint (eigen
+ * workspace, graph maps, H, the K perturbations, rho and rho1) and wait until
+ * the arena has a contiguous piece of that size.  Admitted requests run
+ * concurrently on their threads' streams; the K perturbations of a request
+ * share its device-resident eigenbasis, mu and dF.  No device memory is
+ * allocated or freed while serving.
+ *
+ * gq_server_submit copies the request (host memory) and returns at once with
+ * its id.  gq_server_wait blocks until the request has finished and fills
+ * info (times in seconds on the server clock, which starts at creation); it
+ * returns the request's status (GQ_ENOMEM if it can never fit the arena).
+ * gq_server_fetch copies the results to host arrays (any may be NULL):
+ * mu1[K], rho[nnz], rho1[K][nnz], and the collected CSR pattern
+ * rho_row_ptr[N+1], rho_col[nnz].  gq_server_release forgets a finished
+ * request.  gq_server_destroy fails the requests still waiting (GQ_EBUSY),
+ * waits for the running ones and frees the arena. */
+typedef struct gq_server gq_server;
+typedef struct {
+  int32_t n_atoms;
+  const int32_t* atom_orb_ptr; /* [n_atoms+1] */
+  const gq_csr* H;             /* host CSR, N x N */
+  const gq_csr* rho_prev;      /* host CSR or NULL (graph from H alone) */
+  const int32_t* core_of_atom; /* [n_atoms] */
+  double tau;
+  uint32_t flags;              /* graph_build flags */
+  double kT, n_elec;
+  int32_t K;                   /* perturbations */
+  const double* h1;            /* host [K][N], diagonal perturbations */
+  uint32_t precision;          /* GQ_PREC_FP64 or GQ_PREC_SPLIT32 */
+} gq_request;
+typedef struct {
+  gq_status status;
+  double mu;
+  int32_t n_sub, K;
+  int64_t nnz, footprint;
+  double t_submit, t_admit, t_done;
+} gq_request_info;
+gq_status gq_server_create(int32_t device, int32_t n_slots, int64_t arena_bytes,
+                           gq_server** out);
+gq_status gq_server_submit(gq_server* s, const gq_request* r, int64_t* id);
+gq_status gq_server_wait(gq_server* s, int64_t id, gq_request_info* info);
+gq_status gq_server_fetch(gq_server* s, int64_t id, double* mu1, double* rho, double* rho1,
+                          int32_t* rho_row_ptr, int32_t* rho_col);
+gq_status gq_server_release(gq_server* s, int64_t id);
+gq_status gq_server_arena_used(gq_server* s, int64_t* used, int64_t* size);
+double gq_server_clock(gq_server* s);
+void gq_server_destroy(gq_server* s);
 
 /* ---------------------------------------------------------- profiling
  * Diagnostics, not part of the method.  While enabled, every kernel launch

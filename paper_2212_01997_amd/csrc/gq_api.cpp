@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "gq_internal.hpp"
 
@@ -22,58 +23,153 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
-template <class T>
-static gq_status dev_upload(T** dst, const std::vector<T>& src) {
-  const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
-  GQ_HIP(hipMalloc((void**)dst, bytes));
-  if (!src.empty()) GQ_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
-  return GQ_OK;
+// Device arrays carved out of one block, each 256-byte aligned.  With a null
+// base only the size is computed.
+struct Carve {
+  char* base = nullptr;
+  size_t used = 0;
+  template <class T>
+  T* take(int64_t count) {
+    const size_t at = (used + 255) & ~size_t(255);
+    used = at + (size_t)std::max<int64_t>(1, count) * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + at) : nullptr;
+  }
+};
+
+// Layout of a graph's device maps; copies the host maps in when `upload`.
+static gq_status graph_maps(const gq_graph* g, gq_graph_dev& d, Carve& c, bool upload,
+                            hipStream_t stream) {
+  gq_status st = GQ_OK;
+  auto put = [&](auto*& dst, const auto& src) {
+    using T = typename std::decay_t<decltype(src)>::value_type;
+    dst = c.template take<T>((int64_t)src.size());
+    if (upload && st == GQ_OK && !src.empty() &&
+        hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, stream) !=
+            hipSuccess) {
+      set_error("graph upload: %s", hipGetErrorString(hipGetLastError()));
+      st = GQ_EDEVICE;
+    }
+  };
+  put(d.sub_orb_ptr, g->sub_orb_ptr);
+  put(d.sub_orbs, g->sub_orbs);
+  put(d.n_core, g->n_core_orbs);
+  put(d.sorted_orbs, g->sorted_orbs);
+  put(d.sorted_local, g->sorted_local);
+  put(d.slot, g->slot);
+  put(d.off2, g->off2);
+  put(d.offc, g->offc);
+  put(d.offcd, g->offcd);
+  put(d.order, g->order);
+  put(d.rho_row_ptr, g->rho_row_ptr);
+  put(d.dc_leaves, g->dc_leaves);
+  put(d.dc_merges, g->dc_merges);
+  put(d.dc_tiles, g->dc_tiles);
+  put(d.bt_toff, g->bt_toff);
+  put(d.xy_tiles[0], g->xy_tiles[0]);
+  put(d.xy_tiles[1], g->xy_tiles[1]);
+  d.n_leaves = (int32_t)(g->dc_leaves.size() / 3);
+  return st;
+}
+
+static int64_t graph_maps_bytes(const gq_graph* g) {
+  gq_graph_dev d;
+  Carve c;
+  (void)graph_maps(g, d, c, false, nullptr);
+  return (int64_t)c.used + 256;
 }
 
 void graph_free_dev(const gq_graph* g) {
   gq_graph_dev& d = g->dev;
-  void* ptrs[] = {d.sub_orb_ptr, d.sub_orbs, d.n_core, d.sorted_orbs, d.sorted_local, d.slot,
-                  d.off2, d.offc, d.offcd, d.order, d.rho_row_ptr, d.tiles,
-                  d.dc_leaves, d.dc_merges, d.dc_tiles, d.bt_toff};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  if (d.block) (void)hipFree(d.block);
   d = gq_graph_dev{};
 }
 
-gq_status graph_upload(const gq_graph* g, int device) {
+// Binds the graph to `device`: its maps in `mem` (caller-owned, at least
+// graph_maps_bytes) or, with mem == NULL, in a block of its own.
+static gq_status graph_upload_at(const gq_graph* g, int device, char* mem, hipStream_t stream) {
   gq_graph_dev& d = g->dev;
   if (d.device == device) return GQ_OK;
   if (d.device >= 0) {
     set_error("graph already bound to device %d", d.device);
     return GQ_EINVAL;
   }
-  std::vector<int32_t> tiles;
-  for (int32_t s : g->order) {
-    const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
-    const int32_t nt = (n + 63) / 64;
-    for (int32_t ti = 0; ti < nt; ++ti)
-      for (int32_t tj = 0; tj <= ti; ++tj) {
-        tiles.push_back(s);
-        tiles.push_back(ti);
-        tiles.push_back(tj);
-      }
+  Carve c;
+  char* owned = nullptr;
+  if (!mem) {
+    (void)graph_maps(g, d, c, false, nullptr);
+    if (hipMalloc((void**)&owned, c.used + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("graph upload: device allocation of %zu bytes failed", c.used);
+      d = gq_graph_dev{};
+      return GQ_ENOMEM;
+    }
+    mem = owned;
   }
-  gq_status st;
-  if ((st = dev_upload(&d.sub_orb_ptr, g->sub_orb_ptr)) || (st = dev_upload(&d.sub_orbs, g->sub_orbs)) ||
-      (st = dev_upload(&d.n_core, g->n_core_orbs)) || (st = dev_upload(&d.sorted_orbs, g->sorted_orbs)) ||
-      (st = dev_upload(&d.sorted_local, g->sorted_local)) || (st = dev_upload(&d.slot, g->slot)) ||
-      (st = dev_upload(&d.off2, g->off2)) || (st = dev_upload(&d.offc, g->offc)) ||
-      (st = dev_upload(&d.offcd, g->offcd)) || (st = dev_upload(&d.order, g->order)) ||
-      (st = dev_upload(&d.rho_row_ptr, g->rho_row_ptr)) || (st = dev_upload(&d.tiles, tiles)) ||
-      (st = dev_upload(&d.dc_leaves, g->dc_leaves)) || (st = dev_upload(&d.dc_merges, g->dc_merges)) ||
-      (st = dev_upload(&d.dc_tiles, g->dc_tiles)) || (st = dev_upload(&d.bt_toff, g->bt_toff))) {
-    graph_free_dev(g);
+  c = Carve{};
+  c.base = mem;
+  gq_status st = graph_maps(g, d, c, true, stream);
+  if (st == GQ_OK && hipStreamSynchronize(stream) != hipSuccess) {
+    set_error("graph upload: %s", hipGetErrorString(hipGetLastError()));
+    st = GQ_EDEVICE;
+  }
+  if (st) {
+    if (owned) (void)hipFree(owned);
+    d = gq_graph_dev{};
     return st;
   }
-  d.n_tiles = (int32_t)(tiles.size() / 3);
-  d.n_leaves = (int32_t)(g->dc_leaves.size() / 3);
+  d.block = owned;
   d.device = device;
   return GQ_OK;
+}
+
+gq_status graph_upload(const gq_graph* g, int device) {
+  return graph_upload_at(g, device, nullptr, nullptr);
+}
+
+// Layout of an eigen workspace (pointers filled when c.base is set).
+static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, Carve& c) {
+  const gq_graph_info& in = g->info;
+  const int64_t sum_c = g->offcd[g->n_sub];
+  const int64_t kk = std::max(max_k, 1);
+  gq_eigs tmp;
+  gq_eigs& x = e ? *e : tmp;
+  x.mu_blocks = mu_blocks_for(in.sum_n);
+  x.A = c.take<double>(in.sum_n2);
+  x.Q = c.take<double>(in.sum_n2);
+  x.Y = c.take<double>(kk * in.sum_n2);
+  x.T = c.take<double>(kk * in.sum_n * 32);
+  x.M = c.take<double>(in.nnz);
+  x.eps = c.take<double>(in.sum_n);
+  x.wts = c.take<double>(in.sum_n);
+  x.dd = c.take<double>(in.sum_n);
+  x.ee = c.take<double>(in.sum_n);
+  x.tau = c.take<double>(in.sum_n);
+  x.tmu = c.take<double>(g->n_sub);
+  x.pdiag = c.take<double>(kk * std::max<int64_t>(sum_c, 1));
+  x.mu1 = c.take<double>(kk);
+  x.mu_state = c.take<double>(16);
+  x.mu_part = c.take<double>((int64_t)x.mu_blocks * kMuPoints);
+  x.md_delta = c.take<double>(in.sum_n);
+  x.md_tau = c.take<double>(in.sum_n);
+  x.md_zhat = c.take<double>(in.sum_n);
+  x.md_inv = c.take<double>(in.sum_n);
+  x.tfac = c.take<double>((int64_t)g->bt_nblocks * 256);
+  x.wsc = c.take<double>(in.sum_n * 16);
+  x.hloc = c.take<double>(kk * in.sum_n);
+  x.Q32 = c.take<float>(in.sum_n2);
+  x.status = c.take<int32_t>(g->n_sub);
+  x.md_k = c.take<int32_t>((int64_t)(g->dc_merges.size() / 4));
+  x.md_cols = c.take<int32_t>(in.sum_n);
+  x.md_org = c.take<int32_t>(in.sum_n);
+  x.md_pos = c.take<int32_t>(in.sum_n);
+  x.md_dsrc = c.take<int32_t>(in.sum_n);
+  x.md_dpos = c.take<int32_t>(in.sum_n);
+}
+
+static int64_t eigs_bytes(const gq_graph* g, int32_t max_k) {
+  Carve c;
+  eigs_layout(nullptr, g, max_k, c);
+  return (int64_t)c.used + 256;
 }
 
 }  // namespace gq
@@ -195,21 +291,9 @@ void gq_graph_destroy(gq_graph* g) {
   delete g;
 }
 
+// Device bytes of a workspace plus the graph's device maps.
 static int64_t footprint(const gq_graph* g, int32_t max_k) {
-  const gq_graph_info& in = g->info;
-  const int64_t sum_c = g->offcd[g->n_sub];
-  int64_t b = 0;
-  b += 3 * in.sum_n2 * 8;          // A, Q, Y
-  b += in.nnz * 8 + in.sum_n * 32 * 8;  // M, T
-  b += 5 * in.sum_n * 8;           // eps, wts, dd, ee, tau
-  b += (int64_t)g->n_sub * (8 + 4);  // tmu, status
-  b += (int64_t)std::max(max_k, 1) * (sum_c + 1) * 8;  // pdiag, mu1
-  b += (int64_t)mu_blocks_for(in.sum_n) * kMuPoints * 8 + 16 * 8;
-  b += in.sum_n * (4 * 8 + 5 * 4) + (int64_t)(g->dc_merges.size() / 4 + 1) * 4;  // merge metadata
-  b += (int64_t)g->bt_nblocks * 256 * 8;                                          // WY factors
-  b += in.sum_n * 17 * 8;                                                         // panel scratch, h1
-  b += in.sum_n2 * 4;                                                             // FP32 part of Q
-  return b;
+  return eigs_bytes(g, max_k) + graph_maps_bytes(g);
 }
 
 gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, int64_t* bytes) {
@@ -223,31 +307,29 @@ gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, int64_t* bytes) {
 
 void gq_eigs_destroy(gq_eigs* e) {
   if (!e) return;
-  void* ptrs[] = {e->A, e->Q, e->Y, e->T, e->eps, e->wts, e->dd, e->ee, e->tau, e->M,
-                  e->tmu, e->pdiag, e->mu1, e->mu_state, e->mu_part, e->status,
-                  e->md_k, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
-                  e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->tfac, e->wsc, e->hloc,
-                  e->Q32};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  if (e->block) (void)hipFree(e->block);
   delete e;
 }
 
-gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs** out) {
+static gq_status eigs_check(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs** out,
+                            const char* who) {
   if (!ctx || !g || !out || max_k < 0) {
-    set_error("gq_eigs_create: bad argument");
+    set_error("%s: bad argument", who);
     return GQ_EINVAL;
   }
   if (g->info.max_n > kMaxN) {
-    set_error("gq_eigs_create: subgraph of %d orbitals exceeds the limit %d", g->info.max_n, kMaxN);
+    set_error("%s: subgraph of %d orbitals exceeds the limit %d", who, g->info.max_n, kMaxN);
     return GQ_EINVAL;
   }
   if (g->info.max_c > kMaxCore) {
-    set_error("gq_eigs_create: core of %d orbitals exceeds the limit %d", g->info.max_c, kMaxCore);
+    set_error("%s: core of %d orbitals exceeds the limit %d", who, g->info.max_c, kMaxCore);
     return GQ_EINVAL;
   }
-  GQ_HIP(hipSetDevice(ctx->device));
-  if (gq_status st = graph_upload(g, ctx->device)) return st;
+  return GQ_OK;
+}
+
+static gq_status eigs_make(gq_ctx* ctx, const gq_graph* g, int32_t max_k, char* mem,
+                           gq_eigs** out) {
   gq_eigs* e = new (std::nothrow) gq_eigs;
   if (!e) {
     set_error("gq_eigs_create: out of host memory");
@@ -256,52 +338,52 @@ gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs*
   e->ctx = ctx;
   e->g = g;
   e->max_k = max_k;
-  const gq_graph_info& in = g->info;
-  const int64_t sum_c = g->offcd[g->n_sub];
-  e->mu_blocks = mu_blocks_for(in.sum_n);
-  struct Req {
-    double** p;
-    int64_t count;
-  } reqs[] = {{&e->A, in.sum_n2}, {&e->Q, in.sum_n2}, {&e->Y, in.sum_n2}, {&e->T, in.sum_n * 32},
-              {&e->M, in.nnz}, {&e->eps, in.sum_n}, {&e->wts, in.sum_n}, {&e->dd, in.sum_n},
-              {&e->ee, in.sum_n}, {&e->tau, in.sum_n}, {&e->tmu, g->n_sub},
-              {&e->pdiag, (int64_t)std::max(max_k, 1) * std::max<int64_t>(sum_c, 1)},
-              {&e->mu1, std::max(max_k, 1)}, {&e->mu_state, 16},
-              {&e->mu_part, (int64_t)e->mu_blocks * kMuPoints},
-              {&e->md_delta, in.sum_n}, {&e->md_tau, in.sum_n}, {&e->md_zhat, in.sum_n},
-              {&e->md_inv, in.sum_n}, {&e->tfac, (int64_t)g->bt_nblocks * 256},
-              {&e->wsc, in.sum_n * 16}, {&e->hloc, in.sum_n}};
-  for (auto& r : reqs) {
-    if (hipMalloc((void**)r.p, std::max<int64_t>(1, r.count) * sizeof(double)) != hipSuccess) {
+  if (!mem) {
+    if (hipMalloc((void**)&e->block, (size_t)eigs_bytes(g, max_k)) != hipSuccess) {
       (void)hipGetLastError();
       set_error("gq_eigs_create: device allocation of %lld bytes failed",
-                (long long)(r.count * 8));
-      gq_eigs_destroy(e);
+                (long long)eigs_bytes(g, max_k));
+      delete e;
       return GQ_ENOMEM;
     }
+    mem = e->block;
   }
-  struct ReqI {
-    int32_t** p;
-    int64_t count;
-  } reqi[] = {{&e->status, g->n_sub}, {&e->md_k, (int64_t)(g->dc_merges.size() / 4)},
-              {&e->md_cols, in.sum_n}, {&e->md_org, in.sum_n}, {&e->md_pos, in.sum_n},
-              {&e->md_dsrc, in.sum_n}, {&e->md_dpos, in.sum_n}};
-  for (auto& r : reqi) {
-    if (hipMalloc((void**)r.p, std::max<int64_t>(1, r.count) * sizeof(int32_t)) != hipSuccess) {
-      (void)hipGetLastError();
-      set_error("gq_eigs_create: device allocation failed");
-      gq_eigs_destroy(e);
-      return GQ_ENOMEM;
-    }
-  }
-  if (hipMalloc((void**)&e->Q32, std::max<int64_t>(1, in.sum_n2) * sizeof(float)) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("gq_eigs_create: device allocation failed");
-    gq_eigs_destroy(e);
-    return GQ_ENOMEM;
-  }
+  Carve c;
+  c.base = mem;
+  eigs_layout(e, g, max_k, c);
   *out = e;
   return GQ_OK;
+}
+
+gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs** out) {
+  if (gq_status st = eigs_check(ctx, g, max_k, out, "gq_eigs_create")) return st;
+  GQ_HIP(hipSetDevice(ctx->device));
+  if (gq_status st = graph_upload(g, ctx->device)) return st;
+  return eigs_make(ctx, g, max_k, nullptr, out);
+}
+
+gq_status gq_eigs_create_in(gq_ctx* ctx, const gq_graph* g, int32_t max_k, void* mem,
+                            int64_t bytes, gq_eigs** out) {
+  if (gq_status st = eigs_check(ctx, g, max_k, out, "gq_eigs_create_in")) return st;
+  if (!mem || bytes < footprint(g, max_k)) {
+    set_error("gq_eigs_create_in: %lld bytes given, %lld needed", (long long)bytes,
+              (long long)footprint(g, max_k));
+    return GQ_EINVAL;
+  }
+  if (reinterpret_cast<uintptr_t>(mem) % 256) {
+    set_error("gq_eigs_create_in: memory must be 256-byte aligned");
+    return GQ_EINVAL;
+  }
+  GQ_HIP(hipSetDevice(ctx->device));
+  char* base = static_cast<char*>(mem);
+  const bool bind = g->dev.device < 0;
+  if (bind) {
+    if (gq_status st = graph_upload_at(g, ctx->device, base, ctx->stream)) return st;
+  } else if (g->dev.device != ctx->device) {
+    set_error("gq_eigs_create_in: graph bound to device %d", g->dev.device);
+    return GQ_EINVAL;
+  }
+  return eigs_make(ctx, g, max_k, base + graph_maps_bytes(g), out);
 }
 
 gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev, uint32_t flags,
@@ -354,6 +436,10 @@ gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* 
     set_error("gq_density: N_e = %g outside (0, 2N = %d)", n_elec, 2 * e->g->N);
     return GQ_EINVAL;
   }
+  if (mu_out && ctx->capturing) {
+    set_error("gq_density: mu_out must be NULL while capturing");
+    return GQ_EINVAL;
+  }
   GQ_HIP(hipSetDevice(ctx->device));
   e->kT = kT;
   e->n_elec = n_elec;
@@ -382,6 +468,10 @@ gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const double* h1_dev, int32_t K, 
   }
   if (K < 1 || K > e->max_k) {
     set_error("gq_response: K = %d outside [1, max_k = %d]", K, e->max_k);
+    return GQ_EINVAL;
+  }
+  if (mu1_host && ctx->capturing) {
+    set_error("gq_response: mu1_host must be NULL while capturing");
     return GQ_EINVAL;
   }
   if (precision != GQ_PREC_FP64 && precision != GQ_PREC_SPLIT32) {
@@ -418,6 +508,10 @@ gq_status gq_eigs_export(gq_ctx* ctx, const gq_eigs* e, double* eps, double* w) 
     set_error("gq_eigs_export: NULL argument");
     return GQ_EINVAL;
   }
+  if (ctx->capturing) {
+    set_error("gq_eigs_export: not available while capturing");
+    return GQ_EINVAL;
+  }
   GQ_HIP(hipSetDevice(ctx->device));
   const size_t bytes = e->g->info.sum_n * sizeof(double);
   if (eps) GQ_HIP(hipMemcpyAsync(eps, e->eps, bytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -442,7 +536,7 @@ gq_status gq_eigs_vectors(const gq_eigs* e, int32_t i, const double** q_dev, int
 namespace gq {
 
 void prof_begin(gq_ctx* ctx, const char* name) {
-  if (!ctx->profiling) return;
+  if (!ctx->profiling || ctx->capturing) return;
   gq_prof_rec r{name, nullptr, nullptr};
   if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
     (void)hipGetLastError();
@@ -453,7 +547,7 @@ void prof_begin(gq_ctx* ctx, const char* name) {
 }
 
 void prof_end(gq_ctx* ctx) {
-  if (!ctx->profiling || ctx->pending.empty()) return;
+  if (!ctx->profiling || ctx->capturing || ctx->pending.empty()) return;
   (void)hipEventRecord(ctx->pending.back().stop, ctx->stream);
 }
 
@@ -479,6 +573,125 @@ static void prof_drain(gq_ctx* ctx) {
 
 extern "C" {
 
+struct gq_exec {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+gq_status gq_autotune(gq_ctx* ctx, gq_eigs* e, uint32_t precision, char* report,
+                      size_t report_len) {
+  if (!ctx || !e) {
+    set_error("gq_autotune: NULL argument");
+    return GQ_EINVAL;
+  }
+  if (ctx->capturing) {
+    set_error("gq_autotune: not available while capturing");
+    return GQ_EINVAL;
+  }
+  if (!e->have_density) {
+    set_error("gq_autotune: call gq_density on this workspace first");
+    return GQ_EINVAL;
+  }
+  if (precision != GQ_PREC_FP64 && precision != GQ_PREC_SPLIT32) {
+    set_error("gq_autotune: precision %u not available", precision);
+    return GQ_EINVAL;
+  }
+  GQ_HIP(hipSetDevice(ctx->device));
+  std::string text;
+  gq_status st = autotune_xy(ctx, e->g, e, precision, &text);
+  if (report && report_len > 0) {
+    const size_t m = std::min(report_len - 1, text.size());
+    std::memcpy(report, text.data(), m);
+    report[m] = 0;
+  }
+  return st;
+}
+
+gq_status gq_graph_set_launch(const gq_graph* g, uint32_t precision, int32_t bin,
+                              int32_t variant) {
+  if (!g || (precision != GQ_PREC_FP64 && precision != GQ_PREC_SPLIT32) || bin < 0 ||
+      bin >= kXyBins || variant < 0 || variant > 3) {
+    set_error("gq_graph_set_launch: bad argument");
+    return GQ_EINVAL;
+  }
+  g->xy_choice[precision == GQ_PREC_SPLIT32 ? 1 : 0][bin] = (int8_t)variant;
+  return GQ_OK;
+}
+
+gq_status gq_capture_begin(gq_ctx* ctx) {
+  if (!ctx) {
+    set_error("gq_capture_begin: NULL context");
+    return GQ_EINVAL;
+  }
+  if (ctx->capturing) {
+    set_error("gq_capture_begin: already capturing");
+    return GQ_EINVAL;
+  }
+  if (ctx->stream == nullptr) {
+    set_error("gq_capture_begin: the legacy default stream cannot be captured; create the "
+              "context on a stream of its own");
+    return GQ_EINVAL;
+  }
+  GQ_HIP(hipSetDevice(ctx->device));
+  GQ_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;
+  return GQ_OK;
+}
+
+gq_status gq_capture_end(gq_ctx* ctx, gq_exec** out) {
+  if (!ctx || !out) {
+    set_error("gq_capture_end: NULL argument");
+    return GQ_EINVAL;
+  }
+  if (!ctx->capturing) {
+    set_error("gq_capture_end: not capturing");
+    return GQ_EINVAL;
+  }
+  ctx->capturing = false;
+  GQ_HIP(hipSetDevice(ctx->device));
+  hipGraph_t graph = nullptr;
+  GQ_HIP(hipStreamEndCapture(ctx->stream, &graph));
+  gq_exec* x = new (std::nothrow) gq_exec;
+  if (!x) {
+    (void)hipGraphDestroy(graph);
+    set_error("gq_capture_end: out of host memory");
+    return GQ_ENOMEM;
+  }
+  x->graph = graph;
+  x->device = ctx->device;
+  if (hipGraphInstantiate(&x->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    set_error("gq_capture_end: hipGraphInstantiate failed: %s",
+              hipGetErrorString(hipGetLastError()));
+    (void)hipGraphDestroy(graph);
+    delete x;
+    return GQ_EDEVICE;
+  }
+  *out = x;
+  return GQ_OK;
+}
+
+gq_status gq_exec_launch(gq_ctx* ctx, gq_exec* x) {
+  if (!ctx || !x) {
+    set_error("gq_exec_launch: NULL argument");
+    return GQ_EINVAL;
+  }
+  if (ctx->capturing) {
+    set_error("gq_exec_launch: not available while capturing");
+    return GQ_EINVAL;
+  }
+  GQ_HIP(hipSetDevice(ctx->device));
+  GQ_HIP(hipGraphLaunch(x->exec, ctx->stream));
+  return GQ_OK;
+}
+
+void gq_exec_destroy(gq_exec* x) {
+  if (!x) return;
+  if (x->exec) (void)hipGraphExecDestroy(x->exec);
+  if (x->graph) (void)hipGraphDestroy(x->graph);
+  delete x;
+}
+
 gq_status gq_ctx_set_profiling(gq_ctx* ctx, int32_t enable) {
   if (!ctx) {
     set_error("gq_ctx_set_profiling: NULL context");
@@ -495,6 +708,10 @@ gq_status gq_ctx_kernel_times(gq_ctx* ctx, const char** names, int64_t* launches
                               double* total_ms, int32_t cap, int32_t* count) {
   if (!ctx || !count || cap < 0) {
     set_error("gq_ctx_kernel_times: bad argument");
+    return GQ_EINVAL;
+  }
+  if (ctx->capturing) {
+    set_error("gq_ctx_kernel_times: not available while capturing");
     return GQ_EINVAL;
   }
   GQ_HIP(hipSetDevice(ctx->device));

@@ -268,6 +268,7 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   in.sum_n2 = g->off2[n_sub];
   in.sub_atoms_len = (int64_t)g->sub_atoms.size();
   build_dc_plan(g);
+  build_xy_tiles(g);
   return GQ_OK;
 }
 

@@ -23,6 +23,14 @@ constexpr int kRowChunk = 16;
 // Points per multisection pass of the chemical-potential search.
 constexpr int kMuPoints = 128;
 constexpr int kMuPasses = 9;
+// Size bins of the response's X kernel (upper bounds, orbitals).
+constexpr int kXyBins = 5;
+constexpr int kXyBinMax[kXyBins] = {128, 256, 384, 512, 1024};
+
+// Tile-list ranges [off[x], off[x+1]) served by the workgroups of XCD x.
+struct XcdSplit {
+  int32_t off[9];
+};
 
 void set_error(const char* fmt, ...);
 
@@ -52,6 +60,7 @@ struct gq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool profiling = false;
+  bool capturing = false;
   std::vector<gq_prof_rec> pending;
   std::vector<gq_prof_stat> stats;
 };
@@ -59,6 +68,7 @@ struct gq_ctx {
 // Device copy of the index maps of a graph.
 struct gq_graph_dev {
   int device = -1;
+  char* block = nullptr;           // device block of the maps when owned by the graph
   int32_t* sub_orb_ptr = nullptr;  // [n_sub+1]
   int32_t* sub_orbs = nullptr;     // [sum_n]
   int32_t* n_core = nullptr;       // [n_sub]
@@ -70,13 +80,12 @@ struct gq_graph_dev {
   int32_t* offcd = nullptr;        // [n_sub+1] offsets of c_i arrays
   int32_t* order = nullptr;        // subgraphs by decreasing n
   int32_t* rho_row_ptr = nullptr;  // [N+1]
-  int32_t* tiles = nullptr;        // [n_tiles*3] (subgraph, tile row, tile col), lower triangle
-  int32_t n_tiles = 0;
   int32_t* dc_leaves = nullptr;    // [n_leaves*3] (subgraph, lo, m)
   int32_t* dc_merges = nullptr;    // [n_merges*4] (subgraph, lo, m1, m2), deepest level first
   int32_t* dc_tiles = nullptr;     // [*3] (merge index within its level, tile row, tile col)
   int32_t n_leaves = 0;
   int32_t* bt_toff = nullptr;      // [n_sub] first compact-WY block of each subgraph
+  int32_t* xy_tiles[2] = {nullptr, nullptr};  // X tiles (subgraph, ti, tj): 64x64, 32x32
 };
 
 struct gq_graph {
@@ -93,18 +102,24 @@ struct gq_graph {
   std::vector<int32_t> dc_level_merge_off, dc_level_tile_off, dc_level_maxm;
   std::vector<int32_t> bt_toff;  // compact-WY block offsets (16 reflectors per block)
   int32_t bt_nblocks = 0;
+  // response X tiles per shape (0: 64x64, 1: 32x32), binned by size, XCD ranges
+  std::vector<int32_t> xy_tiles[2];
+  gq::XcdSplit xy_split[2][gq::kXyBins];
+  // launch variant per [precision][bin] (bit 0: 32x32 tiles, bit 1: persistent)
+  mutable int8_t xy_choice[2][gq::kXyBins];
   gq_graph_info info{};
   mutable gq_graph_dev dev;
 };
 
 struct gq_eigs {
+  char* block = nullptr;    // device block of every array below, when owned
   gq_ctx* ctx = nullptr;
   const gq_graph* g = nullptr;
   int32_t max_k = 0;
   double* A = nullptr;      // [sum n^2] gathered matrix / tridiagonal work, then dF
   double* Q = nullptr;      // [sum n^2] eigenvectors, column-major per subgraph
-  double* Y = nullptr;      // [sum n^2] response scratch (X o dF)
-  double* T = nullptr;      // [sum n][32] response scratch (Q_c Y), column by column
+  double* Y = nullptr;      // [max_k][sum n^2] response scratch (X o dF); eigensolver scratch
+  double* T = nullptr;      // [max_k][sum n][32] response scratch (Q_c Y), column by column
   double* eps = nullptr;    // [sum n]
   double* wts = nullptr;    // [sum n]
   double* dd = nullptr;     // [sum n] tridiagonal diagonal
@@ -124,7 +139,7 @@ struct gq_eigs {
   double *md_delta = nullptr, *md_tau = nullptr, *md_zhat = nullptr, *md_inv = nullptr;
   double* tfac = nullptr;  // [bt_nblocks][16*16] compact-WY T factors
   double* wsc = nullptr;   // [sum_n * 16] panel scratch of the tridiagonalisation
-  double* hloc = nullptr;  // [sum_n] perturbation gathered into subgraph order
+  double* hloc = nullptr;  // [max_k][sum_n] perturbations gathered into subgraph order
   float* Q32 = nullptr;    // [sum n^2] FP32 leading part of Q (split-FP32 congruences)
   bool q32_valid = false;  // Q32 matches the current Q
   bool have_density = false;
@@ -158,5 +173,8 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h
                      uint32_t precision, double* p_blocks);
 void launch_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks, int32_t K,
                      double* vals);
+void build_xy_tiles(gq_graph* g);
+gq_status autotune_xy(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, uint32_t precision,
+                      std::string* report);
 
 }  // namespace gq

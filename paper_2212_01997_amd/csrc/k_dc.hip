@@ -875,10 +875,10 @@ void dc_set_attributes() {
 void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   const gq_graph_dev& dv = g->dev;
   hipStream_t st = ctx->stream;
-  // Z lives in e->Y, the merge scratch in e->Q; eigenvalues in e->eps
+  // Z lives in e->Q, the merge scratch in e->Y; eigenvalues in e->eps
   prof_begin(ctx, "k_dc_leaves");
   hipLaunchKernelGGL(k_dc_leaves, dim3(dv.n_leaves), dim3(64), 0, st, dv.dc_leaves, dv.sub_orb_ptr,
-                     dv.off2, e->dd, e->ee, e->Y, e->eps, e->status);
+                     dv.off2, e->dd, e->ee, e->Q, e->eps, e->status);
   prof_end(ctx);
   for (int lv = 0; lv < (int)g->dc_level_merge_off.size() - 1; ++lv) {
     const int m0 = g->dc_level_merge_off[lv], m1 = g->dc_level_merge_off[lv + 1];
@@ -887,19 +887,19 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     const int maxm = g->dc_level_maxm[lv];
     prof_begin(ctx, "k_dc_prep");
     hipLaunchKernelGGL(k_dc_prep, dim3(m1 - m0), dim3(kThreads), dc_prep_lds(maxm), st,
-                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, e->Y, e->eps,
+                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, e->Q, e->eps,
                        e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
                        e->md_delta, e->md_tau, e->md_zhat, e->md_inv);
     prof_end(ctx);
     prof_begin(ctx, "k_dc_gemm");
     hipLaunchKernelGGL(k_dc_gemm, dim3(t1 - t0), dim3(kThreads), 0, st, dv.dc_tiles + 3 * t0,
-                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->Y, e->Q, e->md_k + m0,
+                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->Q, e->Y, e->md_k + m0,
                        e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos, e->md_delta,
                        e->md_tau, e->md_zhat, e->md_inv);
     prof_end(ctx);
     prof_begin(ctx, "k_dc_copy");
     hipLaunchKernelGGL(k_dc_copy, dim3(t1 - t0), dim3(kThreads), 0, st, dv.dc_tiles + 3 * t0,
-                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->Q, e->Y);
+                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->Y, e->Q);
     prof_end(ctx);
   }
   const int maxn = g->info.max_n;
@@ -913,13 +913,13 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   prof_begin(ctx, "k_backtransform");
   if (n_big > 0)
     hipLaunchKernelGGL(k_backtransform, dim3(n_big, (maxn + kCb - 1) / kCb), dim3(kThreads),
-                       (size_t)maxn * kCb * sizeof(double), st, e->A, e->tau, e->Y, dv.off2,
+                       (size_t)maxn * kCb * sizeof(double), st, e->A, e->tau, e->Q, dv.off2,
                        dv.sub_orb_ptr, dv.n_core, dv.order, e->wts);
   if (n_big < g->n_sub) {
     const int nsm = std::min(maxn, kBtSmall);
     hipLaunchKernelGGL(k_backtransform_lds, dim3(g->n_sub - n_big, (nsm + kCb - 1) / kCb),
                        dim3(kThreads), (size_t)nsm * (kCb + kNb) * sizeof(double), st, e->A,
-                       e->tfac, dv.bt_toff, e->Y, dv.off2, dv.sub_orb_ptr, dv.n_core,
+                       e->tfac, dv.bt_toff, e->Q, dv.off2, dv.sub_orb_ptr, dv.n_core,
                        dv.order + n_big, e->wts);
   }
   prof_end(ctx);

@@ -296,8 +296,6 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
                      dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
   prof_end(ctx);
   launch_dc(ctx, g, e);
-  // the eigenvectors were formed in e->Y; from here on they are e->Q
-  std::swap(e->Q, e->Y);
 }
 
 }  // namespace gq

@@ -6,18 +6,26 @@
 // the mu response is beta d0 (I - d0) (Eq. (dddmu)), and Eq. (dmu_1) fixes
 //   mu1 = -sum_i Tr_c d1lambda_i / sum_i Tr_c d1mu_i,
 // so that the collected rho1 = 2 (d1lambda + mu1 d1mu) core rows has zero trace
-// (Eq. (D1)).  Kernels per perturbation q:
-//   k_xy_mfma  lower-triangular 64x64 tiles of X = Q^T diag(h1) Q on FP64
-//              MFMA, times dF, into Y (each symmetric pair stored once)
-//   k_xy32_mfma, k_win_mfma  the split-FP32 variant of the same: X from the
-//              FP32 leading part of Q on FP32 MFMA (FP32 sums within 32-deep
-//              chunks, FP64 across them), then one FP64 correction of the
-//              thermal-window block, where dF amplifies rounding most
+// (Eq. (D1)).  Every kernel takes all K perturbations of a call in one launch
+// (grid dimension q):
+//   k_xy       lower-triangular tiles of X = Q^T diag(h1) Q, times dF, into Y
+//              (each symmetric pair stored once).  Subgraphs are binned by
+//              size; per bin the tile shape (64x64 or 32x32, four waves each)
+//              and the grid (one workgroup per tile or a persistent grid) are
+//              chosen by gq_autotune.  Tiles of one subgraph stay on
+//              one XCD, whose L2 then serves their shared columns of Q.
+//              FP64 MFMA, or in the split-FP32 variant the FP32 leading part
+//              of Q on FP32 MFMA (FP32 sums within 32-deep chunks, FP64
+//              across them) followed by
+//   k_win      one FP64 correction of the thermal-window block, where dF
+//              amplifies rounding most
 //   k_t_mfma   T = Q_c Y;  k_p_mfma  P = 2 T Q^T (c x n core rows) and diag(P)
 //   k_mu1      fixed-order traces -> mu1_q
 //   k_combine  P += mu1_q M
 // Eq. (sub_f) / (dCollect): k_assemble scatters block rows into CSR values.
 #include <algorithm>
+#include <atomic>
+#include <cstdio>
 
 #include "gq_internal.hpp"
 
@@ -26,7 +34,7 @@ namespace gq {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTile = 64;
+constexpr int kTile = 64;  // the storage rule of Y is defined on 64x64 tiles
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -43,27 +51,47 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// v_mfma_f32_16x16x4f32 on gfx950: same operand lanes; D(i, j) is returned in
+// lane j + 16*(i/4), register i%4.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 constexpr int kXK = 32;  // K chunk of the X tiles
 
-// Accumulates the 64x64 block X(k0.., l0..) = sum_m Q(m, k) h(m) Q(m, l) of one
-// subgraph on FP64 MFMA (columns k >= kend or l >= lend read as zero).  Waves
-// own 32x32 quarters; the K dimension is staged through LDS in chunks of kXK
-// rows, the next chunk prefetched into registers while the current one is used.
+// Four waves in a 2x2 arrangement; each wave owns a (TM/2)x(TM/2) quarter of
+// the tile, made of WB x WB 16x16 MFMA blocks.
+template <int TM>
+struct XyShape {
+  static constexpr int kNT = 256;
+  static constexpr int kWB = TM / 32;
+  static constexpr int kPer = kXK * TM / kNT;  // operand values per thread per chunk
+};
+
+// Accumulates the TMxTM block X(k0.., l0..) = sum_m Q(m, k) h(m) Q(m, l) of one
+// subgraph on FP64 MFMA (columns k >= kend or l >= lend read as zero).  The K
+// dimension is staged through LDS in chunks of kXK rows, the next chunk
+// prefetched into registers meanwhile.
+template <int TM>
 __device__ __forceinline__ void xy_block_f64(const double* __restrict__ Q,
                                              const double* __restrict__ hl, int n, int k0,
-                                             int l0, int kend, int lend, v4d (&acc)[2][2]) {
-  __shared__ double As[kXK][kTile + 1];
-  __shared__ double Bs[kXK][kTile + 1];
+                                             int l0, int kend, int lend,
+                                             v4d (&acc)[XyShape<TM>::kWB][XyShape<TM>::kWB]) {
+  using S = XyShape<TM>;
+  constexpr int WB = S::kWB;
+  __shared__ double As[kXK][TM + 1];
+  __shared__ double Bs[kXK][TM + 1];
   __shared__ double hs[kXK];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  constexpr int kPer = kXK * kTile / kThreads;  // values of As (and of Bs) per thread
-  double pa[kPer], pb[kPer], ph = 0.0;
+  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+  double pa[S::kPer], pb[S::kPer], ph = 0.0;
   auto fetch = [&](int m0) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int idx = tid + u * kThreads;
+    for (int u = 0; u < S::kPer; ++u) {
+      const int idx = tid + u * S::kNT;
       const int mm = idx % kXK, kk = idx / kXK;
       const int m = m0 + mm;
       const bool okm = m < n;
@@ -73,15 +101,15 @@ __device__ __forceinline__ void xy_block_f64(const double* __restrict__ Q,
     if (tid < kXK) ph = (m0 + tid < n) ? hl[m0 + tid] : 0.0;
   };
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < WB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < WB; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
   fetch(0);
   for (int m0 = 0; m0 < n; m0 += kXK) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int idx = tid + u * kThreads;
+    for (int u = 0; u < S::kPer; ++u) {
+      const int idx = tid + u * S::kNT;
       As[idx % kXK][idx / kXK] = pa[u];
       Bs[idx % kXK][idx / kXK] = pb[u];
     }
@@ -92,91 +120,40 @@ __device__ __forceinline__ void xy_block_f64(const double* __restrict__ Q,
     for (int ks = 0; ks < kXK / 4; ++ks) {
       const int row = 4 * ks + lk;
       const double hr = hs[row];
-      const double a0 = As[row][wr + li], a1 = As[row][wr + 16 + li];
-      const double b0 = hr * Bs[row][wc + li], b1 = hr * Bs[row][wc + 16 + li];
-      acc[0][0] = mfma16(a0, b0, acc[0][0]);
-      acc[0][1] = mfma16(a0, b1, acc[0][1]);
-      acc[1][0] = mfma16(a1, b0, acc[1][0]);
-      acc[1][1] = mfma16(a1, b1, acc[1][1]);
+      double a[WB], bb[WB];
+#pragma unroll
+      for (int x = 0; x < WB; ++x) {
+        a[x] = As[row][wr + 16 * x + li];
+        bb[x] = hr * Bs[row][wc + 16 * x + li];
+      }
+#pragma unroll
+      for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y) acc[x][y] = mfma16(a[x], bb[y], acc[x][y]);
     }
   }
 }
 
-// Y = (Q^T diag(h1) Q) o dF on the lower 64x64 tiles (ti >= tj).  A tile's
-// value y(k, l), k in tile ti, l in tile tj, is stored at Y[l + n k]
-// (row l, column k): every value of the symmetric Y sits at the position
-// whose row tile is not above its column tile, written coalesced.
-__global__ __launch_bounds__(kThreads) void k_xy_mfma(
-    const double* __restrict__ qbuf, const double* __restrict__ dfbuf, double* __restrict__ ybuf,
-    const double* __restrict__ hloc, const int32_t* __restrict__ tiles,
-    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr) {
-  const int s = tiles[3 * blockIdx.x], ti = tiles[3 * blockIdx.x + 1], tj = tiles[3 * blockIdx.x + 2];
-  const int b = sub_orb_ptr[s];
-  const int n = sub_orb_ptr[s + 1] - b;
-  const int k0 = ti * kTile, l0 = tj * kTile;
-  v4d acc[2][2];
-  xy_block_f64(qbuf + off2[s], hloc + b, n, k0, l0, n, n, acc);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  const double* dF = dfbuf + off2[s];
-  double* Y = ybuf + off2[s];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = k0 + wr + 16 * x + lk + 4 * r;
-        const int l = l0 + wc + 16 * y + li;
-        if (k < n && l < n) {
-          const size_t at = (size_t)l + (size_t)n * k;
-          Y[at] = acc[x][y][r] * dF[at];
-        }
-      }
-}
-
-// ------------------------------------------------- split-FP32 congruence
-// v_mfma_f32_16x16x4f32 on gfx950: lane l supplies A(l%16, l/16) and
-// B(l/16, l%16); D(i, j) is returned in lane j + 16*(i/4), register i%4.
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Leading FP32 part of every eigenvector matrix (once per eigenbasis).
-__global__ __launch_bounds__(kThreads) void k_split32(const double* __restrict__ q,
-                                                      float* __restrict__ q32, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * kThreads)
-    q32[i] = (float)q[i];
-}
-
-// As k_xy_mfma from the FP32 leading parts: each kXK-deep chunk of the sum is
-// accumulated by FP32 MFMA in FP32, and the chunk sums are added in FP64.
-__global__ __launch_bounds__(kThreads) void k_xy32_mfma(
-    const float* __restrict__ q32, const double* __restrict__ dfbuf, double* __restrict__ ybuf,
-    const double* __restrict__ hloc, const int32_t* __restrict__ tiles,
-    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr) {
-  __shared__ float As[kXK][kTile + 1];
-  __shared__ float Bs[kXK][kTile + 1];
+// The same block from the FP32 leading parts: each kXK-deep chunk is summed by
+// FP32 MFMA in FP32 and the chunk sums are added in FP64.  acc[x][y][r] holds
+// row 4*(lane/16) + r of the 16x16 block (x, y).
+template <int TM>
+__device__ __forceinline__ void xy_block_f32(
+    const float* __restrict__ Q, const double* __restrict__ hl, int n, int k0, int l0,
+    double (&acc)[XyShape<TM>::kWB][XyShape<TM>::kWB][4]) {
+  using S = XyShape<TM>;
+  constexpr int WB = S::kWB;
+  __shared__ float As[kXK][TM + 1];
+  __shared__ float Bs[kXK][TM + 1];
   __shared__ float hs[kXK];
-  const int s = tiles[3 * blockIdx.x], ti = tiles[3 * blockIdx.x + 1], tj = tiles[3 * blockIdx.x + 2];
-  const int b = sub_orb_ptr[s];
-  const int n = sub_orb_ptr[s + 1] - b;
-  const float* Q = q32 + off2[s];
-  const double* hl = hloc + b;
-  const int k0 = ti * kTile, l0 = tj * kTile;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  constexpr int kPer = kXK * kTile / kThreads;
-  float pa[kPer], pb[kPer], ph = 0.f;
+  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+  float pa[S::kPer], pb[S::kPer], ph = 0.f;
   auto fetch = [&](int m0) {
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int idx = tid + u * kThreads;
+    for (int u = 0; u < S::kPer; ++u) {
+      const int idx = tid + u * S::kNT;
       const int mm = idx % kXK, kk = idx / kXK;
       const int m = m0 + mm;
       const bool okm = m < n;
@@ -185,63 +162,121 @@ __global__ __launch_bounds__(kThreads) void k_xy32_mfma(
     }
     if (tid < kXK) ph = (m0 + tid < n) ? (float)hl[m0 + tid] : 0.f;
   };
-  double acc[2][2][4];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < WB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < WB; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[x][y][r] = 0.0;
   fetch(0);
   for (int m0 = 0; m0 < n; m0 += kXK) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int idx = tid + u * kThreads;
+    for (int u = 0; u < S::kPer; ++u) {
+      const int idx = tid + u * S::kNT;
       As[idx % kXK][idx / kXK] = pa[u];
       Bs[idx % kXK][idx / kXK] = pb[u];
     }
     if (tid < kXK) hs[tid] = ph;
     __syncthreads();
     if (m0 + kXK < n) fetch(m0 + kXK);
-    v4f c[2][2];
+    v4f c[WB][WB];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < WB; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) c[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int y = 0; y < WB; ++y) c[x][y] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < kXK / 4; ++ks) {
       const int row = 4 * ks + lk;
       const float hr = hs[row];
-      const float a0 = As[row][wr + li], a1 = As[row][wr + 16 + li];
-      const float b0 = hr * Bs[row][wc + li], b1 = hr * Bs[row][wc + 16 + li];
-      c[0][0] = mfma16f(a0, b0, c[0][0]);
-      c[0][1] = mfma16f(a0, b1, c[0][1]);
-      c[1][0] = mfma16f(a1, b0, c[1][0]);
-      c[1][1] = mfma16f(a1, b1, c[1][1]);
+      float a[WB], bb[WB];
+#pragma unroll
+      for (int x = 0; x < WB; ++x) {
+        a[x] = As[row][wr + 16 * x + li];
+        bb[x] = hr * Bs[row][wc + 16 * x + li];
+      }
+#pragma unroll
+      for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y) c[x][y] = mfma16f(a[x], bb[y], c[x][y]);
     }
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < WB; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < WB; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[x][y][r] += (double)c[x][y][r];
   }
-  const double* dF = dfbuf + off2[s];
-  double* Y = ybuf + off2[s];
+}
+
+// Y = X o dF on the tiles of one size bin.  A computed value y(k, l) is stored
+// at Y[l + n k] (row l, column k): the tile lists hold only tiles whose 64x64
+// parent is on or below the diagonal, so every value of the symmetric Y sits at
+// the position whose row tile is not above its column tile, written coalesced.
+// Workgroup b serves XCD b % 8 and walks that XCD's range of the list with
+// stride gridDim.x / 8 (one tile per workgroup, or persistent).
+template <int TM, bool SPLIT>
+__global__ __launch_bounds__(256, 3) void k_xy(
+    const double* __restrict__ qbuf, const float* __restrict__ q32,
+    const double* __restrict__ dfbuf, double* __restrict__ ybuf, const double* __restrict__ hloc,
+    const int32_t* __restrict__ tiles, XcdSplit split, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n) {
+  constexpr int WB = XyShape<TM>::kWB;
+  const int q = blockIdx.y;
+  const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+  for (int t = split.off[xcd] + (int)(blockIdx.x >> 3); t < split.off[xcd + 1]; t += stride) {
+    const int s = tiles[3 * t], ti = tiles[3 * t + 1], tj = tiles[3 * t + 2];
+    const int b = sub_orb_ptr[s];
+    const int n = sub_orb_ptr[s + 1] - b;
+    const int k0 = ti * TM, l0 = tj * TM;
+    const double* hl = hloc + (size_t)q * sum_n + b;
+    const double* dF = dfbuf + off2[s];
+    double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
+    if constexpr (SPLIT) {
+      double acc[WB][WB][4];
+      xy_block_f32<TM>(q32 + off2[s], hl, n, k0, l0, acc);
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < WB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < WB; ++y)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = k0 + wr + 16 * x + 4 * lk + r;
-        const int l = l0 + wc + 16 * y + li;
-        if (k < n && l < n) {
-          const size_t at = (size_t)l + (size_t)n * k;
-          Y[at] = acc[x][y][r] * dF[at];
-        }
-      }
+          for (int r = 0; r < 4; ++r) {
+            const int k = k0 + wr + 16 * x + 4 * lk + r;
+            const int l = l0 + wc + 16 * y + li;
+            if (k < n && l < n) {
+              const size_t at = (size_t)l + (size_t)n * k;
+              Y[at] = acc[x][y][r] * dF[at];
+            }
+          }
+    } else {
+      v4d acc[WB][WB];
+      xy_block_f64<TM>(qbuf + off2[s], hl, n, k0, l0, n, n, acc);
+#pragma unroll
+      for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = k0 + wr + 16 * x + lk + 4 * r;
+            const int l = l0 + wc + 16 * y + li;
+            if (k < n && l < n) {
+              const size_t at = (size_t)l + (size_t)n * k;
+              Y[at] = acc[x][y][r] * dF[at];
+            }
+          }
+    }
+  }
+}
+
+// Leading FP32 part of every eigenvector matrix (once per eigenbasis).
+__global__ __launch_bounds__(kThreads) void k_split32(const double* __restrict__ q,
+                                                      float* __restrict__ q32, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * kThreads)
+    q32[i] = (float)q[i];
 }
 
 // Window half-width, in units of kT, of the FP64 refinement.
@@ -260,15 +295,15 @@ __device__ __forceinline__ int lower_index(const double* v, int n, double x) {
 
 // FP64 refinement of the thermal window: the dF weights are largest, up to
 // beta/4, between states within a few kT of mu, and there the FP32 rounding of
-// X would be amplified most.  One workgroup per subgraph recomputes the block of
-// X over the states with |eps - mu| <= kWinKT kT (at most 64, the ones nearest
-// mu) on FP64 MFMA and overwrites those entries of Y.
-__global__ __launch_bounds__(kThreads) void k_win_mfma(
+// X would be amplified most.  One workgroup per (subgraph, perturbation)
+// recomputes the block of X over the states with |eps - mu| <= kWinKT kT (at
+// most 64, the ones nearest mu) on FP64 MFMA and overwrites those entries of Y.
+__global__ __launch_bounds__(kThreads) void k_win(
     const double* __restrict__ qbuf, const double* __restrict__ dfbuf, double* __restrict__ ybuf,
     const double* __restrict__ hloc, const double* __restrict__ eps,
     const double* __restrict__ mu_state, const int64_t* __restrict__ off2,
-    const int32_t* __restrict__ sub_orb_ptr) {
-  const int s = blockIdx.x;
+    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n) {
+  const int s = blockIdx.x, q = blockIdx.y;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const double mu = mu_state[2], half = kWinKT * mu_state[3];
@@ -283,12 +318,12 @@ __global__ __launch_bounds__(kThreads) void k_win_mfma(
   }
   if (hi <= lo) return;
   v4d acc[2][2];
-  xy_block_f64(qbuf + off2[s], hloc + b, n, lo, lo, hi, hi, acc);
+  xy_block_f64<kTile>(qbuf + off2[s], hloc + (size_t)q * sum_n + b, n, lo, lo, hi, hi, acc);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const double* dF = dfbuf + off2[s];
-  double* Y = ybuf + off2[s];
+  double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -305,16 +340,18 @@ __global__ __launch_bounds__(kThreads) void k_win_mfma(
       }
 }
 
-// h1 restricted to every subgraph, in subgraph order: hloc[b + m] = h1[orbs[b + m]]
-__global__ __launch_bounds__(kThreads) void k_h1_gather(const double* __restrict__ h1,
+// h1 restricted to every subgraph, in subgraph order, for K perturbations:
+// hloc[q][b + m] = h1[q][orbs[b + m]]
+__global__ __launch_bounds__(kThreads) void k_h1_gather(const double* __restrict__ h1, int N,
                                                         const int32_t* __restrict__ sub_orbs,
                                                         int64_t sum_n, double* __restrict__ hloc) {
+  const int q = blockIdx.y;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < sum_n;
        i += (int64_t)gridDim.x * kThreads)
-    hloc[i] = h1[sub_orbs[i]];
+    hloc[(size_t)q * sum_n + i] = h1[(size_t)q * N + sub_orbs[i]];
 }
 
-// Y(k, l) under the storage rule of k_xy_mfma
+// Y(k, l) under the storage rule of k_xy
 __device__ __forceinline__ size_t ypos(int k, int l, int n) {
   return (k / kTile >= l / kTile) ? (size_t)l + (size_t)n * k : (size_t)k + (size_t)n * l;
 }
@@ -323,17 +360,20 @@ __device__ __forceinline__ size_t ypos(int k, int l, int n) {
 __global__ __launch_bounds__(kThreads) void k_t_mfma(
     const double* __restrict__ qbuf, const double* __restrict__ ybuf, double* __restrict__ tbuf,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
-    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order) {
+    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order, int64_t sum_n2,
+    int64_t sum_n) {
   __shared__ double As[16][33];
   __shared__ double Bs[16][kTile + 1];
   const int s = order[blockIdx.x];
+  const int q = blockIdx.z;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
   const int L0 = blockIdx.y * kTile;
   if (L0 >= n) return;
   const double* Q = qbuf + off2[s];
-  const double* Y = ybuf + off2[s];
+  const double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
+  double* Tq = tbuf + (size_t)q * sum_n * 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
@@ -370,8 +410,8 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
   if (l < n) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      tbuf[(size_t)(b + l) * 32 + lk + 4 * r] = acc0[r];
-      tbuf[(size_t)(b + l) * 32 + 16 + lk + 4 * r] = acc1[r];
+      Tq[(size_t)(b + l) * 32 + lk + 4 * r] = acc0[r];
+      Tq[(size_t)(b + l) * 32 + 16 + lk + 4 * r] = acc1[r];
     }
   }
 }
@@ -381,24 +421,29 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
     const double* __restrict__ tbuf, const double* __restrict__ qbuf, double* __restrict__ out,
     double* __restrict__ pdiag, const int64_t* __restrict__ off2, const int64_t* __restrict__ offc,
     const int32_t* __restrict__ offcd, const int32_t* __restrict__ sub_orb_ptr,
-    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order) {
+    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order, int64_t sum_n,
+    int64_t nnz, int sum_c) {
   const int s = order[blockIdx.x];
+  const int q = blockIdx.z;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
   const int L0 = blockIdx.y * kTile;
   if (L0 >= n) return;
   const double* Q = qbuf + off2[s];
+  const double* Tq = tbuf + (size_t)q * sum_n * 32;
+  double* outq = out + (size_t)q * nnz;
+  double* pdq = pdiag + (size_t)q * sum_c;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int lcol = L0 + 16 * w + li;
   v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
   for (int q0 = 0; q0 < n; q0 += 4) {
-    const int q = q0 + lk;
-    const bool ok = q < n;
-    const double a0 = ok ? tbuf[(size_t)(b + q) * 32 + li] : 0.0;
-    const double a1 = ok ? tbuf[(size_t)(b + q) * 32 + 16 + li] : 0.0;
-    const double bv = (ok && lcol < n) ? Q[lcol + (size_t)n * q] : 0.0;
+    const int m = q0 + lk;
+    const bool ok = m < n;
+    const double a0 = ok ? Tq[(size_t)(b + m) * 32 + li] : 0.0;
+    const double a1 = ok ? Tq[(size_t)(b + m) * 32 + 16 + li] : 0.0;
+    const double bv = (ok && lcol < n) ? Q[lcol + (size_t)n * m] : 0.0;
     acc0 = mfma16(a0, bv, acc0);
     acc1 = mfma16(a1, bv, acc1);
   }
@@ -409,23 +454,24 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
       const int j0 = lk + 4 * r, j1 = 16 + lk + 4 * r;
       if (j0 < c) {
         const double v = 2.0 * acc0[r];
-        out[base + (size_t)j0 * n + lcol] = v;
-        if (lcol == j0) pdiag[offcd[s] + j0] = v;
+        outq[base + (size_t)j0 * n + lcol] = v;
+        if (lcol == j0) pdq[offcd[s] + j0] = v;
       }
       if (j1 < c) {
         const double v = 2.0 * acc1[r];
-        out[base + (size_t)j1 * n + lcol] = v;
-        if (lcol == j1) pdiag[offcd[s] + j1] = v;
+        outq[base + (size_t)j1 * n + lcol] = v;
+        if (lcol == j1) pdq[offcd[s] + j1] = v;
       }
     }
   }
 }
 
-// mu1_q = -sum_i sum_{j<c_i} P_i[j,j] / sum_i tmu_i, fixed order
+// mu1_q = -sum_i sum_{j<c_i} P_i[j,j] / sum_i tmu_i, fixed order; one block per q
 __global__ __launch_bounds__(kThreads) void k_mu1(const double* __restrict__ pdiag, int sum_c,
                                                   const double* __restrict__ tmu, int n_sub,
-                                                  double* __restrict__ mu1, int q) {
+                                                  double* __restrict__ mu1) {
   __shared__ double red[8];
+  const int q = blockIdx.x;
   double a = 0.0, t = 0.0;
   for (int i = threadIdx.x; i < sum_c; i += kThreads) a += pdiag[(size_t)q * sum_c + i];
   for (int i = threadIdx.x; i < n_sub; i += kThreads) t += tmu[i];
@@ -446,12 +492,14 @@ __global__ __launch_bounds__(kThreads) void k_mu1(const double* __restrict__ pdi
 
 __global__ __launch_bounds__(kThreads) void k_combine(double* __restrict__ p,
                                                       const double* __restrict__ m,
-                                                      const double* __restrict__ mu1, int q,
+                                                      const double* __restrict__ mu1,
                                                       int64_t nnz) {
+  const int q = blockIdx.y;
   const double f = mu1[q];
+  double* pq = p + (size_t)q * nnz;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nnz;
        i += (int64_t)gridDim.x * kThreads)
-    p[i] += f * m[i];
+    pq[i] += f * m[i];
 }
 
 __global__ __launch_bounds__(kThreads) void k_assemble(
@@ -475,58 +523,206 @@ __global__ __launch_bounds__(kThreads) void k_assemble(
   }
 }
 
+// ------------------------------------------------------------ xy launches
+using XyKernel = void (*)(const double*, const float*, const double*, double*, const double*,
+                          const int32_t*, XcdSplit, const int64_t*, const int32_t*, int64_t,
+                          int64_t);
+
+XyKernel xy_kernel(int shape, bool split) {
+  if (shape == 0) return split ? k_xy<64, true> : k_xy<64, false>;
+  return split ? k_xy<32, true> : k_xy<32, false>;
+}
+
+int xy_threads(int shape) { return shape == 0 ? XyShape<64>::kNT : XyShape<32>::kNT; }
+
+// Workgroups of one variant resident on one XCD (32 CUs) at a time.
+int xy_resident_per_xcd(int shape, bool split) {
+  static std::atomic<int> cache[2][2];
+  std::atomic<int>& c = cache[shape][split ? 1 : 0];
+  int v = c.load(std::memory_order_relaxed);
+  if (v == 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)xy_kernel(shape, split),
+                                                     xy_threads(shape), 0) != hipSuccess ||
+        per_cu < 1) {
+      (void)hipGetLastError();
+      per_cu = 1;
+    }
+    v = per_cu * 32;
+    c.store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
+// Launch of one bin with variant `choice` (bit 0: 32x32 tiles, bit 1: persistent).
+void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int bin, int choice, bool split,
+                   int K) {
+  const int shape = choice & 1;
+  const bool persistent = (choice & 2) != 0;
+  const XcdSplit& sp = g->xy_split[shape][bin];
+  int longest = 0;
+  for (int x = 0; x < 8; ++x) longest = std::max(longest, sp.off[x + 1] - sp.off[x]);
+  if (longest == 0) return;
+  int per_xcd = longest;
+  if (persistent) per_xcd = std::min(longest, xy_resident_per_xcd(shape, split));
+  const gq_graph_dev& dv = g->dev;
+  hipLaunchKernelGGL(xy_kernel(shape, split), dim3(8 * per_xcd, K), dim3(xy_threads(shape)), 0,
+                     ctx->stream, e->Q, e->Q32, e->A, e->Y, e->hloc, dv.xy_tiles[shape], sp,
+                     dv.off2, dv.sub_orb_ptr, g->info.sum_n2, g->info.sum_n);
+}
+
+void launch_split32(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
+  prof_begin(ctx, "k_split32");
+  const int64_t cnt = g->info.sum_n2;
+  hipLaunchKernelGGL(k_split32,
+                     dim3((unsigned)std::min<int64_t>(8192, (cnt + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, ctx->stream, e->Q, e->Q32, cnt);
+  prof_end(ctx);
+}
+
 }  // namespace
+
+void build_xy_tiles(gq_graph* g) {
+  // bins by subgraph size; tiles of a subgraph contiguous, subgraphs in the
+  // order of decreasing size; per bin and shape the list is cut into 8
+  // contiguous XCD ranges of about equal tile count at subgraph boundaries
+  for (int shape = 0; shape < 2; ++shape) {
+    const int tm = shape == 0 ? 64 : 32;
+    std::vector<int32_t>& tl = g->xy_tiles[shape];
+    tl.clear();
+    for (int bin = 0; bin < kXyBins; ++bin) {
+      const int lo = bin == 0 ? 0 : kXyBinMax[bin - 1];
+      const int hi = kXyBinMax[bin];
+      const int32_t start = (int32_t)(tl.size() / 3);
+      std::vector<int32_t> sub_start;  // first tile of each subgraph of the bin
+      for (int32_t s : g->order) {
+        const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
+        if (n <= lo || n > hi) continue;
+        sub_start.push_back((int32_t)(tl.size() / 3));
+        const int32_t nt = (n + tm - 1) / tm;
+        for (int32_t ti = 0; ti < nt; ++ti)
+          for (int32_t tj = 0; tj < nt; ++tj) {
+            // parent 64x64 tile on or below the diagonal
+            if ((ti * tm) / 64 < (tj * tm) / 64) continue;
+            if (tm == 64 && tj > ti) continue;
+            tl.push_back(s);
+            tl.push_back(ti);
+            tl.push_back(tj);
+          }
+      }
+      const int32_t end = (int32_t)(tl.size() / 3);
+      XcdSplit& sp = g->xy_split[shape][bin];
+      const int64_t total = end - start;
+      size_t next = 0;
+      sp.off[0] = start;
+      for (int x = 1; x < 8; ++x) {
+        const int64_t target = start + (total * x + 7) / 8;
+        while (next < sub_start.size() && sub_start[next] < target) ++next;
+        sp.off[x] = next < sub_start.size() ? sub_start[next] : end;
+        sp.off[x] = std::max(sp.off[x], sp.off[x - 1]);
+      }
+      sp.off[8] = end;
+    }
+  }
+  for (int p = 0; p < 2; ++p)
+    for (int bin = 0; bin < kXyBins; ++bin) g->xy_choice[p][bin] = 0;
+}
 
 void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h1, int32_t K,
                      uint32_t precision, double* p_blocks) {
   hipStream_t st = ctx->stream;
   const gq_graph_dev& dv = g->dev;
   const int64_t nnz = g->info.nnz;
+  const int64_t sum_n = g->info.sum_n, sum_n2 = g->info.sum_n2;
   const int sum_c = g->offcd[g->n_sub];
   const bool split = precision == GQ_PREC_SPLIT32;
-  dim3 grid_cols(g->n_sub, (g->info.max_n + kTile - 1) / kTile);
-  if (split && !e->q32_valid) {
-    prof_begin(ctx, "k_split32");
-    const int64_t cnt = g->info.sum_n2;
-    hipLaunchKernelGGL(k_split32, dim3((unsigned)std::min<int64_t>(8192, (cnt + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, st, e->Q, e->Q32, cnt);
-    prof_end(ctx);
+  // a captured sequence must not depend on the host-side validity flag
+  if (split && (!e->q32_valid || ctx->capturing)) {
+    launch_split32(ctx, g, e);
     e->q32_valid = true;
   }
-  for (int q = 0; q < K; ++q) {
-    prof_begin(ctx, split ? "k_xy32" : "k_xy");
-    const int64_t sum_n = g->info.sum_n;
-    hipLaunchKernelGGL(k_h1_gather, dim3((unsigned)std::min<int64_t>(1024, (sum_n + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, st, h1 + (size_t)q * g->N, dv.sub_orbs, sum_n, e->hloc);
-    if (split) {
-      hipLaunchKernelGGL(k_xy32_mfma, dim3(dv.n_tiles), dim3(kThreads), 0, st, e->Q32, e->A, e->Y,
-                         e->hloc, dv.tiles, dv.off2, dv.sub_orb_ptr);
-      prof_end(ctx);
-      prof_begin(ctx, "k_win");
-      hipLaunchKernelGGL(k_win_mfma, dim3(g->n_sub), dim3(kThreads), 0, st, e->Q, e->A, e->Y,
-                         e->hloc, e->eps, e->mu_state, dv.off2, dv.sub_orb_ptr);
-    } else {
-      hipLaunchKernelGGL(k_xy_mfma, dim3(dv.n_tiles), dim3(kThreads), 0, st, e->Q, e->A, e->Y,
-                         e->hloc, dv.tiles, dv.off2, dv.sub_orb_ptr);
-    }
-    prof_end(ctx);
-    prof_begin(ctx, "k_rows");
-    hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, e->Y, e->T, dv.off2,
-                       dv.sub_orb_ptr, dv.n_core, dv.order);
-    hipLaunchKernelGGL(k_p_mfma, grid_cols, dim3(kThreads), 0, st, e->T, e->Q,
-                       p_blocks + (size_t)q * nnz, e->pdiag + (size_t)q * sum_c, dv.off2, dv.offc,
-                       dv.offcd, dv.sub_orb_ptr, dv.n_core, dv.order);
-    prof_end(ctx);
-  }
-  prof_begin(ctx, "k_mu1_combine");
-  for (int q = 0; q < K; ++q) {
-    hipLaunchKernelGGL(k_mu1, dim3(1), dim3(kThreads), 0, st, e->pdiag, sum_c, e->tmu, g->n_sub,
-                       e->mu1, q);
-    const int blocks = (int)std::min<int64_t>(4096, (nnz + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_combine, dim3(blocks), dim3(kThreads), 0, st, p_blocks + (size_t)q * nnz,
-                       e->M, e->mu1, q, nnz);
-  }
+  prof_begin(ctx, split ? "k_xy32" : "k_xy");
+  hipLaunchKernelGGL(k_h1_gather,
+                     dim3((unsigned)std::min<int64_t>(1024, (sum_n + kThreads - 1) / kThreads), K),
+                     dim3(kThreads), 0, st, h1, g->N, dv.sub_orbs, sum_n, e->hloc);
+  for (int bin = 0; bin < kXyBins; ++bin)
+    launch_xy_bin(ctx, g, e, bin, g->xy_choice[split ? 1 : 0][bin], split, K);
   prof_end(ctx);
+  if (split) {
+    prof_begin(ctx, "k_win");
+    hipLaunchKernelGGL(k_win, dim3(g->n_sub, K), dim3(kThreads), 0, st, e->Q, e->A, e->Y, e->hloc,
+                       e->eps, e->mu_state, dv.off2, dv.sub_orb_ptr, sum_n2, sum_n);
+    prof_end(ctx);
+  }
+  prof_begin(ctx, "k_rows");
+  dim3 grid_cols(g->n_sub, (g->info.max_n + kTile - 1) / kTile, K);
+  hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, e->Y, e->T, dv.off2,
+                     dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
+  hipLaunchKernelGGL(k_p_mfma, grid_cols, dim3(kThreads), 0, st, e->T, e->Q, p_blocks, e->pdiag,
+                     dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core, dv.order, sum_n, nnz,
+                     sum_c);
+  prof_end(ctx);
+  prof_begin(ctx, "k_mu1_combine");
+  hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, e->pdiag, sum_c, e->tmu, g->n_sub,
+                     e->mu1);
+  const int blocks = (int)std::min<int64_t>(4096, (nnz + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_combine, dim3(blocks, K), dim3(kThreads), 0, st, p_blocks, e->M, e->mu1,
+                     nnz);
+  prof_end(ctx);
+}
+
+gq_status autotune_xy(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, uint32_t precision,
+                      std::string* report) {
+  const bool split = precision == GQ_PREC_SPLIT32;
+  if (split && !e->q32_valid) {
+    launch_split32(ctx, g, e);
+    e->q32_valid = true;
+  }
+  hipStream_t st = ctx->stream;
+  // the tuning launches read whatever h1 the workspace holds; only their time matters
+  GQ_HIP(hipMemsetAsync(e->hloc, 0, g->info.sum_n * sizeof(double), st));
+  hipEvent_t t0, t1;
+  GQ_HIP(hipEventCreate(&t0));
+  GQ_HIP(hipEventCreate(&t1));
+  char line[256];
+  static const char* names[4] = {"64x64 tiles, one workgroup per tile",
+                                 "32x32 tiles, one workgroup per tile",
+                                 "64x64 tiles, persistent", "32x32 tiles, persistent"};
+  gq_status rc = GQ_OK;
+  for (int bin = 0; bin < kXyBins && rc == GQ_OK; ++bin) {
+    const XcdSplit& sp = g->xy_split[0][bin];
+    if (sp.off[8] == sp.off[0]) continue;
+    float best = 1e30f;
+    int best_c = 0;
+    for (int choice = 0; choice < 4; ++choice) {
+      launch_xy_bin(ctx, g, e, bin, choice, split, 1);  // warm-up
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        if (hipEventRecord(t0, st) != hipSuccess) rc = GQ_EDEVICE;
+        launch_xy_bin(ctx, g, e, bin, choice, split, 1);
+        if (hipEventRecord(t1, st) != hipSuccess || hipEventSynchronize(t1) != hipSuccess)
+          rc = GQ_EDEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t0, t1) != hipSuccess) rc = GQ_EDEVICE;
+        ms_min = std::min(ms_min, ms);
+      }
+      if (rc != GQ_OK) break;
+      std::snprintf(line, sizeof line, "bin n<=%d (%d 64-tiles) %s: %.4f ms\n", kXyBinMax[bin],
+                    sp.off[8] - sp.off[0], names[choice], ms_min);
+      *report += line;
+      if (ms_min < best) {
+        best = ms_min;
+        best_c = choice;
+      }
+    }
+    g->xy_choice[split ? 1 : 0][bin] = (int8_t)best_c;
+    std::snprintf(line, sizeof line, "bin n<=%d -> %s\n", kXyBinMax[bin], names[best_c]);
+    *report += line;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc != GQ_OK) set_error("gq_autotune: timing failed: %s", hipGetErrorString(hipGetLastError()));
+  return rc;
 }
 
 void launch_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks, int32_t K,

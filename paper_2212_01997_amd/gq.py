@@ -42,6 +42,19 @@ class _Info(C.Structure):
                 ("sub_atoms_len", C.c_int64)]
 
 
+class _Request(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("atom_orb_ptr", C.c_void_p), ("H", C.POINTER(_Csr)),
+                ("rho_prev", C.POINTER(_Csr)), ("core_of_atom", C.c_void_p), ("tau", C.c_double),
+                ("flags", C.c_uint32), ("kT", C.c_double), ("n_elec", C.c_double),
+                ("K", C.c_int32), ("h1", C.c_void_p), ("precision", C.c_uint32)]
+
+
+class _ReqInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("mu", C.c_double), ("n_sub", C.c_int32), ("K", C.c_int32),
+                ("nnz", C.c_int64), ("footprint", C.c_int64), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
 # every symbol declared in include/gq.h, with its ctypes signature
 _VP = C.c_void_p
 _SIGS = {
@@ -56,6 +69,7 @@ _SIGS = {
     "gq_graph_block_offsets": ([_VP, _VP], C.c_int32),
     "gq_graph_destroy": ([_VP], None),
     "gq_eigs_create": ([_VP, _VP, C.c_int32, C.POINTER(_VP)], C.c_int32),
+    "gq_eigs_create_in": ([_VP, _VP, C.c_int32, _VP, C.c_int64, C.POINTER(_VP)], C.c_int32),
     "gq_eigs_footprint": ([_VP, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
     "gq_eigs_destroy": ([_VP], None),
     "gq_submatrix_solve": ([_VP, _VP, C.POINTER(_Csr), C.c_uint32, _VP], C.c_int32),
@@ -64,6 +78,20 @@ _SIGS = {
     "gq_assemble": ([_VP, _VP, _VP, C.c_int32, _VP], C.c_int32),
     "gq_eigs_export": ([_VP, _VP, _VP, _VP], C.c_int32),
     "gq_eigs_vectors": ([_VP, C.c_int32, C.POINTER(_VP), C.POINTER(C.c_int32)], C.c_int32),
+    "gq_autotune": ([_VP, _VP, C.c_uint32, C.c_char_p, C.c_size_t], C.c_int32),
+    "gq_graph_set_launch": ([_VP, C.c_uint32, C.c_int32, C.c_int32], C.c_int32),
+    "gq_capture_begin": ([_VP], C.c_int32),
+    "gq_capture_end": ([_VP, C.POINTER(_VP)], C.c_int32),
+    "gq_exec_launch": ([_VP, _VP], C.c_int32),
+    "gq_exec_destroy": ([_VP], None),
+    "gq_server_create": ([C.c_int32, C.c_int32, C.c_int64, C.POINTER(_VP)], C.c_int32),
+    "gq_server_submit": ([_VP, C.POINTER(_Request), C.POINTER(C.c_int64)], C.c_int32),
+    "gq_server_wait": ([_VP, C.c_int64, C.POINTER(_ReqInfo)], C.c_int32),
+    "gq_server_fetch": ([_VP, C.c_int64, _VP, _VP, _VP, _VP, _VP], C.c_int32),
+    "gq_server_release": ([_VP, C.c_int64], C.c_int32),
+    "gq_server_arena_used": ([_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int32),
+    "gq_server_clock": ([_VP], C.c_double),
+    "gq_server_destroy": ([_VP], None),
     "gq_ctx_set_profiling": ([_VP, C.c_int32], C.c_int32),
     "gq_ctx_kernel_times": ([_VP, _VP, _VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int32),
 }
@@ -75,6 +103,9 @@ def lib():
     """Load libgq.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes libgq bind to that one, so both share one runtime
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise GQError(-4, f"{LIB_PATH} is missing: run `python -m paper_2212_01997_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -108,6 +139,17 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _release(obj, fn):
+    """Destroy obj.h with libgq's `fn` (skipped once the interpreter is exiting)."""
+    h = getattr(obj, "h", None)
+    obj.h = None
+    if h and _lib is not None:
+        try:
+            getattr(_lib, fn)(h)
+        except Exception:  # interpreter shutdown
+            pass
+
+
 class Context:
     def __init__(self, device=0, stream=None):
         import torch
@@ -133,10 +175,31 @@ class Context:
                                          C.byref(cnt)))
         return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(cnt.value)}
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            lib().gq_ctx_destroy(self.h)
-            self.h = None
+    def capture_begin(self):
+        """Start recording library calls on this context into a HIP graph."""
+        _check(lib().gq_capture_begin(self.h))
+
+    def capture_end(self):
+        """Stop recording; returns an Exec that replays the recorded work."""
+        x = _VP()
+        _check(lib().gq_capture_end(self.h, C.byref(x)))
+        return Exec(self, x)
+
+    def __del__(self, _rel=_release):
+        _rel(self, "gq_ctx_destroy")
+
+
+class Exec:
+    """Recorded sequence of library calls (gq_capture_end)."""
+
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def launch(self):
+        _check(lib().gq_exec_launch(self.ctx.h, self.h))
+
+    def __del__(self, _rel=_release):
+        _rel(self, "gq_exec_destroy")
 
 
 @dataclass
@@ -197,15 +260,17 @@ class Graph:
         _check(lib().gq_graph_block_offsets(self.h, off.ctypes.data))
         return off
 
+    def set_launch(self, precision, bin_index, variant):
+        """Force the X-kernel launch variant of one size bin (gq_graph_set_launch)."""
+        _check(lib().gq_graph_set_launch(self.h, int(precision), int(bin_index), int(variant)))
+
     def footprint(self, max_k):
         b = C.c_int64()
         _check(lib().gq_eigs_footprint(self.h, int(max_k), C.byref(b)))
         return b.value
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            lib().gq_graph_destroy(self.h)
-            self.h = None
+    def __del__(self, _rel=_release):
+        _rel(self, "gq_graph_destroy")
 
 
 class DeviceCsr:
@@ -262,11 +327,75 @@ class Eigs:
         _check(lib().gq_eigs_vectors(self.h, int(i), C.byref(p), C.byref(n)))
         return p.value, n.value
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            lib().gq_eigs_destroy(self.h)
-            self.h = None
+    def autotune(self, precision=PREC_FP64):
+        """Choose the X-kernel launch variant per size bin (gq_autotune); returns the report."""
+        buf = C.create_string_buffer(8192)
+        _check(lib().gq_autotune(self.ctx.h, self.h, int(precision), buf, len(buf)))
+        return buf.value.decode()
+
+    def __del__(self, _rel=_release):
+        _rel(self, "gq_eigs_destroy")
 
 
 def assemble(ctx: Context, graph: Graph, blocks, vals, K=1):
     _check(lib().gq_assemble(ctx.h, graph.h, _ptr(blocks), int(K), _ptr(vals)))
+
+
+class Server:
+    """Serving runtime (gq_server_*): continuous admission of whole-path
+    requests into one device arena, n_slots requests in flight at a time."""
+
+    def __init__(self, device=0, n_slots=4, arena_bytes=64 << 30):
+        h = _VP()
+        _check(lib().gq_server_create(int(device), int(n_slots), int(arena_bytes), C.byref(h)))
+        self.h = h
+
+    def submit(self, system, core_of_atom, tau, rho_prev=None, flags=0, kT=0.01, h1=None,
+               precision=PREC_FP64, n_elec=None):
+        keep = []
+        H = _host_csr(system.h_row_ptr, system.h_col, system.h_val, keep)
+        P = _host_csr(*rho_prev, keep) if rho_prev is not None else None
+        aop = np.ascontiguousarray(system.atom_orb_ptr, np.int32)
+        core = np.ascontiguousarray(core_of_atom, np.int32)
+        h1 = np.ascontiguousarray(np.atleast_2d(h1), np.float64)
+        req = _Request(system.n_atoms, aop.ctypes.data, C.pointer(H),
+                       C.pointer(P) if P is not None else None, core.ctypes.data, float(tau),
+                       int(flags), float(kT), float(system.n_elec if n_elec is None else n_elec),
+                       h1.shape[0], h1.ctypes.data, int(precision))
+        rid = C.c_int64()
+        _check(lib().gq_server_submit(self.h, C.byref(req), C.byref(rid)))
+        return rid.value
+
+    def wait(self, rid):
+        """Blocks until request rid has finished; returns its info as a dict."""
+        info = _ReqInfo()
+        _check(lib().gq_server_wait(self.h, int(rid), C.byref(info)))
+        return {name: getattr(info, name) for name, _ in _ReqInfo._fields_}
+
+    def fetch(self, rid, info, n_orb):
+        K, nnz = info["K"], info["nnz"]
+        mu1 = np.zeros(K)
+        rho = np.zeros(nnz)
+        rho1 = np.zeros((K, nnz))
+        rp = np.zeros(n_orb + 1, np.int32)
+        col = np.zeros(nnz, np.int32)
+        _check(lib().gq_server_fetch(self.h, int(rid), mu1.ctypes.data, rho.ctypes.data,
+                                     rho1.ctypes.data, rp.ctypes.data, col.ctypes.data))
+        return {"mu1": mu1, "rho": rho, "rho1": rho1, "rho_row_ptr": rp, "rho_col": col}
+
+    def release(self, rid):
+        _check(lib().gq_server_release(self.h, int(rid)))
+
+    def clock(self):
+        return lib().gq_server_clock(self.h)
+
+    def arena_used(self):
+        used, size = C.c_int64(), C.c_int64()
+        _check(lib().gq_server_arena_used(self.h, C.byref(used), C.byref(size)))
+        return used.value, size.value
+
+    def close(self, _rel=_release):
+        _rel(self, "gq_server_destroy")
+
+    def __del__(self):
+        self.close()

@@ -437,6 +437,48 @@ def config_system(k, seed=None):
     raise ValueError(f"unknown config {k}")
 
 
+@dataclass
+class ServingTrace:
+    """Arrival-ordered requests: request j asks for system `system[j]` of the
+    pool with `K[j]` perturbations drawn from seed `h1_seed[j]`."""
+    arrival: np.ndarray        # [n] seconds
+    system: np.ndarray         # [n] index into `pool`
+    K: np.ndarray              # [n]
+    h1_seed: np.ndarray        # [n]
+    pool: list                 # [(kind, n_atoms, seed)]
+
+
+def serving_trace(n_requests=200, rate=20.0, n_systems=24, lo=500, hi=20000, seed=5001):
+    """Poisson arrivals at `rate` per second; system sizes log-uniform over
+    [lo, hi] atoms, water or chain-in-water with probability 1/2 (chain = 20%
+    of the atoms); K uniform over 1..8.  The requests draw their systems from
+    a pool of `n_systems` seeded systems (each request its own perturbations)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), n_systems))
+    kinds = rng.random(n_systems) < 0.5
+    pool = []
+    for i in range(n_systems):
+        n = int(round(sizes[i] / 3.0)) * 3
+        pool.append(("chain" if kinds[i] else "water", n, seed * 100 + i))
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    return ServingTrace(arrival=np.cumsum(gaps) - gaps[0],
+                        system=rng.integers(0, n_systems, n_requests),
+                        K=rng.integers(1, 9, n_requests),
+                        h1_seed=seed * 1000 + np.arange(n_requests), pool=pool)
+
+
+WATER_DENSITY = 1000 / 31.0 ** 3  # molecules per cubic angstrom of the 1,000-water box
+
+
+def pool_system(kind, n_atoms, seed):
+    """A serving-pool system: n_atoms/3 waters at the 1,000-water box density,
+    or a chain of 20% of the atoms in water at 0.1 atoms per cubic angstrom."""
+    if kind == "water":
+        n_mol = n_atoms // 3
+        return water_system(n_mol, (n_mol / WATER_DENSITY) ** (1.0 / 3.0), seed)
+    return chain_water_system(n_atoms, max(2, int(round(0.2 * n_atoms))), seed)
+
+
 def csr_to_dense(row_ptr, col, val, n):
     out = np.zeros((n, n))
     rows = np.repeat(np.arange(n), np.diff(row_ptr))

@@ -31,6 +31,9 @@ class GraphPath:
         self.p_blocks = torch.empty(max_k * nnz, dtype=torch.float64, device=dev)
         self.rho1 = torch.empty(max_k * nnz, dtype=torch.float64, device=dev)
         self.mu1_dev = torch.empty(max_k, dtype=torch.float64, device=dev)
+        # the context may run on a stream of its own: inputs and buffers made on
+        # torch's stream are complete before the library's first call
+        torch.cuda.synchronize(dev)
 
     @property
     def nnz(self):
@@ -52,6 +55,10 @@ class GraphPath:
         gq.assemble(self.ctx, self.graph, self.p_blocks[:K * self.nnz], self.rho1[:K * self.nnz], K)
         return mu1
 
+    def sync(self):
+        """Wait for the work enqueued on the context's stream."""
+        self.ctx.stream.synchronize()
+
     def rho1_view(self, K):
         return self.rho1[:K * self.nnz].view(K, self.nnz)
 
@@ -61,6 +68,7 @@ def bootstrap_prev(ctx, system, core_of_atom, kT):
     the graph of every nonzero of H.  Returns the host CSR triple."""
     p = GraphPath(ctx, system, core_of_atom, 0.0)
     p.ground_state(kT, want_mu=False)
+    p.sync()
     ex = p.graph.export()
     vals = p.rho.cpu().numpy()
     return ex["rho_row_ptr"], ex["rho_col"], vals
