@@ -243,17 +243,15 @@ def form_served(ctx, side, n_slots=4):
     atoms, K = 1..8) served by the runtime, against the same trace run one
     request after another on the plain path (FIFO, same arrival times)."""
     import threading
-    from concurrent.futures import ProcessPoolExecutor
-    import multiprocessing as mp
     import numpy as np
     import torch
     from paper_2212_01997_amd import gq, inputs as I
     from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
     tr = I.serving_trace()
-    log(f"config 5: generating {len(tr.pool)} pool systems")
-    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1),
-                             mp_context=mp.get_context("spawn")) as ex:
-        systems = list(ex.map(_pool_system, tr.pool))
+    systems = []
+    for k, spec in enumerate(tr.pool):
+        systems.append(I.pool_system(*spec))
+        log(f"config 5: pool system {k + 1}/{len(tr.pool)}: {spec[0]}, {systems[-1].n_atoms} atoms")
     cores = [I.spatial_cores(s, 8) for s in systems]
     prevs = [bootstrap_prev(ctx, s, c, KT) for s, c in zip(systems, cores)]
     h1s = [I.h1_diagonal(systems[i], int(k), seed=int(sd))
@@ -277,6 +275,8 @@ def form_served(ctx, side, n_slots=4):
         del rho1
         lat_seq[j] = time.perf_counter() - t0 - tr.arrival[j]
         del p
+        if (j + 1) % 50 == 0:
+            log(f"config 5: sequential {j + 1}/{n}")
     span_seq = time.perf_counter() - t0
     torch.cuda.empty_cache()
     # served
@@ -296,7 +296,9 @@ def form_served(ctx, side, n_slots=4):
     th = threading.Thread(target=feeder)
     th.start()
     th.join()
+    log("config 5: all requests submitted")
     infos = [srv.wait(rid) for rid in ids]
+    log("config 5: all requests served")
     lat_srv = np.array([inf["t_done"] - (start + tr.arrival[j]) for j, inf in enumerate(infos)])
     span_srv = max(inf["t_done"] for inf in infos) - start
     srv.close()
@@ -310,10 +312,6 @@ def form_served(ctx, side, n_slots=4):
                                  "p99_ms": float(np.percentile(lat_seq, 99) * 1e3),
                                  "solves_per_s": solves / span_seq, "makespan_s": span_seq}}
 
-
-def _pool_system(spec):
-    from paper_2212_01997_amd import inputs as I
-    return I.pool_system(*spec)
 
 
 def main():

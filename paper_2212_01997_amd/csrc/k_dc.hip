@@ -15,9 +15,10 @@
 //   k_dc_gemm   tiles of Z_new[:, pos] = Z[:, cols] U with U_ij = zh_i n_j /
 //               (d_i - lambda_j) formed on the fly, plus the deflated columns;
 //   k_dc_copy   the merged block back into place.
-// k_backtransform applies H_0 ... H_{n-3} to the eigenvectors of T in blocks
-// of 16 reflectors (compact WY, I - V T V^T) on 16-column panels held in LDS,
-// and forms the core weights of each eigenvector.
+// k_bt_mfma applies H_0 ... H_{n-3} to the eigenvectors of T in blocks of 16
+// reflectors (compact WY, I - V T V^T; T factors from k_bt_tfactors) on
+// 16-column panels held in registers, both products on FP64 MFMA, and forms
+// the core weights of each eigenvector.
 #include <algorithm>
 #include <cfloat>
 
@@ -31,7 +32,6 @@ constexpr int kThreads = 256;
 constexpr int kTile = 64;
 constexpr int kKc = 16;
 constexpr int kNb = 16;   // reflectors per compact-WY block
-constexpr int kCb = 16;   // eigenvector columns per back-transform workgroup
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -595,125 +595,6 @@ __global__ __launch_bounds__(kThreads) void k_dc_copy(
   }
 }
 
-// ------------------------------------------------------ back-transformation
-// Q = H_0 H_1 ... H_{n-3} Z for a panel of kCb eigenvector columns held in LDS.
-// Reflector k: H_k = I - tau_k v v^T, v = 1 at row k+1, A[k+2.., k] below.
-__global__ __launch_bounds__(kThreads) void k_backtransform(
-    const double* __restrict__ abuf, const double* __restrict__ TAU, double* __restrict__ zbuf,
-    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
-    const int32_t* __restrict__ n_core, const int32_t* __restrict__ order,
-    double* __restrict__ wts) {
-  extern __shared__ double zc[];  // [n][kCb]
-  __shared__ double part[kThreads / 64][2 * kNb][kCb + 1];
-  __shared__ double G[kNb][kNb + 1], Wm[kNb][kCb + 1], Tm[kNb][kNb + 1], W2[kNb][kCb + 1];
-  const int s = order[blockIdx.x];
-  const int b = sub_orb_ptr[s];
-  const int n = sub_orb_ptr[s + 1] - b;
-  const int c0 = blockIdx.y * kCb;
-  if (c0 >= n) return;
-  const int ncol = min(kCb, n - c0);
-  const double* A = abuf + off2[s];
-  double* Z = zbuf + off2[s];
-  const int tid = threadIdx.x;
-  const int cl = tid % kCb, rg = tid / kCb;  // column, row group (16 groups)
-  for (int idx = tid; idx < n * kCb; idx += kThreads) {
-    const int r = idx % n, c = idx / n;
-    zc[r * kCb + c] = c < ncol ? Z[r + (size_t)n * (c0 + c)] : 0.0;
-  }
-  __syncthreads();
-  const int nref = n - 2;  // reflectors 0 .. n-3
-  for (int kb = ((nref - 1) / kNb) * kNb; nref > 0 && kb >= 0; kb -= kNb) {
-    const int nb = min(kNb, nref - kb);
-    // V(r, q) for reflector kb+q: 0 above row kb+q+1, 1 there, A below
-    auto V = [&](int r, int q) -> double {
-      const int top = kb + q + 1;
-      if (q >= nb || r < top) return 0.0;
-      if (r == top) return 1.0;
-      return A[r + (size_t)n * (kb + q)];
-    };
-    double g[kNb], w[kNb];
-#pragma unroll
-    for (int q = 0; q < kNb; ++q) g[q] = w[q] = 0.0;
-    for (int r = kb + 1 + rg; r < n; r += 16) {
-      const double vc = V(r, cl);
-      const double zr = zc[r * kCb + cl];
-#pragma unroll
-      for (int q = 0; q < kNb; ++q) {
-        const double vq = V(r, q);
-        g[q] += vq * vc;
-        w[q] += vq * zr;
-      }
-    }
-    // the four row groups of a wave meet by shuffles, the waves in LDS
-    const int wv = tid >> 6, lane = tid & 63;
-#pragma unroll
-    for (int q = 0; q < kNb; ++q) {
-      g[q] += __shfl_xor(g[q], 16, 64);
-      g[q] += __shfl_xor(g[q], 32, 64);
-      w[q] += __shfl_xor(w[q], 16, 64);
-      w[q] += __shfl_xor(w[q], 32, 64);
-    }
-    if (lane < kCb) {
-#pragma unroll
-      for (int q = 0; q < kNb; ++q) {
-        part[wv][q][cl] = g[q];
-        part[wv][kNb + q][cl] = w[q];
-      }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < 2 * kNb * kCb; idx += kThreads) {
-      const int q = idx / kCb, c = idx % kCb;
-      double t = 0.0;
-      for (int r = 0; r < kThreads / 64; ++r) t += part[r][q][c];
-      if (q < kNb) G[q][c] = t;  // V^T V (column c of the Gram matrix)
-      else Wm[q - kNb][c] = t;   // V^T Zc
-    }
-    __syncthreads();
-    // T upper triangular: T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-    if (tid == 0) {
-      for (int i = 0; i < kNb; ++i)
-        for (int j = 0; j < kNb; ++j) Tm[i][j] = 0.0;
-      for (int i = 0; i < nb; ++i) {
-        const double ti = TAU[b + kb + i];
-        for (int r = 0; r < i; ++r) {
-          double acc = 0.0;
-          for (int q = r; q < i; ++q) acc += Tm[r][q] * G[q][i];
-          Tm[r][i] = -ti * acc;
-        }
-        Tm[i][i] = ti;
-      }
-    }
-    __syncthreads();
-    // W2 = T W
-    for (int idx = tid; idx < kNb * kCb; idx += kThreads) {
-      const int q = idx / kCb, c = idx % kCb;
-      double acc = 0.0;
-      for (int p = q; p < kNb; ++p) acc += Tm[q][p] * Wm[p][c];
-      W2[q][c] = acc;
-    }
-    __syncthreads();
-    // Zc -= V W2
-    for (int r = kb + 1 + rg; r < n; r += 16) {
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < kNb; ++q) acc += V(r, q) * W2[q][cl];
-      zc[r * kCb + cl] -= acc;
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < n * kCb; idx += kThreads) {
-    const int r = idx % n, c = idx / n;
-    if (c < ncol) Z[r + (size_t)n * (c0 + c)] = zc[r * kCb + c];
-  }
-  // core weights of the finished columns
-  if (tid < ncol) {
-    const int c = n_core[s];
-    double acc = 0.0;
-    for (int r = 0; r < c; ++r) acc += zc[r * kCb + tid] * zc[r * kCb + tid];
-    wts[b + c0 + tid] = acc;
-  }
-}
-
 // T factors of the compact-WY blocks: H_kb ... H_{kb+nb-1} = I - V T V^T with
 // T upper triangular (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V^T v_i).
 // One workgroup per (subgraph, block); T stored as kNb x kNb row-major.
@@ -724,11 +605,20 @@ __device__ __forceinline__ double refl(const double* A, int n, int kb, int nb, i
   return A[r + (size_t)n * (kb + q)];
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One workgroup per (subgraph, block): the Gram matrix G = V^T V on FP64 MFMA
+// (the four waves take interleaved 4-row chunks; V^T as the A operand and V as
+// the B operand are the same lane values), then the triangular recurrence.
 __global__ __launch_bounds__(kThreads) void k_bt_tfactors(
     const double* __restrict__ abuf, const double* __restrict__ TAU, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ toff,
     double* __restrict__ tfac) {
-  __shared__ double G[kNb][kNb + 1];
+  __shared__ double Gp[4][kNb][kNb + 1];
   __shared__ double T[kNb][kNb + 1];
   const int s = blockIdx.x;
   const int b = sub_orb_ptr[s];
@@ -738,123 +628,157 @@ __global__ __launch_bounds__(kThreads) void k_bt_tfactors(
   if (kb >= n - 2) return;
   const int nb = min(kNb, n - 2 - kb);
   const double* A = abuf + off2[s];
-  const int q = threadIdx.x % kNb, p = threadIdx.x / kNb;  // G[p][q]
-  double acc = 0.0;
-  for (int r = kb + 1; r < n; ++r) acc += refl(A, n, kb, nb, r, p) * refl(A, n, kb, nb, r, q);
-  G[p][q] = acc;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d G = {0.0, 0.0, 0.0, 0.0};
+  for (int row0 = kb + 1 + 4 * w; row0 < n; row0 += 16) {
+    const int r = row0 + lk;
+    const double a = r < n ? refl(A, n, kb, nb, r, li) : 0.0;
+    G = mfma16(a, a, G);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Gp[w][4 * r + lk][li] = G[r];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid < kNb * kNb) {
+    const int p = tid / kNb, q = tid % kNb;
+    Gp[0][p][q] = Gp[0][p][q] + Gp[1][p][q] + Gp[2][p][q] + Gp[3][p][q];
+  }
+  __syncthreads();
+  if (tid == 0) {
     for (int i = 0; i < kNb; ++i)
       for (int j = 0; j < kNb; ++j) T[i][j] = 0.0;
     for (int i = 0; i < nb; ++i) {
       const double ti = TAU[b + kb + i];
       for (int rr = 0; rr < i; ++rr) {
-        double a = 0.0;
-        for (int qq = rr; qq < i; ++qq) a += T[rr][qq] * G[qq][i];
-        T[rr][i] = -ti * a;
+        double acc = 0.0;
+        for (int qq = rr; qq < i; ++qq) acc += T[rr][qq] * Gp[0][qq][i];
+        T[rr][i] = -ti * acc;
       }
       T[i][i] = ti;
     }
-    double* out = tfac + (size_t)(toff[s] + kbi) * kNb * kNb;
-    for (int i = 0; i < kNb; ++i)
-      for (int j = 0; j < kNb; ++j) out[i * kNb + j] = T[i][j];
   }
+  __syncthreads();
+  if (tid < kNb * kNb)
+    tfac[(size_t)(toff[s] + kbi) * kNb * kNb + tid] = T[tid / kNb][tid % kNb];
 }
 
-// Back-transformation of a 16-column panel with the reflector block staged in
-// LDS (subgraphs of at most kBtSmall orbitals).
-constexpr int kBtSmall = 512;
+// ----------------------------------------- back-transformation on FP64 MFMA
+// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A(l%16, l/16) and
+// B(l/16, l%16); D(i, j) is returned in lane j + 16*(i%4), register i/4.  A
+// 16x16 tile held in that D layout is, register by register, the B operand of
+// four consecutive K steps (register r: rows 4r..4r+3).
 
-__global__ __launch_bounds__(kThreads) void k_backtransform_lds(
+// Q = H_0 ... H_{n-3} Z for a panel of 16 eigenvector columns, one compact-WY
+// block of 16 reflectors at a time from the last: Z <- Z - V (T (V^T Z)).  The
+// panel lives in registers as 16x16 tiles (wave w holds row blocks w, w+4,
+// ...; at most MRB each), the reflector block is staged in LDS, and both
+// products run on MFMA: W = V^T Z (partial per wave, summed in LDS), W2 = T W,
+// Z -= V W2.  Also forms the core weights of the panel's columns.
+template <int MRB>
+__global__ __launch_bounds__(kThreads) void k_bt_mfma(
     const double* __restrict__ abuf, const double* __restrict__ tfac,
     const int32_t* __restrict__ toff, double* __restrict__ zbuf, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core,
-    const int32_t* __restrict__ order, double* __restrict__ wts) {
-  extern __shared__ double sm[];
-  __shared__ double part[kThreads / 64][kNb][kCb + 1];
-  __shared__ double Wm[kNb][kCb + 1], Tm[kNb][kNb + 1], W2[kNb][kCb + 1];
-  const int s = order[blockIdx.x];
+    const int32_t* __restrict__ list, double* __restrict__ wts) {
+  extern __shared__ double vb[];  // [16 * nrb][16]: reflector block, row-major
+  __shared__ double Wp[4][16][17];
+  __shared__ double Ts[16][17];
+  __shared__ double csum[4][16];
+  const int s = list[blockIdx.y];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
-  const int c0 = blockIdx.y * kCb;
+  const int c0 = blockIdx.x * 16;
   if (c0 >= n) return;
-  const int ncol = min(kCb, n - c0);
-  double* zc = sm;                       // [n][kCb]
-  double* vb = sm + (size_t)n * kCb;     // [n][kNb] (rows kb+1.. used)
+  const int nrb = (n + 15) / 16;
   const double* A = abuf + off2[s];
   double* Z = zbuf + off2[s];
-  const int tid = threadIdx.x;
-  const int cl = tid % kCb, rg = tid / kCb;
-  const int wv = tid >> 6, lane = tid & 63;
-  for (int idx = tid; idx < n * kCb; idx += kThreads) {
-    const int r = idx % n, c = idx / n;
-    zc[r * kCb + c] = c < ncol ? Z[r + (size_t)n * (c0 + c)] : 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int col = c0 + li;
+  v4d zt[MRB];
+#pragma unroll
+  for (int i = 0; i < MRB; ++i) {
+    const int rb = w + 4 * i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + 4 * r + lk;
+      zt[i][r] = (rb < nrb && row < n && col < n) ? Z[row + (size_t)n * col] : 0.0;
+    }
   }
   const int nref = n - 2;
   for (int kbi = (nref - 1) / kNb; nref > 0 && kbi >= 0; --kbi) {
     const int kb = kbi * kNb;
     const int nb = min(kNb, nref - kb);
-    const int nr = n - (kb + 1);
+    const int rb0 = (kb + 1) / 16;  // first row block with a nonzero reflector row
+    const int r0 = 16 * rb0;
+    const int nrows = 16 * nrb - r0;
     __syncthreads();
-    for (int idx = tid; idx < nr * kNb; idx += kThreads) {
-      const int rr = idx % nr, q = idx / nr;
-      vb[(kb + 1 + rr) * kNb + q] = refl(A, n, kb, nb, kb + 1 + rr, q);
+    for (int idx = tid; idx < nrows * kNb; idx += kThreads) {
+      const int rr = idx % nrows, q = idx / nrows;
+      const int r = r0 + rr;
+      const int top = kb + q + 1;
+      double v = 0.0;
+      if (q < nb && r < n && r >= top) v = (r == top) ? 1.0 : A[r + (size_t)n * (kb + q)];
+      vb[r * kNb + q] = v;
     }
-    if (tid < kNb * kNb) Tm[tid / kNb][tid % kNb] = tfac[(size_t)(toff[s] + kbi) * kNb * kNb + tid];
+    if (tid < kNb * kNb) Ts[tid / kNb][tid % kNb] = tfac[(size_t)(toff[s] + kbi) * kNb * kNb + tid];
     __syncthreads();
-    double w[kNb];
+    // W = V^T Z over this wave's row blocks
+    v4d W = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < kNb; ++q) w[q] = 0.0;
-    for (int r = kb + 1 + rg; r < n; r += 16) {
-      const double zr = zc[r * kCb + cl];
-      const double* vr = vb + r * kNb;
+    for (int i = 0; i < MRB; ++i) {
+      const int rb = w + 4 * i;
+      if (rb < rb0 || rb >= nrb) continue;
 #pragma unroll
-      for (int q = 0; q < kNb; ++q) w[q] += vr[q] * zr;
+      for (int r = 0; r < 4; ++r) {
+        const double a = vb[(16 * rb + 4 * r + lk) * kNb + li];
+        W = mfma16(a, zt[i][r], W);
+      }
     }
 #pragma unroll
-    for (int q = 0; q < kNb; ++q) {
-      w[q] += __shfl_xor(w[q], 16, 64);
-      w[q] += __shfl_xor(w[q], 32, 64);
-    }
-    if (lane < kCb) {
-#pragma unroll
-      for (int q = 0; q < kNb; ++q) part[wv][q][cl] = w[q];
-    }
+    for (int r = 0; r < 4; ++r) Wp[w][4 * r + lk][li] = W[r];
     __syncthreads();
-    {
-      const int q = tid / kCb, c = tid % kCb;
-      Wm[q][c] = part[0][q][c] + part[1][q][c] + part[2][q][c] + part[3][q][c];
-    }
-    __syncthreads();
-    {
-      const int q = tid / kCb, c = tid % kCb;
-      double acc = 0.0;
-      for (int p = q; p < kNb; ++p) acc += Tm[q][p] * Wm[p][c];
-      W2[q][c] = acc;
-    }
-    __syncthreads();
-    double w2[kNb];
+    // W2 = T W (every wave, for its own use as the B operand below)
+    v4d W2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < kNb; ++q) w2[q] = W2[q][cl];
-    for (int r = kb + 1 + rg; r < n; r += 16) {
-      const double* vr = vb + r * kNb;
-      double acc = 0.0;
+    for (int kc = 0; kc < 4; ++kc) {
+      const int q = 4 * kc + lk;
+      const double bw = Wp[0][q][li] + Wp[1][q][li] + Wp[2][q][li] + Wp[3][q][li];
+      W2 = mfma16(Ts[li][q], bw, W2);
+    }
+    // Z -= V W2
 #pragma unroll
-      for (int q = 0; q < kNb; ++q) acc += vr[q] * w2[q];
-      zc[r * kCb + cl] -= acc;
+    for (int i = 0; i < MRB; ++i) {
+      const int rb = w + 4 * i;
+      if (rb < rb0 || rb >= nrb) continue;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const double a = vb[(16 * rb + li) * kNb + 4 * kc + lk];
+        zt[i] = mfma16(a, -W2[kc], zt[i]);
+      }
     }
   }
+  // write back and core weights of the panel's columns
+  const int c = n_core[s];
+  double cw = 0.0;
+#pragma unroll
+  for (int i = 0; i < MRB; ++i) {
+    const int rb = w + 4 * i;
+    if (rb >= nrb) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + 4 * r + lk;
+      if (row < n && col < n) {
+        Z[row + (size_t)n * col] = zt[i][r];
+        if (row < c) cw += zt[i][r] * zt[i][r];
+      }
+    }
+  }
+  cw += __shfl_xor(cw, 16, 64);
+  cw += __shfl_xor(cw, 32, 64);
+  if (lk == 0) csum[w][li] = cw;
   __syncthreads();
-  for (int idx = tid; idx < n * kCb; idx += kThreads) {
-    const int r = idx % n, c = idx / n;
-    if (c < ncol) Z[r + (size_t)n * (c0 + c)] = zc[r * kCb + c];
-  }
-  if (tid < ncol) {
-    const int c = n_core[s];
-    double acc = 0.0;
-    for (int r = 0; r < c; ++r) acc += zc[r * kCb + tid] * zc[r * kCb + tid];
-    wts[b + c0 + tid] = acc;
-  }
+  if (tid < 16 && c0 + tid < n) wts[b + c0 + tid] = csum[0][tid] + csum[1][tid] + csum[2][tid] + csum[3][tid];
 }
 
 }  // namespace
@@ -864,12 +788,12 @@ size_t dc_prep_lds(int m) { return (size_t)m * (12 * sizeof(double) + 7 * sizeof
 void dc_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_dc_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)dc_prep_lds(kMaxN));
-  (void)hipFuncSetAttribute((const void*)k_backtransform,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kMaxN * kCb * sizeof(double)));
-  (void)hipFuncSetAttribute((const void*)k_backtransform_lds,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kBtSmall * (kCb + kNb) * sizeof(double)));
+  (void)hipFuncSetAttribute((const void*)k_bt_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(256 * kNb * sizeof(double)));
+  (void)hipFuncSetAttribute((const void*)k_bt_mfma<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(512 * kNb * sizeof(double)));
+  (void)hipFuncSetAttribute((const void*)k_bt_mfma<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kMaxN * kNb * sizeof(double)));
 }
 
 void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
@@ -903,24 +827,30 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     prof_end(ctx);
   }
   const int maxn = g->info.max_n;
-  // subgraphs are ordered by decreasing size: the first n_big exceed kBtSmall
-  int n_big = 0;
-  while (n_big < g->n_sub && g->sub_orb_ptr[g->order[n_big] + 1] - g->sub_orb_ptr[g->order[n_big]] > kBtSmall) ++n_big;
   prof_begin(ctx, "k_bt_tfactors");
   hipLaunchKernelGGL(k_bt_tfactors, dim3(g->n_sub, (maxn + kNb - 1) / kNb), dim3(kThreads), 0, st,
                      e->A, e->tau, dv.off2, dv.sub_orb_ptr, dv.bt_toff, e->tfac);
   prof_end(ctx);
   prof_begin(ctx, "k_backtransform");
-  if (n_big > 0)
-    hipLaunchKernelGGL(k_backtransform, dim3(n_big, (maxn + kCb - 1) / kCb), dim3(kThreads),
-                       (size_t)maxn * kCb * sizeof(double), st, e->A, e->tau, e->Q, dv.off2,
-                       dv.sub_orb_ptr, dv.n_core, dv.order, e->wts);
-  if (n_big < g->n_sub) {
-    const int nsm = std::min(maxn, kBtSmall);
-    hipLaunchKernelGGL(k_backtransform_lds, dim3(g->n_sub - n_big, (nsm + kCb - 1) / kCb),
-                       dim3(kThreads), (size_t)nsm * (kCb + kNb) * sizeof(double), st, e->A,
-                       e->tfac, dv.bt_toff, e->Q, dv.off2, dv.sub_orb_ptr, dv.n_core,
-                       dv.order + n_big, e->wts);
+  // subgraphs are ordered by decreasing size: classes n <= 256, <= 512, <= 1024
+  // are contiguous ranges of that order, each launched with its register panel
+  int lo = 0;
+  for (int cls = 2; cls >= 0; --cls) {
+    const int cap = cls == 0 ? 256 : cls == 1 ? 512 : kMaxN;
+    const int floor_n = cls == 0 ? 0 : cls == 1 ? 256 : 512;
+    int hi = lo;
+    while (hi < g->n_sub && g->sub_orb_ptr[g->order[hi] + 1] - g->sub_orb_ptr[g->order[hi]] > floor_n) ++hi;
+    if (hi > lo) {
+      const int nmax = g->sub_orb_ptr[g->order[lo] + 1] - g->sub_orb_ptr[g->order[lo]];
+      const int nrb = (nmax + 15) / 16;
+      dim3 grid((nmax + 15) / 16, hi - lo);
+      const size_t lds = (size_t)16 * nrb * kNb * sizeof(double);
+      auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<8> : k_bt_mfma<16>;
+      (void)cap;
+      hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, e->A, e->tfac, dv.bt_toff, e->Q,
+                         dv.off2, dv.sub_orb_ptr, dv.n_core, dv.order + lo, e->wts);
+    }
+    lo = hi;
   }
   prof_end(ctx);
 }

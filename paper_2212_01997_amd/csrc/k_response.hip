@@ -351,19 +351,21 @@ __global__ __launch_bounds__(kThreads) void k_h1_gather(const double* __restrict
     hloc[(size_t)q * sum_n + i] = h1[(size_t)q * N + sub_orbs[i]];
 }
 
-// Y(k, l) under the storage rule of k_xy
-__device__ __forceinline__ size_t ypos(int k, int l, int n) {
-  return (k / kTile >= l / kTile) ? (size_t)l + (size_t)n * k : (size_t)k + (size_t)n * l;
-}
 
 // T = Q_c Y for 64 columns of one subgraph; T stored as tbuf[(b + l) * 32 + j].
+// K (the rows of Y) is staged through LDS 64 rows at a time, exactly one
+// 64-row tile of Y, so every stage is read along its stored direction; the
+// next stage is prefetched into registers meanwhile.  Each wave owns 16
+// columns and the (at most 32) core rows.
+constexpr int kTK = 64;
+
 __global__ __launch_bounds__(kThreads) void k_t_mfma(
     const double* __restrict__ qbuf, const double* __restrict__ ybuf, double* __restrict__ tbuf,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
     const int32_t* __restrict__ n_core, const int32_t* __restrict__ order, int64_t sum_n2,
     int64_t sum_n) {
-  __shared__ double As[16][33];
-  __shared__ double Bs[16][kTile + 1];
+  __shared__ double As[kTK][33];
+  __shared__ double Bs[kTK][kTile + 1];
   const int s = order[blockIdx.x];
   const int q = blockIdx.z;
   const int b = sub_orb_ptr[s];
@@ -376,30 +378,52 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
   double* Tq = tbuf + (size_t)q * sum_n * 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < n; k0 += 16) {
-    __syncthreads();
-    for (int idx = tid; idx < 16 * 32; idx += kThreads) {
+  constexpr int kPa = kTK * 32 / kThreads, kPb = kTK * kTile / kThreads;
+  double pa[kPa], pb[kPb];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < kPa; ++u) {
+      const int idx = tid + u * kThreads;
       const int j = idx % 32, kk = idx / 32;
-      As[kk][j] = (j < c && k0 + kk < n) ? Q[j + (size_t)n * (k0 + kk)] : 0.0;
+      pa[u] = (j < c && k0 + kk < n) ? Q[j + (size_t)n * (k0 + kk)] : 0.0;
     }
-    // Y rows k0..k0+15, columns L0..L0+63; coalesced along the stored direction
     const bool lower = (k0 / kTile) >= (L0 / kTile);
-    for (int idx = tid; idx < 16 * kTile; idx += kThreads) {
+#pragma unroll
+    for (int u = 0; u < kPb; ++u) {
+      const int idx = tid + u * kThreads;
       int kk, ll;
       if (lower) {
         ll = idx % kTile;
         kk = idx / kTile;
       } else {
-        kk = idx % 16;
-        ll = idx / 16;
+        kk = idx % kTK;
+        ll = idx / kTK;
       }
       const int k = k0 + kk, l = L0 + ll;
-      Bs[kk][ll] = (k < n && l < n) ? Y[ypos(k, l, n)] : 0.0;
+      pb[u] = (k < n && l < n) ? (lower ? Y[(size_t)l + (size_t)n * k] : Y[(size_t)k + (size_t)n * l])
+                               : 0.0;
     }
+  };
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  for (int k0 = 0; k0 < n; k0 += kTK) {
+    const bool lower = (k0 / kTile) >= (L0 / kTile);
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int u = 0; u < kPa; ++u) {
+      const int idx = tid + u * kThreads;
+      As[idx / 32][idx % 32] = pa[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kPb; ++u) {
+      const int idx = tid + u * kThreads;
+      if (lower) Bs[idx / kTile][idx % kTile] = pb[u];
+      else Bs[idx % kTK][idx / kTK] = pb[u];
+    }
+    __syncthreads();
+    if (k0 + kTK < n) fetch(k0 + kTK);
+#pragma unroll
+    for (int ks = 0; ks < kTK / 4; ++ks) {
       const int row = 4 * ks + lk;
       const double bv = Bs[row][16 * w + li];
       acc0 = mfma16(As[row][li], bv, acc0);
@@ -416,7 +440,11 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
   }
 }
 
-// P = 2 T Q^T (c x n core rows, block layout) and its diagonal.
+// P = 2 T Q^T (c x n core rows, block layout) and its diagonal.  Each wave owns
+// 16 columns; T and Q are read straight from memory along their stored
+// directions, kPU steps of 4 rows loaded ahead of their MFMAs.
+constexpr int kPU = 8;
+
 __global__ __launch_bounds__(kThreads) void k_p_mfma(
     const double* __restrict__ tbuf, const double* __restrict__ qbuf, double* __restrict__ out,
     double* __restrict__ pdiag, const int64_t* __restrict__ off2, const int64_t* __restrict__ offc,
@@ -437,17 +465,25 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int lcol = L0 + 16 * w + li;
+  const bool colok = lcol < n;
   v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  for (int q0 = 0; q0 < n; q0 += 4) {
-    const int m = q0 + lk;
-    const bool ok = m < n;
-    const double a0 = ok ? Tq[(size_t)(b + m) * 32 + li] : 0.0;
-    const double a1 = ok ? Tq[(size_t)(b + m) * 32 + 16 + li] : 0.0;
-    const double bv = (ok && lcol < n) ? Q[lcol + (size_t)n * m] : 0.0;
-    acc0 = mfma16(a0, bv, acc0);
-    acc1 = mfma16(a1, bv, acc1);
+  for (int m0 = 0; m0 < n; m0 += 4 * kPU) {
+    double a0[kPU], a1[kPU], bv[kPU];
+#pragma unroll
+    for (int u = 0; u < kPU; ++u) {
+      const int m = m0 + 4 * u + lk;
+      const bool ok = m < n;
+      a0[u] = ok ? Tq[(size_t)(b + m) * 32 + li] : 0.0;
+      a1[u] = ok ? Tq[(size_t)(b + m) * 32 + 16 + li] : 0.0;
+      bv[u] = (ok && colok) ? Q[lcol + (size_t)n * m] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPU; ++u) {
+      acc0 = mfma16(a0[u], bv[u], acc0);
+      acc1 = mfma16(a1[u], bv[u], acc1);
+    }
   }
-  if (lcol < n) {
+  if (colok) {
     const size_t base = offc[s];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

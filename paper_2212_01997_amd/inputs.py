@@ -224,7 +224,7 @@ def place_waters(rng, n_mol, box, fixed=None, oo_min=2.5, inter_min=1.5, batch=2
     return np.concatenate(out, axis=0) if out else np.zeros((0, 3))
 
 
-def chain_walk(rng, n_chain, box, step=1.5, min_sep=2.4, retries=100):
+def chain_walk(rng, n_chain, box, step=1.5, min_sep=2.4, retries=100, max_fails=4):
     """Self-avoiding random walk of heavy atoms under periodic boundaries.
 
     Every new atom keeps `min_sep` from all chain atoms except its
@@ -249,17 +249,22 @@ def chain_walk(rng, n_chain, box, step=1.5, min_sep=2.4, retries=100):
                 placed = True
                 break
         if not placed:
-            # backtrack one atom
-            if len(pts) <= 1:
-                raise RuntimeError("chain walk stuck at the first atom")
-            last = len(pts) - 1
-            key = grid._key(pts[last])
-            grid.cells[key].remove(last)
-            grid.pos.pop()
-            grid.tag.pop()
-            pts.pop()
-            fails.pop()
-            fails[-1] += 1
+            # backtrack one atom; an atom whose continuation failed more than
+            # `max_fails` times is itself taken back (escapes dead ends)
+            while True:
+                if len(pts) <= 1:
+                    raise RuntimeError("chain walk stuck at the first atom")
+                last = len(pts) - 1
+                key = grid._key(pts[last])
+                grid.cells[key].remove(last)
+                grid.pos.pop()
+                grid.tag.pop()
+                pts.pop()
+                fails.pop()
+                fails[-1] += 1
+                if fails[-1] <= max_fails:
+                    break
+                fails[-1] = 0
     return np.array(pts)
 
 

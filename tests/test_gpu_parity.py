@@ -284,3 +284,46 @@ def test_error_paths(ctx):
     p.eigs.density(0.01, s.n_elec)
     with pytest.raises(gq.GQError, match="max_k"):
         p.eigs.response(torch.zeros((2, s.n_orb), dtype=torch.float64, device="cuda"), p.p_blocks)
+
+
+# ------------------------------------------------ config 3 at full size
+def test_config3_full_size_sampled():
+    """The 30,000-atom chain-in-water system (3,750 subgraphs of 148..638
+    orbitals, K = 6) at kT = 0.003, 0.01, 0.03: the graph bit-exact (digests of
+    the oracle's maps), mu and mu1 against the oracle, rho and rho1 at 4,096
+    sampled positions; FP64 within 1e-10, split-FP32 response within 1e-6.
+    The stored values come from tests/golden/make_config3_golden.py (oracle only)."""
+    import hashlib
+    import json
+    import torch
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config3_oracle.json")) as f:
+        gold = json.load(f)
+    s = I.config_system(3)
+    core = I.spatial_cores(s, 8)
+    ctx = gq.Context(0)
+    prev = bootstrap_prev(ctx, s, core, KT)
+    graph = gq.Graph.for_system(s, core, 0.07, prev, gq.PATHS2)
+    ex = graph.export()
+    for name, dig in gold["graph"].items():
+        got = hashlib.sha256(np.ascontiguousarray(ex[name], np.int32).tobytes()).hexdigest()[:16]
+        assert got == dig, name
+    K = 6
+    p = GraphPath(ctx, s, core, 0.07, graph=graph, max_k=K)
+    h1 = torch.as_tensor(I.h1_diagonal(s, K, seed=3002), device="cuda")
+    idx = np.array(gold["idx"])
+    for kT in (0.003, 0.01, 0.03):
+        g = gold["kT"][repr(kT)]
+        mu = p.ground_state(kT)
+        for precision, tol in ((0, TOL), (1, 1e-6)):
+            mu1 = p.respond(h1, precision=precision)
+            p.sync()
+            rho = p.rho.cpu().numpy()[idx]
+            rho1 = p.rho1_view(K).cpu().numpy()[:, idx]
+            err = (abs(mu - g["mu"]), np.abs(rho - np.array(g["rho"])).max(),
+                   np.abs(mu1 - np.array(g["mu1"])).max(), np.abs(rho1 - np.array(g["rho1"])).max())
+            _say(f"config3 kT={kT} precision={precision}: |dmu| {err[0]:.1e} |drho| {err[1]:.1e} "
+                 f"|dmu1| {err[2]:.1e} |drho1| {err[3]:.1e}")
+            assert err[0] <= TOL_MU and err[1] <= TOL
+            assert err[2] <= tol and err[3] <= tol
