@@ -26,6 +26,14 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A(l%16, l/16) and
+// B(l/16, l%16); D(i, j) is returned in lane j + 16*(i%4), register i/4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Sum over the workgroup in a fixed order; every thread gets the total.
 __device__ double block_sum(double x, double* red) {
   x = wave_sum(x);
@@ -84,11 +92,10 @@ __global__ __launch_bounds__(kThreads) void k_gather(
 //   A_cur = A - sum_q (v_q w_q^T + w_q v_q^T);
 // v_q is kept in A's column k0+q (v[0] = 1 stored at row k0+q+1) and w_q in a
 // global panel scratch, so the symmetric product keeps its registers for 16
-// loads in flight.  At the end of the panel one pass applies the rank-2*kPanel
-// update.  d, e and tau go to D, E, TAU.
+// loads in flight.  At the end of the panel the rank-2*kPanel update runs on
+// FP64 MFMA.  d, e and tau go to D, E, TAU.
 constexpr int kTdThreads = 1024;
 constexpr int kPanel = 16;
-constexpr int kStage = 128;
 constexpr int kUnroll = 8;
 
 __device__ double tsum(double x, double* red) {
@@ -107,12 +114,12 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
     double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
-  __shared__ double vl[kMaxN], part[kTdThreads];
+  __shared__ __align__(16) double vl[kMaxN];
+  __shared__ double part[kTdThreads];
   __shared__ double red[kTdThreads / 64];
   __shared__ double ysh[2 * kPanel][kTdThreads / 64];
   __shared__ double yfin[2 * kPanel];
   __shared__ double rowc[2 * kPanel];
-  __shared__ double stage[kStage][kPanel + 1];
   __shared__ double alpha_sh;
   const int s = order[blockIdx.x];
   const int b = sub_orb_ptr[s];
@@ -171,22 +178,35 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
         continue;
       }
       const double vr = r < n ? vl[r] : 0.0;
-      // p = A22 v over the stale trailing matrix (row r, columns = h mod H)
+      // p = A22 v over the stale trailing matrix: row r, in chunks of kUnroll
+      // columns aligned to multiples of kUnroll (chunk g goes to the thread
+      // with h = g mod H).  v is 0 at columns <= c, so the chunk holding c+1
+      // may start early; the chunk's v values are one wave-uniform run of LDS,
+      // read two at a time.
       double acc = 0.0;
       if (r >= c + 1 && r < n) {
         const double* row = A + r;
-        int col = c + 1 + h;
         double ac[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) ac[u] = 0.0;
-        for (; col + (kUnroll - 1) * H < n; col += kUnroll * H) {
+        const int g_end = n / kUnroll;  // full chunks
+        int g = (c + 1) / kUnroll + h;
+        for (; g < g_end; g += H) {
+          const int col = g * kUnroll;
           double x[kUnroll];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * (col + u * H)];
+          for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * (col + u)];
+          const double2* v2 = reinterpret_cast<const double2*>(vl + col);
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) ac[u] += x[u] * vl[col + u * H];
+          for (int u = 0; u < kUnroll / 2; ++u) {
+            const double2 vv = v2[u];
+            ac[2 * u] += x[2 * u] * vv.x;
+            ac[2 * u + 1] += x[2 * u + 1] * vv.y;
+          }
         }
-        for (; col < n; col += H) ac[0] += row[(size_t)n * col] * vl[col];
+        if (g == g_end) {  // the partial chunk at the end (this thread's turn)
+          for (int col = max(g_end * kUnroll, c + 1); col < n; ++col) ac[0] += row[(size_t)n * col] * vl[col];
+        }
 #pragma unroll
         for (int u = 1; u < kUnroll; ++u) ac[0] += ac[u];
         acc = ac[0];
@@ -224,37 +244,43 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
       if (own) W[j * n + r] = r >= c + 1 ? p - K * vr : 0.0;
     }
     __syncthreads();
-    // trailing update of rows/cols >= k0 + nb, in two halves of the panel so
-    // that a thread's row factors fit in registers
-    const int t0 = k0 + nb;
-#pragma unroll 1
-    for (int qh = 0; qh < kPanel; qh += kPanel / 2) {
-      double Vr[kPanel / 2], Wr[kPanel / 2];
+    // trailing update A22 -= V W^T + W V^T of rows/cols >= k0 + nb on FP64
+    // MFMA: 16x16 tiles dealt to the 16 waves, K = the panel's reflectors
+    // (twice).  Tile element (row0 + j, col0 + i) sits in lane j + 16 (i%4),
+    // register i/4, so every load and store of a register is a 128-byte run of
+    // one column.
+    {
+      const int t0 = k0 + nb;
+      const int nt = (n - t0 + 15) / 16;
+      const int li = lane & 15, lk = lane >> 4;
+      for (int tile = wv; tile < nt * nt; tile += kTdThreads / 64) {
+        const int row0 = t0 + 16 * (tile / nt), col0 = t0 + 16 * (tile % nt);
+        const int row = row0 + li;
+        const bool rok = row < n;
+        v4d acc;
 #pragma unroll
-      for (int q = 0; q < kPanel / 2; ++q) {
-        const bool ok = qh + q < nb && r >= t0 && r < n;
-        Vr[q] = ok ? A[r + (size_t)n * (k0 + qh + q)] : 0.0;
-        Wr[q] = ok ? W[(qh + q) * n + r] : 0.0;
-      }
-      for (int cc0 = t0; cc0 < n; cc0 += kStage) {
-        __syncthreads();
-        if (own && r >= cc0 && r < cc0 + kStage) {
-#pragma unroll
-          for (int q = 0; q < kPanel / 2; ++q) {
-            stage[r - cc0][q] = Vr[q];
-            stage[r - cc0][kPanel / 2 + q] = Wr[q];
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int col = col0 + 4 * r + lk;
+          acc[r] = (rok && col < n) ? A[row + (size_t)n * col] : 0.0;
         }
-        __syncthreads();
-        if (r >= t0 && r < n) {
-          const int cend = min(n, cc0 + kStage);
-          for (int col = cc0 + h; col < cend; col += H) {
-            double* ap = A + r + (size_t)n * col;
-            double a = *ap;
-            const double* sv = stage[col - cc0];
+        const int cl = col0 + li;
+        const bool cok = cl < n;
 #pragma unroll
-            for (int q = 0; q < kPanel / 2; ++q) a -= Vr[q] * sv[kPanel / 2 + q] + Wr[q] * sv[q];
-            *ap = a;
+        for (int kq = 0; kq < kPanel / 4; ++kq) {
+          const int q = 4 * kq + lk;
+          const bool qok = q < nb;
+          const double wc = (qok && cok) ? W[q * n + cl] : 0.0;
+          const double vc = (qok && cok) ? A[cl + (size_t)n * (k0 + q)] : 0.0;
+          const double vr = (qok && rok) ? A[row + (size_t)n * (k0 + q)] : 0.0;
+          const double wr = (qok && rok) ? W[q * n + row] : 0.0;
+          acc = mfma16(-wc, vr, acc);
+          acc = mfma16(-vc, wr, acc);
+        }
+        if (rok) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int col = col0 + 4 * r + lk;
+            if (col < n) A[row + (size_t)n * col] = acc[r];
           }
         }
       }
