@@ -352,12 +352,13 @@ __global__ __launch_bounds__(kThreads) void k_h1_gather(const double* __restrict
 }
 
 
-// T = Q_c Y for 64 columns of one subgraph; T stored as tbuf[(b + l) * 32 + j].
-// K (the rows of Y) is staged through LDS 64 rows at a time, exactly one
-// 64-row tile of Y, so every stage is read along its stored direction; the
-// next stage is prefetched into registers meanwhile.  Each wave owns 16
-// columns and the (at most 32) core rows.
-constexpr int kTK = 64;
+// T = Q_c Y for 128 columns of one subgraph; T stored as tbuf[(b + l) * 32 + j].
+// K (the rows of Y) is staged through LDS 32 rows at a time, each half of the
+// 128 columns read along its stored direction (a 32-row stage lies inside one
+// 64-row tile of Y); the next stage is prefetched into registers meanwhile.
+// Each wave owns 32 columns and the (at most 32) core rows.
+constexpr int kTC = 128;  // columns per workgroup of the row products
+constexpr int kTK = 32;
 
 __global__ __launch_bounds__(kThreads) void k_t_mfma(
     const double* __restrict__ qbuf, const double* __restrict__ ybuf, double* __restrict__ tbuf,
@@ -365,21 +366,21 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
     const int32_t* __restrict__ n_core, const int32_t* __restrict__ order, int64_t sum_n2,
     int64_t sum_n) {
   __shared__ double As[kTK][33];
-  __shared__ double Bs[kTK][kTile + 1];
+  __shared__ double Bs[kTK][kTC + 1];
   const int s = order[blockIdx.x];
   const int q = blockIdx.z;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
-  const int L0 = blockIdx.y * kTile;
+  const int L0 = blockIdx.y * kTC;
   if (L0 >= n) return;
   const double* Q = qbuf + off2[s];
   const double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
   double* Tq = tbuf + (size_t)q * sum_n * 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  constexpr int kPa = kTK * 32 / kThreads, kPb = kTK * kTile / kThreads;
-  double pa[kPa], pb[kPb];
+  constexpr int kPa = kTK * 32 / kThreads, kPh = kTK * kTile / kThreads;
+  double pa[kPa], pb[2][kPh];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < kPa; ++u) {
@@ -387,27 +388,35 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
       const int j = idx % 32, kk = idx / 32;
       pa[u] = (j < c && k0 + kk < n) ? Q[j + (size_t)n * (k0 + kk)] : 0.0;
     }
-    const bool lower = (k0 / kTile) >= (L0 / kTile);
 #pragma unroll
-    for (int u = 0; u < kPb; ++u) {
-      const int idx = tid + u * kThreads;
-      int kk, ll;
-      if (lower) {
-        ll = idx % kTile;
-        kk = idx / kTile;
-      } else {
-        kk = idx % kTK;
-        ll = idx / kTK;
+    for (int hlf = 0; hlf < 2; ++hlf) {
+      const int C0 = L0 + hlf * kTile;
+      const bool lower = (k0 / kTile) >= (C0 / kTile);
+#pragma unroll
+      for (int u = 0; u < kPh; ++u) {
+        const int idx = tid + u * kThreads;
+        int kk, ll;
+        if (lower) {
+          ll = idx % kTile;
+          kk = idx / kTile;
+        } else {
+          kk = idx % kTK;
+          ll = idx / kTK;
+        }
+        const int k = k0 + kk, l = C0 + ll;
+        pb[hlf][u] = (k < n && l < n)
+                         ? (lower ? Y[(size_t)l + (size_t)n * k] : Y[(size_t)k + (size_t)n * l])
+                         : 0.0;
       }
-      const int k = k0 + kk, l = L0 + ll;
-      pb[u] = (k < n && l < n) ? (lower ? Y[(size_t)l + (size_t)n * k] : Y[(size_t)k + (size_t)n * l])
-                               : 0.0;
     }
   };
-  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
   fetch(0);
   for (int k0 = 0; k0 < n; k0 += kTK) {
-    const bool lower = (k0 / kTile) >= (L0 / kTile);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kPa; ++u) {
@@ -415,34 +424,44 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
       As[idx / 32][idx % 32] = pa[u];
     }
 #pragma unroll
-    for (int u = 0; u < kPb; ++u) {
-      const int idx = tid + u * kThreads;
-      if (lower) Bs[idx / kTile][idx % kTile] = pb[u];
-      else Bs[idx % kTK][idx / kTK] = pb[u];
+    for (int hlf = 0; hlf < 2; ++hlf) {
+      const bool lower = (k0 / kTile) >= ((L0 + hlf * kTile) / kTile);
+#pragma unroll
+      for (int u = 0; u < kPh; ++u) {
+        const int idx = tid + u * kThreads;
+        if (lower) Bs[idx / kTile][hlf * kTile + idx % kTile] = pb[hlf][u];
+        else Bs[idx % kTK][hlf * kTile + idx / kTK] = pb[hlf][u];
+      }
     }
     __syncthreads();
     if (k0 + kTK < n) fetch(k0 + kTK);
 #pragma unroll
     for (int ks = 0; ks < kTK / 4; ++ks) {
       const int row = 4 * ks + lk;
-      const double bv = Bs[row][16 * w + li];
-      acc0 = mfma16(As[row][li], bv, acc0);
-      acc1 = mfma16(As[row][16 + li], bv, acc1);
+      const double a0 = As[row][li], a1 = As[row][16 + li];
+      const double b0 = Bs[row][32 * w + li], b1 = Bs[row][32 * w + 16 + li];
+      acc[0][0] = mfma16(a0, b0, acc[0][0]);
+      acc[1][0] = mfma16(a1, b0, acc[1][0]);
+      acc[0][1] = mfma16(a0, b1, acc[0][1]);
+      acc[1][1] = mfma16(a1, b1, acc[1][1]);
     }
   }
-  const int l = L0 + 16 * w + li;
-  if (l < n) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Tq[(size_t)(b + l) * 32 + lk + 4 * r] = acc0[r];
-      Tq[(size_t)(b + l) * 32 + 16 + lk + 4 * r] = acc1[r];
+  for (int y = 0; y < 2; ++y) {
+    const int l = L0 + 32 * w + 16 * y + li;
+    if (l < n) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        Tq[(size_t)(b + l) * 32 + lk + 4 * r] = acc[0][y][r];
+        Tq[(size_t)(b + l) * 32 + 16 + lk + 4 * r] = acc[1][y][r];
+      }
     }
   }
 }
 
-// P = 2 T Q^T (c x n core rows, block layout) and its diagonal.  Each wave owns
-// 16 columns; T and Q are read straight from memory along their stored
-// directions, kPU steps of 4 rows loaded ahead of their MFMAs.
+// P = 2 T Q^T (c x n core rows, block layout) and its diagonal, 128 columns per
+// workgroup.  Each wave owns 32 columns; T and Q are read straight from memory
+// along their stored directions, kPU steps of 4 rows loaded ahead of their MFMAs.
 constexpr int kPU = 8;
 
 __global__ __launch_bounds__(kThreads) void k_p_mfma(
@@ -456,7 +475,7 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
-  const int L0 = blockIdx.y * kTile;
+  const int L0 = blockIdx.y * kTC;
   if (L0 >= n) return;
   const double* Q = qbuf + off2[s];
   const double* Tq = tbuf + (size_t)q * sum_n * 32;
@@ -464,39 +483,53 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
   double* pdq = pdiag + (size_t)q * sum_c;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int lcol = L0 + 16 * w + li;
-  const bool colok = lcol < n;
-  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  int lcol[2];
+  bool colok[2];
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    lcol[y] = L0 + 32 * w + 16 * y + li;
+    colok[y] = lcol[y] < n;
+  }
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int m0 = 0; m0 < n; m0 += 4 * kPU) {
-    double a0[kPU], a1[kPU], bv[kPU];
+    double a0[kPU], a1[kPU], bv[2][kPU];
 #pragma unroll
     for (int u = 0; u < kPU; ++u) {
       const int m = m0 + 4 * u + lk;
       const bool ok = m < n;
       a0[u] = ok ? Tq[(size_t)(b + m) * 32 + li] : 0.0;
       a1[u] = ok ? Tq[(size_t)(b + m) * 32 + 16 + li] : 0.0;
-      bv[u] = (ok && colok) ? Q[lcol + (size_t)n * m] : 0.0;
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y][u] = (ok && colok[y]) ? Q[lcol[y] + (size_t)n * m] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < kPU; ++u) {
-      acc0 = mfma16(a0[u], bv[u], acc0);
-      acc1 = mfma16(a1[u], bv[u], acc1);
-    }
+    for (int u = 0; u < kPU; ++u)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        acc[0][y] = mfma16(a0[u], bv[y][u], acc[0][y]);
+        acc[1][y] = mfma16(a1[u], bv[y][u], acc[1][y]);
+      }
   }
-  if (colok) {
-    const size_t base = offc[s];
+  const size_t base = offc[s];
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    if (!colok[y]) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j0 = lk + 4 * r, j1 = 16 + lk + 4 * r;
       if (j0 < c) {
-        const double v = 2.0 * acc0[r];
-        outq[base + (size_t)j0 * n + lcol] = v;
-        if (lcol == j0) pdq[offcd[s] + j0] = v;
+        const double v = 2.0 * acc[0][y][r];
+        outq[base + (size_t)j0 * n + lcol[y]] = v;
+        if (lcol[y] == j0) pdq[offcd[s] + j0] = v;
       }
       if (j1 < c) {
-        const double v = 2.0 * acc1[r];
-        outq[base + (size_t)j1 * n + lcol] = v;
-        if (lcol == j1) pdq[offcd[s] + j1] = v;
+        const double v = 2.0 * acc[1][y][r];
+        outq[base + (size_t)j1 * n + lcol[y]] = v;
+        if (lcol[y] == j1) pdq[offcd[s] + j1] = v;
       }
     }
   }
@@ -691,7 +724,7 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h
     prof_end(ctx);
   }
   prof_begin(ctx, "k_rows");
-  dim3 grid_cols(g->n_sub, (g->info.max_n + kTile - 1) / kTile, K);
+  dim3 grid_cols(g->n_sub, (g->info.max_n + kTC - 1) / kTC, K);
   hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, e->Y, e->T, dv.off2,
                      dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
   hipLaunchKernelGGL(k_p_mfma, grid_cols, dim3(kThreads), 0, st, e->T, e->Q, p_blocks, e->pdiag,
