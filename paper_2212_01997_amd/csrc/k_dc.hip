@@ -32,6 +32,9 @@ constexpr int kThreads = 256;
 constexpr int kTile = 64;
 constexpr int kKc = 16;
 constexpr int kNb = 16;   // reflectors per compact-WY block
+// row stride of the staged reflector block: 17 doubles keep both the 16-row
+// reads of the update and the 16-column reads of V^T Z in distinct LDS banks
+constexpr int kLdv = kNb + 1;
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -226,11 +229,12 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
     double w = 1.0 / rho, err = 1.0 / rho, psi1 = 0.0, phi1 = 0.0, Dl = 0.0, Dr = 0.0;
     for (int i = 0; i < k; ++i) {
       const double Di = (delta[i] - dlo) - x;
-      const double t = zeta[i] * zeta[i] / Di;
+      const double ri = 1.0 / Di;  // one division per term; t / Di = t * ri
+      const double t = zeta[i] * zeta[i] * ri;
       w += t;
       err += fabs(t);
-      if (i <= jl) psi1 += t / Di;
-      else phi1 += t / Di;
+      if (i <= jl) psi1 += t * ri;
+      else phi1 += t * ri;
       if (i == jl) Dl = Di;
       if (i == jl + 1) Dr = Di;
     }
@@ -432,20 +436,41 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
   }
   __syncthreads();
   // recomputed z: zh_i^2 = (lambda_i - d_i)/rho * prod_{j != i} (d_i - lambda_j)/(d_i - d_j)
+  // (numerators and denominators gathered in groups of four, one division per
+  // group: every factor lies between about 1e-18 and 10, so a group cannot
+  // leave the double range)
   for (int i = tid; i < k; i += kThreads) {
     const double di = L.delta[i];
     double prod = -((di - L.delta[L.org[i]]) - L.tau[i]) / rho2;
+    double num = 1.0, den = 1.0;
+    int cnt = 0;
     for (int j = 0; j < k; ++j) {
       if (j == i) continue;
-      prod *= ((di - L.delta[L.org[j]]) - L.tau[j]) / (di - L.delta[j]);
+      num *= (di - L.delta[L.org[j]]) - L.tau[j];
+      den *= di - L.delta[j];
+      if (++cnt == 4) {
+        prod *= num / den;
+        num = den = 1.0;
+        cnt = 0;
+      }
     }
+    prod *= num / den;
     L.zhat[i] = copysign(sqrt(fmax(prod, 0.0)), L.zeta[i]);
   }
   __syncthreads();
+  // sum_i (zh_i / D_i)^2 with pairs over a common denominator:
+  // (za^2 Db^2 + zb^2 Da^2) / (Da^2 Db^2)
   for (int j = tid; j < k; j += kThreads) {
     const double dO = L.delta[L.org[j]], tj = L.tau[j];
     double acc = 0.0;
-    for (int i = 0; i < k; ++i) {
+    int i = 0;
+    for (; i + 1 < k; i += 2) {
+      const double da = (L.delta[i] - dO) - tj, db = (L.delta[i + 1] - dO) - tj;
+      const double za = L.zhat[i], zb = L.zhat[i + 1];
+      const double da2 = da * da, db2 = db * db;
+      acc += (za * za * db2 + zb * zb * da2) / (da2 * db2);
+    }
+    if (i < k) {
       const double u = L.zhat[i] / ((L.delta[i] - dO) - tj);
       acc += u * u;
     }
@@ -680,7 +705,7 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
     const int32_t* __restrict__ toff, double* __restrict__ zbuf, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core,
     const int32_t* __restrict__ list, double* __restrict__ wts) {
-  extern __shared__ double vb[];  // [16 * nrb][16]: reflector block, row-major
+  extern __shared__ double vb[];  // [16 * nrb][kLdv]: reflector block, row-major
   __shared__ double Wp[4][16][17];
   __shared__ double Ts[16][17];
   __shared__ double csum[4][16];
@@ -719,7 +744,7 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
       const int top = kb + q + 1;
       double v = 0.0;
       if (q < nb && r < n && r >= top) v = (r == top) ? 1.0 : A[r + (size_t)n * (kb + q)];
-      vb[r * kNb + q] = v;
+      vb[r * kLdv + q] = v;
     }
     if (tid < kNb * kNb) Ts[tid / kNb][tid % kNb] = tfac[(size_t)(toff[s] + kbi) * kNb * kNb + tid];
     __syncthreads();
@@ -731,7 +756,7 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
       if (rb < rb0 || rb >= nrb) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double a = vb[(16 * rb + 4 * r + lk) * kNb + li];
+        const double a = vb[(16 * rb + 4 * r + lk) * kLdv + li];
         W = mfma16(a, zt[i][r], W);
       }
     }
@@ -753,7 +778,7 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
       if (rb < rb0 || rb >= nrb) continue;
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) {
-        const double a = vb[(16 * rb + li) * kNb + 4 * kc + lk];
+        const double a = vb[(16 * rb + li) * kLdv + 4 * kc + lk];
         zt[i] = mfma16(a, -W2[kc], zt[i]);
       }
     }
@@ -789,11 +814,11 @@ void dc_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_dc_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)dc_prep_lds(kMaxN));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(256 * kNb * sizeof(double)));
+                            (int)(256 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(512 * kNb * sizeof(double)));
+                            (int)(512 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kMaxN * kNb * sizeof(double)));
+                            (int)(kMaxN * kLdv * sizeof(double)));
 }
 
 void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
@@ -844,7 +869,7 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
       const int nmax = g->sub_orb_ptr[g->order[lo] + 1] - g->sub_orb_ptr[g->order[lo]];
       const int nrb = (nmax + 15) / 16;
       dim3 grid((nmax + 15) / 16, hi - lo);
-      const size_t lds = (size_t)16 * nrb * kNb * sizeof(double);
+      const size_t lds = (size_t)16 * nrb * kLdv * sizeof(double);
       auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<8> : k_bt_mfma<16>;
       (void)cap;
       hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, e->A, e->tfac, dv.bt_toff, e->Q,

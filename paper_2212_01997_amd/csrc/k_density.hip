@@ -122,6 +122,8 @@ __global__ __launch_bounds__(kMuPoints * kMuGroups) void k_mu_update(
   __shared__ double F[kMuPoints];
   const int j = threadIdx.x % kMuPoints, g = threadIdx.x / kMuPoints;
   double acc = 0.0;
+  // unrolled so that the loads are in flight together; the adds keep their order
+#pragma unroll 8
   for (int b = g; b < nblk; b += kMuGroups) acc += part[(size_t)b * kMuPoints + j];
   G[g][j] = acc;
   __syncthreads();

@@ -61,8 +61,8 @@ __device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
 
 constexpr int kXK = 32;  // K chunk of the X tiles
 
-// Four waves in a 2x2 arrangement; each wave owns a (TM/2)x(TM/2) quarter of
-// the tile, made of WB x WB 16x16 MFMA blocks.
+// FP32 tiles: four waves in a 2x2 arrangement; each wave owns a (TM/2)x(TM/2)
+// quarter of the tile, made of WB x WB 16x16 MFMA blocks.
 template <int TM>
 struct XyShape {
   static constexpr int kNT = 256;
@@ -70,66 +70,77 @@ struct XyShape {
   static constexpr int kPer = kXK * TM / kNT;  // operand values per thread per chunk
 };
 
-// Accumulates the TMxTM block X(k0.., l0..) = sum_m Q(m, k) h(m) Q(m, l) of one
-// subgraph on FP64 MFMA (columns k >= kend or l >= lend read as zero).  The K
-// dimension is staged through LDS in chunks of kXK rows, the next chunk
-// prefetched into registers meanwhile.
+// v_mfma_f64_4x4x4f64 on gfx950 (four blocks per instruction): lane l supplies
+// A_b(l%4, l/16) and B_b(l/16, l%4) of block b = (l/4)%4 and receives
+// D_b(l/16, l%4).  With the four blocks side by side along the columns, one
+// instruction yields a 4x16 strip: A (4 rows x 4 deep) is shared by the four
+// blocks, B is the 4 x 16 slice, and lane l holds row l/16, column l%16.
+__device__ __forceinline__ double mfma4b(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+// The TMxTM block X(k0.., l0..) of one subgraph (columns k >= kend or l >= lend
+// read as zero) on the four-block 4x4x4 FP64 MFMA.  Wave w owns rows [w TM/4, (w+1) TM/4) and
+// all TM columns: TM/16 x TM/16 independent accumulators, lane l holding row
+// w TM/4 + 4 r + l/16, column 16 c + l%16 in acc[r][c].  The K dimension is
+// staged through LDS in chunks of kXK rows, stored [column][m] so that both the
+// staging writes (consecutive m) and the operand reads (16 columns x 4 m, or
+// 4 columns x 4 m broadcast) fall in distinct banks; h(m) is applied to the B
+// side while staging.
 template <int TM>
-__device__ __forceinline__ void xy_block_f64(const double* __restrict__ Q,
-                                             const double* __restrict__ hl, int n, int k0,
-                                             int l0, int kend, int lend,
-                                             v4d (&acc)[XyShape<TM>::kWB][XyShape<TM>::kWB]) {
-  using S = XyShape<TM>;
-  constexpr int WB = S::kWB;
-  __shared__ double As[kXK][TM + 1];
-  __shared__ double Bs[kXK][TM + 1];
-  __shared__ double hs[kXK];
+__device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
+                                            const double* __restrict__ hl, int n, int k0, int l0,
+                                            int kend, int lend, double (&acc)[TM / 16][TM / 16]) {
+  constexpr int kNT = 256, LD = kXK + 2, R4 = TM / 16, C16 = TM / 16;
+  constexpr int kPer = kXK * TM / kNT;
+  __shared__ double As[TM][LD];
+  __shared__ double Bs[TM][LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
-  double pa[S::kPer], pb[S::kPer], ph = 0.0;
+  const int lq = lane & 3, lr = lane >> 4, l15 = lane & 15;
+  const int mm_t = tid & (kXK - 1), c_t = tid / kXK;
+  double pa[kPer], pb[kPer];
+  // out-of-range elements load a clamped (valid) address; the zeroing and the
+  // h factor are applied when the registers are written to LDS, after the
+  // MFMAs of the current chunk, so the loads stay in flight across them
+  double ph = 0.0;
   auto fetch = [&](int m0) {
+    const int mc = min(m0 + mm_t, n - 1);
+    ph = hl[mc];
 #pragma unroll
-    for (int u = 0; u < S::kPer; ++u) {
-      const int idx = tid + u * S::kNT;
-      const int mm = idx % kXK, kk = idx / kXK;
-      const int m = m0 + mm;
-      const bool okm = m < n;
-      pa[u] = (okm && k0 + kk < kend) ? Q[m + (size_t)n * (k0 + kk)] : 0.0;
-      pb[u] = (okm && l0 + kk < lend) ? Q[m + (size_t)n * (l0 + kk)] : 0.0;
+    for (int u = 0; u < kPer; ++u) {
+      const int c = c_t + u * (kNT / kXK);
+      pa[u] = Q[mc + (size_t)n * min(k0 + c, n - 1)];
+      pb[u] = Q[mc + (size_t)n * min(l0 + c, n - 1)];
     }
-    if (tid < kXK) ph = (m0 + tid < n) ? hl[m0 + tid] : 0.0;
   };
 #pragma unroll
-  for (int x = 0; x < WB; ++x)
+  for (int r = 0; r < R4; ++r)
 #pragma unroll
-    for (int y = 0; y < WB; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < C16; ++c) acc[r][c] = 0.0;
   fetch(0);
   for (int m0 = 0; m0 < n; m0 += kXK) {
     __syncthreads();
+    const bool okm = m0 + mm_t < n;
 #pragma unroll
-    for (int u = 0; u < S::kPer; ++u) {
-      const int idx = tid + u * S::kNT;
-      As[idx % kXK][idx / kXK] = pa[u];
-      Bs[idx % kXK][idx / kXK] = pb[u];
+    for (int u = 0; u < kPer; ++u) {
+      const int c = c_t + u * (kNT / kXK);
+      As[c][mm_t] = (okm && k0 + c < kend) ? pa[u] : 0.0;
+      Bs[c][mm_t] = (okm && l0 + c < lend) ? ph * pb[u] : 0.0;
     }
-    if (tid < kXK) hs[tid] = ph;
     __syncthreads();
     if (m0 + kXK < n) fetch(m0 + kXK);
 #pragma unroll
     for (int ks = 0; ks < kXK / 4; ++ks) {
-      const int row = 4 * ks + lk;
-      const double hr = hs[row];
-      double a[WB], bb[WB];
+      const int mm = 4 * ks + lr;
+      double a[R4], bb[C16];
 #pragma unroll
-      for (int x = 0; x < WB; ++x) {
-        a[x] = As[row][wr + 16 * x + li];
-        bb[x] = hr * Bs[row][wc + 16 * x + li];
-      }
+      for (int r = 0; r < R4; ++r) a[r] = As[w * (TM / 4) + 4 * r + lq][mm];
 #pragma unroll
-      for (int x = 0; x < WB; ++x)
+      for (int c = 0; c < C16; ++c) bb[c] = Bs[16 * c + l15][mm];
 #pragma unroll
-        for (int y = 0; y < WB; ++y) acc[x][y] = mfma16(a[x], bb[y], acc[x][y]);
+      for (int r = 0; r < R4; ++r)
+#pragma unroll
+        for (int c = 0; c < C16; ++c) acc[r][c] = mfma4b(a[r], bb[c], acc[r][c]);
     }
   }
 }
@@ -150,17 +161,18 @@ __device__ __forceinline__ void xy_block_f32(
   const int li = lane & 15, lk = lane >> 4;
   const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
   float pa[S::kPer], pb[S::kPer], ph = 0.f;
+  // clamped (valid) addresses; zeroing is applied at the LDS write, after the
+  // current chunk's MFMAs, so the loads stay in flight across them
   auto fetch = [&](int m0) {
 #pragma unroll
     for (int u = 0; u < S::kPer; ++u) {
       const int idx = tid + u * S::kNT;
       const int mm = idx % kXK, kk = idx / kXK;
-      const int m = m0 + mm;
-      const bool okm = m < n;
-      pa[u] = (okm && k0 + kk < n) ? Q[m + (size_t)n * (k0 + kk)] : 0.f;
-      pb[u] = (okm && l0 + kk < n) ? Q[m + (size_t)n * (l0 + kk)] : 0.f;
+      const int mc = min(m0 + mm, n - 1);
+      pa[u] = Q[mc + (size_t)n * min(k0 + kk, n - 1)];
+      pb[u] = Q[mc + (size_t)n * min(l0 + kk, n - 1)];
     }
-    if (tid < kXK) ph = (m0 + tid < n) ? (float)hl[m0 + tid] : 0.f;
+    ph = (float)hl[min(m0 + (tid & (kXK - 1)), n - 1)];
   };
 #pragma unroll
   for (int x = 0; x < WB; ++x)
@@ -174,10 +186,12 @@ __device__ __forceinline__ void xy_block_f32(
 #pragma unroll
     for (int u = 0; u < S::kPer; ++u) {
       const int idx = tid + u * S::kNT;
-      As[idx % kXK][idx / kXK] = pa[u];
-      Bs[idx % kXK][idx / kXK] = pb[u];
+      const int mm = idx % kXK, kk = idx / kXK;
+      const bool okm = m0 + mm < n;
+      As[mm][kk] = (okm && k0 + kk < n) ? pa[u] : 0.f;
+      Bs[mm][kk] = (okm && l0 + kk < n) ? pb[u] : 0.f;
     }
-    if (tid < kXK) hs[tid] = ph;
+    if (tid < kXK) hs[tid] = (m0 + tid < n) ? ph : 0.f;
     __syncthreads();
     if (m0 + kXK < n) fetch(m0 + kXK);
     v4f c[WB][WB];
@@ -238,6 +252,18 @@ __global__ __launch_bounds__(256, 3) void k_xy(
     if constexpr (SPLIT) {
       double acc[WB][WB][4];
       xy_block_f32<TM>(q32 + off2[s], hl, n, k0, l0, acc);
+      // all dF loads first (clamped addresses), then the stores
+      double dfv[WB][WB][4];
+#pragma unroll
+      for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = min(k0 + wr + 16 * x + 4 * lk + r, n - 1);
+            const int l = min(l0 + wc + 16 * y + li, n - 1);
+            dfv[x][y][r] = dF[(size_t)l + (size_t)n * k];
+          }
 #pragma unroll
       for (int x = 0; x < WB; ++x)
 #pragma unroll
@@ -246,27 +272,28 @@ __global__ __launch_bounds__(256, 3) void k_xy(
           for (int r = 0; r < 4; ++r) {
             const int k = k0 + wr + 16 * x + 4 * lk + r;
             const int l = l0 + wc + 16 * y + li;
-            if (k < n && l < n) {
-              const size_t at = (size_t)l + (size_t)n * k;
-              Y[at] = acc[x][y][r] * dF[at];
-            }
+            if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[x][y][r] * dfv[x][y][r];
           }
     } else {
-      v4d acc[WB][WB];
-      xy_block_f64<TM>(qbuf + off2[s], hl, n, k0, l0, n, n, acc);
+      double acc[TM / 16][TM / 16];
+      xy_block_4b<TM>(qbuf + off2[s], hl, n, k0, l0, n, n, acc);
+      double dfv[TM / 16][TM / 16];
 #pragma unroll
-      for (int x = 0; x < WB; ++x)
+      for (int r = 0; r < TM / 16; ++r)
 #pragma unroll
-        for (int y = 0; y < WB; ++y)
+        for (int c = 0; c < TM / 16; ++c) {
+          const int k = min(k0 + w * (TM / 4) + 4 * r + (lane >> 4), n - 1);
+          const int l = min(l0 + 16 * c + (lane & 15), n - 1);
+          dfv[r][c] = dF[(size_t)l + (size_t)n * k];
+        }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int k = k0 + wr + 16 * x + lk + 4 * r;
-            const int l = l0 + wc + 16 * y + li;
-            if (k < n && l < n) {
-              const size_t at = (size_t)l + (size_t)n * k;
-              Y[at] = acc[x][y][r] * dF[at];
-            }
-          }
+      for (int r = 0; r < TM / 16; ++r)
+#pragma unroll
+        for (int c = 0; c < TM / 16; ++c) {
+          const int k = k0 + w * (TM / 4) + 4 * r + (lane >> 4);
+          const int l = l0 + 16 * c + (lane & 15);
+          if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[r][c] * dfv[r][c];
+        }
     }
   }
 }
@@ -279,8 +306,12 @@ __global__ __launch_bounds__(kThreads) void k_split32(const double* __restrict__
     q32[i] = (float)q[i];
 }
 
-// Window half-width, in units of kT, of the FP64 refinement.
+// The FP64 refinement window: the states with |eps - mu| <= kWinKT kT, at most
+// kWinMax of them (the ones nearest mu).  The cap is wide enough that a dense
+// or degenerate level next to mu is not cut in two: pairs inside such a level
+// carry dF = f'(eps), up to beta/4, and must not be left in FP32.
 constexpr double kWinKT = 8.0;
+constexpr int kWinMax = 128;
 
 // first index i in [0, n) with v[i] >= x (n if none)
 __device__ __forceinline__ int lower_index(const double* v, int n, double x) {
@@ -295,15 +326,16 @@ __device__ __forceinline__ int lower_index(const double* v, int n, double x) {
 
 // FP64 refinement of the thermal window: the dF weights are largest, up to
 // beta/4, between states within a few kT of mu, and there the FP32 rounding of
-// X would be amplified most.  One workgroup per (subgraph, perturbation)
-// recomputes the block of X over the states with |eps - mu| <= kWinKT kT (at
-// most 64, the ones nearest mu) on FP64 MFMA and overwrites those entries of Y.
+// X would be amplified most.  Workgroup (subgraph, perturbation, z) recomputes
+// the 64x64 sub-block z = 2 bi + bj of the window block X[lo..hi, lo..hi]
+// (hi - lo <= kWinMax) on FP64 MFMA and overwrites those entries of Y.
 __global__ __launch_bounds__(kThreads) void k_win(
     const double* __restrict__ qbuf, const double* __restrict__ dfbuf, double* __restrict__ ybuf,
     const double* __restrict__ hloc, const double* __restrict__ eps,
     const double* __restrict__ mu_state, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n) {
   const int s = blockIdx.x, q = blockIdx.y;
+  const int bi = blockIdx.z >> 1, bj = blockIdx.z & 1;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const double mu = mu_state[2], half = kWinKT * mu_state[3];
@@ -311,33 +343,30 @@ __global__ __launch_bounds__(kThreads) void k_win(
   int lo = lower_index(e, n, mu - half);
   int hi = lower_index(e, n, mu + half);
   while (hi < n && e[hi] <= mu + half) ++hi;
-  if (hi - lo > kTile) {
+  if (hi - lo > kWinMax) {
     const int mid = lower_index(e, n, mu);
-    lo = max(lo, min(mid - kTile / 2, hi - kTile));
-    hi = lo + kTile;
+    lo = max(lo, min(mid - kWinMax / 2, hi - kWinMax));
+    hi = lo + kWinMax;
   }
-  if (hi <= lo) return;
-  v4d acc[2][2];
-  xy_block_f64<kTile>(qbuf + off2[s], hloc + (size_t)q * sum_n + b, n, lo, lo, hi, hi, acc);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int k0 = lo + kTile * bi, l0 = lo + kTile * bj;
+  if (k0 >= hi || l0 >= hi) return;
+  double acc[kTile / 16][kTile / 16];
+  xy_block_4b<kTile>(qbuf + off2[s], hloc + (size_t)q * sum_n + b, n, k0, l0, hi, hi, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* dF = dfbuf + off2[s];
   double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int r = 0; r < kTile / 16; ++r)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = lo + wr + 16 * x + lk + 4 * r;
-        const int l = lo + wc + 16 * y + li;
-        // each stored position is written by the one (k, l) that owns it
-        if (k < hi && l < hi && k / kTile >= l / kTile) {
-          const size_t at = (size_t)l + (size_t)n * k;
-          Y[at] = acc[x][y][r] * dF[at];
-        }
+    for (int c = 0; c < kTile / 16; ++c) {
+      const int k = k0 + w * (kTile / 4) + 4 * r + (lane >> 4);
+      const int l = l0 + 16 * c + (lane & 15);
+      // each stored position is written by the one (k, l) that owns it
+      if (k < hi && l < hi && k / kTile >= l / kTile) {
+        const size_t at = (size_t)l + (size_t)n * k;
+        Y[at] = acc[r][c] * dF[at];
       }
+    }
 }
 
 // h1 restricted to every subgraph, in subgraph order, for K perturbations:
@@ -469,13 +498,20 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
     double* __restrict__ pdiag, const int64_t* __restrict__ off2, const int64_t* __restrict__ offc,
     const int32_t* __restrict__ offcd, const int32_t* __restrict__ sub_orb_ptr,
     const int32_t* __restrict__ n_core, const int32_t* __restrict__ order, int64_t sum_n,
-    int64_t nnz, int sum_c) {
-  const int s = order[blockIdx.x];
-  const int q = blockIdx.z;
+    int64_t nnz, int sum_c, int n_sub, int ncb, int K) {
+  // group g = (subgraph in order, column block) holds the K perturbations that
+  // read the same 128 rows of Q.  Groups go round-robin to the XCDs (workgroup
+  // b runs on XCD b mod 8), and on each XCD a group's K workgroups are
+  // consecutive, so they run together and share those rows through its L2.
+  const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+  const int g = (j / K) * 8 + x;
+  const int q = j % K;
+  if (g >= n_sub * ncb) return;
+  const int s = order[g / ncb];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
-  const int L0 = blockIdx.y * kTC;
+  const int L0 = (g % ncb) * kTC;
   if (L0 >= n) return;
   const double* Q = qbuf + off2[s];
   const double* Tq = tbuf + (size_t)q * sum_n * 32;
@@ -719,7 +755,7 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h
   prof_end(ctx);
   if (split) {
     prof_begin(ctx, "k_win");
-    hipLaunchKernelGGL(k_win, dim3(g->n_sub, K), dim3(kThreads), 0, st, e->Q, e->A, e->Y, e->hloc,
+    hipLaunchKernelGGL(k_win, dim3(g->n_sub, K, 4), dim3(kThreads), 0, st, e->Q, e->A, e->Y, e->hloc,
                        e->eps, e->mu_state, dv.off2, dv.sub_orb_ptr, sum_n2, sum_n);
     prof_end(ctx);
   }
@@ -727,9 +763,11 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h
   dim3 grid_cols(g->n_sub, (g->info.max_n + kTC - 1) / kTC, K);
   hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, e->Y, e->T, dv.off2,
                      dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
-  hipLaunchKernelGGL(k_p_mfma, grid_cols, dim3(kThreads), 0, st, e->T, e->Q, p_blocks, e->pdiag,
-                     dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core, dv.order, sum_n, nnz,
-                     sum_c);
+  const int ncb = (g->info.max_n + kTC - 1) / kTC;
+  const int groups_per_xcd = (g->n_sub * ncb + 7) / 8;
+  hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, e->T, e->Q,
+                     p_blocks, e->pdiag, dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core,
+                     dv.order, sum_n, nnz, sum_c, g->n_sub, ncb, K);
   prof_end(ctx);
   prof_begin(ctx, "k_mu1_combine");
   hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, e->pdiag, sum_c, e->tmu, g->n_sub,
