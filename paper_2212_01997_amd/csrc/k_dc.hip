@@ -30,11 +30,17 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kTile = 64;
-constexpr int kKc = 16;
 constexpr int kNb = 16;   // reflectors per compact-WY block
 // row stride of the staged reflector block: 17 doubles keep both the 16-row
 // reads of the update and the 16-column reads of V^T Z in distinct LDS banks
 constexpr int kLdv = kNb + 1;
+
+// v_mfma_f64_4x4x4f64 (four blocks): lane l supplies A_b(l%4, l/16) and
+// B_b(l/16, l%4) of block b = (l/4)%4 and receives D_b(l/16, l%4); with the
+// blocks side by side along the columns one instruction yields a 4x16 strip.
+__device__ __forceinline__ double mfma4b(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -524,8 +530,9 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
     const int32_t* __restrict__ md_dpos, const double* __restrict__ md_delta,
     const double* __restrict__ md_tau, const double* __restrict__ md_zhat,
     const double* __restrict__ md_inv) {
-  __shared__ double As[kKc][kTile + 1];
-  __shared__ double Bs[kKc][kTile + 1];
+  constexpr int kKg = 32;  // K chunk of the product
+  __shared__ double As[kKg][kTile + 1];
+  __shared__ double Bs[kKg][kTile + 1];
   __shared__ double cdo[kTile], ctau[kTile], cinv[kTile];
   const int mid = tiles[3 * blockIdx.x], tr = tiles[3 * blockIdx.x + 1], tc = tiles[3 * blockIdx.x + 2];
   const int s = merges[4 * mid], lo = merges[4 * mid + 1];
@@ -537,7 +544,6 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
   const double* Z = zbuf + off2[s];
   double* W = wbuf + off2[s];
   const int r0 = tr * kTile, c0 = tc * kTile;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   if (threadIdx.x < kTile) {
     const int c = c0 + threadIdx.x;
     if (c < k) {
@@ -550,48 +556,68 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
       cinv[threadIdx.x] = 0.0;
     }
   }
+  // On the four-block 4x4x4 MFMA as the transposed product D = U^T Z^T: wave w
+  // owns D rows (columns of W) 16w .. 16w+15 as four blocks of 4, and all 64 D
+  // columns (rows of W) as four strips of 16; lane l holds W row
+  // r0 + 16 s + l%16, W column c0 + 16 w + 4 b + l/16 in acc[b][s].
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lq = lane & 3, lr = lane >> 4, l15 = lane & 15;
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // the next chunk's gathered Z values and the roots' zhat, delta are loaded
+  // (clamped, branch-free) while the current chunk's MFMAs run; U is formed
+  // when they are written to LDS
+  constexpr int kPf = kKg * kTile / kThreads;
+  double pz[kPf], pzh[kPf], pdl[kPf];
+  auto fetch = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+      const int idx = threadIdx.x + u * kThreads;
+      const int i = min(i0 + idx / kTile, k - 1), r = min(r0 + idx % kTile, m - 1);
+      pz[u] = Z[(lo + r) + (size_t)n * (lo + md_cols[base + i])];
+      pzh[u] = md_zhat[base + i];
+      pdl[u] = md_delta[base + i];
+    }
+  };
   if (c0 < k) {
-    for (int i0 = 0; i0 < k; i0 += kKc) {
+    fetch(0);
+    for (int i0 = 0; i0 < k; i0 += kKg) {
       __syncthreads();
-      for (int idx = threadIdx.x; idx < kKc * kTile; idx += kThreads) {
+#pragma unroll
+      for (int u = 0; u < kPf; ++u) {
+        const int idx = threadIdx.x + u * kThreads;
         const int rr = idx % kTile, ii = idx / kTile;
-        const int r = r0 + rr, i = i0 + ii;
-        As[ii][rr] = (r < m && i < k) ? Z[(lo + r) + (size_t)n * (lo + md_cols[base + i])] : 0.0;
-      }
-      for (int idx = threadIdx.x; idx < kKc * kTile; idx += kThreads) {
-        const int cc = idx % kTile, ii = idx / kTile;
-        const int c = c0 + cc, i = i0 + ii;
-        double u = 0.0;
-        if (c < k && i < k) u = md_zhat[base + i] * cinv[cc] / ((md_delta[base + i] - cdo[cc]) - ctau[cc]);
-        Bs[ii][cc] = u;
+        const bool iok = i0 + ii < k;
+        As[ii][rr] = (iok && r0 + rr < m) ? pz[u] : 0.0;
+        Bs[ii][rr] = (iok && c0 + rr < k) ? pzh[u] * cinv[rr] / ((pdl[u] - cdo[rr]) - ctau[rr]) : 0.0;
       }
       __syncthreads();
-#pragma unroll 4
-      for (int ii = 0; ii < kKc; ++ii) {
+      if (i0 + kKg < k) fetch(i0 + kKg);
+#pragma unroll
+      for (int ks = 0; ks < kKg / 4; ++ks) {
+        const int kk = 4 * ks + lr;
         double a[4], bv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = As[ii][tx + 16 * q];
+        for (int q = 0; q < 4; ++q) a[q] = Bs[kk][16 * w + 4 * q + lq];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bv[q] = Bs[ii][ty + 16 * q];
+        for (int q = 0; q < 4; ++q) bv[q] = As[kk][16 * q + l15];
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * bv[q];
+          for (int q = 0; q < 4; ++q) acc[p][q] = mfma4b(a[p], bv[q], acc[p][q]);
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = c0 + ty + 16 * q;
+  for (int p = 0; p < 4; ++p) {
+    const int c = c0 + 16 * w + 4 * p + lr;
     if (c >= m) continue;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int r = r0 + tx + 16 * p;
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + 16 * q + l15;
       if (r >= m) continue;
       if (c < k) {
         W[(lo + r) + (size_t)n * (lo + md_pos[base + c])] = acc[p][q];

@@ -59,7 +59,7 @@ __device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int kXK = 32;  // K chunk of the X tiles
+constexpr int kXK = 32;  // K chunk of the FP32 X tiles
 
 // FP32 tiles: four waves in a 2x2 arrangement; each wave owns a (TM/2)x(TM/2)
 // quarter of the tile, made of WB x WB 16x16 MFMA blocks.
@@ -83,18 +83,20 @@ __device__ __forceinline__ double mfma4b(double a, double b, double c) {
 // read as zero) on the four-block 4x4x4 FP64 MFMA.  Wave w owns rows [w TM/4, (w+1) TM/4) and
 // all TM columns: TM/16 x TM/16 independent accumulators, lane l holding row
 // w TM/4 + 4 r + l/16, column 16 c + l%16 in acc[r][c].  The K dimension is
-// staged through LDS in chunks of kXK rows, stored [column][m] so that both the
-// staging writes (consecutive m) and the operand reads (16 columns x 4 m, or
-// 4 columns x 4 m broadcast) fall in distinct banks; h(m) is applied to the B
-// side while staging.
+// staged through LDS in chunks of kXK rows, stored [m][column] with a row
+// stride of TM + 1 doubles: each group of 16 lanes then touches 16 distinct
+// 8-byte bank pairs in the staging writes (16 consecutive m) and in the B reads
+// (16 consecutive columns), and 4 broadcast addresses in the A reads.  h(m) is
+// applied to the B side while staging.
 template <int TM>
 __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
                                             const double* __restrict__ hl, int n, int k0, int l0,
                                             int kend, int lend, double (&acc)[TM / 16][TM / 16]) {
-  constexpr int kNT = 256, LD = kXK + 2, R4 = TM / 16, C16 = TM / 16;
+  constexpr int kXK = 16;  // FP64 K chunk: 16 rows keep four workgroups per CU
+  constexpr int kNT = 256, LD = TM + 1, R4 = TM / 16, C16 = TM / 16;
   constexpr int kPer = kXK * TM / kNT;
-  __shared__ double As[TM][LD];
-  __shared__ double Bs[TM][LD];
+  __shared__ double As[kXK][LD];
+  __shared__ double Bs[kXK][LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lq = lane & 3, lr = lane >> 4, l15 = lane & 15;
   const int mm_t = tid & (kXK - 1), c_t = tid / kXK;
@@ -124,8 +126,8 @@ __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int c = c_t + u * (kNT / kXK);
-      As[c][mm_t] = (okm && k0 + c < kend) ? pa[u] : 0.0;
-      Bs[c][mm_t] = (okm && l0 + c < lend) ? ph * pb[u] : 0.0;
+      As[mm_t][c] = (okm && k0 + c < kend) ? pa[u] : 0.0;
+      Bs[mm_t][c] = (okm && l0 + c < lend) ? ph * pb[u] : 0.0;
     }
     __syncthreads();
     if (m0 + kXK < n) fetch(m0 + kXK);
@@ -134,9 +136,9 @@ __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
       const int mm = 4 * ks + lr;
       double a[R4], bb[C16];
 #pragma unroll
-      for (int r = 0; r < R4; ++r) a[r] = As[w * (TM / 4) + 4 * r + lq][mm];
+      for (int r = 0; r < R4; ++r) a[r] = As[mm][w * (TM / 4) + 4 * r + lq];
 #pragma unroll
-      for (int c = 0; c < C16; ++c) bb[c] = Bs[16 * c + l15][mm];
+      for (int c = 0; c < C16; ++c) bb[c] = Bs[mm][16 * c + l15];
 #pragma unroll
       for (int r = 0; r < R4; ++r)
 #pragma unroll
@@ -230,7 +232,7 @@ __device__ __forceinline__ void xy_block_f32(
 // Workgroup b serves XCD b % 8 and walks that XCD's range of the list with
 // stride gridDim.x / 8 (one tile per workgroup, or persistent).
 template <int TM, bool SPLIT>
-__global__ __launch_bounds__(256, 3) void k_xy(
+__global__ __launch_bounds__(256, 4) void k_xy(
     const double* __restrict__ qbuf, const float* __restrict__ q32,
     const double* __restrict__ dfbuf, double* __restrict__ ybuf, const double* __restrict__ hloc,
     const int32_t* __restrict__ tiles, XcdSplit split, const int64_t* __restrict__ off2,
