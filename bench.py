@@ -177,6 +177,23 @@ def form_batched_and_mixed(ctx, side):
     out["plain"] = {"ground_state_ms": g_ms, "response_ms_K6": r_ms,
                     "response_solves_per_s": K * 1e3 / r_ms,
                     "step_ms": g_ms + r_ms, "step_solves_per_s": K * 1e3 / (g_ms + r_ms)}
+    # the congruence kernel at K = 6 (two perturbations per workgroup), timed
+    # with the library's hipEvent pairs on its own stream
+    ctx.set_profiling(True)
+    for _ in range(3):
+        path.respond(h1, want_mu1=False)
+    sync()
+    kt = ctx.kernel_times()
+    ctx.set_profiling(False)
+    if "k_xy" in kt:
+        n3 = np.diff(graph.export()["sub_orb_ptr"]).astype(float)
+        flops = K * float((n3 ** 3 + n3 ** 2).sum())
+        xy_ms = kt["k_xy"][1] / kt["k_xy"][0]
+        out["congruence_roofline_K6"] = {
+            "bound": "mfma", "kernel": "k_xy", "achieved": flops / (xy_ms * 1e-3) / 1e12,
+            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": flops / (xy_ms * 1e-3) / PEAK_FP64,
+            "algorithmic_flops_per_launch": flops, "launch_ms": xy_ms}
     # batched: autotuned bins + one captured graph per step
     report = path.eigs.autotune(gq.PREC_FP64)
     ctx.capture_begin()

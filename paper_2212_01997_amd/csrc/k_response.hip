@@ -14,9 +14,11 @@
 //              and the grid (one workgroup per tile or a persistent grid) are
 //              chosen by gq_autotune.  Tiles of one subgraph stay on
 //              one XCD, whose L2 then serves their shared columns of Q.
-//              FP64 MFMA, or in the split-FP32 variant the FP32 leading part
-//              of Q on FP32 MFMA (FP32 sums within 32-deep chunks, FP64
-//              across them) followed by
+//              FP64 on the four-block 4x4x4 MFMA, or in the split-FP32
+//              variant the FP32 leading part of Q on FP32 MFMA (FP32 sums
+//              within 32-deep chunks, FP64 across them); k_xy_kq takes two
+//              perturbations per workgroup, sharing the staged columns of Q,
+//              when K > 1.  The split variant is followed by
 //   k_win      one FP64 correction of the thermal-window block, where dF
 //              amplifies rounding most
 //   k_t_mfma   T = Q_c Y;  k_p_mfma  P = 2 T Q^T (c x n core rows) and diag(P)
@@ -60,6 +62,7 @@ __device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
 }
 
 constexpr int kXK = 32;  // K chunk of the FP32 X tiles
+constexpr int kXyKq = 2;  // FP64 perturbations per workgroup when K > 1
 
 // FP32 tiles: four waves in a 2x2 arrangement; each wave owns a (TM/2)x(TM/2)
 // quarter of the tile, made of WB x WB 16x16 MFMA blocks.
@@ -147,6 +150,78 @@ __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
   }
 }
 
+// The same TMxTM block for nq <= KQ perturbations at once: the Q columns are
+// staged once, and each perturbation's h(m) multiplies the B operand in
+// registers (the same double product h(m) Q(m, l) as in xy_block_4b, so each
+// perturbation's block is bit for bit what xy_block_4b gives).
+template <int TM, int KQ>
+__device__ __forceinline__ void xy_block_4b_kq(const double* __restrict__ Q,
+                                               const double* __restrict__ hl, int64_t hstride,
+                                               int nq, int n, int k0, int l0,
+                                               double (&acc)[KQ][TM / 16][TM / 16]) {
+  constexpr int kXK = 16;
+  constexpr int kNT = 256, LD = TM + 1, R4 = TM / 16, C16 = TM / 16;
+  constexpr int kPer = kXK * TM / kNT;
+  __shared__ double As[kXK][LD];
+  __shared__ double Bs[kXK][LD];
+  __shared__ double hs[KQ][kXK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lq = lane & 3, lr = lane >> 4, l15 = lane & 15;
+  const int mm_t = tid & (kXK - 1), c_t = tid / kXK;
+  const int hq_t = min(c_t, nq - 1);  // perturbation whose h this thread stages (c_t < KQ)
+  double pa[kPer], pb[kPer], ph = 0.0;
+  auto fetch = [&](int m0) {
+    const int mc = min(m0 + mm_t, n - 1);
+    ph = hl[(int64_t)hq_t * hstride + mc];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int c = c_t + u * (kNT / kXK);
+      pa[u] = Q[mc + (size_t)n * min(k0 + c, n - 1)];
+      pb[u] = Q[mc + (size_t)n * min(l0 + c, n - 1)];
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+#pragma unroll
+    for (int r = 0; r < R4; ++r)
+#pragma unroll
+      for (int c = 0; c < C16; ++c) acc[q][r][c] = 0.0;
+  fetch(0);
+  for (int m0 = 0; m0 < n; m0 += kXK) {
+    __syncthreads();
+    const bool okm = m0 + mm_t < n;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int c = c_t + u * (kNT / kXK);
+      As[mm_t][c] = (okm && k0 + c < n) ? pa[u] : 0.0;
+      Bs[mm_t][c] = (okm && l0 + c < n) ? pb[u] : 0.0;
+    }
+    if (c_t < KQ) hs[c_t][mm_t] = ph;
+    __syncthreads();
+    if (m0 + kXK < n) fetch(m0 + kXK);
+#pragma unroll
+    for (int ks = 0; ks < kXK / 4; ++ks) {
+      const int mm = 4 * ks + lr;
+      double a[R4], braw[C16];
+#pragma unroll
+      for (int r = 0; r < R4; ++r) a[r] = As[mm][w * (TM / 4) + 4 * r + lq];
+#pragma unroll
+      for (int c = 0; c < C16; ++c) braw[c] = Bs[mm][16 * c + l15];
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const double h = hs[q][mm];
+        double bb[C16];
+#pragma unroll
+        for (int c = 0; c < C16; ++c) bb[c] = h * braw[c];
+#pragma unroll
+        for (int r = 0; r < R4; ++r)
+#pragma unroll
+          for (int c = 0; c < C16; ++c) acc[q][r][c] = mfma4b(a[r], bb[c], acc[q][r][c]);
+      }
+    }
+  }
+}
+
 // The same block from the FP32 leading parts: each kXK-deep chunk is summed by
 // FP32 MFMA in FP32 and the chunk sums are added in FP64.  acc[x][y][r] holds
 // row 4*(lane/16) + r of the 16x16 block (x, y).
@@ -225,6 +300,95 @@ __device__ __forceinline__ void xy_block_f32(
   }
 }
 
+// The FP32 block for nq <= KQ perturbations at once: the FP32 columns of Q are
+// staged once and each perturbation's h(m) multiplies the B operand in FP32
+// registers, as xy_block_f32 does for one (same products, same sums).
+template <int TM, int KQ>
+__device__ __forceinline__ void xy_block_f32_kq(
+    const float* __restrict__ Q, const double* __restrict__ hl, int64_t hstride, int nq, int n,
+    int k0, int l0, double (&acc)[KQ][XyShape<TM>::kWB][XyShape<TM>::kWB][4]) {
+  using S = XyShape<TM>;
+  constexpr int WB = S::kWB;
+  __shared__ float As[kXK][TM + 1];
+  __shared__ float Bs[kXK][TM + 1];
+  __shared__ float hs[KQ][kXK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+  const int hq_t = min(tid / kXK, nq - 1);  // perturbation whose h this thread stages
+  float pa[S::kPer], pb[S::kPer], ph = 0.f;
+  auto fetch = [&](int m0) {
+#pragma unroll
+    for (int u = 0; u < S::kPer; ++u) {
+      const int idx = tid + u * S::kNT;
+      const int mm = idx % kXK, kk = idx / kXK;
+      const int mc = min(m0 + mm, n - 1);
+      pa[u] = Q[mc + (size_t)n * min(k0 + kk, n - 1)];
+      pb[u] = Q[mc + (size_t)n * min(l0 + kk, n - 1)];
+    }
+    ph = (float)hl[(int64_t)hq_t * hstride + min(m0 + (tid & (kXK - 1)), n - 1)];
+  };
+#pragma unroll
+  for (int q = 0; q < KQ; ++q)
+#pragma unroll
+    for (int x = 0; x < WB; ++x)
+#pragma unroll
+      for (int y = 0; y < WB; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[q][x][y][r] = 0.0;
+  fetch(0);
+  for (int m0 = 0; m0 < n; m0 += kXK) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < S::kPer; ++u) {
+      const int idx = tid + u * S::kNT;
+      const int mm = idx % kXK, kk = idx / kXK;
+      const bool okm = m0 + mm < n;
+      As[mm][kk] = (okm && k0 + kk < n) ? pa[u] : 0.f;
+      Bs[mm][kk] = (okm && l0 + kk < n) ? pb[u] : 0.f;
+    }
+    if (tid < KQ * kXK) hs[tid / kXK][tid & (kXK - 1)] = (m0 + (tid & (kXK - 1)) < n) ? ph : 0.f;
+    __syncthreads();
+    if (m0 + kXK < n) fetch(m0 + kXK);
+    v4f c[KQ][WB][WB];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q)
+#pragma unroll
+      for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y) c[q][x][y] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kXK / 4; ++ks) {
+      const int row = 4 * ks + lk;
+      float a[WB], braw[WB];
+#pragma unroll
+      for (int x = 0; x < WB; ++x) {
+        a[x] = As[row][wr + 16 * x + li];
+        braw[x] = Bs[row][wc + 16 * x + li];
+      }
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const float hr = hs[q][row];
+        float bb[WB];
+#pragma unroll
+        for (int x = 0; x < WB; ++x) bb[x] = hr * braw[x];
+#pragma unroll
+        for (int x = 0; x < WB; ++x)
+#pragma unroll
+          for (int y = 0; y < WB; ++y) c[q][x][y] = mfma16f(a[x], bb[y], c[q][x][y]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KQ; ++q)
+#pragma unroll
+      for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[q][x][y][r] += (double)c[q][x][y][r];
+  }
+}
+
 // Y = X o dF on the tiles of one size bin.  A computed value y(k, l) is stored
 // at Y[l + n k] (row l, column k): the tile lists hold only tiles whose 64x64
 // parent is on or below the diagonal, so every value of the symmetric Y sits at
@@ -296,6 +460,85 @@ __global__ __launch_bounds__(256, 4) void k_xy(
           const int l = l0 + 16 * c + (lane & 15);
           if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[r][c] * dfv[r][c];
         }
+    }
+  }
+}
+
+// Y tiles for KQ perturbations per workgroup (grid.y = ceil(K / KQ)), FP64 or
+// split-FP32.
+template <int TM, int KQ, bool SPLIT>
+__global__ __launch_bounds__(256, 3) void k_xy_kq(
+    const double* __restrict__ qbuf, const float* __restrict__ q32,
+    const double* __restrict__ dfbuf, double* __restrict__ ybuf, const double* __restrict__ hloc,
+    const int32_t* __restrict__ tiles, XcdSplit split, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n, int K) {
+  const int q0 = blockIdx.y * KQ, nq = min(KQ, K - q0);
+  const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int t = split.off[xcd] + (int)(blockIdx.x >> 3); t < split.off[xcd + 1]; t += stride) {
+    const int s = tiles[3 * t], ti = tiles[3 * t + 1], tj = tiles[3 * t + 2];
+    const int b = sub_orb_ptr[s];
+    const int n = sub_orb_ptr[s + 1] - b;
+    const int k0 = ti * TM, l0 = tj * TM;
+    const double* dF = dfbuf + off2[s];
+    const double* hl = hloc + (size_t)q0 * sum_n + b;
+    if constexpr (SPLIT) {
+      constexpr int WB = XyShape<TM>::kWB;
+      const int li = lane & 15, lk = lane >> 4;
+      const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+      double acc[KQ][WB][WB][4];
+      xy_block_f32_kq<TM, KQ>(q32 + off2[s], hl, sum_n, nq, n, k0, l0, acc);
+      double dfv[WB][WB][4];
+#pragma unroll
+      for (int x = 0; x < WB; ++x)
+#pragma unroll
+        for (int y = 0; y < WB; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = min(k0 + wr + 16 * x + 4 * lk + r, n - 1);
+            const int l = min(l0 + wc + 16 * y + li, n - 1);
+            dfv[x][y][r] = dF[(size_t)l + (size_t)n * k];
+          }
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        if (q >= nq) break;
+        double* Y = ybuf + (size_t)(q0 + q) * sum_n2 + off2[s];
+#pragma unroll
+        for (int x = 0; x < WB; ++x)
+#pragma unroll
+          for (int y = 0; y < WB; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int k = k0 + wr + 16 * x + 4 * lk + r;
+              const int l = l0 + wc + 16 * y + li;
+              if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[q][x][y][r] * dfv[x][y][r];
+            }
+      }
+    } else {
+      double acc[KQ][TM / 16][TM / 16];
+      xy_block_4b_kq<TM, KQ>(qbuf + off2[s], hl, sum_n, nq, n, k0, l0, acc);
+      double dfv[TM / 16][TM / 16];
+#pragma unroll
+      for (int r = 0; r < TM / 16; ++r)
+#pragma unroll
+        for (int c = 0; c < TM / 16; ++c) {
+          const int k = min(k0 + w * (TM / 4) + 4 * r + (lane >> 4), n - 1);
+          const int l = min(l0 + 16 * c + (lane & 15), n - 1);
+          dfv[r][c] = dF[(size_t)l + (size_t)n * k];
+        }
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        if (q >= nq) break;
+        double* Y = ybuf + (size_t)(q0 + q) * sum_n2 + off2[s];
+#pragma unroll
+        for (int r = 0; r < TM / 16; ++r)
+#pragma unroll
+          for (int c = 0; c < TM / 16; ++c) {
+            const int k = k0 + w * (TM / 4) + 4 * r + (lane >> 4);
+            const int l = l0 + 16 * c + (lane & 15);
+            if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[q][r][c] * dfv[r][c];
+          }
+      }
     }
   }
 }
@@ -634,23 +877,34 @@ __global__ __launch_bounds__(kThreads) void k_assemble(
 using XyKernel = void (*)(const double*, const float*, const double*, double*, const double*,
                           const int32_t*, XcdSplit, const int64_t*, const int32_t*, int64_t,
                           int64_t);
+using XyKqKernel = void (*)(const double*, const float*, const double*, double*, const double*,
+                            const int32_t*, XcdSplit, const int64_t*, const int32_t*, int64_t,
+                            int64_t, int);
 
 XyKernel xy_kernel(int shape, bool split) {
   if (shape == 0) return split ? k_xy<64, true> : k_xy<64, false>;
   return split ? k_xy<32, true> : k_xy<32, false>;
 }
 
+XyKqKernel xy_kq_kernel(int shape, bool split) {
+  if (shape == 0) return split ? k_xy_kq<64, kXyKq, true> : k_xy_kq<64, kXyKq, false>;
+  return split ? k_xy_kq<32, kXyKq, true> : k_xy_kq<32, kXyKq, false>;
+}
+
 int xy_threads(int shape) { return shape == 0 ? XyShape<64>::kNT : XyShape<32>::kNT; }
 
-// Workgroups of one variant resident on one XCD (32 CUs) at a time.
-int xy_resident_per_xcd(int shape, bool split) {
-  static std::atomic<int> cache[2][2];
-  std::atomic<int>& c = cache[shape][split ? 1 : 0];
+// Workgroups of one variant (0: FP64, 1: split, 2 / 3: FP64 / split with kXyKq
+// perturbations per workgroup) resident on one XCD (32 CUs) at a time.
+int xy_resident_per_xcd(int shape, int variant) {
+  static std::atomic<int> cache[2][4];
+  std::atomic<int>& c = cache[shape][variant];
   int v = c.load(std::memory_order_relaxed);
   if (v == 0) {
+    const void* fn = variant >= 2 ? (const void*)xy_kq_kernel(shape, variant == 3)
+                                  : (const void*)xy_kernel(shape, variant == 1);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)xy_kernel(shape, split),
-                                                     xy_threads(shape), 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, xy_threads(shape), 0) !=
+            hipSuccess ||
         per_cu < 1) {
       (void)hipGetLastError();
       per_cu = 1;
@@ -662,17 +916,27 @@ int xy_resident_per_xcd(int shape, bool split) {
 }
 
 // Launch of one bin with variant `choice` (bit 0: 32x32 tiles, bit 1: persistent).
+// Launches with K > 1 take kXyKq perturbations per workgroup.
 void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int bin, int choice, bool split,
                    int K) {
   const int shape = choice & 1;
   const bool persistent = (choice & 2) != 0;
+  const bool kq = K > 1;
   const XcdSplit& sp = g->xy_split[shape][bin];
   int longest = 0;
   for (int x = 0; x < 8; ++x) longest = std::max(longest, sp.off[x + 1] - sp.off[x]);
   if (longest == 0) return;
   int per_xcd = longest;
-  if (persistent) per_xcd = std::min(longest, xy_resident_per_xcd(shape, split));
+  if (persistent)
+    per_xcd = std::min(longest, xy_resident_per_xcd(shape, (kq ? 2 : 0) + (split ? 1 : 0)));
   const gq_graph_dev& dv = g->dev;
+  if (kq) {
+    hipLaunchKernelGGL(xy_kq_kernel(shape, split), dim3(8 * per_xcd, (K + kXyKq - 1) / kXyKq),
+                       dim3(xy_threads(shape)), 0, ctx->stream, e->Q, e->Q32, e->A, e->Y, e->hloc,
+                       dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr, g->info.sum_n2,
+                       g->info.sum_n, K);
+    return;
+  }
   hipLaunchKernelGGL(xy_kernel(shape, split), dim3(8 * per_xcd, K), dim3(xy_threads(shape)), 0,
                      ctx->stream, e->Q, e->Q32, e->A, e->Y, e->hloc, dv.xy_tiles[shape], sp,
                      dv.off2, dv.sub_orb_ptr, g->info.sum_n2, g->info.sum_n);

@@ -137,3 +137,25 @@ def test_capture_replay(water60, precision):
         side.synchronize()
         assert not torch.equal(p.rho1_view(K), ref_rho1)
     del x
+
+
+def test_grouped_perturbations_equal_single(ctx, water60):
+    """K = 3 perturbations in one call (two per workgroup in the X kernel, the
+    last one alone) give, bit for bit, what three K = 1 calls give, on the FP64
+    and the split-FP32 path."""
+    import torch
+    s, core, prev, h1, r = water60
+    K = h1.shape[0]
+    assert K == 3
+    p = _path(ctx, s, core, prev, K)
+    p.ground_state(KT)
+    h1d = torch.as_tensor(h1, device="cuda")
+    for precision in (0, 1):
+        mu1_all = p.respond(h1d, precision=precision)
+        all_rho1 = p.rho1_view(K).cpu().numpy().copy()
+        for q in range(K):
+            mu1_q = p.respond(h1d[q:q + 1].contiguous(), precision=precision)
+            one = p.rho1_view(1).cpu().numpy()
+            _say(f"precision {precision} q {q}: mu1 {mu1_q[0]!r} vs {mu1_all[q]!r}")
+            assert np.array_equal(one[0], all_rho1[q]), (precision, q)
+            assert mu1_q[0] == mu1_all[q], (precision, q)
