@@ -764,13 +764,30 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
     const int r0 = 16 * rb0;
     const int nrows = 16 * nrb - r0;
     __syncthreads();
-    for (int idx = tid; idx < nrows * kNb; idx += kThreads) {
-      const int rr = idx % nrows, q = idx / nrows;
-      const int r = r0 + rr;
+    // stage the block: thread (q, rl) takes reflector q, rows r0 + rl + 16 i;
+    // eight loads from clamped (valid) addresses are issued before their
+    // stores, so they are in flight together
+    {
+      const int q = tid >> 4, rl = tid & 15;  // kThreads = 16 x 16
+      const int colq = kb + min(q, nb - 1);
       const int top = kb + q + 1;
-      double v = 0.0;
-      if (q < nb && r < n && r >= top) v = (r == top) ? 1.0 : A[r + (size_t)n * (kb + q)];
-      vb[r * kLdv + q] = v;
+      const int nr16 = nrows / 16;
+      for (int i0 = 0; i0 < nr16; i0 += 8) {
+        double vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = r0 + rl + 16 * min(i0 + u, nr16 - 1);
+          vv[u] = A[min(r, n - 1) + (size_t)n * colq];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = r0 + rl + 16 * (i0 + u);
+          if (i0 + u < nr16) {
+            const double v = (q < nb && r < n && r >= top) ? ((r == top) ? 1.0 : vv[u]) : 0.0;
+            vb[r * kLdv + q] = v;
+          }
+        }
+      }
     }
     if (tid < kNb * kNb) Ts[tid / kNb][tid % kNb] = tfac[(size_t)(toff[s] + kbi) * kNb * kNb + tid];
     __syncthreads();

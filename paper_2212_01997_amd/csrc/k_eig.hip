@@ -257,22 +257,33 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
         const int row0 = t0 + 16 * (tile / nt), col0 = t0 + 16 * (tile % nt);
         const int row = row0 + li;
         const bool rok = row < n;
-        v4d acc;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int col = col0 + 4 * r + lk;
-          acc[r] = (rok && col < n) ? A[row + (size_t)n * col] : 0.0;
-        }
         const int cl = col0 + li;
         const bool cok = cl < n;
+        // every operand of the tile is loaded from a clamped (valid) address
+        // first and zeroed where out of range afterwards, so the loads carry
+        // no branches and are in flight together
+        const int rowc = min(row, n - 1), clc = min(cl, n - 1);
+        double a4[4], wcv[kPanel / 4], vcv[kPanel / 4], vrv[kPanel / 4], wrv[kPanel / 4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a4[r] = A[rowc + (size_t)n * min(col0 + 4 * r + lk, n - 1)];
 #pragma unroll
         for (int kq = 0; kq < kPanel / 4; ++kq) {
-          const int q = 4 * kq + lk;
-          const bool qok = q < nb;
-          const double wc = (qok && cok) ? W[q * n + cl] : 0.0;
-          const double vc = (qok && cok) ? A[cl + (size_t)n * (k0 + q)] : 0.0;
-          const double vr = (qok && rok) ? A[row + (size_t)n * (k0 + q)] : 0.0;
-          const double wr = (qok && rok) ? W[q * n + row] : 0.0;
+          const int qc = min(4 * kq + lk, nb - 1);
+          wcv[kq] = W[qc * n + clc];
+          vcv[kq] = A[clc + (size_t)n * (k0 + qc)];
+          vrv[kq] = A[rowc + (size_t)n * (k0 + qc)];
+          wrv[kq] = W[qc * n + rowc];
+        }
+        v4d acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = (rok && col0 + 4 * r + lk < n) ? a4[r] : 0.0;
+#pragma unroll
+        for (int kq = 0; kq < kPanel / 4; ++kq) {
+          const bool qok = 4 * kq + lk < nb;
+          const double wc = (qok && cok) ? wcv[kq] : 0.0;
+          const double vc = (qok && cok) ? vcv[kq] : 0.0;
+          const double vr = (qok && rok) ? vrv[kq] : 0.0;
+          const double wr = (qok && rok) ? wrv[kq] : 0.0;
           acc = mfma16(-wc, vr, acc);
           acc = mfma16(-vc, wr, acc);
         }
