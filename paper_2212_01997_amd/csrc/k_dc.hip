@@ -611,6 +611,27 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
       }
     }
   }
+  // destination columns (and sources of deflated ones) of this lane's four
+  // columns, then every deflated value, all loaded from clamped (valid)
+  // entries before the guarded stores
+  int dst[4], src[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int c = c0 + 16 * w + 4 * p + lr;
+    const int ck = min(c, max(k - 1, 0));
+    const int dq = max(min(c - k, m - k - 1), 0);
+    const int pos = md_pos[base + ck], dpos = md_dpos[base + dq], dsrc = md_dsrc[base + dq];
+    dst[p] = c < k ? pos : dpos;
+    src[p] = min(max(dsrc, 0), m - 1);
+  }
+  double zc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = min(r0 + 16 * q + l15, m - 1);
+      zc[p][q] = Z[(lo + r) + (size_t)n * (lo + src[p])];
+    }
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     const int c = c0 + 16 * w + 4 * p + lr;
@@ -618,14 +639,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = r0 + 16 * q + l15;
-      if (r >= m) continue;
-      if (c < k) {
-        W[(lo + r) + (size_t)n * (lo + md_pos[base + c])] = acc[p][q];
-      } else {
-        const int dq = c - k;
-        W[(lo + r) + (size_t)n * (lo + md_dpos[base + dq])] =
-            Z[(lo + r) + (size_t)n * (lo + md_dsrc[base + dq])];
-      }
+      if (r < m) W[(lo + r) + (size_t)n * (lo + dst[p])] = c < k ? acc[p][q] : zc[p][q];
     }
   }
 }
@@ -640,9 +654,20 @@ __global__ __launch_bounds__(kThreads) void k_dc_copy(
   const int n = sub_orb_ptr[s + 1] - sub_orb_ptr[s];
   const double* W = wbuf + off2[s];
   double* Z = zbuf + off2[s];
-  for (int idx = threadIdx.x; idx < kTile * kTile; idx += kThreads) {
+  // all loads of the tile (clamped, valid addresses) before the guarded stores
+  constexpr int kPer = kTile * kTile / kThreads;
+  double v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + u * kThreads;
+    const int r = min(tr * kTile + idx % kTile, m - 1), c = min(tc * kTile + idx / kTile, m - 1);
+    v[u] = W[(lo + r) + (size_t)n * (lo + c)];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + u * kThreads;
     const int r = tr * kTile + idx % kTile, c = tc * kTile + idx / kTile;
-    if (r < m && c < m) Z[(lo + r) + (size_t)n * (lo + c)] = W[(lo + r) + (size_t)n * (lo + c)];
+    if (r < m && c < m) Z[(lo + r) + (size_t)n * (lo + c)] = v[u];
   }
 }
 
