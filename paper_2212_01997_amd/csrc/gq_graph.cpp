@@ -309,13 +309,16 @@ void build_dc_plan(gq_graph* g) {
   g->dc_level_merge_off.assign(1, 0);
   g->dc_level_tile_off.assign(1, 0);
   g->dc_level_maxm.clear();
+  g->dc_level_msum.clear();
   for (int d = (int)by_depth.size() - 1; d >= 0; --d) {
     const auto& v = by_depth[d];
     int32_t maxm = 0;
+    int64_t msum = 0;
     for (size_t q = 0; q < v.size(); q += 4) {
       const int32_t li = (int32_t)(q / 4);
       const int32_t m = v[q + 2] + v[q + 3];
       maxm = std::max(maxm, m);
+      msum += m;
       const int32_t nt = (m + 63) / 64;
       for (int32_t tr = 0; tr < nt; ++tr)
         for (int32_t tc = 0; tc < nt; ++tc) g->dc_tiles.insert(g->dc_tiles.end(), {li, tr, tc});
@@ -324,6 +327,7 @@ void build_dc_plan(gq_graph* g) {
     g->dc_level_merge_off.push_back((int32_t)(g->dc_merges.size() / 4));
     g->dc_level_tile_off.push_back((int32_t)(g->dc_tiles.size() / 3));
     g->dc_level_maxm.push_back(maxm);
+    g->dc_level_msum.push_back(msum);
   }
   g->bt_toff.assign(g->n_sub, 0);
   int32_t nb = 0;

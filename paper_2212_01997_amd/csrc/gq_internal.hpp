@@ -100,6 +100,7 @@ struct gq_graph {
   // divide-and-conquer plan of the tridiagonal eigensolves
   std::vector<int32_t> dc_leaves, dc_merges, dc_tiles;
   std::vector<int32_t> dc_level_merge_off, dc_level_tile_off, dc_level_maxm;
+  std::vector<int64_t> dc_level_msum;  // sum of the merge sizes of each level
   std::vector<int32_t> bt_toff;  // compact-WY block offsets (16 reflectors per block)
   int32_t bt_nblocks = 0;
   // response X tiles per shape (0: 64x64, 1: 32x32), binned by size, XCD ranges

@@ -48,6 +48,7 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+template <int NT>
 __device__ double block_sum(double x, double* red) {
   x = wave_sum(x);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -56,10 +57,11 @@ __device__ double block_sum(double x, double* red) {
   __syncthreads();
   double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < kThreads / 64; ++i) t += red[i];
+  for (int i = 0; i < NT / 64; ++i) t += red[i];
   return t;
 }
 
+template <int NT>
 __device__ double block_max(double x, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
@@ -69,7 +71,7 @@ __device__ double block_max(double x, double* red) {
   __syncthreads();
   double t = red[0];
 #pragma unroll
-  for (int i = 1; i < kThreads / 64; ++i) t = fmax(t, red[i]);
+  for (int i = 1; i < NT / 64; ++i) t = fmax(t, red[i]);
   return t;
 }
 
@@ -203,15 +205,25 @@ __device__ PrepLds carve(void* base, int m) {
 }
 
 // Root j of 1/rho + sum_i zeta_i^2 / (delta_i - lambda) = 0 for strictly
-// increasing delta.  Returns the origin pole index and the offset tau from it.
+// increasing delta, evaluated by the G lanes g = 0..G-1 of a wave that share j
+// (G a power of two, the group aligned to G): lane g sums the terms i = g,
+// g+G, ...  The partial sums are combined by xor butterflies, which leave the
+// same bits in every lane of the group, so the group takes the same branches
+// and returns the same root.  Returns the origin pole index and the offset tau
+// from it.
 __device__ void secular_root(const double* __restrict__ delta, const double* __restrict__ zeta,
-                             int k, double rho, int j, int& org, double& tau_out) {
+                             int k, double rho, int j, int G, int g, int& org, double& tau_out) {
+  auto gsum = [G](double x) {
+    for (int o = 1; o < G; o <<= 1) x += __shfl_xor(x, o, 64);
+    return x;
+  };
   double a, b;
   int o;
   if (j < k - 1) {
     const double gap = delta[j + 1] - delta[j];
-    double w = 1.0 / rho;
-    for (int i = 0; i < k; ++i) w += zeta[i] * zeta[i] / ((delta[i] - delta[j]) - 0.5 * gap);
+    double w = 0.0;
+    for (int i = g; i < k; i += G) w += zeta[i] * zeta[i] / ((delta[i] - delta[j]) - 0.5 * gap);
+    w = 1.0 / rho + gsum(w);
     if (w >= 0.0) {
       o = j;
       a = 0.0;
@@ -223,7 +235,8 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
     }
   } else {
     double zz = 0.0;
-    for (int i = 0; i < k; ++i) zz += zeta[i] * zeta[i];
+    for (int i = g; i < k; i += G) zz += zeta[i] * zeta[i];
+    zz = gsum(zz);
     o = j;
     a = 0.0;
     b = rho * zz * (1.0 + 8.0 * DBL_EPSILON);
@@ -232,8 +245,8 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
   const int jl = j;  // left pole of the interval is delta[j], right delta[j+1]
   double x = 0.5 * (a + b);
   for (int it = 0; it < 100; ++it) {
-    double w = 1.0 / rho, err = 1.0 / rho, psi1 = 0.0, phi1 = 0.0, Dl = 0.0, Dr = 0.0;
-    for (int i = 0; i < k; ++i) {
+    double w = 0.0, err = 0.0, psi1 = 0.0, phi1 = 0.0;
+    for (int i = g; i < k; i += G) {
       const double Di = (delta[i] - dlo) - x;
       const double ri = 1.0 / Di;  // one division per term; t / Di = t * ri
       const double t = zeta[i] * zeta[i] * ri;
@@ -241,9 +254,13 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
       err += fabs(t);
       if (i <= jl) psi1 += t * ri;
       else phi1 += t * ri;
-      if (i == jl) Dl = Di;
-      if (i == jl + 1) Dr = Di;
     }
+    w = 1.0 / rho + gsum(w);
+    err = 1.0 / rho + gsum(err);
+    psi1 = gsum(psi1);
+    phi1 = gsum(phi1);
+    const double Dl = (delta[jl] - dlo) - x;
+    const double Dr = jl + 1 < k ? (delta[jl + 1] - dlo) - x : 0.0;
     if (w < 0.0) a = x;
     else if (w > 0.0) b = x;
     if (fabs(w) <= 8.0 * DBL_EPSILON * err || b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)))
@@ -272,7 +289,8 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
   tau_out = x;
 }
 
-__global__ __launch_bounds__(kThreads) void k_dc_prep(
+template <int NT>
+__global__ __launch_bounds__(NT) void k_dc_prep(
     const int32_t* __restrict__ merges, const int32_t* __restrict__ sub_orb_ptr,
     const int64_t* __restrict__ off2, const double* __restrict__ E, double* __restrict__ zbuf,
     double* __restrict__ lam, int32_t* __restrict__ md_k, int32_t* __restrict__ md_cols,
@@ -280,7 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
     int32_t* __restrict__ md_dpos, double* __restrict__ md_delta, double* __restrict__ md_tau,
     double* __restrict__ md_zhat, double* __restrict__ md_inv) {
   extern __shared__ double smem[];
-  __shared__ double red[8];
+  __shared__ double red[NT / 64];
   __shared__ int sh_k, sh_nrot;
   const int mid = blockIdx.x;
   const int s = merges[4 * mid], lo = merges[4 * mid + 1];
@@ -296,27 +314,27 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
   const double rho = fabs(beta);
   const double sg = beta >= 0.0 ? 1.0 : -1.0;
 
-  for (int i = tid; i < m; i += kThreads) {
+  for (int i = tid; i < m; i += NT) {
     L.D[i] = lam[b + lo + i];
     L.z[i] = i < m1 ? Z[(lo + m1 - 1) + (size_t)n * (lo + i)] : sg * Z[(lo + m1) + (size_t)n * (lo + i)];
   }
   // the off-diagonal child blocks hold stale data from earlier levels
-  for (int idx = tid; idx < m1 * m2; idx += kThreads) {
+  for (int idx = tid; idx < m1 * m2; idx += NT) {
     const int r = idx % m1, c = idx / m1;
     Z[(lo + r) + (size_t)n * (lo + m1 + c)] = 0.0;
   }
-  for (int idx = tid; idx < m1 * m2; idx += kThreads) {
+  for (int idx = tid; idx < m1 * m2; idx += NT) {
     const int r = idx % m2, c = idx / m2;
     Z[(lo + m1 + r) + (size_t)n * (lo + c)] = 0.0;
   }
   __syncthreads();
   double part = 0.0;
-  for (int i = tid; i < m; i += kThreads) part += L.z[i] * L.z[i];
-  const double zz = block_sum(part, red);
+  for (int i = tid; i < m; i += NT) part += L.z[i] * L.z[i];
+  const double zz = block_sum<NT>(part, red);
   const double zn = sqrt(zz);
   const double rho2 = rho * zz;
   // stable merge of the two ascending lists (first list wins ties)
-  for (int i = tid; i < m; i += kThreads) {
+  for (int i = tid; i < m; i += NT) {
     const double x = L.D[i];
     int rk;
     if (i < m1) {
@@ -340,12 +358,12 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
   }
   __syncthreads();
   double mx = 0.0;
-  for (int r = tid; r < m; r += kThreads) {
+  for (int r = tid; r < m; r += NT) {
     L.dS[r] = L.D[L.perm[r]];
     L.zS[r] = zn > 0.0 ? L.z[L.perm[r]] / zn : 0.0;
     mx = fmax(mx, fabs(L.dS[r]));
   }
-  const double dmax = block_max(mx, red);
+  const double dmax = block_max<NT>(mx, red);
   const double tol = 8.0 * DBL_EPSILON * fmax(dmax, rho2);
 
   // deflation (sequential scan over the sorted poles)
@@ -393,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
   // i of the previous step (then forwarded from a register).  Operands are
   // therefore loaded kPre steps ahead.
   constexpr int kPre = 8;
-  for (int r = tid; r < m; r += kThreads) {
+  for (int r = tid; r < m; r += NT) {
     double* row = Z + (lo + r);
     double qa[kPre], qb[kPre];
 #pragma unroll
@@ -427,25 +445,32 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
       }
     }
   }
-  for (int j = tid; j < k; j += kThreads) {
+  for (int j = tid; j < k; j += NT) {
     L.delta[j] = L.dS[L.nd[j]];
     L.zeta[j] = L.zS[L.nd[j]];
   }
   __syncthreads();
-  // secular roots
-  for (int j = tid; j < k; j += kThreads) {
-    int o;
-    double t;
-    secular_root(L.delta, L.zeta, k, rho2, j, o, t);
-    L.org[j] = o;
-    L.tau[j] = t;
+  // secular roots, G lanes per root (up to 8, as many as one round allows)
+  {
+    int G = 1;
+    while (G < 8 && 2 * G * k <= NT) G *= 2;
+    const int g = tid & (G - 1);
+    for (int j = tid / G; j < k; j += NT / G) {
+      int o;
+      double t;
+      secular_root(L.delta, L.zeta, k, rho2, j, G, g, o, t);
+      if (g == 0) {
+        L.org[j] = o;
+        L.tau[j] = t;
+      }
+    }
   }
   __syncthreads();
   // recomputed z: zh_i^2 = (lambda_i - d_i)/rho * prod_{j != i} (d_i - lambda_j)/(d_i - d_j)
   // (numerators and denominators gathered in groups of four, one division per
   // group: every factor lies between about 1e-18 and 10, so a group cannot
   // leave the double range)
-  for (int i = tid; i < k; i += kThreads) {
+  for (int i = tid; i < k; i += NT) {
     const double di = L.delta[i];
     double prod = -((di - L.delta[L.org[i]]) - L.tau[i]) / rho2;
     double num = 1.0, den = 1.0;
@@ -466,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
   __syncthreads();
   // sum_i (zh_i / D_i)^2 with pairs over a common denominator:
   // (za^2 Db^2 + zb^2 Da^2) / (Da^2 Db^2)
-  for (int j = tid; j < k; j += kThreads) {
+  for (int j = tid; j < k; j += NT) {
     const double dO = L.delta[L.org[j]], tj = L.tau[j];
     double acc = 0.0;
     int i = 0;
@@ -483,7 +508,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
     L.inv[j] = 1.0 / sqrt(acc);
   }
   // output order: roots first (items 0..k-1), then deflated items
-  for (int j = tid; j < k; j += kThreads) L.vals[j] = L.delta[L.org[j]] + L.tau[j];
+  for (int j = tid; j < k; j += NT) L.vals[j] = L.delta[L.org[j]] + L.tau[j];
   __syncthreads();
   if (tid == 0) {
     int q = k;
@@ -495,7 +520,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
       }
   }
   __syncthreads();
-  for (int it = tid; it < m; it += kThreads) {
+  for (int it = tid; it < m; it += NT) {
     const double x = L.vals[it];
     int rk = 0;
     for (int j = 0; j < m; ++j) rk += (L.vals[j] < x) || (L.vals[j] == x && j < it);
@@ -503,8 +528,8 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
   }
   __syncthreads();
   const int base = b + lo;
-  for (int it = tid; it < m; it += kThreads) lam[base + L.pos[it]] = L.vals[it];
-  for (int j = tid; j < k; j += kThreads) {
+  for (int it = tid; it < m; it += NT) lam[base + L.pos[it]] = L.vals[it];
+  for (int j = tid; j < k; j += NT) {
     md_cols[base + j] = L.perm[L.nd[j]];
     md_org[base + j] = L.org[j];
     md_pos[base + j] = L.pos[j];
@@ -513,7 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_prep(
     md_zhat[base + j] = L.zhat[j];
     md_inv[base + j] = L.inv[j];
   }
-  for (int q = tid; q < m - k; q += kThreads) {
+  for (int q = tid; q < m - k; q += NT) {
     md_dsrc[base + q] = L.perm[L.nd[k + q]];
     md_dpos[base + q] = L.pos[k + q];
   }
@@ -879,8 +904,10 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
 size_t dc_prep_lds(int m) { return (size_t)m * (12 * sizeof(double) + 7 * sizeof(int)); }
 
 void dc_set_attributes() {
-  (void)hipFuncSetAttribute((const void*)k_dc_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)dc_prep_lds(kMaxN));
+  (void)hipFuncSetAttribute((const void*)k_dc_prep<kThreads>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
+  (void)hipFuncSetAttribute((const void*)k_dc_prep<1024>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(256 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -903,7 +930,11 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     if (m1 == m0) continue;
     const int maxm = g->dc_level_maxm[lv];
     prof_begin(ctx, "k_dc_prep");
-    hipLaunchKernelGGL(k_dc_prep, dim3(m1 - m0), dim3(kThreads), dc_prep_lds(maxm), st,
+    // levels whose merges average over 256 run on 1024 threads, so that one
+    // round covers their roots
+    const bool big = g->dc_level_msum[lv] > 256L * (m1 - m0);
+    auto prep = big ? k_dc_prep<1024> : k_dc_prep<kThreads>;
+    hipLaunchKernelGGL(prep, dim3(m1 - m0), dim3(big ? 1024 : kThreads), dc_prep_lds(maxm), st,
                        dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, e->Q, e->eps,
                        e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
                        e->md_delta, e->md_tau, e->md_zhat, e->md_inv);
