@@ -8,6 +8,7 @@
 //               kept in the lower triangle
 //   then the tridiagonal eigenproblem by divide and conquer and the
 //   back-transformation (k_dc.hip).
+#include <algorithm>
 #include <cfloat>
 #include <utility>
 
@@ -90,10 +91,11 @@ __global__ __launch_bounds__(kThreads) void k_gather(
 // the trailing matrix is touched: inside the panel the current column and the
 // symmetric product use the stale trailing matrix plus the panel corrections
 //   A_cur = A - sum_q (v_q w_q^T + w_q v_q^T);
-// v_q is kept in A's column k0+q (v[0] = 1 stored at row k0+q+1) and w_q in a
-// global panel scratch, so the symmetric product keeps its registers for 16
-// loads in flight.  At the end of the panel the rank-2*kPanel update runs on
-// FP64 MFMA.  d, e and tau go to D, E, TAU.
+// v_q is kept in A's column k0+q (v[0] = 1 stored at row k0+q+1); for the
+// corrections the panel's v_q and w_q sit in LDS (subgraphs of up to
+// kLdsPanelN orbitals) or are read back from A and a global scratch.  At the
+// end of the panel the rank-2*kPanel update runs on FP64 MFMA.  d, e and tau
+// go to D, E, TAU.
 constexpr int kTdThreads = 1024;
 constexpr int kPanel = 16;
 constexpr int kUnroll = 8;
@@ -110,50 +112,94 @@ __device__ double tsum(double x, double* red) {
   return t;
 }
 
-__global__ __launch_bounds__(kTdThreads) void k_tridiag(
-    double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
-    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
-    double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
-  __shared__ __align__(16) double vl[kMaxN];
-  __shared__ double part[kTdThreads];
-  __shared__ double red[kTdThreads / 64];
-  __shared__ double ysh[2 * kPanel][kTdThreads / 64];
-  __shared__ double yfin[2 * kPanel];
-  __shared__ double rowc[2 * kPanel];
-  __shared__ double alpha_sh;
-  const int s = order[blockIdx.x];
-  const int b = sub_orb_ptr[s];
-  const int n = sub_orb_ptr[s + 1] - b;
-  double* A = abuf + off2[s];
-  double* W = wsc + (size_t)b * kPanel;  // W[q * n + r]
+// Row r of p = A22 v over columns > c, in chunks of kUnroll columns aligned
+// to multiples of kUnroll (chunk g goes to the thread with h = g mod H).  v is
+// 0 at columns <= c, so the chunk holding c+1 may start early; the chunk's v
+// values are one wave-uniform run of LDS, read two at a time.
+__device__ __forceinline__ double symv_row(const double* __restrict__ row,
+                                           const double* __restrict__ vl, int n, int c, int h,
+                                           int H) {
+  double ac[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) ac[u] = 0.0;
+  const int g_end = n / kUnroll;  // full chunks
+  int g = (c + 1) / kUnroll + h;
+  for (; g < g_end; g += H) {
+    const int col = g * kUnroll;
+    double x[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * (col + u)];
+    const double2* v2 = reinterpret_cast<const double2*>(vl + col);
+#pragma unroll
+    for (int u = 0; u < kUnroll / 2; ++u) {
+      const double2 vv = v2[u];
+      ac[2 * u] += x[2 * u] * vv.x;
+      ac[2 * u + 1] += x[2 * u + 1] * vv.y;
+    }
+  }
+  if (g == g_end) {  // the partial chunk at the end (this thread's turn)
+    for (int col = max(g_end * kUnroll, c + 1); col < n; ++col) ac[0] += row[(size_t)n * col] * vl[col];
+  }
+#pragma unroll
+  for (int u = 1; u < kUnroll; ++u) ac[0] += ac[u];
+  return ac[0];
+}
+
+// Panel columns q < kPanel: V (v_q, rows > k0+q) and W (w_q).  Subgraphs of
+// up to kLdsPanelN orbitals keep both in LDS (pan[q n + r], pan[(kPanel+q) n
+// + r]); larger ones read V from A's columns and W from the global scratch.
+constexpr int kLdsPanelN = 512;
+
+template <bool LP>
+__device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __restrict__ Wg,
+                                             double* __restrict__ pan, int n, int b,
+                                             double* __restrict__ D, double* __restrict__ E,
+                                             double* __restrict__ TAU, double* vl, double* part,
+                                             double* red, double (*ysh)[kTdThreads / 64],
+                                             double* yfin, double* rowc, double* alpha_sh) {
   const int tid = threadIdx.x;
   const int H = n <= 128 ? 8 : n <= 256 ? 4 : n <= 512 ? 2 : 1;
   const int P = kTdThreads / H;
   const int r = tid % P, h = tid / P;
   const bool own = (h == 0) && (r < n);
+  const int rr = min(r, n - 1);  // a valid row for the loads of threads without one
   const int lane = tid & 63, wv = tid >> 6;
 
   for (int k0 = 0; k0 + 2 < n; k0 += kPanel) {
     const int nb = min(kPanel, n - 2 - k0);
+    auto Vp = [&](int q, int row) -> double {
+      if constexpr (LP) return pan[q * n + row];
+      else return A[row + (size_t)n * (k0 + q)];
+    };
+    auto Wp = [&](int q, int row) -> double {
+      if constexpr (LP) return pan[(kPanel + q) * n + row];
+      else return Wg[q * n + row];
+    };
     for (int j = 0; j < nb; ++j) {
       const int c = k0 + j;
-      if (own && r == c) {
-        for (int q = 0; q < j; ++q) {
-          rowc[q] = A[r + (size_t)n * (k0 + q)];
-          rowc[kPanel + q] = W[q * n + r];
+      if constexpr (!LP) {
+        if (own && r == c) {
+          for (int q = 0; q < j; ++q) {
+            rowc[q] = Vp(q, r);
+            rowc[kPanel + q] = Wp(q, r);
+          }
         }
       }
       __syncthreads();
       double a = 0.0;
       if (own && r >= c) {
         a = A[r + (size_t)n * c];
-        for (int q = 0; q < j; ++q)
-          a -= A[r + (size_t)n * (k0 + q)] * rowc[kPanel + q] + W[q * n + r] * rowc[q];
+#pragma unroll 4
+        for (int q = 0; q < j; ++q) {
+          const double vc = LP ? Vp(q, c) : rowc[q];
+          const double wc = LP ? Wp(q, c) : rowc[kPanel + q];
+          a -= Vp(q, r) * wc + Wp(q, r) * vc;
+        }
         if (r == c) D[b + c] = a;
-        if (r == c + 1) alpha_sh = a;
+        if (r == c + 1) *alpha_sh = a;
       }
       const double sigma = tsum(own && r >= c + 2 ? a * a : 0.0, red);
-      const double alpha = alpha_sh;
+      const double alpha = *alpha_sh;
       double tau = 0.0, beta = alpha, scale = 0.0;
       if (sigma != 0.0) {
         const double nrm = sqrt(alpha * alpha + sigma);
@@ -164,6 +210,7 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
       if (own) {
         const double v = r == c + 1 ? 1.0 : (r >= c + 2 ? a * scale : 0.0);
         vl[r] = v;
+        if constexpr (LP) pan[j * n + r] = v;
         if (r >= c + 1) A[r + (size_t)n * c] = v;
         if (r == c) {
           TAU[b + c] = tau;
@@ -173,57 +220,44 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
       __syncthreads();
       if (tau == 0.0) {
         // H = I (column already reduced): it adds no correction to the panel
-        if (own) W[j * n + r] = 0.0;
+        if (own) {
+          if constexpr (LP) pan[(kPanel + j) * n + r] = 0.0;
+          else Wg[j * n + r] = 0.0;
+        }
         if (own && r >= c + 1) A[r + (size_t)n * c] = 0.0;
+        if constexpr (LP)
+          if (own) pan[j * n + r] = 0.0;
         continue;
       }
       const double vr = r < n ? vl[r] : 0.0;
-      // p = A22 v over the stale trailing matrix: row r, in chunks of kUnroll
-      // columns aligned to multiples of kUnroll (chunk g goes to the thread
-      // with h = g mod H).  v is 0 at columns <= c, so the chunk holding c+1
-      // may start early; the chunk's v values are one wave-uniform run of LDS,
-      // read two at a time.
+      // p = A22 v over the stale trailing matrix
       double acc = 0.0;
-      if (r >= c + 1 && r < n) {
-        const double* row = A + r;
-        double ac[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) ac[u] = 0.0;
-        const int g_end = n / kUnroll;  // full chunks
-        int g = (c + 1) / kUnroll + h;
-        for (; g < g_end; g += H) {
-          const int col = g * kUnroll;
-          double x[kUnroll];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * (col + u)];
-          const double2* v2 = reinterpret_cast<const double2*>(vl + col);
-#pragma unroll
-          for (int u = 0; u < kUnroll / 2; ++u) {
-            const double2 vv = v2[u];
-            ac[2 * u] += x[2 * u] * vv.x;
-            ac[2 * u + 1] += x[2 * u + 1] * vv.y;
-          }
-        }
-        if (g == g_end) {  // the partial chunk at the end (this thread's turn)
-          for (int col = max(g_end * kUnroll, c + 1); col < n; ++col) ac[0] += row[(size_t)n * col] * vl[col];
-        }
-#pragma unroll
-        for (int u = 1; u < kUnroll; ++u) ac[0] += ac[u];
-        acc = ac[0];
-      }
+      if (r >= c + 1 && r < n) acc = symv_row(A + r, vl, n, c, h, H);
       part[tid] = acc;
-      // y1 = W^T v, y2 = V^T v over the panel so far (rows > c; V, W vanish above)
-      for (int q = 0; q < j; ++q) {
-        double t1 = 0.0, t2 = 0.0;
-        if (own && r > c) {
-          t1 = W[q * n + r] * vr;
-          t2 = A[r + (size_t)n * (k0 + q)] * vr;
+      // y1 = W^T v, y2 = V^T v over the panel so far (rows > c; V, W vanish
+      // above), four panel columns at a time so that their sums interleave
+      for (int q0 = 0; q0 < j; q0 += 4) {
+        double t[8];
+        const bool rok = own && r > c;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = min(q0 + u, j - 1);
+          const bool ok = rok && q0 + u < j;
+          const double wq = Wp(q, rr), vq = Vp(q, rr);
+          t[u] = ok ? wq * vr : 0.0;
+          t[4 + u] = ok ? vq * vr : 0.0;
         }
-        t1 = wave_sum(t1);
-        t2 = wave_sum(t2);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) t[u] += __shfl_xor(t[u], o, 64);
         if (lane == 0) {
-          ysh[q][wv] = t1;
-          ysh[kPanel + q][wv] = t2;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (q0 + u < j) {
+              ysh[q0 + u][wv] = t[u];
+              ysh[kPanel + q0 + u][wv] = t[4 + u];
+            }
         }
       }
       __syncthreads();
@@ -236,12 +270,16 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
       double p = 0.0;
       if (own && r >= c + 1) {
         for (int hh = 0; hh < H; ++hh) p += part[hh * P + r];
-        for (int q = 0; q < j; ++q)
-          p -= A[r + (size_t)n * (k0 + q)] * yfin[q] + W[q * n + r] * yfin[kPanel + q];
+#pragma unroll 4
+        for (int q = 0; q < j; ++q) p -= Vp(q, r) * yfin[q] + Wp(q, r) * yfin[kPanel + q];
         p *= tau;
       }
       const double K = 0.5 * tau * tsum(own && r >= c + 1 ? p * vr : 0.0, red);
-      if (own) W[j * n + r] = r >= c + 1 ? p - K * vr : 0.0;
+      if (own) {
+        const double w = r >= c + 1 ? p - K * vr : 0.0;
+        if constexpr (LP) pan[(kPanel + j) * n + r] = w;
+        else Wg[j * n + r] = w;
+      }
     }
     __syncthreads();
     // trailing update A22 -= V W^T + W V^T of rows/cols >= k0 + nb on FP64
@@ -262,36 +300,36 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
         // every operand of the tile is loaded from a clamped (valid) address
         // first and zeroed where out of range afterwards, so the loads carry
         // no branches and are in flight together
-        const int rowc = min(row, n - 1), clc = min(cl, n - 1);
+        const int rowc_ = min(row, n - 1), clc = min(cl, n - 1);
         double a4[4], wcv[kPanel / 4], vcv[kPanel / 4], vrv[kPanel / 4], wrv[kPanel / 4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a4[r] = A[rowc + (size_t)n * min(col0 + 4 * r + lk, n - 1)];
+        for (int i = 0; i < 4; ++i) a4[i] = A[rowc_ + (size_t)n * min(col0 + 4 * i + lk, n - 1)];
 #pragma unroll
         for (int kq = 0; kq < kPanel / 4; ++kq) {
           const int qc = min(4 * kq + lk, nb - 1);
-          wcv[kq] = W[qc * n + clc];
-          vcv[kq] = A[clc + (size_t)n * (k0 + qc)];
-          vrv[kq] = A[rowc + (size_t)n * (k0 + qc)];
-          wrv[kq] = W[qc * n + rowc];
+          wcv[kq] = Wp(qc, clc);
+          vcv[kq] = Vp(qc, clc);
+          vrv[kq] = Vp(qc, rowc_);
+          wrv[kq] = Wp(qc, rowc_);
         }
         v4d acc;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = (rok && col0 + 4 * r + lk < n) ? a4[r] : 0.0;
+        for (int i = 0; i < 4; ++i) acc[i] = (rok && col0 + 4 * i + lk < n) ? a4[i] : 0.0;
 #pragma unroll
         for (int kq = 0; kq < kPanel / 4; ++kq) {
           const bool qok = 4 * kq + lk < nb;
           const double wc = (qok && cok) ? wcv[kq] : 0.0;
           const double vc = (qok && cok) ? vcv[kq] : 0.0;
-          const double vr = (qok && rok) ? vrv[kq] : 0.0;
+          const double vrr = (qok && rok) ? vrv[kq] : 0.0;
           const double wr = (qok && rok) ? wrv[kq] : 0.0;
-          acc = mfma16(-wc, vr, acc);
+          acc = mfma16(-wc, vrr, acc);
           acc = mfma16(-vc, wr, acc);
         }
         if (rok) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int col = col0 + 4 * r + lk;
-            if (col < n) A[row + (size_t)n * col] = acc[r];
+          for (int i = 0; i < 4; ++i) {
+            const int col = col0 + 4 * i + lk;
+            if (col < n) A[row + (size_t)n * col] = acc[i];
           }
         }
       }
@@ -308,9 +346,39 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
   }
 }
 
+__global__ __launch_bounds__(kTdThreads) void k_tridiag(
+    double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
+    double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
+  extern __shared__ double pan[];  // 2 kPanel min(max n, kLdsPanelN) doubles
+  __shared__ __align__(16) double vl[kMaxN];
+  __shared__ double part[kTdThreads];
+  __shared__ double red[kTdThreads / 64];
+  __shared__ double ysh[2 * kPanel][kTdThreads / 64];
+  __shared__ double yfin[2 * kPanel];
+  __shared__ double rowc[2 * kPanel];
+  __shared__ double alpha_sh;
+  const int s = order[blockIdx.x];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  double* A = abuf + off2[s];
+  double* W = wsc + (size_t)b * kPanel;  // W[q * n + r]
+  if (n <= kLdsPanelN)
+    tridiag_body<true>(A, W, pan, n, b, D, E, TAU, vl, part, red, ysh, yfin, rowc, &alpha_sh);
+  else
+    tridiag_body<false>(A, W, pan, n, b, D, E, TAU, vl, part, red, ysh, yfin, rowc, &alpha_sh);
+}
+
 }  // namespace
 
-void eig_set_attributes() {}
+static size_t tridiag_lds(int maxn) {
+  return (size_t)2 * kPanel * std::min(maxn, kLdsPanelN) * sizeof(double);
+}
+
+void eig_set_attributes() {
+  (void)hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)tridiag_lds(kLdsPanelN));
+}
 
 void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status) {
   const gq_graph_dev& dv = g->dev;
@@ -328,9 +396,8 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   const int maxn = g->info.max_n;
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_tridiag");
-  (void)maxn;
-  hipLaunchKernelGGL(k_tridiag, dim3(g->n_sub), dim3(kTdThreads), 0, st, e->A, e->wsc, dv.off2,
-                     dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
+  hipLaunchKernelGGL(k_tridiag, dim3(g->n_sub), dim3(kTdThreads), tridiag_lds(maxn), st, e->A,
+                     e->wsc, dv.off2, dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
   prof_end(ctx);
   launch_dc(ctx, g, e);
 }
