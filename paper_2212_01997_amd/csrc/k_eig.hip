@@ -155,7 +155,7 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
                                              double* __restrict__ pan, int n, int b,
                                              double* __restrict__ D, double* __restrict__ E,
                                              double* __restrict__ TAU, double* vl, double* part,
-                                             double* red, double (*ysh)[kTdThreads / 64],
+                                             double* red, double (*yp)[2 * kPanel + 1],
                                              double* yfin, double* rowc, double* alpha_sh) {
   const int tid = threadIdx.x;
   const int H = n <= 128 ? 8 : n <= 256 ? 4 : n <= 512 ? 2 : 1;
@@ -230,40 +230,29 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
         continue;
       }
       const double vr = r < n ? vl[r] : 0.0;
+      // y1 = W^T v, y2 = V^T v over the panel so far (rows > c; V, W vanish
+      // above): thread t sums panel column t mod 32 (W for q < kPanel, V
+      // above) over rows c+1+seg, c+1+seg+32, ... of segment seg = t / 32
+      {
+        const int q = tid & 31, seg = tid >> 5;
+        const int qp = q & (kPanel - 1);
+        double t = 0.0;
+        if (qp < j) {
+          const bool isw = q < kPanel;
+#pragma unroll 4
+          for (int row = c + 1 + seg; row < n; row += kTdThreads / 32)
+            t += (isw ? Wp(qp, row) : Vp(qp, row)) * vl[row];
+        }
+        yp[seg][q] = t;
+      }
       // p = A22 v over the stale trailing matrix
       double acc = 0.0;
       if (r >= c + 1 && r < n) acc = symv_row(A + r, vl, n, c, h, H);
       part[tid] = acc;
-      // y1 = W^T v, y2 = V^T v over the panel so far (rows > c; V, W vanish
-      // above), four panel columns at a time so that their sums interleave
-      for (int q0 = 0; q0 < j; q0 += 4) {
-        double t[8];
-        const bool rok = own && r > c;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = min(q0 + u, j - 1);
-          const bool ok = rok && q0 + u < j;
-          const double wq = Wp(q, rr), vq = Vp(q, rr);
-          t[u] = ok ? wq * vr : 0.0;
-          t[4 + u] = ok ? vq * vr : 0.0;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) t[u] += __shfl_xor(t[u], o, 64);
-        if (lane == 0) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (q0 + u < j) {
-              ysh[q0 + u][wv] = t[u];
-              ysh[kPanel + q0 + u][wv] = t[4 + u];
-            }
-        }
-      }
       __syncthreads();
       if (tid < 2 * kPanel && (tid % kPanel) < j) {
         double t = 0.0;
-        for (int w = 0; w < kTdThreads / 64; ++w) t += ysh[tid][w];
+        for (int sg = 0; sg < kTdThreads / 32; ++sg) t += yp[sg][tid];
         yfin[tid] = t;
       }
       __syncthreads();
@@ -354,7 +343,7 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
   __shared__ __align__(16) double vl[kMaxN];
   __shared__ double part[kTdThreads];
   __shared__ double red[kTdThreads / 64];
-  __shared__ double ysh[2 * kPanel][kTdThreads / 64];
+  __shared__ double yp[kTdThreads / 32][2 * kPanel + 1];
   __shared__ double yfin[2 * kPanel];
   __shared__ double rowc[2 * kPanel];
   __shared__ double alpha_sh;
@@ -364,9 +353,9 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
   double* A = abuf + off2[s];
   double* W = wsc + (size_t)b * kPanel;  // W[q * n + r]
   if (n <= kLdsPanelN)
-    tridiag_body<true>(A, W, pan, n, b, D, E, TAU, vl, part, red, ysh, yfin, rowc, &alpha_sh);
+    tridiag_body<true>(A, W, pan, n, b, D, E, TAU, vl, part, red, yp, yfin, rowc, &alpha_sh);
   else
-    tridiag_body<false>(A, W, pan, n, b, D, E, TAU, vl, part, red, ysh, yfin, rowc, &alpha_sh);
+    tridiag_body<false>(A, W, pan, n, b, D, E, TAU, vl, part, red, yp, yfin, rowc, &alpha_sh);
 }
 
 }  // namespace
