@@ -42,6 +42,16 @@ __device__ __forceinline__ double mfma4b(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
+// x from the lane given by the DPP control kCtrl (quad_perm, row_mirror, ...),
+// both 32-bit halves moved by VALU permutes rather than the LDS crossbar.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -206,15 +216,20 @@ __device__ PrepLds carve(void* base, int m) {
 
 // Root j of 1/rho + sum_i zeta_i^2 / (delta_i - lambda) = 0 for strictly
 // increasing delta, evaluated by the G lanes g = 0..G-1 of a wave that share j
-// (G a power of two, the group aligned to G): lane g sums the terms i = g,
-// g+G, ...  The partial sums are combined by xor butterflies, which leave the
-// same bits in every lane of the group, so the group takes the same branches
-// and returns the same root.  Returns the origin pole index and the offset tau
+// (G a power of two up to 8, the group aligned to G): lane g sums the terms
+// i = g, g+G, ...  The partial sums are combined pairwise, exchanging equal
+// values at every step, which leaves the same bits in every lane of the
+// group, so the group takes the same branches and returns the same root.  Returns the origin pole index and the offset tau
 // from it.
 __device__ void secular_root(const double* __restrict__ delta, const double* __restrict__ zeta,
                              int k, double rho, int j, int G, int g, int& org, double& tau_out) {
+  // sum over the group by DPP: quad_perm 1032 (pairs), quad_perm 2301
+  // (quads), row_half_mirror (eights; after the quad steps it exchanges equal
+  // quad sums); the lanes of a group are active together
   auto gsum = [G](double x) {
-    for (int o = 1; o < G; o <<= 1) x += __shfl_xor(x, o, 64);
+    if (G >= 2) x += dpp_f64<0xB1>(x);
+    if (G >= 4) x += dpp_f64<0x4E>(x);
+    if (G >= 8) x += dpp_f64<0x141>(x);
     return x;
   };
   double a, b;

@@ -100,8 +100,38 @@ constexpr int kTdThreads = 1024;
 constexpr int kPanel = 16;
 constexpr int kUnroll = 8;
 
+// x from the lane given by the DPP control kCtrl (quad_perm, row_mirror, ...),
+// both 32-bit halves moved by VALU permutes rather than the LDS crossbar.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave (all lanes active), the same in every lane: rows of 16
+// lanes summed by DPP (quad_perm 1032, quad_perm 2301, row_half_mirror,
+// row_mirror; after the quad steps a mirror is an exchange of equal sums),
+// then the four row sums read out.
+__device__ __forceinline__ double wave_total(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  x += dpp_f64<0x140>(x);
+  const long long b = __double_as_longlong(x);
+  double rs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int lo = __builtin_amdgcn_readlane((int)b, 16 * i);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * i);
+    rs[i] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  return (rs[0] + rs[1]) + (rs[2] + rs[3]);
+}
+
 __device__ double tsum(double x, double* red) {
-  x = wave_sum(x);
+  x = wave_total(x);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[w] = x;
