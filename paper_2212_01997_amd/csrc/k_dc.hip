@@ -925,6 +925,8 @@ void dc_set_attributes() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(256 * kLdv * sizeof(double)));
+  (void)hipFuncSetAttribute((const void*)k_bt_mfma<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(384 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(512 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -971,12 +973,13 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
                      e->A, e->tau, dv.off2, dv.sub_orb_ptr, dv.bt_toff, e->tfac);
   prof_end(ctx);
   prof_begin(ctx, "k_backtransform");
-  // subgraphs are ordered by decreasing size: classes n <= 256, <= 512, <= 1024
-  // are contiguous ranges of that order, each launched with its register panel
+  // subgraphs are ordered by decreasing size: classes n <= 256, <= 384, <= 512,
+  // <= 1024 are contiguous ranges of that order, each launched with its
+  // register panel (the smallest that holds its row blocks)
+  static constexpr int kClassN[4] = {256, 384, 512, kMaxN};
   int lo = 0;
-  for (int cls = 2; cls >= 0; --cls) {
-    const int cap = cls == 0 ? 256 : cls == 1 ? 512 : kMaxN;
-    const int floor_n = cls == 0 ? 0 : cls == 1 ? 256 : 512;
+  for (int cls = 3; cls >= 0; --cls) {
+    const int floor_n = cls == 0 ? 0 : kClassN[cls - 1];
     int hi = lo;
     while (hi < g->n_sub && g->sub_orb_ptr[g->order[hi] + 1] - g->sub_orb_ptr[g->order[hi]] > floor_n) ++hi;
     if (hi > lo) {
@@ -984,8 +987,7 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
       const int nrb = (nmax + 15) / 16;
       dim3 grid((nmax + 15) / 16, hi - lo);
       const size_t lds = (size_t)16 * nrb * kLdv * sizeof(double);
-      auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<8> : k_bt_mfma<16>;
-      (void)cap;
+      auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<6> : cls == 2 ? k_bt_mfma<8> : k_bt_mfma<16>;
       hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, e->A, e->tfac, dv.bt_toff, e->Q,
                          dv.off2, dv.sub_orb_ptr, dv.n_core, dv.order + lo, e->wts);
     }
