@@ -263,7 +263,11 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
     double w = 0.0, err = 0.0, psi1 = 0.0, phi1 = 0.0;
     for (int i = g; i < k; i += G) {
       const double Di = (delta[i] - dlo) - x;
-      const double ri = 1.0 / Di;  // one division per term; t / Di = t * ri
+      // 1/Di: hardware reciprocal and two Newton steps (within about an ulp,
+      // enough for the iteration's tolerance tests); t / Di = t * ri
+      double ri = __builtin_amdgcn_rcp(Di);
+      ri = fma(ri, fma(-Di, ri, 1.0), ri);
+      ri = fma(ri, fma(-Di, ri, 1.0), ri);
       const double t = zeta[i] * zeta[i] * ri;
       w += t;
       err += fabs(t);
