@@ -52,6 +52,14 @@ __device__ __forceinline__ double dpp_f64(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1/x from the hardware reciprocal and two Newton steps: within about an ulp,
+// without the scaling and fix-up steps of an IEEE division
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -263,11 +271,9 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
     double w = 0.0, err = 0.0, psi1 = 0.0, phi1 = 0.0;
     for (int i = g; i < k; i += G) {
       const double Di = (delta[i] - dlo) - x;
-      // 1/Di: hardware reciprocal and two Newton steps (within about an ulp,
-      // enough for the iteration's tolerance tests); t / Di = t * ri
-      double ri = __builtin_amdgcn_rcp(Di);
-      ri = fma(ri, fma(-Di, ri, 1.0), ri);
-      ri = fma(ri, fma(-Di, ri, 1.0), ri);
+      // 1/Di within about an ulp (enough for the iteration's tolerance
+      // tests); t / Di = t * ri
+      const double ri = rcp_nr(Di);
       const double t = zeta[i] * zeta[i] * ri;
       w += t;
       err += fabs(t);
@@ -518,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
       const double da = (L.delta[i] - dO) - tj, db = (L.delta[i + 1] - dO) - tj;
       const double za = L.zhat[i], zb = L.zhat[i + 1];
       const double da2 = da * da, db2 = db * db;
-      acc += (za * za * db2 + zb * zb * da2) / (da2 * db2);
+      acc += (za * za * db2 + zb * zb * da2) * rcp_nr(da2 * db2);
     }
     if (i < k) {
       const double u = L.zhat[i] / ((L.delta[i] - dO) - tj);
@@ -636,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
         const int rr = idx % kTile, ii = idx / kTile;
         const bool iok = i0 + ii < k;
         As[ii][rr] = (iok && r0 + rr < m) ? pz[u] : 0.0;
-        Bs[ii][rr] = (iok && c0 + rr < k) ? pzh[u] * cinv[rr] / ((pdl[u] - cdo[rr]) - ctau[rr]) : 0.0;
+        Bs[ii][rr] = (iok && c0 + rr < k) ? pzh[u] * cinv[rr] * rcp_nr((pdl[u] - cdo[rr]) - ctau[rr]) : 0.0;
       }
       __syncthreads();
       if (i0 + kKg < k) fetch(i0 + kKg);
