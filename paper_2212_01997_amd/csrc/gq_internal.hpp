@@ -19,7 +19,6 @@ constexpr int kLeaf = 16;
 // Largest core (orbitals): the response products keep two 16-row MFMA blocks.
 constexpr int kMaxCore = 32;
 // Core rows handled per workgroup in the core-row products.
-constexpr int kRowChunk = 16;
 // Points per multisection pass of the chemical-potential search.
 constexpr int kMuPoints = 128;
 constexpr int kMuPasses = 9;

@@ -149,31 +149,43 @@ __global__ __launch_bounds__(kMuPoints * kMuGroups) void k_mu_update(
   }
 }
 
-// Core-row products out[j, l] = sum_k L[j, k] R[l + n k] for a chunk of
-// kRowChunk core rows j and kThreads columns l of one subgraph.  The density
-// form has L = Q_c diag(g) for two weight vectors g at once.
+// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A(l%16, l/16) and
+// B(l/16, l%16); D(i, j) is returned in lane j + 16*(i%4), register i/4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kDC = 128;  // columns per workgroup of the core-row products
+constexpr int kDU = 4;    // K steps of operands loaded ahead
+
+// Core rows of both products for kDC columns l of one subgraph:
+//   rho[j, l] = sum_m Q[j, m] 2 f_m Q[l, m],
+//   M[j, l]   = sum_m Q[j, m] 2 beta f_m (1 - f_m) Q[l, m],   j < c <= 32.
+// Wave w owns columns L0 + 32 w .. + 31 (two 16-column tiles) and both 16-row
+// tiles of core rows; the K steps run over m, the A operand Q[j, m] g(m) is
+// formed in registers and one load of Q[l, m] feeds both products.  The
+// workgroup of the first column block also forms tmu = 2 beta sum f(1-f) w.
 __global__ __launch_bounds__(kThreads) void k_density_rows(
     const double* __restrict__ qbuf, const double* __restrict__ eps,
     const double* __restrict__ wts, const int64_t* __restrict__ off2,
     const int64_t* __restrict__ offc, const int32_t* __restrict__ sub_orb_ptr,
     const int32_t* __restrict__ n_core, const int32_t* __restrict__ order,
     const double* __restrict__ state, double* __restrict__ rho, double* __restrict__ mrows,
-    double* __restrict__ tmu) {
-  __shared__ double gf[64], gm[64];
-  __shared__ double Lr[kRowChunk][64 + 1], Lm[kRowChunk][64 + 1];
-  __shared__ double red[8];
-  const int s = order[blockIdx.x];
+    double* __restrict__ tmu, int ncb) {
+  __shared__ double red[kThreads / 64];
+  const int s = order[blockIdx.x / ncb];
+  const int L0 = (blockIdx.x % ncb) * kDC;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
+  if (L0 >= n) return;
   const int c = n_core[s];
-  const int l = blockIdx.y * kThreads + threadIdx.x;
-  const int j0 = blockIdx.z * kRowChunk;
-  if (blockIdx.y * kThreads >= n || j0 >= c) return;
   const double mu = state[2], beta = 1.0 / state[3];
   const double* Q = qbuf + off2[s];
   const double* e = eps + b;
 
-  if (blockIdx.y == 0 && blockIdx.z == 0) {
+  if (L0 == 0) {
     double acc = 0.0;
     for (int k = threadIdx.x; k < n; k += kThreads) {
       double f, f1f;
@@ -184,47 +196,64 @@ __global__ __launch_bounds__(kThreads) void k_density_rows(
     if (threadIdx.x == 0) tmu[s] = 2.0 * beta * t;
   }
 
-  double ar[kRowChunk], am[kRowChunk];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  int lcol[2];
+  bool colok[2];
 #pragma unroll
-  for (int jj = 0; jj < kRowChunk; ++jj) ar[jj] = am[jj] = 0.0;
-  for (int k0 = 0; k0 < n; k0 += 64) {
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int k = k0 + threadIdx.x;
-      double f = 0.0, f1f = 0.0;
-      if (k < n) fermi2(e[k], mu, beta, f, f1f);
-      gf[threadIdx.x] = 2.0 * f;
-      gm[threadIdx.x] = 2.0 * beta * f1f;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kRowChunk * 64; idx += kThreads) {
-      const int jj = idx % kRowChunk, kk = idx / kRowChunk;
-      const int j = j0 + jj, k = k0 + kk;
-      const double q = (j < c && k < n) ? Q[j + (size_t)n * k] : 0.0;
-      Lr[jj][kk] = q * gf[kk];
-      Lm[jj][kk] = q * gm[kk];
-    }
-    __syncthreads();
-    if (l < n) {
-      const int kend = min(64, n - k0);
-      for (int kk = 0; kk < kend; ++kk) {
-        const double r = Q[l + (size_t)n * (k0 + kk)];
+  for (int y = 0; y < 2; ++y) {
+    lcol[y] = L0 + 32 * w + 16 * y + li;
+    colok[y] = lcol[y] < n;
+  }
+  // rows li and 16 + li of Q, clamped to valid rows (zeroed below when not core)
+  const int r0 = min(li, n - 1), r1 = min(16 + li, n - 1);
+  const bool ok0 = li < c, ok1 = 16 + li < c;
+  v4d ar[2][2], am[2][2];
 #pragma unroll
-        for (int jj = 0; jj < kRowChunk; ++jj) {
-          ar[jj] += Lr[jj][kk] * r;
-          am[jj] += Lm[jj][kk] * r;
-        }
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) ar[x][y] = am[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int m0 = 0; m0 < n; m0 += 4 * kDU) {
+    double q0[kDU], q1[kDU], bv[2][kDU], em[kDU];
+#pragma unroll
+    for (int u = 0; u < kDU; ++u) {
+      const int mc = min(m0 + 4 * u + lk, n - 1);
+      q0[u] = Q[r0 + (size_t)n * mc];
+      q1[u] = Q[r1 + (size_t)n * mc];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y][u] = Q[min(lcol[y], n - 1) + (size_t)n * mc];
+      em[u] = e[mc];
+    }
+#pragma unroll
+    for (int u = 0; u < kDU; ++u) {
+      const bool ok = m0 + 4 * u + lk < n;
+      double f, f1f;
+      fermi2(em[u], mu, beta, f, f1f);
+      const double gf = ok ? 2.0 * f : 0.0, gm = ok ? 2.0 * beta * f1f : 0.0;
+      const double a0 = ok0 ? q0[u] : 0.0, a1 = ok1 ? q1[u] : 0.0;
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        ar[0][y] = mfma16(a0 * gf, bv[y][u], ar[0][y]);
+        ar[1][y] = mfma16(a1 * gf, bv[y][u], ar[1][y]);
+        am[0][y] = mfma16(a0 * gm, bv[y][u], am[0][y]);
+        am[1][y] = mfma16(a1 * gm, bv[y][u], am[1][y]);
       }
     }
   }
-  if (l < n) {
-    const size_t base = offc[s];
+  const size_t base = offc[s];
 #pragma unroll
-    for (int jj = 0; jj < kRowChunk; ++jj) {
-      const int j = j0 + jj;
-      if (j < c) {
-        if (rho) rho[base + (size_t)j * n + l] = ar[jj];
-        mrows[base + (size_t)j * n + l] = am[jj];
+  for (int y = 0; y < 2; ++y) {
+    if (!colok[y]) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j0 = lk + 4 * r, j1 = 16 + lk + 4 * r;
+      if (j0 < c) {
+        if (rho) rho[base + (size_t)j0 * n + lcol[y]] = ar[0][y][r];
+        mrows[base + (size_t)j0 * n + lcol[y]] = am[0][y][r];
+      }
+      if (j1 < c) {
+        if (rho) rho[base + (size_t)j1 * n + lcol[y]] = ar[1][y][r];
+        mrows[base + (size_t)j1 * n + lcol[y]] = am[1][y][r];
       }
     }
   }
@@ -284,11 +313,10 @@ void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_bloc
   const gq_graph_dev& dv = g->dev;
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_density_rows");
-  dim3 grid(g->n_sub, (g->info.max_n + kThreads - 1) / kThreads,
-            (g->info.max_c + kRowChunk - 1) / kRowChunk);
-  hipLaunchKernelGGL(k_density_rows, grid, dim3(kThreads), 0, st, e->Q, e->eps, e->wts, dv.off2,
-                     dv.offc, dv.sub_orb_ptr, dv.n_core, dv.order, e->mu_state, rho_blocks, e->M,
-                     e->tmu);
+  const int ncb = (g->info.max_n + kDC - 1) / kDC;
+  hipLaunchKernelGGL(k_density_rows, dim3(g->n_sub * ncb), dim3(kThreads), 0, st, e->Q, e->eps,
+                     e->wts, dv.off2, dv.offc, dv.sub_orb_ptr, dv.n_core, dv.order, e->mu_state,
+                     rho_blocks, e->M, e->tmu, ncb);
   prof_end(ctx);
 }
 

@@ -130,10 +130,12 @@ __device__ __forceinline__ double wave_total(double x) {
   return (rs[0] + rs[1]) + (rs[2] + rs[3]);
 }
 
+// Sum over the workgroup in a fixed order; every thread gets the total.  One
+// barrier: each call site has a buffer of its own, and other barriers separate
+// its uses, so no wave can overwrite red before every wave has read it.
 __device__ double tsum(double x, double* red) {
   x = wave_total(x);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
   if (lane == 0) red[w] = x;
   __syncthreads();
   double t = 0.0;
@@ -293,7 +295,7 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
         for (int q = 0; q < j; ++q) p -= Vp(q, r) * yfin[q] + Wp(q, r) * yfin[kPanel + q];
         p *= tau;
       }
-      const double K = 0.5 * tau * tsum(own && r >= c + 1 ? p * vr : 0.0, red);
+      const double K = 0.5 * tau * tsum(own && r >= c + 1 ? p * vr : 0.0, red + kTdThreads / 64);
       if (own) {
         const double w = r >= c + 1 ? p - K * vr : 0.0;
         if constexpr (LP) pan[(kPanel + j) * n + r] = w;
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
   extern __shared__ double pan[];  // 2 kPanel min(max n, kLdsPanelN) doubles
   __shared__ __align__(16) double vl[kMaxN];
   __shared__ double part[kTdThreads];
-  __shared__ double red[kTdThreads / 64];
+  __shared__ double red[2 * (kTdThreads / 64)];  // the two sums of a column
   __shared__ double yp[kTdThreads / 32][2 * kPanel + 1];
   __shared__ double yfin[2 * kPanel];
   __shared__ double rowc[2 * kPanel];
