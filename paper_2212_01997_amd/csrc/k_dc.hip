@@ -314,6 +314,33 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
   tau_out = x;
 }
 
+// Stream compaction in index order over the workgroup: out[base + r] = i for
+// every i < m with flag(i), r being the number of flagged j < i (wave ballots,
+// then the wave totals in LDS).  Returns the count in every thread; ends with
+// a barrier.
+template <int NT, class F>
+__device__ int compact(int m, F flag, int* out, int base, int* wtot) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int total = 0;
+  for (int i0 = 0; i0 < m; i0 += NT) {
+    const int i = i0 + (int)threadIdx.x;
+    const bool f = i < m && flag(i);
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) wtot[w] = __popcll(bal);
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < NT / 64; ++ww) {
+      off += ww < w ? wtot[ww] : 0;
+      tot += wtot[ww];
+    }
+    if (f) out[base + total + off + __popcll(bal & ((1ull << lane) - 1))] = i;
+    __syncthreads();
+    total += tot;
+  }
+  return total;
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_dc_prep(
     const int32_t* __restrict__ merges, const int32_t* __restrict__ sub_orb_ptr,
@@ -324,7 +351,8 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
     double* __restrict__ md_zhat, double* __restrict__ md_inv) {
   extern __shared__ double smem[];
   __shared__ double red[NT / 64];
-  __shared__ int sh_k, sh_nrot;
+  __shared__ int sh_k, sh_nrot, sh_rot;
+  __shared__ int wtot[NT / 64];
   const int mid = blockIdx.x;
   const int s = merges[4 * mid], lo = merges[4 * mid + 1];
   const int m1 = merges[4 * mid + 2], m2 = merges[4 * mid + 3];
@@ -391,8 +419,30 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   const double dmax = block_max<NT>(mx, red);
   const double tol = 8.0 * DBL_EPSILON * fmax(dmax, rho2);
 
-  // deflation (sequential scan over the sorted poles)
-  if (tid == 0) {
+  // deflation.  An entry with a negligible z deflates on its own; a kept entry
+  // whose pole is close to that of the previous kept entry deflates by a
+  // Givens rotation.  The kept entries are compacted in order first (the
+  // scan's result when no rotation happens) and every consecutive pair is
+  // tested with the scan's own arithmetic; only if some pair needs a rotation
+  // does thread 0 run the sequential scan, which then decides everything.
+  for (int i = tid; i < m; i += NT) L.defl[i] = rho2 * fabs(L.zS[i]) <= tol ? 1 : 0;
+  if (tid == 0) sh_rot = 0;
+  __syncthreads();
+  const int kept = compact<NT>(m, [&](int i) { return L.defl[i] == 0; }, L.nd, 0, wtot);
+  for (int q = 1 + tid; q < kept; q += NT) {
+    const int p = L.nd[q - 1], i = L.nd[q];
+    const double t = hypot(L.zS[p], L.zS[i]);
+    const double c = L.zS[i] / t;
+    const double sn = -L.zS[p] / t;
+    if (fabs((L.dS[i] - L.dS[p]) * c * sn) <= tol) sh_rot = 1;
+  }
+  __syncthreads();
+  const bool any_rot = sh_rot != 0;
+  if (!any_rot && tid == 0) {
+    sh_k = kept;
+    sh_nrot = 0;
+  }
+  if (any_rot && tid == 0) {
     int p = -1, k = 0, nrot = 0;
     for (int i = 0; i < m; ++i) {
       L.defl[i] = 0;
@@ -532,18 +582,11 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
     }
     L.inv[j] = 1.0 / sqrt(acc);
   }
-  // output order: roots first (items 0..k-1), then deflated items
+  // output order: roots first (items 0..k-1), then the deflated items in
+  // index order (the tail of nd lists their sorted indices)
   for (int j = tid; j < k; j += NT) L.vals[j] = L.delta[L.org[j]] + L.tau[j];
-  __syncthreads();
-  if (tid == 0) {
-    int q = k;
-    for (int i = 0; i < m; ++i)
-      if (L.defl[i]) {
-        L.vals[q] = L.dS[i];
-        L.nd[q] = i;  // the tail of nd lists the deflated sorted indices
-        ++q;
-      }
-  }
+  compact<NT>(m, [&](int i) { return L.defl[i] != 0; }, L.nd, k, wtot);
+  for (int q = k + tid; q < m; q += NT) L.vals[q] = L.dS[L.nd[q]];
   __syncthreads();
   for (int it = tid; it < m; it += NT) {
     const double x = L.vals[it];
