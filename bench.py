@@ -48,6 +48,26 @@ def algorithmic_work(sizes, cores):
     }
 
 
+def tridiag_bytes(sizes):
+    """Algorithmic HBM bytes of one k_tridiag launch (Sec. II.D eigensolve,
+    one-stage Householder reduction): for every column c the symmetric product
+    reads the trailing matrix (rows and columns > c) once, and every panel of
+    16 reflectors reads and writes the trailing matrix once in its rank-2x16
+    update; 8 bytes per FP64 element."""
+    total = 0.0
+    for n in sizes.astype(int):
+        m = n - 1
+        symv = m * (m + 1) * (2 * m + 1) / 6.0 - 1.0 if n >= 3 else 0.0  # sum_{c<=n-3} (n-c-1)^2
+        upd = 0.0
+        k0 = 0
+        while k0 + 2 < n:
+            t0 = k0 + min(16, n - 2 - k0)
+            upd += 2.0 * (n - t0) ** 2
+            k0 += 16
+        total += 8.0 * (symv + upd)
+    return total
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factor), or None
@@ -411,13 +431,25 @@ def main():
     dominant = max(per_step, key=per_step.get)
     flops = work.get(dominant, 0.0)
     launches_per_step = kt[dominant][0] / nprof
-    achieved = flops / (per_launch[dominant] * 1e-3) if flops else 0.0
-    bound = "alu" if dominant in ("k_tridiag", "k_dc_prep", "k_dc_leaves") else "mfma"
-    roofline = {"bound": bound, "kernel": dominant, "achieved": achieved / 1e12,
-                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
-                "traffic": measured_traffic(dominant),
-                "algorithmic_flops_per_launch": flops, "launch_ms": per_launch[dominant],
-                "launches_per_step": launches_per_step}
+    launch_s = per_launch[dominant] * 1e-3
+    achieved = flops / launch_s if flops else 0.0
+    if dominant == "k_tridiag":
+        # BLAS-2 bound: the symmetric product streams the trailing matrix once
+        # per column, so the roofline is HBM with the algorithm's own bytes
+        nbytes = tridiag_bytes(sizes)
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": nbytes / launch_s / 1e9,
+                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": nbytes / launch_s / PEAK_HBM,
+                    "traffic": measured_traffic(dominant),
+                    "algorithmic_bytes_per_launch": nbytes,
+                    "algorithmic_flops_per_launch": flops, "achieved_tflops": achieved / 1e12,
+                    "launch_ms": per_launch[dominant], "launches_per_step": launches_per_step}
+    else:
+        bound = "alu" if dominant in ("k_dc_prep", "k_dc_leaves") else "mfma"
+        roofline = {"bound": bound, "kernel": dominant, "achieved": achieved / 1e12,
+                    "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                    "traffic": measured_traffic(dominant),
+                    "algorithmic_flops_per_launch": flops, "launch_ms": per_launch[dominant],
+                    "launches_per_step": launches_per_step}
     xy_flops = work["k_xy"]
     xy_ms = per_launch.get("k_xy", 0.0)
     roofline_congruence = None

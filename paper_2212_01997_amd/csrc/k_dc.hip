@@ -149,8 +149,9 @@ __global__ __launch_bounds__(64) void k_dc_leaves(
           early = true;
           break;
         }
-        sn = f / r;
-        c = g / r;
+        const double ri = rcp_nr(r);
+        sn = f * ri;
+        c = g * ri;
         g = d[i + 1] - p;
         r = (d[i] - g) * sn + 2.0 * c * bb;
         p = sn * r;
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(64) void k_dc_leaves(
 // ------------------------------------------------------------- merge prep
 
 struct PrepLds {
-  double *D, *z, *dS, *zS, *rc, *rs, *delta, *zeta, *tau, *zhat, *inv, *vals;
+  double *D, *z, *dS, *zS, *rc, *rs, *delta, *zeta, *z2, *tau, *zhat, *inv, *vals;
   int *perm, *defl, *nd, *rp, *ri, *org, *pos;
 };
 
@@ -207,6 +208,7 @@ __device__ PrepLds carve(void* base, int m) {
   L.rs = dp; dp += m;
   L.delta = dp; dp += m;
   L.zeta = dp; dp += m;
+  L.z2 = dp; dp += m;
   L.tau = dp; dp += m;
   L.zhat = dp; dp += m;
   L.inv = dp; dp += m;
@@ -229,7 +231,7 @@ __device__ PrepLds carve(void* base, int m) {
 // values at every step, which leaves the same bits in every lane of the
 // group, so the group takes the same branches and returns the same root.  Returns the origin pole index and the offset tau
 // from it.
-__device__ void secular_root(const double* __restrict__ delta, const double* __restrict__ zeta,
+__device__ void secular_root(const double* __restrict__ delta, const double* __restrict__ z2,
                              int k, double rho, int j, int G, int g, int& org, double& tau_out) {
   // sum over the group by DPP: quad_perm 1032 (pairs), quad_perm 2301
   // (quads), row_half_mirror (eights; after the quad steps it exchanges equal
@@ -245,7 +247,7 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
   if (j < k - 1) {
     const double gap = delta[j + 1] - delta[j];
     double w = 0.0;
-    for (int i = g; i < k; i += G) w += zeta[i] * zeta[i] / ((delta[i] - delta[j]) - 0.5 * gap);
+    for (int i = g; i < k; i += G) w += z2[i] / ((delta[i] - delta[j]) - 0.5 * gap);
     w = 1.0 / rho + gsum(w);
     if (w >= 0.0) {
       o = j;
@@ -258,7 +260,7 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
     }
   } else {
     double zz = 0.0;
-    for (int i = g; i < k; i += G) zz += zeta[i] * zeta[i];
+    for (int i = g; i < k; i += G) zz += z2[i];
     zz = gsum(zz);
     o = j;
     a = 0.0;
@@ -269,16 +271,24 @@ __device__ void secular_root(const double* __restrict__ delta, const double* __r
   double x = 0.5 * (a + b);
   for (int it = 0; it < 100; ++it) {
     double w = 0.0, err = 0.0, psi1 = 0.0, phi1 = 0.0;
-    for (int i = g; i < k; i += G) {
+    // terms up to the left pole feed psi', the rest phi'; 1/Di within about an
+    // ulp (enough for the iteration's tolerance tests), t / Di = t * ri
+    int i = g;
+    for (; i <= jl && i < k; i += G) {
       const double Di = (delta[i] - dlo) - x;
-      // 1/Di within about an ulp (enough for the iteration's tolerance
-      // tests); t / Di = t * ri
       const double ri = rcp_nr(Di);
-      const double t = zeta[i] * zeta[i] * ri;
+      const double t = z2[i] * ri;
       w += t;
       err += fabs(t);
-      if (i <= jl) psi1 += t * ri;
-      else phi1 += t * ri;
+      psi1 += t * ri;
+    }
+    for (; i < k; i += G) {
+      const double Di = (delta[i] - dlo) - x;
+      const double ri = rcp_nr(Di);
+      const double t = z2[i] * ri;
+      w += t;
+      err += fabs(t);
+      phi1 += t * ri;
     }
     w = 1.0 / rho + gsum(w);
     err = 1.0 / rho + gsum(err);
@@ -522,18 +532,21 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   }
   for (int j = tid; j < k; j += NT) {
     L.delta[j] = L.dS[L.nd[j]];
-    L.zeta[j] = L.zS[L.nd[j]];
+    const double zj = L.zS[L.nd[j]];
+    L.zeta[j] = zj;
+    L.z2[j] = zj * zj;
   }
   __syncthreads();
-  // secular roots, G lanes per root (up to 8, as many as one round allows)
+  // secular roots and the recomputed z, G lanes per root (up to 8, as many
+  // as one round allows)
+  int G = 1;
+  while (G < 8 && 2 * G * k <= NT) G *= 2;
+  const int g = tid & (G - 1);
   {
-    int G = 1;
-    while (G < 8 && 2 * G * k <= NT) G *= 2;
-    const int g = tid & (G - 1);
     for (int j = tid / G; j < k; j += NT / G) {
       int o;
       double t;
-      secular_root(L.delta, L.zeta, k, rho2, j, G, g, o, t);
+      secular_root(L.delta, L.z2, k, rho2, j, G, g, o, t);
       if (g == 0) {
         L.org[j] = o;
         L.tau[j] = t;
@@ -544,13 +557,15 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   // recomputed z: zh_i^2 = (lambda_i - d_i)/rho * prod_{j != i} (d_i - lambda_j)/(d_i - d_j)
   // (numerators and denominators gathered in groups of four, one division per
   // group: every factor lies between about 1e-18 and 10, so a group cannot
-  // leave the double range)
-  for (int i = tid; i < k; i += NT) {
+  // leave the double range).  Lane g of root i's group takes j = g, g+G, ...;
+  // the partial products are combined by DPP (quad_perm 1032, 2301,
+  // row_half_mirror), as the secular sums are.
+  for (int i = tid / G; i < k; i += NT / G) {
     const double di = L.delta[i];
-    double prod = -((di - L.delta[L.org[i]]) - L.tau[i]) / rho2;
+    double prod = g == 0 ? -((di - L.delta[L.org[i]]) - L.tau[i]) / rho2 : 1.0;
     double num = 1.0, den = 1.0;
     int cnt = 0;
-    for (int j = 0; j < k; ++j) {
+    for (int j = g; j < k; j += G) {
       if (j == i) continue;
       num *= (di - L.delta[L.org[j]]) - L.tau[j];
       den *= di - L.delta[j];
@@ -561,7 +576,10 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
       }
     }
     prod *= num / den;
-    L.zhat[i] = copysign(sqrt(fmax(prod, 0.0)), L.zeta[i]);
+    if (G >= 2) prod *= dpp_f64<0xB1>(prod);
+    if (G >= 4) prod *= dpp_f64<0x4E>(prod);
+    if (G >= 8) prod *= dpp_f64<0x141>(prod);
+    if (g == 0) L.zhat[i] = copysign(sqrt(fmax(prod, 0.0)), L.zeta[i]);
   }
   __syncthreads();
   // sum_i (zh_i / D_i)^2 with pairs over a common denominator:
@@ -969,7 +987,7 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
 
 }  // namespace
 
-size_t dc_prep_lds(int m) { return (size_t)m * (12 * sizeof(double) + 7 * sizeof(int)); }
+size_t dc_prep_lds(int m) { return (size_t)m * (13 * sizeof(double) + 7 * sizeof(int)); }
 
 void dc_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_dc_prep<kThreads>,
