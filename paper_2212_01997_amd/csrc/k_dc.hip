@@ -583,22 +583,27 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   }
   __syncthreads();
   // sum_i (zh_i / D_i)^2 with pairs over a common denominator:
-  // (za^2 Db^2 + zb^2 Da^2) / (Da^2 Db^2)
-  for (int j = tid; j < k; j += NT) {
+  // (za^2 Db^2 + zb^2 Da^2) / (Da^2 Db^2); lane g of root j's group takes the
+  // pairs starting at i = 2g, 2g + 2G, ... (and the odd last term if it falls
+  // to it), the partial sums combined by DPP
+  for (int j = tid / G; j < k; j += NT / G) {
     const double dO = L.delta[L.org[j]], tj = L.tau[j];
     double acc = 0.0;
-    int i = 0;
-    for (; i + 1 < k; i += 2) {
+    int i = 2 * g;
+    for (; i + 1 < k; i += 2 * G) {
       const double da = (L.delta[i] - dO) - tj, db = (L.delta[i + 1] - dO) - tj;
       const double za = L.zhat[i], zb = L.zhat[i + 1];
       const double da2 = da * da, db2 = db * db;
       acc += (za * za * db2 + zb * zb * da2) * rcp_nr(da2 * db2);
     }
-    if (i < k) {
+    if (i == k - 1) {
       const double u = L.zhat[i] / ((L.delta[i] - dO) - tj);
       acc += u * u;
     }
-    L.inv[j] = 1.0 / sqrt(acc);
+    if (G >= 2) acc += dpp_f64<0xB1>(acc);
+    if (G >= 4) acc += dpp_f64<0x4E>(acc);
+    if (G >= 8) acc += dpp_f64<0x141>(acc);
+    if (g == 0) L.inv[j] = 1.0 / sqrt(acc);
   }
   // output order: roots first (items 0..k-1), then the deflated items in
   // index order (the tail of nd lists their sorted indices)
@@ -606,11 +611,20 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   compact<NT>(m, [&](int i) { return L.defl[i] != 0; }, L.nd, k, wtot);
   for (int q = k + tid; q < m; q += NT) L.vals[q] = L.dS[L.nd[q]];
   __syncthreads();
-  for (int it = tid; it < m; it += NT) {
-    const double x = L.vals[it];
-    int rk = 0;
-    for (int j = 0; j < m; ++j) rk += (L.vals[j] < x) || (L.vals[j] == x && j < it);
-    L.pos[it] = rk;
+  // ranks of the output values, Gm lanes per value (counts combined by DPP)
+  {
+    int Gm = 1;
+    while (Gm < 8 && 2 * Gm * m <= NT) Gm *= 2;
+    const int gm = tid & (Gm - 1);
+    for (int it = tid / Gm; it < m; it += NT / Gm) {
+      const double x = L.vals[it];
+      int rk = 0;
+      for (int j = gm; j < m; j += Gm) rk += (L.vals[j] < x) || (L.vals[j] == x && j < it);
+      if (Gm >= 2) rk += __builtin_amdgcn_update_dpp(0, rk, 0xB1, 0xF, 0xF, false);
+      if (Gm >= 4) rk += __builtin_amdgcn_update_dpp(0, rk, 0x4E, 0xF, 0xF, false);
+      if (Gm >= 8) rk += __builtin_amdgcn_update_dpp(0, rk, 0x141, 0xF, 0xF, false);
+      if (gm == 0) L.pos[it] = rk;
+    }
   }
   __syncthreads();
   const int base = b + lo;
