@@ -300,7 +300,11 @@ void build_dc_plan(gq_graph* g) {
         stack.push_back({nd.lo, m1, nd.depth + 1});
         stack.push_back({nd.lo + m1, nd.m - m1, nd.depth + 1});
       } else {
-        g->dc_leaves.insert(g->dc_leaves.end(), {s, nd.lo, nd.m});
+        // the leaf goes where its parent merge reads: a merge at depth d reads
+        // Q for odd d and the scratch for even d (and writes the other one),
+        // so the top merges write Q; a subgraph that is one leaf writes Q
+        const int32_t tgt = nd.depth == 0 ? 0 : ((nd.depth - 1) % 2 == 1 ? 0 : 1);
+        g->dc_leaves.insert(g->dc_leaves.end(), {s, nd.lo, nd.m, tgt});
       }
     }
   }

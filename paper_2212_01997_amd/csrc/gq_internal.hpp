@@ -79,7 +79,7 @@ struct gq_graph_dev {
   int32_t* offcd = nullptr;        // [n_sub+1] offsets of c_i arrays
   int32_t* order = nullptr;        // subgraphs by decreasing n
   int32_t* rho_row_ptr = nullptr;  // [N+1]
-  int32_t* dc_leaves = nullptr;    // [n_leaves*3] (subgraph, lo, m)
+  int32_t* dc_leaves = nullptr;    // [n_leaves*4] (subgraph, lo, m, buffer: 0 Q, 1 scratch)
   int32_t* dc_merges = nullptr;    // [n_merges*4] (subgraph, lo, m1, m2), deepest level first
   int32_t* dc_tiles = nullptr;     // [*3] (merge index within its level, tile row, tile col)
   int32_t n_leaves = 0;

@@ -13,8 +13,11 @@
 //               offsets from the nearer pole), Gu-Eisenstat recomputed z for
 //               orthogonal vectors, column norms and the output order;
 //   k_dc_gemm   tiles of Z_new[:, pos] = Z[:, cols] U with U_ij = zh_i n_j /
-//               (d_i - lambda_j) formed on the fly, plus the deflated columns;
-//   k_dc_copy   the merged block back into place.
+//               (d_i - lambda_j) formed on the fly, plus the deflated columns.
+// The vectors alternate between Q and a scratch of the same layout: a merge at
+// depth d reads Q for odd d and the scratch for even d and writes the other,
+// so the top merges (d = 0) leave them in Q, and every leaf is written where
+// its parent merge reads.
 // k_bt_mfma applies H_0 ... H_{n-3} to the eigenvectors of T in blocks of 16
 // reflectors (compact WY, I - V T V^T; T factors from k_bt_tfactors) on
 // 16-column panels held in registers, both products on FP64 MFMA, and forms
@@ -100,11 +103,13 @@ __device__ double block_max(double x, double* red) {
 __global__ __launch_bounds__(64) void k_dc_leaves(
     const int32_t* __restrict__ leaves, const int32_t* __restrict__ sub_orb_ptr,
     const int64_t* __restrict__ off2, const double* __restrict__ D, const double* __restrict__ E,
-    double* __restrict__ zbuf, double* __restrict__ lam, int32_t* __restrict__ status) {
+    double* __restrict__ qbuf, double* __restrict__ sbuf, double* __restrict__ lam,
+    int32_t* __restrict__ status) {
   __shared__ double zl[kLeaf][kLeaf + 1];
   __shared__ double d[kLeaf], e[kLeaf], cs[2 * kLeaf];
   __shared__ int rank[kLeaf];
-  const int s = leaves[3 * blockIdx.x], lo = leaves[3 * blockIdx.x + 1], m = leaves[3 * blockIdx.x + 2];
+  const int s = leaves[4 * blockIdx.x], lo = leaves[4 * blockIdx.x + 1], m = leaves[4 * blockIdx.x + 2];
+  double* zbuf = leaves[4 * blockIdx.x + 3] ? sbuf : qbuf;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int lane = threadIdx.x;
@@ -769,33 +774,6 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_dc_copy(
-    const int32_t* __restrict__ tiles, const int32_t* __restrict__ merges,
-    const int32_t* __restrict__ sub_orb_ptr, const int64_t* __restrict__ off2,
-    const double* __restrict__ wbuf, double* __restrict__ zbuf) {
-  const int mid = tiles[3 * blockIdx.x], tr = tiles[3 * blockIdx.x + 1], tc = tiles[3 * blockIdx.x + 2];
-  const int s = merges[4 * mid], lo = merges[4 * mid + 1];
-  const int m = merges[4 * mid + 2] + merges[4 * mid + 3];
-  const int n = sub_orb_ptr[s + 1] - sub_orb_ptr[s];
-  const double* W = wbuf + off2[s];
-  double* Z = zbuf + off2[s];
-  // all loads of the tile (clamped, valid addresses) before the guarded stores
-  constexpr int kPer = kTile * kTile / kThreads;
-  double v[kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int idx = threadIdx.x + u * kThreads;
-    const int r = min(tr * kTile + idx % kTile, m - 1), c = min(tc * kTile + idx / kTile, m - 1);
-    v[u] = W[(lo + r) + (size_t)n * (lo + c)];
-  }
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int idx = threadIdx.x + u * kThreads;
-    const int r = tr * kTile + idx % kTile, c = tc * kTile + idx / kTile;
-    if (r < m && c < m) Z[(lo + r) + (size_t)n * (lo + c)] = v[u];
-  }
-}
-
 // T factors of the compact-WY blocks: H_kb ... H_{kb+nb-1} = I - V T V^T with
 // T upper triangular (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V^T v_i).
 // One workgroup per (subgraph, block); T stored as kNb x kNb row-major.
@@ -1021,12 +999,17 @@ void dc_set_attributes() {
 void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   const gq_graph_dev& dv = g->dev;
   hipStream_t st = ctx->stream;
-  // Z lives in e->Q, the merge scratch in e->Y; eigenvalues in e->eps
+  // the vectors alternate between e->Q and the scratch e->Y by merge depth
+  // (the top merges write Q); eigenvalues in e->eps
   prof_begin(ctx, "k_dc_leaves");
   hipLaunchKernelGGL(k_dc_leaves, dim3(dv.n_leaves), dim3(64), 0, st, dv.dc_leaves, dv.sub_orb_ptr,
-                     dv.off2, e->dd, e->ee, e->Q, e->eps, e->status);
+                     dv.off2, e->dd, e->ee, e->Q, e->Y, e->eps, e->status);
   prof_end(ctx);
-  for (int lv = 0; lv < (int)g->dc_level_merge_off.size() - 1; ++lv) {
+  const int nlev = (int)g->dc_level_merge_off.size() - 1;
+  for (int lv = 0; lv < nlev; ++lv) {
+    const int depth = nlev - 1 - lv;  // levels run from the deepest merges up
+    double* zin = depth % 2 == 1 ? e->Q : e->Y;
+    double* zout = depth % 2 == 1 ? e->Y : e->Q;
     const int m0 = g->dc_level_merge_off[lv], m1 = g->dc_level_merge_off[lv + 1];
     const int t0 = g->dc_level_tile_off[lv], t1 = g->dc_level_tile_off[lv + 1];
     if (m1 == m0) continue;
@@ -1037,19 +1020,15 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     const bool big = g->dc_level_msum[lv] > 256L * (m1 - m0);
     auto prep = big ? k_dc_prep<1024> : k_dc_prep<kThreads>;
     hipLaunchKernelGGL(prep, dim3(m1 - m0), dim3(big ? 1024 : kThreads), dc_prep_lds(maxm), st,
-                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, e->Q, e->eps,
+                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, zin, e->eps,
                        e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
                        e->md_delta, e->md_tau, e->md_zhat, e->md_inv);
     prof_end(ctx);
     prof_begin(ctx, "k_dc_gemm");
     hipLaunchKernelGGL(k_dc_gemm, dim3(t1 - t0), dim3(kThreads), 0, st, dv.dc_tiles + 3 * t0,
-                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->Q, e->Y, e->md_k + m0,
+                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, zin, zout, e->md_k + m0,
                        e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos, e->md_delta,
                        e->md_tau, e->md_zhat, e->md_inv);
-    prof_end(ctx);
-    prof_begin(ctx, "k_dc_copy");
-    hipLaunchKernelGGL(k_dc_copy, dim3(t1 - t0), dim3(kThreads), 0, st, dv.dc_tiles + 3 * t0,
-                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->Y, e->Q);
     prof_end(ctx);
   }
   const int maxn = g->info.max_n;
