@@ -777,13 +777,6 @@ __global__ __launch_bounds__(kThreads) void k_dc_gemm(
 // T factors of the compact-WY blocks: H_kb ... H_{kb+nb-1} = I - V T V^T with
 // T upper triangular (T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V^T v_i).
 // One workgroup per (subgraph, block); T stored as kNb x kNb row-major.
-__device__ __forceinline__ double refl(const double* A, int n, int kb, int nb, int r, int q) {
-  const int top = kb + q + 1;
-  if (q >= nb || r < top) return 0.0;
-  if (r == top) return 1.0;
-  return A[r + (size_t)n * (kb + q)];
-}
-
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
@@ -809,11 +802,21 @@ __global__ __launch_bounds__(kThreads) void k_bt_tfactors(
   const double* A = abuf + off2[s];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  // Gram matrix V^T V: four row groups per step, their reflector entries
+  // loaded from clamped (valid) addresses together and masked at use
   v4d G = {0.0, 0.0, 0.0, 0.0};
-  for (int row0 = kb + 1 + 4 * w; row0 < n; row0 += 16) {
-    const int r = row0 + lk;
-    const double a = r < n ? refl(A, n, kb, nb, r, li) : 0.0;
-    G = mfma16(a, a, G);
+  const int qc = kb + min(li, nb - 1);
+  const int top = kb + li + 1;
+  for (int row0 = kb + 1 + 4 * w; row0 < n; row0 += 64) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = A[min(row0 + 16 * u + lk, n - 1) + (size_t)n * qc];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = row0 + 16 * u + lk;
+      const double a = (li < nb && r < n && r >= top) ? (r == top ? 1.0 : v[u]) : 0.0;
+      G = mfma16(a, a, G);
+    }
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) Gp[w][4 * r + lk][li] = G[r];
@@ -823,18 +826,26 @@ __global__ __launch_bounds__(kThreads) void k_bt_tfactors(
     Gp[0][p][q] = Gp[0][p][q] + Gp[1][p][q] + Gp[2][p][q] + Gp[3][p][q];
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < kNb; ++i)
-      for (int j = 0; j < kNb; ++j) T[i][j] = 0.0;
-    for (int i = 0; i < nb; ++i) {
-      const double ti = TAU[b + kb + i];
-      for (int rr = 0; rr < i; ++rr) {
+  // T column by column: T[rr][i] = -tau_i sum_{rr <= qq < i} T[rr][qq] G[qq][i],
+  // T[i][i] = tau_i.  Lane rr of the first wave keeps row rr of T in
+  // registers, so the 16 steps need no barrier.
+  if (tid < kNb) {
+    const int rr = tid;
+    double trow[kNb];
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) trow[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) {
+      if (i < nb) {
+        const double ti = TAU[b + kb + i];
         double acc = 0.0;
-        for (int qq = rr; qq < i; ++qq) acc += T[rr][qq] * Gp[0][qq][i];
-        T[rr][i] = -ti * acc;
+#pragma unroll
+        for (int qq = 0; qq < i; ++qq) acc += (qq >= rr ? trow[qq] : 0.0) * Gp[0][qq][i];
+        trow[i] = rr < i ? -ti * acc : (rr == i ? ti : 0.0);
       }
-      T[i][i] = ti;
     }
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) T[rr][i] = trow[i];
   }
   __syncthreads();
   if (tid < kNb * kNb)
