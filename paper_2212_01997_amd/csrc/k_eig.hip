@@ -1,7 +1,7 @@
 // Principal submatrices and their FP64 eigendecomposition on gfx950.
 //
 // Fig. 1: each subgraph selects the principal submatrix h = H[orbs, orbs].
-// Eq. (SmallKS): h = Q diag(eps) Q^T.  One workgroup (4 waves) per subgraph:
+// Eq. (SmallKS): h = Q diag(eps) Q^T.  One 1024-thread workgroup per subgraph:
 //   k_gather    CSR rows of H -> dense column-major h (binary search of each
 //               column index in the subgraph's sorted orbital list, in LDS)
 //   k_tridiag   blocked Householder reduction to tridiagonal form, reflectors
@@ -18,15 +18,6 @@ namespace gq {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
 // v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A(l%16, l/16) and
 // B(l/16, l%16); D(i, j) is returned in lane j + 16*(i%4), register i/4.
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -35,20 +26,9 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Sum over the workgroup in a fixed order; every thread gets the total.
-__device__ double block_sum(double x, double* red) {
-  x = wave_sum(x);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[w] = x;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int i = 0; i < kWaves; ++i) t += red[i];
-  return t;
-}
+constexpr int kGaThreads = 1024;
 
-__global__ __launch_bounds__(kThreads) void k_gather(
+__global__ __launch_bounds__(kGaThreads) void k_gather(
     const int32_t* __restrict__ h_rp, const int32_t* __restrict__ h_col,
     const double* __restrict__ h_val, double* __restrict__ abuf,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
@@ -63,24 +43,46 @@ __global__ __launch_bounds__(kThreads) void k_gather(
   int32_t* so = si;
   int32_t* sl = si + n;
   double* A = abuf + off2[s];
-  for (int i = threadIdx.x; i < n; i += kThreads) {
+  for (int i = threadIdx.x; i < n; i += kGaThreads) {
     so[i] = sorted_orbs[b + i];
     sl[i] = sorted_local[b + i];
   }
   const size_t nn = (size_t)n * n;
-  for (size_t i = threadIdx.x; i < nn; i += kThreads) A[i] = 0.0;
+  for (size_t i = threadIdx.x; i < nn; i += kGaThreads) A[i] = 0.0;
   __syncthreads();
-  for (int r = threadIdx.x; r < n; r += kThreads) {
+  // T threads share a row (T = kGaThreads / next power of two >= n, at most 8)
+  // and take its nonzeros p = start + h, start + h + T, ...  Four nonzeros at a
+  // time: their column and value loads are issued together, then four
+  // interleaved branch-free binary searches for the column in the sorted
+  // orbital list (the trip count depends only on n).
+  int np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  const int T = min(8, max(1, kGaThreads / np2));
+  const int h = threadIdx.x % T;
+  for (int r = threadIdx.x / T; r < n; r += kGaThreads / T) {
     const int a = sub_orbs[b + r];
-    for (int p = h_rp[a]; p < h_rp[a + 1]; ++p) {
-      const int c = h_col[p];
-      int lo = 0, hi = n;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (so[mid] < c) lo = mid + 1;
-        else hi = mid;
+    const int p_end = h_rp[a + 1];
+    for (int p0 = h_rp[a] + h; p0 < p_end; p0 += 4 * T) {
+      int c[4], base[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int pp = min(p0 + u * T, p_end - 1);
+        c[u] = h_col[pp];
+        v[u] = h_val[pp];
+        base[u] = 0;
       }
-      if (lo < n && so[lo] == c) A[r + (size_t)n * sl[lo]] = h_val[p];
+      for (int len = n; len > 1;) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) base[u] = so[base[u] + half] < c[u] ? base[u] + half : base[u];
+        len -= half;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int pos = base[u] + (so[base[u]] < c[u] ? 1 : 0);  // first index with so >= c
+        if (p0 + u * T < p_end && pos < n && so[pos] == c[u]) A[r + (size_t)n * sl[pos]] = v[u];
+      }
     }
   }
 }
@@ -194,7 +196,6 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
   const int P = kTdThreads / H;
   const int r = tid % P, h = tid / P;
   const bool own = (h == 0) && (r < n);
-  const int rr = min(r, n - 1);  // a valid row for the loads of threads without one
   const int lane = tid & 63, wv = tid >> 6;
 
   for (int k0 = 0; k0 + 2 < n; k0 += kPanel) {
@@ -406,7 +407,7 @@ void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, i
   const int maxn = g->info.max_n;
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_gather");
-  hipLaunchKernelGGL(k_gather, dim3(g->n_sub), dim3(kThreads), 2 * maxn * sizeof(int32_t), st,
+  hipLaunchKernelGGL(k_gather, dim3(g->n_sub), dim3(kGaThreads), 2 * maxn * sizeof(int32_t), st,
                      H->row_ptr, H->col, H->val, A, dv.off2, dv.sub_orb_ptr, dv.sub_orbs,
                      dv.sorted_orbs, dv.sorted_local, dv.order, status);
   prof_end(ctx);
