@@ -259,33 +259,63 @@ __global__ __launch_bounds__(kThreads) void k_density_rows(
   }
 }
 
+constexpr int kDdCols = 32;  // columns of dF per workgroup
+
+// sinh(x)/x for |x| < 0.5 by its Taylor series sum_k x^2k / (2k+1)! up to
+// x^16 (the first omitted term is below 1e-19)
+__device__ __forceinline__ double sinhc_small(double x) {
+  const double u = x * x;
+  double p = 1.0 / 355687428096000.0;
+  p = fma(p, u, 1.0 / 1307674368000.0);
+  p = fma(p, u, 1.0 / 6227020800.0);
+  p = fma(p, u, 1.0 / 39916800.0);
+  p = fma(p, u, 1.0 / 362880.0);
+  p = fma(p, u, 1.0 / 5040.0);
+  p = fma(p, u, 1.0 / 120.0);
+  p = fma(p, u, 1.0 / 6.0);
+  return fma(p, u, 1.0);
+}
+
+// dF for kDdCols columns l of one subgraph, all rows k.  The per-orbital
+// factors |y_k|, e^{-|y_k|} and 1 + e^{-2|y_k|} are formed once in LDS; an
+// element then needs no exponential for x < 0.5 and two otherwise.
 __global__ __launch_bounds__(kThreads) void k_divided_differences(
     const double* __restrict__ eps, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     const double* __restrict__ state, double* __restrict__ dfbuf) {
+  __shared__ double se[kMaxN], sa[kMaxN], sx[kMaxN], sd[kMaxN];
   const int s = order[blockIdx.x];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
-  const size_t nn = (size_t)n * n;
-  const size_t start = (size_t)blockIdx.y * kThreads * 16;
-  if (start >= nn) return;
+  const int l0 = blockIdx.y * kDdCols;
+  if (l0 >= n) return;
   const double mu = state[2], beta = 1.0 / state[3];
+  for (int k = threadIdx.x; k < n; k += kThreads) {
+    const double ek = eps[b + k];
+    const double ak = fabs(0.5 * beta * (ek - mu));
+    const double xk = exp(-ak);
+    se[k] = ek;
+    sa[k] = ak;
+    sx[k] = xk;
+    sd[k] = 1.0 + xk * xk;
+  }
+  __syncthreads();
   double* dF = dfbuf + off2[s];
-  const size_t end = min(nn, start + (size_t)kThreads * 16);
-  for (size_t idx = start + threadIdx.x; idx < end; idx += kThreads) {
-    const int k = (int)(idx % n), l = (int)(idx / n);
-    const double ek = eps[b + k], el = eps[b + l];
-    const double ak = fabs(0.5 * beta * (ek - mu)), al = fabs(0.5 * beta * (el - mu));
-    const double den = (1.0 + exp(-2.0 * ak)) * (1.0 + exp(-2.0 * al));
-    const double x = fabs(0.5 * beta * (ek - el));
-    double val;
-    if (x < 0.5) {
-      const double shc = x == 0.0 ? 1.0 : sinh(x) / x;
-      val = -beta * shc * exp(-(ak + al)) / den;
-    } else {
-      val = -beta * (exp(x - ak - al) - exp(-x - ak - al)) / (2.0 * x * den);
+  const int l1 = min(n, l0 + kDdCols);
+  for (int l = l0; l < l1; ++l) {
+    const double el = se[l], al = sa[l], xl = sx[l], dl = sd[l];
+    for (int k = threadIdx.x; k < n; k += kThreads) {
+      const double den = sd[k] * dl;
+      const double x = fabs(0.5 * beta * (se[k] - el));
+      double val;
+      if (x < 0.5) {
+        val = -beta * sinhc_small(x) * (sx[k] * xl) / den;
+      } else {
+        const double g = exp(x - sa[k] - al), t = exp(-2.0 * x);
+        val = -beta * g * (1.0 - t) / (2.0 * x * den);
+      }
+      dF[k + (size_t)n * l] = val;
     }
-    dF[idx] = val;
   }
 }
 
@@ -324,8 +354,7 @@ void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   const gq_graph_dev& dv = g->dev;
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_divided_differences");
-  const size_t maxnn = (size_t)g->info.max_n * g->info.max_n;
-  dim3 grid(g->n_sub, (unsigned)((maxnn + kThreads * 16 - 1) / (kThreads * 16)));
+  dim3 grid(g->n_sub, (g->info.max_n + kDdCols - 1) / kDdCols);
   hipLaunchKernelGGL(k_divided_differences, grid, dim3(kThreads), 0, st, e->eps, dv.off2,
                      dv.sub_orb_ptr, dv.order, e->mu_state, e->A);
   prof_end(ctx);
