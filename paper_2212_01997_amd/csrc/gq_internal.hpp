@@ -20,8 +20,8 @@ constexpr int kLeaf = 16;
 constexpr int kMaxCore = 32;
 // Core rows handled per workgroup in the core-row products.
 // Points per multisection pass of the chemical-potential search.
-constexpr int kMuPoints = 128;
-constexpr int kMuPasses = 9;
+constexpr int kMuPoints = 32;  // chemical potentials per multisection pass
+constexpr int kMuPasses = 11;  // the bracket shrinks 33^11 = 5e16 fold
 // Size bins of the response's X kernel (upper bounds, orbitals).
 constexpr int kXyBins = 5;
 constexpr int kXyBinMax[kXyBins] = {128, 256, 384, 512, 1024};

@@ -20,7 +20,7 @@ namespace gq {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMuChunk = 128;  // (eps, w) pairs per block of the occupation pass
+constexpr int kMuChunk = 256;  // (eps, w) pairs per block of the occupation pass
 
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
@@ -88,8 +88,9 @@ __global__ __launch_bounds__(kThreads) void k_mu_eval(const double* __restrict__
                                                       const double* __restrict__ wts, int64_t count,
                                                       const double* __restrict__ state,
                                                       double* __restrict__ part) {
+  constexpr int kH = kThreads / kMuPoints;  // threads per point
   __shared__ double se[kMuChunk], sw[kMuChunk];
-  __shared__ double half[kMuPoints];
+  __shared__ double hp[kH][kMuPoints];
   const int64_t base = (int64_t)blockIdx.x * kMuChunk;
   const int cnt = (int)min<int64_t>(kMuChunk, count - base);
   for (int i = threadIdx.x; i < cnt; i += kThreads) {
@@ -99,17 +100,22 @@ __global__ __launch_bounds__(kThreads) void k_mu_eval(const double* __restrict__
   __syncthreads();
   const double lo = state[0], hi = state[1], beta = 1.0 / state[3];
   const int j = threadIdx.x % kMuPoints;
-  const int h = threadIdx.x / kMuPoints;  // 0 or 1
+  const int h = threadIdx.x / kMuPoints;
   const double mu = mu_point(lo, hi, j);
   double acc = 0.0;
-  for (int p = h; p < cnt; p += kThreads / kMuPoints) {
+  for (int p = h; p < cnt; p += kH) {
     double f, f1f;
     fermi2(se[p], mu, beta, f, f1f);
     acc += sw[p] * f;
   }
-  if (h == 1) half[j] = acc;
+  hp[h][j] = acc;
   __syncthreads();
-  if (h == 0) part[(size_t)blockIdx.x * kMuPoints + j] = acc + half[j];
+  if (h == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kH; ++q) t += hp[q][j];
+    part[(size_t)blockIdx.x * kMuPoints + j] = t;
+  }
 }
 
 // Fixed-order reduction of the block partials: group g of kMuGroups sums the
