@@ -869,15 +869,21 @@ __global__ __launch_bounds__(kThreads) void k_bt_mfma(
     const double* __restrict__ abuf, const double* __restrict__ tfac,
     const int32_t* __restrict__ toff, double* __restrict__ zbuf, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core,
-    const int32_t* __restrict__ list, double* __restrict__ wts) {
+    const int32_t* __restrict__ list, double* __restrict__ wts, int count, int npanel) {
   extern __shared__ double vb[];  // [16 * nrb][kLdv]: reflector block, row-major
   __shared__ double Wp[4][16][17];
   __shared__ double Ts[16][17];
   __shared__ double csum[4][16];
-  const int s = list[blockIdx.y];
+  // workgroup id -> (subgraph, column panel): workgroup w runs on XCD w mod 8,
+  // and the npanel panels of a subgraph take consecutive slots of one XCD, so
+  // they stage the same reflector blocks through one L2
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int si = 8 * (slot / npanel) + xcd;
+  if (si >= count) return;
+  const int s = list[si];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
-  const int c0 = blockIdx.x * 16;
+  const int c0 = (slot % npanel) * 16;
   if (c0 >= n) return;
   const int nrb = (n + 15) / 16;
   const double* A = abuf + off2[s];
@@ -1060,11 +1066,12 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     if (hi > lo) {
       const int nmax = g->sub_orb_ptr[g->order[lo] + 1] - g->sub_orb_ptr[g->order[lo]];
       const int nrb = (nmax + 15) / 16;
-      dim3 grid((nmax + 15) / 16, hi - lo);
+      const int npanel = (nmax + 15) / 16, count = hi - lo;
+      dim3 grid(8 * npanel * ((count + 7) / 8));
       const size_t lds = (size_t)16 * nrb * kLdv * sizeof(double);
       auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<6> : cls == 2 ? k_bt_mfma<8> : k_bt_mfma<16>;
       hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, e->A, e->tfac, dv.bt_toff, e->Q,
-                         dv.off2, dv.sub_orb_ptr, dv.n_core, dv.order + lo, e->wts);
+                         dv.off2, dv.sub_orb_ptr, dv.n_core, dv.order + lo, e->wts, count, npanel);
     }
     lo = hi;
   }
