@@ -148,21 +148,23 @@ __device__ double tsum(double x, double* red) {
 
 // Row r of p = A22 v over columns > c, in chunks of kUnroll columns aligned
 // to multiples of kUnroll (chunk g goes to the thread with h = g mod H).  v is
-// 0 at columns <= c, so the chunk holding c+1 may start early; the chunk's v
-// values are one wave-uniform run of LDS, read two at a time.
+// 0 at columns <= c, so the chunk holding c+1 may start early, and 0 at the
+// padding columns n .. n + kUnroll - 1, so the last, partial chunk is loaded
+// like the others (columns clamped to n - 1) and all its loads are in flight
+// together; the chunk's v values are one wave-uniform run of LDS, read two at
+// a time.
 __device__ __forceinline__ double symv_row(const double* __restrict__ row,
                                            const double* __restrict__ vl, int n, int c, int h,
                                            int H) {
   double ac[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) ac[u] = 0.0;
-  const int g_end = n / kUnroll;  // full chunks
-  int g = (c + 1) / kUnroll + h;
-  for (; g < g_end; g += H) {
+  const int g_end = (n + kUnroll - 1) / kUnroll;
+  for (int g = (c + 1) / kUnroll + h; g < g_end; g += H) {
     const int col = g * kUnroll;
     double x[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * (col + u)];
+    for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * min(col + u, n - 1)];
     const double2* v2 = reinterpret_cast<const double2*>(vl + col);
 #pragma unroll
     for (int u = 0; u < kUnroll / 2; ++u) {
@@ -170,9 +172,6 @@ __device__ __forceinline__ double symv_row(const double* __restrict__ row,
       ac[2 * u] += x[2 * u] * vv.x;
       ac[2 * u + 1] += x[2 * u + 1] * vv.y;
     }
-  }
-  if (g == g_end) {  // the partial chunk at the end (this thread's turn)
-    for (int col = max(g_end * kUnroll, c + 1); col < n; ++col) ac[0] += row[(size_t)n * col] * vl[col];
   }
 #pragma unroll
   for (int u = 1; u < kUnroll; ++u) ac[0] += ac[u];
@@ -197,6 +196,7 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
   const int r = tid % P, h = tid / P;
   const bool own = (h == 0) && (r < n);
   const int lane = tid & 63, wv = tid >> 6;
+  if (tid < kUnroll) vl[n + tid] = 0.0;  // padding of the last chunk (the first barrier orders it)
 
   for (int k0 = 0; k0 + 2 < n; k0 += kPanel) {
     const int nb = min(kPanel, n - 2 - k0);
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
   extern __shared__ double pan[];  // 2 kPanel min(max n, kLdsPanelN) doubles
-  __shared__ __align__(16) double vl[kMaxN];
+  __shared__ __align__(16) double vl[kMaxN + kUnroll];  // v, then kUnroll zeros
   __shared__ double part[kTdThreads];
   __shared__ double red[2 * (kTdThreads / 64)];  // the two sums of a column
   __shared__ double yp[kTdThreads / 32][2 * kPanel + 1];
