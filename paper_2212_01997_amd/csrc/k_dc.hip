@@ -542,10 +542,10 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
     L.z2[j] = zj * zj;
   }
   __syncthreads();
-  // secular roots and the recomputed z, G lanes per root (up to 8, as many
-  // as one round allows)
+  // secular roots and the recomputed z, G lanes per root: G doubles (up to
+  // 8) while G k fits the workgroup, so the roots take one or two rounds
   int G = 1;
-  while (G < 8 && 2 * G * k <= NT) G *= 2;
+  while (G < 8 && G * k <= NT) G *= 2;
   const int g = tid & (G - 1);
   {
     for (int j = tid / G; j < k; j += NT / G) {
@@ -1001,6 +1001,8 @@ size_t dc_prep_lds(int m) { return (size_t)m * (13 * sizeof(double) + 7 * sizeof
 void dc_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_dc_prep<kThreads>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
+  (void)hipFuncSetAttribute((const void*)k_dc_prep<512>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
   (void)hipFuncSetAttribute((const void*)k_dc_prep<1024>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1032,11 +1034,12 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     if (m1 == m0) continue;
     const int maxm = g->dc_level_maxm[lv];
     prof_begin(ctx, "k_dc_prep");
-    // levels whose merges average over 256 run on 1024 threads, so that one
-    // round covers their roots
-    const bool big = g->dc_level_msum[lv] > 256L * (m1 - m0);
-    auto prep = big ? k_dc_prep<1024> : k_dc_prep<kThreads>;
-    hipLaunchKernelGGL(prep, dim3(m1 - m0), dim3(big ? 1024 : kThreads), dc_prep_lds(maxm), st,
+    // levels whose merges average over 256 run on 1024 threads, over 128 on
+    // 512, the rest on 256, so that a merge's roots take one or two rounds
+    const int64_t msum = g->dc_level_msum[lv], nm = m1 - m0;
+    const int ntl = msum > 256 * nm ? 1024 : msum > 128 * nm ? 512 : kThreads;
+    auto prep = ntl == 1024 ? k_dc_prep<1024> : ntl == 512 ? k_dc_prep<512> : k_dc_prep<kThreads>;
+    hipLaunchKernelGGL(prep, dim3(m1 - m0), dim3(ntl), dc_prep_lds(maxm), st,
                        dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, zin, e->eps,
                        e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
                        e->md_delta, e->md_tau, e->md_zhat, e->md_inv);
