@@ -97,22 +97,33 @@ __device__ double block_max(double x, double* red) {
 }
 
 // ------------------------------------------------------------------ leaves
-// One wave per leaf [lo, lo+m) of subgraph s; every lane runs the scalar QL
-// recurrence on a wave-private copy of (d, e) and applies each rotation to its
-// own row of Z, kept in LDS.
+// Sixteen lanes per leaf [lo, lo+m) of subgraph s, four leaves per wave:
+// every lane of a group runs the scalar QL recurrence on the group's copy of
+// (d, e) and applies each rotation to its own row of Z, kept in LDS.
 __global__ __launch_bounds__(64) void k_dc_leaves(
-    const int32_t* __restrict__ leaves, const int32_t* __restrict__ sub_orb_ptr,
+    const int32_t* __restrict__ leaves, int n_leaves, const int32_t* __restrict__ sub_orb_ptr,
     const int64_t* __restrict__ off2, const double* __restrict__ D, const double* __restrict__ E,
     double* __restrict__ qbuf, double* __restrict__ sbuf, double* __restrict__ lam,
     int32_t* __restrict__ status) {
-  __shared__ double zl[kLeaf][kLeaf + 1];
-  __shared__ double d[kLeaf], e[kLeaf], cs[2 * kLeaf];
-  __shared__ int rank[kLeaf];
-  const int s = leaves[4 * blockIdx.x], lo = leaves[4 * blockIdx.x + 1], m = leaves[4 * blockIdx.x + 2];
-  double* zbuf = leaves[4 * blockIdx.x + 3] ? sbuf : qbuf;
+  // four leaves per wave: lanes 16 gi .. 16 gi + 15 take leaf 4 blockIdx.x + gi
+  // with arrays of their own (the QL loop below has no barrier, so the groups
+  // may diverge)
+  __shared__ double zls[4][kLeaf][kLeaf + 1];
+  __shared__ double ds[4][kLeaf], es[4][kLeaf], css[4][2 * kLeaf];
+  __shared__ int ranks[4][kLeaf];
+  const int gi = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  const int leaf = 4 * blockIdx.x + gi;
+  const bool live = leaf < n_leaves;
+  const int lf = live ? leaf : n_leaves - 1;
+  const int s = leaves[4 * lf], lo = leaves[4 * lf + 1], m = live ? leaves[4 * lf + 2] : 0;
+  double* zbuf = leaves[4 * lf + 3] ? sbuf : qbuf;
+  double(*zl)[kLeaf + 1] = zls[gi];
+  double* d = ds[gi];
+  double* e = es[gi];
+  double* cs = css[gi];
+  int* rank = ranks[gi];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
-  const int lane = threadIdx.x;
   if (lane < m) {
     double dv = D[b + lo + lane];
     if (lane == 0 && lo > 0) dv -= fabs(E[b + lo - 1]);
@@ -1021,8 +1032,9 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   // the vectors alternate between e->Q and the scratch e->Y by merge depth
   // (the top merges write Q); eigenvalues in e->eps
   prof_begin(ctx, "k_dc_leaves");
-  hipLaunchKernelGGL(k_dc_leaves, dim3(dv.n_leaves), dim3(64), 0, st, dv.dc_leaves, dv.sub_orb_ptr,
-                     dv.off2, e->dd, e->ee, e->Q, e->Y, e->eps, e->status);
+  hipLaunchKernelGGL(k_dc_leaves, dim3((dv.n_leaves + 3) / 4), dim3(64), 0, st, dv.dc_leaves,
+                     dv.n_leaves, dv.sub_orb_ptr, dv.off2, e->dd, e->ee, e->Q, e->Y, e->eps,
+                     e->status);
   prof_end(ctx);
   const int nlev = (int)g->dc_level_merge_off.size() - 1;
   for (int lv = 0; lv < nlev; ++lv) {
