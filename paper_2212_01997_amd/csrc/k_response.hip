@@ -62,7 +62,7 @@ __device__ __forceinline__ v4f mfma16f(float a, float b, v4f c) {
 }
 
 constexpr int kXK = 32;  // K chunk of the FP32 X tiles
-constexpr int kXyKq = 2;  // FP64 perturbations per workgroup when K > 1
+constexpr int kXyKq = 3;  // perturbations per workgroup when K > 1 (two workgroups per CU)
 
 // FP32 tiles: four waves in a 2x2 arrangement; each wave owns a (TM/2)x(TM/2)
 // quarter of the tile, made of WB x WB 16x16 MFMA blocks.
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256, 4) void k_xy(
 // Y tiles for KQ perturbations per workgroup (grid.y = ceil(K / KQ)), FP64 or
 // split-FP32.
 template <int TM, int KQ, bool SPLIT>
-__global__ __launch_bounds__(256, 3) void k_xy_kq(
+__global__ __launch_bounds__(256, 2) void k_xy_kq(
     const double* __restrict__ qbuf, const float* __restrict__ q32,
     const double* __restrict__ dfbuf, double* __restrict__ ybuf, const double* __restrict__ hloc,
     const int32_t* __restrict__ tiles, XcdSplit split, const int64_t* __restrict__ off2,

@@ -140,13 +140,14 @@ def test_capture_replay(water60, precision):
 
 
 def test_grouped_perturbations_equal_single(ctx, water60):
-    """K = 3 perturbations in one call (two per workgroup in the X kernel, the
-    last one alone) give, bit for bit, what three K = 1 calls give, on the FP64
-    and the split-FP32 path."""
+    """K = 4 perturbations in one call (three per workgroup in the X kernel,
+    the last one alone) give, bit for bit, what four K = 1 calls give, on the
+    FP64 and the split-FP32 path."""
     import torch
     s, core, prev, h1, r = water60
+    assert h1.shape[0] == 3
+    h1 = np.concatenate([h1, (0.5 * h1[0] + h1[2])[None]])
     K = h1.shape[0]
-    assert K == 3
     p = _path(ctx, s, core, prev, K)
     p.ground_state(KT)
     h1d = torch.as_tensor(h1, device="cuda")
