@@ -876,7 +876,7 @@ __global__ __launch_bounds__(kThreads) void k_bt_tfactors(
 // products run on MFMA: W = V^T Z (partial per wave, summed in LDS), W2 = T W,
 // Z -= V W2.  Also forms the core weights of the panel's columns.
 template <int MRB>
-__global__ __launch_bounds__(kThreads) void k_bt_mfma(
+__global__ __launch_bounds__(kThreads, MRB <= 4 ? 4 : MRB <= 6 ? 3 : MRB <= 10 ? 2 : 1) void k_bt_mfma(
     const double* __restrict__ abuf, const double* __restrict__ tfac,
     const int32_t* __restrict__ toff, double* __restrict__ zbuf, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core,
@@ -1022,6 +1022,8 @@ void dc_set_attributes() {
                             (int)(384 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(512 * kLdv * sizeof(double)));
+  (void)hipFuncSetAttribute((const void*)k_bt_mfma<10>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(640 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(kMaxN * kLdv * sizeof(double)));
 }
@@ -1070,11 +1072,11 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   prof_end(ctx);
   prof_begin(ctx, "k_backtransform");
   // subgraphs are ordered by decreasing size: classes n <= 256, <= 384, <= 512,
-  // <= 1024 are contiguous ranges of that order, each launched with its
-  // register panel (the smallest that holds its row blocks)
-  static constexpr int kClassN[4] = {256, 384, 512, kMaxN};
+  // <= 640, <= 1024 are contiguous ranges of that order, each launched with
+  // its register panel (the smallest that holds its row blocks)
+  static constexpr int kClassN[5] = {256, 384, 512, 640, kMaxN};
   int lo = 0;
-  for (int cls = 3; cls >= 0; --cls) {
+  for (int cls = 4; cls >= 0; --cls) {
     const int floor_n = cls == 0 ? 0 : kClassN[cls - 1];
     int hi = lo;
     while (hi < g->n_sub && g->sub_orb_ptr[g->order[hi] + 1] - g->sub_orb_ptr[g->order[hi]] > floor_n) ++hi;
@@ -1084,7 +1086,7 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
       const int npanel = (nmax + 15) / 16, count = hi - lo;
       dim3 grid(8 * npanel * ((count + 7) / 8));
       const size_t lds = (size_t)16 * nrb * kLdv * sizeof(double);
-      auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<6> : cls == 2 ? k_bt_mfma<8> : k_bt_mfma<16>;
+      auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<6> : cls == 2 ? k_bt_mfma<8> : cls == 3 ? k_bt_mfma<10> : k_bt_mfma<16>;
       hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, e->A, e->tfac, dv.bt_toff, e->Q,
                          dv.off2, dv.sub_orb_ptr, dv.n_core, dv.order + lo, e->wts, count, npanel);
     }
