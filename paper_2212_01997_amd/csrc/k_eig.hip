@@ -153,18 +153,28 @@ __device__ double tsum(double x, double* red) {
 // like the others (columns clamped to n - 1) and all its loads are in flight
 // together; the chunk's v values are one wave-uniform run of LDS, read two at
 // a time.
+// The thread with h = 0 also returns its row's entry in column c + 1 (first
+// chunk), which the next column of the panel starts from.
 __device__ __forceinline__ double symv_row(const double* __restrict__ row,
                                            const double* __restrict__ vl, int n, int c, int h,
-                                           int H) {
+                                           int H, double& next_col) {
   double ac[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) ac[u] = 0.0;
   const int g_end = (n + kUnroll - 1) / kUnroll;
+  const int u1 = (c + 1) % kUnroll;
+  bool first = true;
   for (int g = (c + 1) / kUnroll + h; g < g_end; g += H) {
     const int col = g * kUnroll;
     double x[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * min(col + u, n - 1)];
+    if (first) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (u == u1) next_col = x[u];
+      first = false;
+    }
     const double2* v2 = reinterpret_cast<const double2*>(vl + col);
 #pragma unroll
     for (int u = 0; u < kUnroll / 2; ++u) {
@@ -208,6 +218,11 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
       if constexpr (LP) return pan[(kPanel + q) * n + row];
       else return Wg[q * n + row];
     };
+    // A[r, c] of the panel's next column, taken from this column's symmetric
+    // product (the row's first chunk holds column c + 1); the panel's first
+    // column and a column after a skipped one load it
+    double a_next = 0.0;
+    bool have_next = false;
     for (int j = 0; j < nb; ++j) {
       const int c = k0 + j;
       if constexpr (!LP) {
@@ -221,7 +236,7 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
       __syncthreads();
       double a = 0.0;
       if (own && r >= c) {
-        a = A[r + (size_t)n * c];
+        a = have_next ? a_next : A[r + (size_t)n * c];
 #pragma unroll 4
         for (int q = 0; q < j; ++q) {
           const double vc = LP ? Vp(q, c) : rowc[q];
@@ -251,6 +266,7 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
         }
       }
       __syncthreads();
+      have_next = false;
       if (tau == 0.0) {
         // H = I (column already reduced): it adds no correction to the panel
         if (own) {
@@ -280,7 +296,8 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
       }
       // p = A22 v over the stale trailing matrix
       double acc = 0.0;
-      if (r >= c + 1 && r < n) acc = symv_row(A + r, vl, n, c, h, H);
+      if (r >= c + 1 && r < n) acc = symv_row(A + r, vl, n, c, h, H, a_next);
+      have_next = true;
       part[tid] = acc;
       __syncthreads();
       if (tid < 2 * kPanel && (tid % kPanel) < j) {
