@@ -449,8 +449,11 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   // whose pole is close to that of the previous kept entry deflates by a
   // Givens rotation.  The kept entries are compacted in order first (the
   // scan's result when no rotation happens) and every consecutive pair is
-  // tested with the scan's own arithmetic; only if some pair needs a rotation
-  // does thread 0 run the sequential scan, which then decides everything.
+  // tested with the scan's own arithmetic (the result kept per pair in pos);
+  // only if some pair needs a rotation does thread 0 run the scan, over the
+  // kept entries: a pair whose left entry no rotation has changed holds the
+  // values the parallel test saw, so it takes that result, and only the pair
+  // after a rotation is tested again.
   for (int i = tid; i < m; i += NT) L.defl[i] = rho2 * fabs(L.zS[i]) <= tol ? 1 : 0;
   if (tid == 0) sh_rot = 0;
   __syncthreads();
@@ -460,7 +463,9 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
     const double t = hypot(L.zS[p], L.zS[i]);
     const double c = L.zS[i] / t;
     const double sn = -L.zS[p] / t;
-    if (fabs((L.dS[i] - L.dS[p]) * c * sn) <= tol) sh_rot = 1;
+    const bool rot = fabs((L.dS[i] - L.dS[p]) * c * sn) <= tol;
+    L.pos[q] = rot ? 1 : 0;
+    if (rot) sh_rot = 1;
   }
   __syncthreads();
   const bool any_rot = sh_rot != 0;
@@ -469,21 +474,20 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
     sh_nrot = 0;
   }
   if (any_rot && tid == 0) {
-    int p = -1, k = 0, nrot = 0;
-    for (int i = 0; i < m; ++i) {
-      L.defl[i] = 0;
-      if (rho2 * fabs(L.zS[i]) <= tol) {
-        L.defl[i] = 1;
-        continue;
+    // nd is rewritten in place: entry q is read before any write reaches it
+    int p = kept > 0 ? L.nd[0] : -1, k = 0, nrot = 0;
+    bool pmod = false;  // p changed by the previous rotation
+    for (int q = 1; q < kept; ++q) {
+      const int i = L.nd[q];
+      bool rot = false;
+      double t = 0.0, c = 0.0, sn = 0.0;
+      if (pmod || L.pos[q]) {
+        t = hypot(L.zS[p], L.zS[i]);
+        c = L.zS[i] / t;
+        sn = -L.zS[p] / t;
+        rot = fabs((L.dS[i] - L.dS[p]) * c * sn) <= tol;
       }
-      if (p < 0) {
-        p = i;
-        continue;
-      }
-      const double t = hypot(L.zS[p], L.zS[i]);
-      const double c = L.zS[i] / t;
-      const double sn = -L.zS[p] / t;
-      if (fabs((L.dS[i] - L.dS[p]) * c * sn) <= tol) {
+      if (rot) {
         L.rp[nrot] = p;
         L.ri[nrot] = i;
         L.rc[nrot] = c;
@@ -498,6 +502,7 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
       } else {
         L.nd[k++] = p;
       }
+      pmod = rot;
       p = i;
     }
     if (p >= 0) L.nd[k++] = p;
