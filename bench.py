@@ -34,7 +34,7 @@ def log(msg):
 
 
 def algorithmic_work(sizes, cores):
-    """Per-launch algorithmic flops of each kernel (sum over subgraphs)."""
+    """Algorithmic flops of each kernel per step (sum over subgraphs)."""
     n = sizes.astype(float)
     c = cores.astype(float)
     return {
@@ -49,7 +49,7 @@ def algorithmic_work(sizes, cores):
 
 
 def tridiag_bytes(sizes):
-    """Algorithmic HBM bytes of one k_tridiag launch (Sec. II.D eigensolve,
+    """Algorithmic HBM bytes of k_tridiag per step (Sec. II.D eigensolve,
     one-stage Householder reduction): for every column c the symmetric product
     reads the trailing matrix (rows and columns > c) once, and every panel of
     16 reflectors reads and writes the trailing matrix once in its rank-2x16
@@ -429,14 +429,18 @@ def main():
     per_launch = {k: v[1] / v[0] for k, v in kt.items()}
     work = algorithmic_work(sizes, cores_n)
     dominant = max(per_step, key=per_step.get)
-    flops = work.get(dominant, 0.0)
+    # work per step over the kernel's summed launch durations per step, which
+    # is work per launch over the average launch duration when the launches
+    # share the work evenly (the eigensolve launches k_tridiag once per size
+    # class, on two streams, so their durations overlap and this understates)
     launches_per_step = kt[dominant][0] / nprof
+    flops = work.get(dominant, 0.0) / launches_per_step
     launch_s = per_launch[dominant] * 1e-3
     achieved = flops / launch_s if flops else 0.0
     if dominant == "k_tridiag":
         # BLAS-2 bound: the symmetric product streams the trailing matrix once
         # per column, so the roofline is HBM with the algorithm's own bytes
-        nbytes = tridiag_bytes(sizes)
+        nbytes = tridiag_bytes(sizes) / launches_per_step
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": nbytes / launch_s / 1e9,
                     "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": nbytes / launch_s / PEAK_HBM,
                     "traffic": measured_traffic(dominant),

@@ -26,9 +26,13 @@
  *   - Host pointers are borrowed for the call; the library copies what it
  *     keeps.  Device pointers named *_dev point to memory on the context's
  *     device; output buffers are allocated by the caller.
- *   - All device work is enqueued on the context's stream (a hipStream_t
- *     given at gq_ctx_create).  A call blocks the host only where it returns
- *     a host scalar (noted per call).
+ *   - All device work is ordered on the context's stream (a hipStream_t
+ *     given at gq_ctx_create).  The eigensolve runs its smaller subgraphs on
+ *     a second stream that the context owns, forked from the context's
+ *     stream by an event and joined back into it before the call's later
+ *     work, so callers (and a HIP graph captured on the context's stream)
+ *     see one stream.  A call blocks the host only where it returns a host
+ *     scalar (noted per call).
  *   - Errors: every call returns gq_status; on error the outputs are
  *     unspecified, handles stay valid, and gq_last_error() gives a message
  *     (thread-local).  No exception crosses the ABI.
@@ -278,7 +282,8 @@ void gq_server_destroy(gq_server* s);
 
 /* ---------------------------------------------------------- profiling
  * Diagnostics, not part of the method.  While enabled, every kernel launch
- * of the context is bracketed by a hipEvent pair on its stream.
+ * of the context is bracketed by a hipEvent pair on the stream it runs on
+ * (launches on the two streams of the eigensolve overlap in time).
  * gq_ctx_kernel_times waits for the stream and reports per kernel name the
  * launch count and total milliseconds since profiling was last enabled
  * (arrays of `cap` entries, host; *count = entries filled; the name strings

@@ -67,7 +67,7 @@ static gq_status graph_maps(const gq_graph* g, gq_graph_dev& d, Carve& c, bool u
   put(d.bt_toff, g->bt_toff);
   put(d.xy_tiles[0], g->xy_tiles[0]);
   put(d.xy_tiles[1], g->xy_tiles[1]);
-  d.n_leaves = (int32_t)(g->dc_leaves.size() / 4);
+  d.n_leaves = (int32_t)(g->dc_leaves.size() / 4);  // both size classes
   return st;
 }
 
@@ -209,11 +209,24 @@ gq_status gq_ctx_create(int32_t device, void* hip_stream, gq_ctx** out) {
   }
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    set_error("gq_ctx_create: cannot create the side stream and its events");
+    gq_ctx_destroy(c);
+    return GQ_EDEVICE;
+  }
   *out = c;
   return GQ_OK;
 }
 
-void gq_ctx_destroy(gq_ctx* ctx) { delete ctx; }
+void gq_ctx_destroy(gq_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  delete ctx;
+}
 
 gq_status gq_graph_build(int32_t n_atoms, const int32_t* atom_orb_ptr, const gq_csr* H,
                          const gq_csr* rho_prev, const int32_t* core_of_atom, double tau,
@@ -535,20 +548,22 @@ gq_status gq_eigs_vectors(const gq_eigs* e, int32_t i, const double** q_dev, int
 
 namespace gq {
 
-void prof_begin(gq_ctx* ctx, const char* name) {
+void prof_begin_on(gq_ctx* ctx, const char* name, hipStream_t st) {
   if (!ctx->profiling || ctx->capturing) return;
-  gq_prof_rec r{name, nullptr, nullptr};
+  gq_prof_rec r{name, nullptr, nullptr, st};
   if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
     (void)hipGetLastError();
     return;
   }
-  (void)hipEventRecord(r.start, ctx->stream);
+  (void)hipEventRecord(r.start, st);
   ctx->pending.push_back(r);
 }
 
+void prof_begin(gq_ctx* ctx, const char* name) { prof_begin_on(ctx, name, ctx->stream); }
+
 void prof_end(gq_ctx* ctx) {
   if (!ctx->profiling || ctx->capturing || ctx->pending.empty()) return;
-  (void)hipEventRecord(ctx->pending.back().stop, ctx->stream);
+  (void)hipEventRecord(ctx->pending.back().stop, ctx->pending.back().stream);
 }
 
 static void prof_drain(gq_ctx* ctx) {

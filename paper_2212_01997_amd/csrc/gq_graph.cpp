@@ -284,55 +284,69 @@ void build_dc_plan(gq_graph* g) {
   struct Node {
     int32_t lo, m, depth;
   };
-  std::vector<std::vector<int32_t>> by_depth;
+  // class 0: the largest fifth of the subgraphs (order[0..n_big)), class 1:
+  // the rest; the eigensolve runs the two classes on two streams (a larger
+  // first class leaves fewer small subgraphs to fill the CUs while the
+  // largest are reduced, a smaller one puts more of them in its way)
+  g->n_big = std::min(g->n_sub, std::max(1, (g->n_sub + 2) / 5));
   g->dc_leaves.clear();
-  for (int32_t s = 0; s < g->n_sub; ++s) {
-    const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
-    std::vector<Node> stack{{0, n, 0}};
-    while (!stack.empty()) {
-      const Node nd = stack.back();
-      stack.pop_back();
-      if (nd.m > kLeaf) {
-        const int32_t m1 = nd.m / 2;
-        if ((int32_t)by_depth.size() <= nd.depth) by_depth.resize(nd.depth + 1);
-        auto& v = by_depth[nd.depth];
-        v.insert(v.end(), {s, nd.lo, m1, nd.m - m1});
-        stack.push_back({nd.lo, m1, nd.depth + 1});
-        stack.push_back({nd.lo + m1, nd.m - m1, nd.depth + 1});
-      } else {
-        // the leaf goes where its parent merge reads: a merge at depth d reads
-        // Q for odd d and the scratch for even d (and writes the other one),
-        // so the top merges write Q; a subgraph that is one leaf writes Q
-        const int32_t tgt = nd.depth == 0 ? 0 : ((nd.depth - 1) % 2 == 1 ? 0 : 1);
-        g->dc_leaves.insert(g->dc_leaves.end(), {s, nd.lo, nd.m, tgt});
-      }
-    }
-  }
   g->dc_merges.clear();
   g->dc_tiles.clear();
-  g->dc_level_merge_off.assign(1, 0);
-  g->dc_level_tile_off.assign(1, 0);
-  g->dc_level_maxm.clear();
-  g->dc_level_msum.clear();
-  for (int d = (int)by_depth.size() - 1; d >= 0; --d) {
-    const auto& v = by_depth[d];
-    int32_t maxm = 0;
-    int64_t msum = 0;
-    for (size_t q = 0; q < v.size(); q += 4) {
-      const int32_t li = (int32_t)(q / 4);
-      const int32_t m = v[q + 2] + v[q + 3];
-      maxm = std::max(maxm, m);
-      msum += m;
-      const int32_t nt = (m + 63) / 64;
-      for (int32_t tr = 0; tr < nt; ++tr)
-        for (int32_t tc = 0; tc < nt; ++tc) g->dc_tiles.insert(g->dc_tiles.end(), {li, tr, tc});
+  for (int cls = 0; cls < 2; ++cls) {
+    const int32_t i0 = cls == 0 ? 0 : g->n_big, i1 = cls == 0 ? g->n_big : g->n_sub;
+    std::vector<std::vector<int32_t>> by_depth;
+    g->dc_leaf_off[cls] = (int32_t)(g->dc_leaves.size() / 4);
+    for (int32_t oi = i0; oi < i1; ++oi) {
+      const int32_t s = g->order[oi];
+      const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
+      std::vector<Node> stack{{0, n, 0}};
+      while (!stack.empty()) {
+        const Node nd = stack.back();
+        stack.pop_back();
+        if (nd.m > kLeaf) {
+          const int32_t m1 = nd.m / 2;
+          if ((int32_t)by_depth.size() <= nd.depth) by_depth.resize(nd.depth + 1);
+          auto& v = by_depth[nd.depth];
+          v.insert(v.end(), {s, nd.lo, m1, nd.m - m1});
+          stack.push_back({nd.lo, m1, nd.depth + 1});
+          stack.push_back({nd.lo + m1, nd.m - m1, nd.depth + 1});
+        } else {
+          // the leaf goes where its parent merge reads: a merge at depth d
+          // reads Q for odd d and the scratch for even d (and writes the other
+          // one), so the top merges write Q; a subgraph that is one leaf
+          // writes Q
+          const int32_t tgt = nd.depth == 0 ? 0 : ((nd.depth - 1) % 2 == 1 ? 0 : 1);
+          g->dc_leaves.insert(g->dc_leaves.end(), {s, nd.lo, nd.m, tgt});
+        }
+      }
     }
-    g->dc_merges.insert(g->dc_merges.end(), v.begin(), v.end());
-    g->dc_level_merge_off.push_back((int32_t)(g->dc_merges.size() / 4));
-    g->dc_level_tile_off.push_back((int32_t)(g->dc_tiles.size() / 3));
-    g->dc_level_maxm.push_back(maxm);
-    g->dc_level_msum.push_back(msum);
+    auto& mo = g->dc_level_merge_off[cls];
+    auto& to = g->dc_level_tile_off[cls];
+    mo.assign(1, (int32_t)(g->dc_merges.size() / 4));
+    to.assign(1, (int32_t)(g->dc_tiles.size() / 3));
+    g->dc_level_maxm[cls].clear();
+    g->dc_level_msum[cls].clear();
+    for (int d = (int)by_depth.size() - 1; d >= 0; --d) {
+      const auto& v = by_depth[d];
+      int32_t maxm = 0;
+      int64_t msum = 0;
+      for (size_t q = 0; q < v.size(); q += 4) {
+        const int32_t li = (int32_t)(q / 4);
+        const int32_t m = v[q + 2] + v[q + 3];
+        maxm = std::max(maxm, m);
+        msum += m;
+        const int32_t nt = (m + 63) / 64;
+        for (int32_t tr = 0; tr < nt; ++tr)
+          for (int32_t tc = 0; tc < nt; ++tc) g->dc_tiles.insert(g->dc_tiles.end(), {li, tr, tc});
+      }
+      g->dc_merges.insert(g->dc_merges.end(), v.begin(), v.end());
+      mo.push_back((int32_t)(g->dc_merges.size() / 4));
+      to.push_back((int32_t)(g->dc_tiles.size() / 3));
+      g->dc_level_maxm[cls].push_back(maxm);
+      g->dc_level_msum[cls].push_back(msum);
+    }
   }
+  g->dc_leaf_off[2] = (int32_t)(g->dc_leaves.size() / 4);
   g->bt_toff.assign(g->n_sub, 0);
   int32_t nb = 0;
   for (int32_t s = 0; s < g->n_sub; ++s) {

@@ -48,6 +48,7 @@ void set_error(const char* fmt, ...);
 struct gq_prof_rec {
   const char* name;
   hipEvent_t start, stop;
+  hipStream_t stream;
 };
 struct gq_prof_stat {
   const char* name;
@@ -58,6 +59,10 @@ struct gq_prof_stat {
 struct gq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // second stream (default priority) for the eigensolve of the smaller
+  // subgraphs, forked from and joined back into `stream` by events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool profiling = false;
   bool capturing = false;
   std::vector<gq_prof_rec> pending;
@@ -98,8 +103,13 @@ struct gq_graph {
   std::vector<int32_t> order;
   // divide-and-conquer plan of the tridiagonal eigensolves
   std::vector<int32_t> dc_leaves, dc_merges, dc_tiles;
-  std::vector<int32_t> dc_level_merge_off, dc_level_tile_off, dc_level_maxm;
-  std::vector<int64_t> dc_level_msum;  // sum of the merge sizes of each level
+  // two size classes: class 0 = the n_big largest subgraphs (order[0..n_big)),
+  // class 1 = the rest; each has its own leaves and merge levels, stored one
+  // after the other in dc_leaves / dc_merges / dc_tiles
+  int32_t n_big = 0;
+  int32_t dc_leaf_off[3] = {0, 0, 0};
+  std::vector<int32_t> dc_level_merge_off[2], dc_level_tile_off[2], dc_level_maxm[2];
+  std::vector<int64_t> dc_level_msum[2];  // sum of the merge sizes of each level
   std::vector<int32_t> bt_toff;  // compact-WY block offsets (16 reflectors per block)
   int32_t bt_nblocks = 0;
   // response X tiles per shape (0: 64x64, 1: 32x32), binned by size, XCD ranges
@@ -156,6 +166,7 @@ void graph_free_dev(const gq_graph* g);
 
 // Marks the start / end of a timed launch on ctx->stream (no-ops unless profiling).
 void prof_begin(gq_ctx* ctx, const char* name);
+void prof_begin_on(gq_ctx* ctx, const char* name, hipStream_t st);
 void prof_end(gq_ctx* ctx);
 
 // kernel launchers (all asynchronous on ctx->stream)
@@ -163,7 +174,7 @@ void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, i
 void eig_set_attributes();
 void dc_set_attributes();
 void build_dc_plan(gq_graph* g);
-void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t st);
 int mu_blocks_for(int64_t count);
 void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
 void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);

@@ -805,10 +805,10 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
 __global__ __launch_bounds__(kThreads) void k_bt_tfactors(
     const double* __restrict__ abuf, const double* __restrict__ TAU, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ toff,
-    double* __restrict__ tfac) {
+    const int32_t* __restrict__ subs, double* __restrict__ tfac) {
   __shared__ double Gp[4][kNb][kNb + 1];
   __shared__ double T[kNb][kNb + 1];
-  const int s = blockIdx.x;
+  const int s = subs[blockIdx.x];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const int kbi = blockIdx.y;
@@ -1033,29 +1033,33 @@ void dc_set_attributes() {
                             (int)(kMaxN * kLdv * sizeof(double)));
 }
 
-void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
+void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t st) {
   const gq_graph_dev& dv = g->dev;
-  hipStream_t st = ctx->stream;
-  // the vectors alternate between e->Q and the scratch e->Y by merge depth
-  // (the top merges write Q); eigenvalues in e->eps
-  prof_begin(ctx, "k_dc_leaves");
-  hipLaunchKernelGGL(k_dc_leaves, dim3((dv.n_leaves + 3) / 4), dim3(64), 0, st, dv.dc_leaves,
-                     dv.n_leaves, dv.sub_orb_ptr, dv.off2, e->dd, e->ee, e->Q, e->Y, e->eps,
-                     e->status);
+  // size class cls: subgraphs order[i0..i1) with their leaves, merges and
+  // tiles; the vectors alternate between e->Q and the scratch e->Y by merge
+  // depth (the top merges write Q); eigenvalues in e->eps
+  const int i0 = cls == 0 ? 0 : g->n_big, i1 = cls == 0 ? g->n_big : g->n_sub;
+  if (i1 <= i0) return;
+  const int l0 = g->dc_leaf_off[cls], nleaf = g->dc_leaf_off[cls + 1] - l0;
+  prof_begin_on(ctx, "k_dc_leaves", st);
+  hipLaunchKernelGGL(k_dc_leaves, dim3((nleaf + 3) / 4), dim3(64), 0, st, dv.dc_leaves + 4 * l0,
+                     nleaf, dv.sub_orb_ptr, dv.off2, e->dd, e->ee, e->Q, e->Y, e->eps, e->status);
   prof_end(ctx);
-  const int nlev = (int)g->dc_level_merge_off.size() - 1;
+  const auto& mo = g->dc_level_merge_off[cls];
+  const auto& to = g->dc_level_tile_off[cls];
+  const int nlev = (int)mo.size() - 1;
   for (int lv = 0; lv < nlev; ++lv) {
     const int depth = nlev - 1 - lv;  // levels run from the deepest merges up
     double* zin = depth % 2 == 1 ? e->Q : e->Y;
     double* zout = depth % 2 == 1 ? e->Y : e->Q;
-    const int m0 = g->dc_level_merge_off[lv], m1 = g->dc_level_merge_off[lv + 1];
-    const int t0 = g->dc_level_tile_off[lv], t1 = g->dc_level_tile_off[lv + 1];
+    const int m0 = mo[lv], m1 = mo[lv + 1];
+    const int t0 = to[lv], t1 = to[lv + 1];
     if (m1 == m0) continue;
-    const int maxm = g->dc_level_maxm[lv];
-    prof_begin(ctx, "k_dc_prep");
+    const int maxm = g->dc_level_maxm[cls][lv];
+    prof_begin_on(ctx, "k_dc_prep", st);
     // levels whose merges average over 256 run on 1024 threads, over 128 on
     // 512, the rest on 256, so that a merge's roots take one or two rounds
-    const int64_t msum = g->dc_level_msum[lv], nm = m1 - m0;
+    const int64_t msum = g->dc_level_msum[cls][lv], nm = m1 - m0;
     const int ntl = msum > 256 * nm ? 1024 : msum > 128 * nm ? 512 : kThreads;
     auto prep = ntl == 1024 ? k_dc_prep<1024> : ntl == 512 ? k_dc_prep<512> : k_dc_prep<kThreads>;
     hipLaunchKernelGGL(prep, dim3(m1 - m0), dim3(ntl), dc_prep_lds(maxm), st,
@@ -1063,35 +1067,35 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
                        e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
                        e->md_delta, e->md_tau, e->md_zhat, e->md_inv);
     prof_end(ctx);
-    prof_begin(ctx, "k_dc_gemm");
+    prof_begin_on(ctx, "k_dc_gemm", st);
     hipLaunchKernelGGL(k_dc_gemm, dim3(t1 - t0), dim3(kThreads), 0, st, dv.dc_tiles + 3 * t0,
                        dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, zin, zout, e->md_k + m0,
                        e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos, e->md_delta,
                        e->md_tau, e->md_zhat, e->md_inv);
     prof_end(ctx);
   }
-  const int maxn = g->info.max_n;
-  prof_begin(ctx, "k_bt_tfactors");
-  hipLaunchKernelGGL(k_bt_tfactors, dim3(g->n_sub, (maxn + kNb - 1) / kNb), dim3(kThreads), 0, st,
-                     e->A, e->tau, dv.off2, dv.sub_orb_ptr, dv.bt_toff, e->tfac);
+  const int maxn = g->sub_orb_ptr[g->order[i0] + 1] - g->sub_orb_ptr[g->order[i0]];
+  prof_begin_on(ctx, "k_bt_tfactors", st);
+  hipLaunchKernelGGL(k_bt_tfactors, dim3(i1 - i0, (maxn + kNb - 1) / kNb), dim3(kThreads), 0, st,
+                     e->A, e->tau, dv.off2, dv.sub_orb_ptr, dv.bt_toff, dv.order + i0, e->tfac);
   prof_end(ctx);
-  prof_begin(ctx, "k_backtransform");
+  prof_begin_on(ctx, "k_backtransform", st);
   // subgraphs are ordered by decreasing size: classes n <= 256, <= 384, <= 512,
   // <= 640, <= 1024 are contiguous ranges of that order, each launched with
   // its register panel (the smallest that holds its row blocks)
   static constexpr int kClassN[5] = {256, 384, 512, 640, kMaxN};
-  int lo = 0;
-  for (int cls = 4; cls >= 0; --cls) {
-    const int floor_n = cls == 0 ? 0 : kClassN[cls - 1];
+  int lo = i0;
+  for (int c = 4; c >= 0; --c) {
+    const int floor_n = c == 0 ? 0 : kClassN[c - 1];
     int hi = lo;
-    while (hi < g->n_sub && g->sub_orb_ptr[g->order[hi] + 1] - g->sub_orb_ptr[g->order[hi]] > floor_n) ++hi;
+    while (hi < i1 && g->sub_orb_ptr[g->order[hi] + 1] - g->sub_orb_ptr[g->order[hi]] > floor_n) ++hi;
     if (hi > lo) {
       const int nmax = g->sub_orb_ptr[g->order[lo] + 1] - g->sub_orb_ptr[g->order[lo]];
       const int nrb = (nmax + 15) / 16;
       const int npanel = (nmax + 15) / 16, count = hi - lo;
       dim3 grid(8 * npanel * ((count + 7) / 8));
       const size_t lds = (size_t)16 * nrb * kLdv * sizeof(double);
-      auto kern = cls == 0 ? k_bt_mfma<4> : cls == 1 ? k_bt_mfma<6> : cls == 2 ? k_bt_mfma<8> : cls == 3 ? k_bt_mfma<10> : k_bt_mfma<16>;
+      auto kern = c == 0 ? k_bt_mfma<4> : c == 1 ? k_bt_mfma<6> : c == 2 ? k_bt_mfma<8> : c == 3 ? k_bt_mfma<10> : k_bt_mfma<16>;
       hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, e->A, e->tfac, dv.bt_toff, e->Q,
                          dv.off2, dv.sub_orb_ptr, dv.n_core, dv.order + lo, e->wts, count, npanel);
     }

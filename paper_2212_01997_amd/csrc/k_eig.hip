@@ -432,13 +432,34 @@ void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, i
 
 void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   const gq_graph_dev& dv = g->dev;
-  const int maxn = g->info.max_n;
+  // two size classes on two streams: the n_big largest subgraphs on the
+  // caller's stream, the rest on a side stream forked from it and joined
+  // back, so that the small subgraphs' divide and conquer and
+  // back-transformation fill the CUs the long tridiagonalisations leave idle
   hipStream_t st = ctx->stream;
-  prof_begin(ctx, "k_tridiag");
-  hipLaunchKernelGGL(k_tridiag, dim3(g->n_sub), dim3(kTdThreads), tridiag_lds(maxn), st, e->A,
-                     e->wsc, dv.off2, dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
-  prof_end(ctx);
-  launch_dc(ctx, g, e);
+  const int nbig = g->n_big, nsmall = g->n_sub - g->n_big;
+  if (nsmall > 0) {
+    (void)hipEventRecord(ctx->ev_fork, st);
+    (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+    const int n1 = g->sub_orb_ptr[g->order[nbig] + 1] - g->sub_orb_ptr[g->order[nbig]];
+    prof_begin_on(ctx, "k_tridiag", ctx->side);
+    hipLaunchKernelGGL(k_tridiag, dim3(nsmall), dim3(kTdThreads), tridiag_lds(n1), ctx->side,
+                       e->A, e->wsc, dv.off2, dv.sub_orb_ptr, dv.order + nbig, e->dd, e->ee,
+                       e->tau);
+    prof_end(ctx);
+    launch_dc(ctx, g, e, 1, ctx->side);
+  }
+  if (nbig > 0) {
+    prof_begin(ctx, "k_tridiag");
+    hipLaunchKernelGGL(k_tridiag, dim3(nbig), dim3(kTdThreads), tridiag_lds(g->info.max_n), st,
+                       e->A, e->wsc, dv.off2, dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
+    prof_end(ctx);
+    launch_dc(ctx, g, e, 0, st);
+  }
+  if (nsmall > 0) {
+    (void)hipEventRecord(ctx->ev_join, ctx->side);
+    (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
+  }
 }
 
 }  // namespace gq
