@@ -457,8 +457,15 @@ gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* 
   e->kT = kT;
   e->n_elec = n_elec;
   launch_mu(ctx, e->g, e);
+  // the divided differences (eigenvalues and mu only, written over the
+  // reflectors in A) run on the side stream beside the density rows (Q, into
+  // rho), joined back before the call returns
+  GQ_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
+  GQ_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  launch_divided_differences(ctx, e->g, e, ctx->side);
   launch_density(ctx, e->g, e, rho_blocks_dev);
-  launch_divided_differences(ctx, e->g, e);
+  GQ_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+  GQ_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
   GQ_HIP(hipGetLastError());
   e->have_density = true;
   if (mu_out) {

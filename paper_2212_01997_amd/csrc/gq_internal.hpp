@@ -179,7 +179,7 @@ int mu_blocks_for(int64_t count);
 void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
 void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
 void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_blocks);
-void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st);
 void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h1, int32_t K,
                      uint32_t precision, double* p_blocks);
 void launch_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks, int32_t K,

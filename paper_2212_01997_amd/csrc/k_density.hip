@@ -356,10 +356,9 @@ void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_bloc
   prof_end(ctx);
 }
 
-void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
+void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st) {
   const gq_graph_dev& dv = g->dev;
-  hipStream_t st = ctx->stream;
-  prof_begin(ctx, "k_divided_differences");
+  prof_begin_on(ctx, "k_divided_differences", st);
   dim3 grid(g->n_sub, (g->info.max_n + kDdCols - 1) / kDdCols);
   hipLaunchKernelGGL(k_divided_differences, grid, dim3(kThreads), 0, st, e->eps, dv.off2,
                      dv.sub_orb_ptr, dv.order, e->mu_state, e->A);
