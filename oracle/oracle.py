@@ -6,7 +6,8 @@ plain single-threaded FP64 implementation of the paper's method
 (arXiv:2212.01997, Secs. II and IV).  `solve_pool` runs the same per-subgraph
 routines in worker processes for large systems; every reduction that couples
 subgraphs (mu, mu1) still runs in fixed subgraph order in the parent, so its
-results equal the serial ones.
+results equal the serial ones bit for bit (pinned against the serial path in
+tests/test_oracle_pool.py for 1, 3, 5 and 16 workers).
 """
 from __future__ import annotations
 
