@@ -100,8 +100,19 @@ const char* gq_last_error(void);
 const char* gq_version(void);
 
 /* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL = the
- * default stream).  The stream is borrowed and must outlive the context. */
-gq_status gq_ctx_create(int32_t device, void* hip_stream, gq_ctx** out);
+ * default stream).  The stream is borrowed and must outlive the context.
+ * arena_bytes > 0 allocates one device arena of that size here, once: every
+ * eigen workspace later created on this context (gq_eigs_create), and the
+ * device index maps of a graph first bound by such a call, then take a piece
+ * of the arena (first fit, 256-byte aligned) and return it when destroyed, so
+ * that no device allocation happens after this call.  gq_eigs_create reports
+ * GQ_ENOMEM when no piece fits.  The context must outlive every workspace and
+ * graph that holds a piece of its arena.  arena_bytes = 0: workspaces allocate
+ * their own device memory.  GQ_ENOMEM if the arena cannot be allocated;
+ * GQ_EINVAL if arena_bytes < 0. */
+gq_status gq_ctx_create(int32_t device, void* hip_stream, int64_t arena_bytes, gq_ctx** out);
+/* Bytes of the context's arena in use and its size (0, 0 without one). */
+gq_status gq_ctx_arena_used(gq_ctx* ctx, int64_t* used, int64_t* size);
 void gq_ctx_destroy(gq_ctx* ctx);
 
 /* ---------------------------------------------------------- graph_build
@@ -137,20 +148,27 @@ void gq_graph_destroy(gq_graph* g);
 /* ------------------------------------------------------- eigen workspace
  * Device-resident state of one graph: eigenpairs, core weights, the mu
  * response rows and the divided differences, sized for up to `max_k`
- * perturbations per response call.  Allocates device memory (GQ_ENOMEM). */
-gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs** out);
-/* Device bytes held by an eigen workspace for graph g and max_k (for
- * admission control); no allocation. */
-gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, int64_t* bytes);
+ * perturbations per response call.  flags: GQ_EIGS_GENERAL_H1 also reserves
+ * the buffer (max_k x sum n_i^2 doubles) that perturbations given as CSR
+ * matrices need (GQ_H1_CSR); diagonal perturbations do not need it.
+ * Allocates device memory, or takes a piece of the context's arena
+ * (GQ_ENOMEM when neither is available); GQ_EINVAL for unknown flags, a
+ * subgraph above 1024 orbitals or a core above 32 orbitals. */
+#define GQ_EIGS_GENERAL_H1 1u
+gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
+                         gq_eigs** out);
+/* Device bytes held by an eigen workspace for graph g, max_k and flags, plus
+ * the graph's device index maps (for admission control); no allocation. */
+gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, uint32_t flags, int64_t* bytes);
 /* As gq_eigs_create, with every device array of the workspace (and the
  * graph's device maps, if the graph is not bound to a device yet) placed in
- * caller-owned device memory `mem` of `bytes` >= gq_eigs_footprint(g, max_k),
- * 256-byte aligned.  For allocators that hand out pieces of one arena (the
- * serving runtime): neither this call nor gq_eigs_destroy / gq_graph_destroy
- * allocate or free device memory for such a workspace.  mem must outlive both
- * handles. */
-gq_status gq_eigs_create_in(gq_ctx* ctx, const gq_graph* g, int32_t max_k, void* mem,
-                            int64_t bytes, gq_eigs** out);
+ * caller-owned device memory `mem` of `bytes` >= gq_eigs_footprint(g, max_k,
+ * flags), 256-byte aligned.  For allocators that hand out pieces of one arena
+ * (the serving runtime): neither this call nor gq_eigs_destroy /
+ * gq_graph_destroy allocate or free device memory for such a workspace.  mem
+ * must outlive both handles. */
+gq_status gq_eigs_create_in(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
+                            void* mem, int64_t bytes, gq_eigs** out);
 void gq_eigs_destroy(gq_eigs* e);
 
 /* ------------------------------------------------------ submatrix_solve
@@ -169,21 +187,37 @@ gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev
  * core rows rho_i = 2 Q_i[0:c_i,:] diag(f) Q_i^T into rho_blocks_dev (device,
  * nnz doubles; may be NULL), and the mu-response rows
  * 2 beta Q_c diag(f(1-f)) Q^T kept in the workspace.  kT > 0 and
- * 0 < n_elec < 2N (GQ_EINVAL).  *mu_out (host, may be NULL) makes the call
- * wait for the stream. */
-gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* mu_out,
+ * 0 < n_elec < 2N (GQ_EINVAL).
+ * mu_inout (host, may be NULL): on entry a warm-start guess, as the previous
+ * step's mu in Sec. II.G (NaN: none); on return the root, after waiting for
+ * the stream.  With a guess the first pass places its points at
+ * guess +- kT 4^j (j = -8..7, clipped to the eigenvalue span), so the passes
+ * after it start from the bracket that holds the root, however far the guess
+ * is; passes whose bracket has reached adjacent doubles do no work.  Twelve
+ * passes run with a guess, eleven without.  NULL while capturing. */
+gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* mu_inout,
                      double* rho_blocks_dev);
 
 /* ------------------------------------------------------------- response
- * K perturbations H1_q given as diagonals h1_dev[K][N] (device).  For each
- * subgraph: X = Q^T diag(h1) Q, Y = X o dF with dF_kl = (f_k - f_l)/(e_k - e_l)
- * (f'(e_k) when equal), P = 2 Q_c Y Q^T, and the canonical
- * mu1_q = -sum_i Tr_c P_i / sum_i Tr_c M_i (Sec. IV.A).  Writes
- * p_blocks_dev[K][nnz] = P + mu1_q M (the collected rho1 rows in block layout)
- * and mu1_dev[K] (device; may be NULL).  `precision` is GQ_PREC_FP64 or
- * GQ_PREC_SPLIT32.  Requires gq_density on the same workspace first; K <= max_k.
- * mu1_host (may be NULL) makes the call wait for the stream. */
-gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const double* h1_dev, int32_t K,
+ * K perturbations H1_q of the Hamiltonian, H(lambda) = H + lambda H1
+ * (Sec. IV.A, Eq. (ddlambda)), each symmetric N x N, as
+ *   GQ_H1_DIAG: h1 is `const double*`, diagonals h1[K][N] in device memory;
+ *   GQ_H1_CSR:  h1 is `const gq_csr*`, a host array of K CSR matrices whose
+ *               row_ptr/col/val arrays are device memory (N rows each, sorted
+ *               columns, symmetric values); the workspace must have been
+ *               created with GQ_EIGS_GENERAL_H1.
+ * For each subgraph: h1_s = H1[orbs, orbs], X = Q^T h1_s Q (the molecular-
+ * orbital representation, as remarked at the end of Sec. IV.A),
+ * Y = X o dF with dF_kl = (f_k - f_l)/(e_k - e_l) (f'(e_k) when equal),
+ * P = 2 Q_c Y Q^T, and the canonical mu1_q = -sum_i Tr_c P_i / sum_i Tr_c M_i
+ * (Eq. (dmu_1)).  Writes p_blocks_dev[K][nnz] = P + mu1_q M (the collected
+ * rho1 rows in block layout) and mu1_dev[K] (device; may be NULL).
+ * `precision` is GQ_PREC_FP64 or GQ_PREC_SPLIT32.  Requires gq_density on the
+ * same workspace first; 1 <= K <= max_k.  mu1_host (may be NULL) makes the
+ * call wait for the stream; NULL while capturing. */
+#define GQ_H1_DIAG 0u
+#define GQ_H1_CSR 1u
+gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t h1_kind, int32_t K,
                       uint32_t precision, double* p_blocks_dev, double* mu1_dev,
                       double* mu1_host);
 

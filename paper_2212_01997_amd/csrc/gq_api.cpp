@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <type_traits>
 
@@ -78,10 +79,36 @@ static int64_t graph_maps_bytes(const gq_graph* g) {
   return (int64_t)c.used + 256;
 }
 
+// Waits for the context's streams, so that a piece of its arena can be
+// handed out again (hipFree waits for the device in the same way).
+static void ctx_drain(gq_ctx* ctx) {
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->side);
+  (void)hipStreamSynchronize(ctx->stream);
+}
+
 void graph_free_dev(const gq_graph* g) {
   gq_graph_dev& d = g->dev;
-  if (d.block) (void)hipFree(d.block);
+  if (d.arena_ctx) {
+    ctx_drain(d.arena_ctx);
+    std::lock_guard<std::mutex> lk(d.arena_ctx->arena_mu);
+    d.arena_ctx->arena->release(d.arena_off, d.arena_bytes);
+  } else if (d.block) {
+    (void)hipFree(d.block);
+  }
   d = gq_graph_dev{};
+}
+
+// Piece of ctx's arena (nullptr when the arena has no room).
+static char* arena_take(gq_ctx* ctx, size_t bytes, size_t* off) {
+  std::lock_guard<std::mutex> lk(ctx->arena_mu);
+  if (!ctx->arena->alloc(bytes, off)) return nullptr;
+  return ctx->arena_mem + *off;
+}
+
+static void arena_give(gq_ctx* ctx, size_t off, size_t bytes) {
+  std::lock_guard<std::mutex> lk(ctx->arena_mu);
+  ctx->arena->release(off, bytes);
 }
 
 // Binds the graph to `device`: its maps in `mem` (caller-owned, at least
@@ -126,8 +153,30 @@ gq_status graph_upload(const gq_graph* g, int device) {
   return graph_upload_at(g, device, nullptr, nullptr);
 }
 
+// Binds the graph to ctx's device, its maps in a piece of ctx's arena when the
+// context has one.
+static gq_status graph_upload_ctx(const gq_graph* g, gq_ctx* ctx) {
+  if (!ctx->arena || g->dev.device >= 0) return graph_upload_at(g, ctx->device, nullptr, ctx->stream);
+  const size_t bytes = (size_t)graph_maps_bytes(g);
+  size_t off = 0;
+  char* mem = arena_take(ctx, bytes, &off);
+  if (!mem) {
+    set_error("graph upload: %zu bytes do not fit the context's arena (%zu of %zu in use)", bytes,
+              ctx->arena->used(), ctx->arena->size());
+    return GQ_ENOMEM;
+  }
+  if (gq_status st = graph_upload_at(g, ctx->device, mem, ctx->stream)) {
+    arena_give(ctx, off, bytes);
+    return st;
+  }
+  g->dev.arena_ctx = ctx;
+  g->dev.arena_off = off;
+  g->dev.arena_bytes = bytes;
+  return GQ_OK;
+}
+
 // Layout of an eigen workspace (pointers filled when c.base is set).
-static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, Carve& c) {
+static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, uint32_t flags, Carve& c) {
   const gq_graph_info& in = g->info;
   const int64_t sum_c = g->offcd[g->n_sub];
   const int64_t kk = std::max(max_k, 1);
@@ -156,6 +205,7 @@ static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, Carve& c) 
   x.tfac = c.take<double>((int64_t)g->bt_nblocks * 256);
   x.wsc = c.take<double>(in.sum_n * 16);
   x.hloc = c.take<double>(kk * in.sum_n);
+  x.G = (flags & GQ_EIGS_GENERAL_H1) ? c.take<double>(kk * in.sum_n2) : nullptr;
   x.Q32 = c.take<float>(in.sum_n2);
   x.status = c.take<int32_t>(g->n_sub);
   x.md_k = c.take<int32_t>((int64_t)(g->dc_merges.size() / 4));
@@ -166,9 +216,9 @@ static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, Carve& c) 
   x.md_dpos = c.take<int32_t>(in.sum_n);
 }
 
-static int64_t eigs_bytes(const gq_graph* g, int32_t max_k) {
+static int64_t eigs_bytes(const gq_graph* g, int32_t max_k, uint32_t flags) {
   Carve c;
-  eigs_layout(nullptr, g, max_k, c);
+  eigs_layout(nullptr, g, max_k, flags, c);
   return (int64_t)c.used + 256;
 }
 
@@ -182,9 +232,9 @@ const char* gq_last_error(void) { return g_err; }
 
 const char* gq_version(void) { return "gq 0.1 (gfx950, FP64)"; }
 
-gq_status gq_ctx_create(int32_t device, void* hip_stream, gq_ctx** out) {
-  if (!out) {
-    set_error("gq_ctx_create: out is NULL");
+gq_status gq_ctx_create(int32_t device, void* hip_stream, int64_t arena_bytes, gq_ctx** out) {
+  if (!out || arena_bytes < 0) {
+    set_error("gq_ctx_create: out is NULL or arena_bytes < 0");
     return GQ_EINVAL;
   }
   int count = 0;
@@ -211,19 +261,54 @@ gq_status gq_ctx_create(int32_t device, void* hip_stream, gq_ctx** out) {
   c->stream = (hipStream_t)hip_stream;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork_dd, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join_dd, hipEventDisableTiming) != hipSuccess) {
     set_error("gq_ctx_create: cannot create the side stream and its events");
     gq_ctx_destroy(c);
     return GQ_EDEVICE;
+  }
+  if (arena_bytes > 0) {
+    if (hipMalloc((void**)&c->arena_mem, (size_t)arena_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      c->arena_mem = nullptr;
+      set_error("gq_ctx_create: arena of %lld bytes not available", (long long)arena_bytes);
+      gq_ctx_destroy(c);
+      return GQ_ENOMEM;
+    }
+    c->arena = new (std::nothrow) Arena((size_t)arena_bytes);
+    if (!c->arena) {
+      set_error("gq_ctx_create: out of host memory");
+      gq_ctx_destroy(c);
+      return GQ_ENOMEM;
+    }
   }
   *out = c;
   return GQ_OK;
 }
 
+gq_status gq_ctx_arena_used(gq_ctx* ctx, int64_t* used, int64_t* size) {
+  if (!ctx) {
+    set_error("gq_ctx_arena_used: NULL context");
+    return GQ_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(ctx->arena_mu);
+  if (used) *used = ctx->arena ? (int64_t)ctx->arena->used() : 0;
+  if (size) *size = ctx->arena ? (int64_t)ctx->arena->size() : 0;
+  return GQ_OK;
+}
+
 void gq_ctx_destroy(gq_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->arena_mem) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->arena_mem);
+  }
+  delete ctx->arena;
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_fork_dd) (void)hipEventDestroy(ctx->ev_fork_dd);
+  if (ctx->ev_join_dd) (void)hipEventDestroy(ctx->ev_join_dd);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   delete ctx;
 }
@@ -305,29 +390,37 @@ void gq_graph_destroy(gq_graph* g) {
 }
 
 // Device bytes of a workspace plus the graph's device maps.
-static int64_t footprint(const gq_graph* g, int32_t max_k) {
-  return eigs_bytes(g, max_k) + graph_maps_bytes(g);
+static int64_t footprint(const gq_graph* g, int32_t max_k, uint32_t flags) {
+  return eigs_bytes(g, max_k, flags) + graph_maps_bytes(g);
 }
 
-gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, int64_t* bytes) {
-  if (!g || !bytes || max_k < 0) {
+gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, uint32_t flags, int64_t* bytes) {
+  if (!g || !bytes || max_k < 0 || (flags & ~GQ_EIGS_GENERAL_H1)) {
     set_error("gq_eigs_footprint: bad argument");
     return GQ_EINVAL;
   }
-  *bytes = footprint(g, max_k);
+  *bytes = footprint(g, max_k, flags);
   return GQ_OK;
 }
 
 void gq_eigs_destroy(gq_eigs* e) {
   if (!e) return;
-  if (e->block) (void)hipFree(e->block);
+  if (e->block_in_arena) {
+    ctx_drain(e->ctx);
+    arena_give(e->ctx, e->arena_off, e->arena_bytes);
+  }
+  else if (e->block) (void)hipFree(e->block);
   delete e;
 }
 
-static gq_status eigs_check(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs** out,
-                            const char* who) {
+static gq_status eigs_check(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
+                            gq_eigs** out, const char* who) {
   if (!ctx || !g || !out || max_k < 0) {
     set_error("%s: bad argument", who);
+    return GQ_EINVAL;
+  }
+  if (flags & ~GQ_EIGS_GENERAL_H1) {
+    set_error("%s: unknown flags 0x%x", who, flags);
     return GQ_EINVAL;
   }
   if (g->info.max_n > kMaxN) {
@@ -341,8 +434,9 @@ static gq_status eigs_check(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_ei
   return GQ_OK;
 }
 
-static gq_status eigs_make(gq_ctx* ctx, const gq_graph* g, int32_t max_k, char* mem,
-                           gq_eigs** out) {
+// mem: caller memory; otherwise a piece of ctx's arena or a block of its own.
+static gq_status eigs_make(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
+                           char* mem, gq_eigs** out) {
   gq_eigs* e = new (std::nothrow) gq_eigs;
   if (!e) {
     set_error("gq_eigs_create: out of host memory");
@@ -351,11 +445,22 @@ static gq_status eigs_make(gq_ctx* ctx, const gq_graph* g, int32_t max_k, char* 
   e->ctx = ctx;
   e->g = g;
   e->max_k = max_k;
+  e->flags = flags;
   if (!mem) {
-    if (hipMalloc((void**)&e->block, (size_t)eigs_bytes(g, max_k)) != hipSuccess) {
+    const size_t bytes = (size_t)eigs_bytes(g, max_k, flags);
+    if (ctx->arena) {
+      e->block = arena_take(ctx, bytes, &e->arena_off);
+      if (!e->block) {
+        set_error("gq_eigs_create: %zu bytes do not fit the context's arena (%zu of %zu in use)",
+                  bytes, ctx->arena->used(), ctx->arena->size());
+        delete e;
+        return GQ_ENOMEM;
+      }
+      e->block_in_arena = true;
+      e->arena_bytes = bytes;
+    } else if (hipMalloc((void**)&e->block, bytes) != hipSuccess) {
       (void)hipGetLastError();
-      set_error("gq_eigs_create: device allocation of %lld bytes failed",
-                (long long)eigs_bytes(g, max_k));
+      set_error("gq_eigs_create: device allocation of %zu bytes failed", bytes);
       delete e;
       return GQ_ENOMEM;
     }
@@ -363,24 +468,25 @@ static gq_status eigs_make(gq_ctx* ctx, const gq_graph* g, int32_t max_k, char* 
   }
   Carve c;
   c.base = mem;
-  eigs_layout(e, g, max_k, c);
+  eigs_layout(e, g, max_k, flags, c);
   *out = e;
   return GQ_OK;
 }
 
-gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, gq_eigs** out) {
-  if (gq_status st = eigs_check(ctx, g, max_k, out, "gq_eigs_create")) return st;
+gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
+                         gq_eigs** out) {
+  if (gq_status st = eigs_check(ctx, g, max_k, flags, out, "gq_eigs_create")) return st;
   GQ_HIP(hipSetDevice(ctx->device));
-  if (gq_status st = graph_upload(g, ctx->device)) return st;
-  return eigs_make(ctx, g, max_k, nullptr, out);
+  if (gq_status st = graph_upload_ctx(g, ctx)) return st;
+  return eigs_make(ctx, g, max_k, flags, nullptr, out);
 }
 
-gq_status gq_eigs_create_in(gq_ctx* ctx, const gq_graph* g, int32_t max_k, void* mem,
-                            int64_t bytes, gq_eigs** out) {
-  if (gq_status st = eigs_check(ctx, g, max_k, out, "gq_eigs_create_in")) return st;
-  if (!mem || bytes < footprint(g, max_k)) {
+gq_status gq_eigs_create_in(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
+                            void* mem, int64_t bytes, gq_eigs** out) {
+  if (gq_status st = eigs_check(ctx, g, max_k, flags, out, "gq_eigs_create_in")) return st;
+  if (!mem || bytes < footprint(g, max_k, flags)) {
     set_error("gq_eigs_create_in: %lld bytes given, %lld needed", (long long)bytes,
-              (long long)footprint(g, max_k));
+              (long long)footprint(g, max_k, flags));
     return GQ_EINVAL;
   }
   if (reinterpret_cast<uintptr_t>(mem) % 256) {
@@ -396,7 +502,7 @@ gq_status gq_eigs_create_in(gq_ctx* ctx, const gq_graph* g, int32_t max_k, void*
     set_error("gq_eigs_create_in: graph bound to device %d", g->dev.device);
     return GQ_EINVAL;
   }
-  return eigs_make(ctx, g, max_k, base + graph_maps_bytes(g), out);
+  return eigs_make(ctx, g, max_k, flags, base + graph_maps_bytes(g), out);
 }
 
 gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev, uint32_t flags,
@@ -435,7 +541,7 @@ static gq_status check_status(gq_ctx* ctx, const gq_eigs* e) {
   return GQ_OK;
 }
 
-gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* mu_out,
+gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* mu_inout,
                      double* rho_blocks_dev) {
   if (!ctx || !e) {
     set_error("gq_density: NULL argument");
@@ -449,57 +555,96 @@ gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* 
     set_error("gq_density: N_e = %g outside (0, 2N = %d)", n_elec, 2 * e->g->N);
     return GQ_EINVAL;
   }
-  if (mu_out && ctx->capturing) {
-    set_error("gq_density: mu_out must be NULL while capturing");
+  if (mu_inout && ctx->capturing) {
+    set_error("gq_density: mu_inout must be NULL while capturing");
     return GQ_EINVAL;
   }
   GQ_HIP(hipSetDevice(ctx->device));
   e->kT = kT;
   e->n_elec = n_elec;
-  launch_mu(ctx, e->g, e);
+  const double guess = mu_inout ? *mu_inout : std::numeric_limits<double>::quiet_NaN();
+  launch_mu(ctx, e->g, e, guess);
   // the divided differences (eigenvalues and mu only, written over the
   // reflectors in A) run on the side stream beside the density rows (Q, into
   // rho), joined back before the call returns
-  GQ_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
-  GQ_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  GQ_HIP(hipEventRecord(ctx->ev_fork_dd, ctx->stream));
+  GQ_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork_dd, 0));
   launch_divided_differences(ctx, e->g, e, ctx->side);
   launch_density(ctx, e->g, e, rho_blocks_dev);
-  GQ_HIP(hipEventRecord(ctx->ev_join, ctx->side));
-  GQ_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+  GQ_HIP(hipEventRecord(ctx->ev_join_dd, ctx->side));
+  GQ_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join_dd, 0));
   GQ_HIP(hipGetLastError());
   e->have_density = true;
-  if (mu_out) {
-    GQ_HIP(hipMemcpyAsync(mu_out, e->mu_state + 2, sizeof(double), hipMemcpyDeviceToHost,
+  if (mu_inout) {
+    GQ_HIP(hipMemcpyAsync(mu_inout, e->mu_state + 2, sizeof(double), hipMemcpyDeviceToHost,
                           ctx->stream));
     if (gq_status st = check_status(ctx, e)) return st;
   }
   return GQ_OK;
 }
 
-gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const double* h1_dev, int32_t K, uint32_t precision,
-                      double* p_blocks_dev, double* mu1_dev, double* mu1_host) {
-  if (!ctx || !e || !h1_dev || !p_blocks_dev) {
-    set_error("gq_response: NULL argument");
+// Validation shared by the response entry points.
+static gq_status response_check(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t kind,
+                                int32_t K, uint32_t precision, double* p_blocks_dev,
+                                const char* who, H1Spec* spec) {
+  if (!ctx || !e || !h1 || !p_blocks_dev) {
+    set_error("%s: NULL argument", who);
     return GQ_EINVAL;
   }
   if (!e->have_density) {
-    set_error("gq_response: call gq_density on this workspace first");
+    set_error("%s: call gq_density on this workspace first", who);
     return GQ_EINVAL;
   }
-  if (K < 1 || K > e->max_k) {
-    set_error("gq_response: K = %d outside [1, max_k = %d]", K, e->max_k);
+  if (precision != GQ_PREC_FP64 && precision != GQ_PREC_SPLIT32) {
+    set_error("%s: precision %u not available", who, precision);
+    return GQ_EINVAL;
+  }
+  if (K < 1) {
+    set_error("%s: K = %d < 1", who, K);
+    return GQ_EINVAL;
+  }
+  *spec = H1Spec{kind, nullptr, nullptr};
+  if (kind == GQ_H1_DIAG) {
+    spec->diag = static_cast<const double*>(h1);
+  } else if (kind == GQ_H1_CSR) {
+    spec->csr = static_cast<const gq_csr*>(h1);
+    for (int32_t q = 0; q < K; ++q) {
+      const gq_csr& m = spec->csr[q];
+      if (m.n_rows != e->g->N || m.nnz < 0 || !m.row_ptr || (m.nnz > 0 && (!m.col || !m.val))) {
+        set_error("%s: perturbation %d: %d rows (N = %d) or missing arrays", who, q, m.n_rows,
+                  e->g->N);
+        return GQ_EINVAL;
+      }
+    }
+  } else {
+    set_error("%s: unknown perturbation kind %u", who, kind);
+    return GQ_EINVAL;
+  }
+  return GQ_OK;
+}
+
+gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t h1_kind, int32_t K,
+                      uint32_t precision, double* p_blocks_dev, double* mu1_dev,
+                      double* mu1_host) {
+  H1Spec spec;
+  if (gq_status st = response_check(ctx, e, h1, h1_kind, K, precision, p_blocks_dev,
+                                    "gq_response", &spec))
+    return st;
+  if (K > e->max_k) {
+    set_error("gq_response: K = %d above max_k = %d", K, e->max_k);
+    return GQ_EINVAL;
+  }
+  if (h1_kind == GQ_H1_CSR && !e->G) {
+    set_error("gq_response: CSR perturbations need a workspace created with GQ_EIGS_GENERAL_H1");
     return GQ_EINVAL;
   }
   if (mu1_host && ctx->capturing) {
     set_error("gq_response: mu1_host must be NULL while capturing");
     return GQ_EINVAL;
   }
-  if (precision != GQ_PREC_FP64 && precision != GQ_PREC_SPLIT32) {
-    set_error("gq_response: precision %u not available", precision);
-    return GQ_EINVAL;
-  }
   GQ_HIP(hipSetDevice(ctx->device));
-  launch_response(ctx, e->g, e, h1_dev, K, precision, p_blocks_dev);
+  const RespBufs rb{e->hloc, e->Y, e->G, e->T, e->pdiag, e->mu1};
+  launch_response(ctx, e->g, e, rb, spec, K, precision, p_blocks_dev);
   GQ_HIP(hipGetLastError());
   if (mu1_dev)
     GQ_HIP(hipMemcpyAsync(mu1_dev, e->mu1, K * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +31,55 @@ constexpr int kXyBinMax[kXyBins] = {128, 256, 384, 512, 1024};
 // Tile-list ranges [off[x], off[x+1]) served by the workgroups of XCD x.
 struct XcdSplit {
   int32_t off[9];
+};
+
+constexpr size_t kArenaAlign = 256;
+inline size_t arena_align(size_t x) { return (x + kArenaAlign - 1) & ~(kArenaAlign - 1); }
+
+// First-fit allocator over [0, size) with coalescing (host bookkeeping only;
+// the caller serialises access).
+class Arena {
+ public:
+  explicit Arena(size_t size) : size_(size) {
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = arena_align(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = arena_align(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t size() const { return size_; }
+  size_t used() const { return used_; }
+
+ private:
+  size_t size_, used_ = 0;
+  std::map<size_t, size_t> free_;
 };
 
 void set_error(const char* fmt, ...);
@@ -62,9 +113,17 @@ struct gq_ctx {
   // second stream (default priority) for the eigensolve of the smaller
   // subgraphs, forked from and joined back into `stream` by events
   hipStream_t side = nullptr;
+  // fork/join of the eigensolve's two size classes, and of the divided
+  // differences beside the density rows: one event pair per fork point
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork_dd = nullptr, ev_join_dd = nullptr;
   bool profiling = false;
   bool capturing = false;
+  // optional device arena (gq_ctx_create with arena_bytes > 0): workspaces and
+  // graph maps created on this context take pieces of it
+  char* arena_mem = nullptr;
+  gq::Arena* arena = nullptr;
+  std::mutex arena_mu;
   std::vector<gq_prof_rec> pending;
   std::vector<gq_prof_stat> stats;
 };
@@ -73,6 +132,8 @@ struct gq_ctx {
 struct gq_graph_dev {
   int device = -1;
   char* block = nullptr;           // device block of the maps when owned by the graph
+  gq_ctx* arena_ctx = nullptr;     // context whose arena holds `block`, if any
+  size_t arena_off = 0, arena_bytes = 0;
   int32_t* sub_orb_ptr = nullptr;  // [n_sub+1]
   int32_t* sub_orbs = nullptr;     // [sum_n]
   int32_t* n_core = nullptr;       // [n_sub]
@@ -123,9 +184,12 @@ struct gq_graph {
 
 struct gq_eigs {
   char* block = nullptr;    // device block of every array below, when owned
+  bool block_in_arena = false;  // block is a piece of ctx's arena
+  size_t arena_off = 0, arena_bytes = 0;
   gq_ctx* ctx = nullptr;
   const gq_graph* g = nullptr;
   int32_t max_k = 0;
+  uint32_t flags = 0;       // GQ_EIGS_* given at creation
   double* A = nullptr;      // [sum n^2] gathered matrix / tridiagonal work, then dF
   double* Q = nullptr;      // [sum n^2] eigenvectors, column-major per subgraph
   double* Y = nullptr;      // [max_k][sum n^2] response scratch (X o dF); eigensolver scratch
@@ -150,6 +214,7 @@ struct gq_eigs {
   double* tfac = nullptr;  // [bt_nblocks][16*16] compact-WY T factors
   double* wsc = nullptr;   // [sum_n * 16] panel scratch of the tridiagonalisation
   double* hloc = nullptr;  // [max_k][sum_n] perturbations gathered into subgraph order
+  double* G = nullptr;     // [max_k][sum n^2] general perturbations (GQ_EIGS_GENERAL_H1 only)
   float* Q32 = nullptr;    // [sum n^2] FP32 leading part of Q (split-FP32 congruences)
   bool q32_valid = false;  // Q32 matches the current Q
   bool have_density = false;
@@ -170,18 +235,37 @@ void prof_begin_on(gq_ctx* ctx, const char* name, hipStream_t st);
 void prof_end(gq_ctx* ctx);
 
 // kernel launchers (all asynchronous on ctx->stream)
-void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status);
+// Principal submatrices of the device CSR matrix H for every subgraph into A
+// (n_i x n_i column-major at off2[i]); resets the eigensolver status when
+// status is not NULL.
+void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status,
+                   const char* label = "k_gather");
 void eig_set_attributes();
 void dc_set_attributes();
 void build_dc_plan(gq_graph* g);
 void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t st);
 int mu_blocks_for(int64_t count);
 void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
-void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+// mu by multisection; `guess` (NaN: none) places the first pass's points
+// around a warm-start value.
+void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double guess);
 void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_blocks);
 void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st);
-void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h1, int32_t K,
-                     uint32_t precision, double* p_blocks);
+// Per-call buffers of the response for K perturbations: hloc [K][sum_n]
+// (diagonal kind), Y [K][sum n^2], G [K][sum n^2] (general kind), T
+// [K][sum_n][32], pdiag [K][sum_c], mu1 [K].
+struct RespBufs {
+  double *hloc, *Y, *G, *T, *pdiag, *mu1;
+};
+// Perturbations of one response call: diagonals h1[K][N] (device), or K
+// device CSR matrices (host array of gq_csr with device pointers).
+struct H1Spec {
+  uint32_t kind;
+  const double* diag;
+  const gq_csr* csr;
+};
+void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb,
+                     const H1Spec& h1, int32_t K, uint32_t precision, double* p_blocks);
 void launch_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks, int32_t K,
                      double* vals);
 void build_xy_tiles(gq_graph* g);

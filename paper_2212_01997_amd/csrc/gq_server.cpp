@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -32,53 +33,6 @@
 
 namespace gq {
 namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
-
-// First-fit allocator over [0, size) with coalescing (host bookkeeping only).
-class Arena {
- public:
-  explicit Arena(size_t size) : size_(size) { free_[0] = size; }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = align_up(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes, at = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        used_ += bytes;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = align_up(bytes);
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != free_.end() && it->first + it->second == next->first) {
-      it->second += next->second;
-      free_.erase(next);
-    }
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == it->first) {
-        prev->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t size() const { return size_; }
-  size_t used() const { return used_; }
-
- private:
-  size_t size_, used_ = 0;
-  std::map<size_t, size_t> free_;
-};
 
 struct Request {
   int64_t id = 0;
@@ -158,25 +112,25 @@ void gq_server::run(Request& r, gq_ctx* ctx) {
   r.n_sub = g->n_sub;
   r.nnz = nnz;
   int64_t ws = 0;
-  ok(gq_eigs_footprint(g, r.K, &ws));
+  ok(gq_eigs_footprint(g, r.K, 0u, &ws));
   // footprint: workspace + graph maps, H, h1, rho blocks and values, P blocks and rho1
-  size_t bytes = align_up((size_t)ws);
+  size_t bytes = arena_align((size_t)ws);
   const size_t o_hrp = bytes;
-  bytes = align_up(bytes + r.h_rp.size() * 4);
+  bytes = arena_align(bytes + r.h_rp.size() * 4);
   const size_t o_hcol = bytes;
-  bytes = align_up(bytes + r.h_col.size() * 4);
+  bytes = arena_align(bytes + r.h_col.size() * 4);
   const size_t o_hval = bytes;
-  bytes = align_up(bytes + r.h_val.size() * 8);
+  bytes = arena_align(bytes + r.h_val.size() * 8);
   const size_t o_h1 = bytes;
-  bytes = align_up(bytes + r.h1.size() * 8);
+  bytes = arena_align(bytes + r.h1.size() * 8);
   const size_t o_rb = bytes;
-  bytes = align_up(bytes + (size_t)nnz * 8);
+  bytes = arena_align(bytes + (size_t)nnz * 8);
   const size_t o_rho = bytes;
-  bytes = align_up(bytes + (size_t)nnz * 8);
+  bytes = arena_align(bytes + (size_t)nnz * 8);
   const size_t o_pb = bytes;
-  bytes = align_up(bytes + (size_t)r.K * nnz * 8);
+  bytes = arena_align(bytes + (size_t)r.K * nnz * 8);
   const size_t o_rho1 = bytes;
-  bytes = align_up(bytes + (size_t)r.K * nnz * 8);
+  bytes = arena_align(bytes + (size_t)r.K * nnz * 8);
   r.footprint = (int64_t)bytes;
   if (bytes > arena->size()) {
     set_error("request %lld needs %zu bytes, the arena holds %zu", (long long)r.id, bytes,
@@ -207,7 +161,7 @@ void gq_server::run(Request& r, gq_ctx* ctx) {
   } piece{this, off, bytes, ctx->stream};
   char* base = arena_mem + off;
   gq_eigs* e = nullptr;
-  ok(gq_eigs_create_in(ctx, g, r.K, base, ws, &e));
+  ok(gq_eigs_create_in(ctx, g, r.K, 0u, base, ws, &e));
   std::unique_ptr<gq_eigs, void (*)(gq_eigs*)> eh(e, gq_eigs_destroy);
   hipStream_t st = ctx->stream;
   hip_ok(hipMemcpyAsync(base + o_hrp, r.h_rp.data(), r.h_rp.size() * 4, hipMemcpyHostToDevice, st),
@@ -228,10 +182,10 @@ void gq_server::run(Request& r, gq_ctx* ctx) {
   double* pb = reinterpret_cast<double*>(base + o_pb);
   double* rho1 = reinterpret_cast<double*>(base + o_rho1);
   ok(gq_submatrix_solve(ctx, g, &Hd, GQ_SOLVE_DEFAULT, e));
+  r.mu = std::numeric_limits<double>::quiet_NaN();  // no warm start
   ok(gq_density(ctx, e, r.kT, r.n_elec, &r.mu, rb));
   r.mu1.assign(r.K, 0.0);
-  ok(gq_response(ctx, e, reinterpret_cast<const double*>(base + o_h1), r.K, r.precision, pb,
-                 nullptr, r.mu1.data()));
+  ok(gq_response(ctx, e, base + o_h1, GQ_H1_DIAG, r.K, r.precision, pb, nullptr, r.mu1.data()));
   ok(gq_assemble(ctx, g, rb, 1, rho));
   ok(gq_assemble(ctx, g, pb, r.K, rho1));
   r.rho.resize(nnz);
@@ -250,7 +204,7 @@ void gq_server::worker() {
   hipStream_t st = nullptr;
   gq_ctx* ctx = nullptr;
   bool ready = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
-               gq_ctx_create(device, st, &ctx) == GQ_OK;
+               gq_ctx_create(device, st, 0, &ctx) == GQ_OK;
   for (;;) {
     std::shared_ptr<Request> r;
     {
@@ -307,7 +261,7 @@ gq_status gq_server_create(int32_t device, int32_t n_slots, int64_t arena_bytes,
     return GQ_EINVAL;
   }
   gq_ctx* probe = nullptr;
-  if (gq_status st = gq_ctx_create(device, nullptr, &probe)) return st;  // checks the device
+  if (gq_status st = gq_ctx_create(device, nullptr, 0, &probe)) return st;  // checks the device
   gq_ctx_destroy(probe);
   gq_server* s = new (std::nothrow) gq_server;
   if (!s) {

@@ -49,12 +49,15 @@ __device__ __forceinline__ void fermi2(double e, double mu, double beta, double&
   f1f = t * inv * inv;
 }
 
-// state: [0] lo, [1] hi, [2] mu, [3] kT, [4] n_elec.  Eigenvalues are ascending
-// within each subgraph, so the extremes are the first and last of each.
+// state: [0] lo, [1] hi, [2] mu, [3] kT, [4] n_elec, [5] warm-start guess,
+// [6] 1 while the next pass is the warm-start pass, else 0.  Eigenvalues are
+// ascending within each subgraph, so the extremes are the first and last of
+// each.  The bracket starts at the eigenvalue span widened by 50 kT, where the
+// occupation sum is below and above N_e.
 __global__ __launch_bounds__(kThreads) void k_mu_init(const double* __restrict__ eps,
                                                       const int32_t* __restrict__ sub_orb_ptr,
                                                       int n_sub, double* __restrict__ state,
-                                                      double kT, double n_elec) {
+                                                      double kT, double n_elec, double guess) {
   __shared__ double rmin[kThreads], rmax[kThreads];
   double lo = DBL_MAX, hi = -DBL_MAX;
   for (int s = threadIdx.x; s < n_sub; s += kThreads) {
@@ -77,12 +80,28 @@ __global__ __launch_bounds__(kThreads) void k_mu_init(const double* __restrict__
     state[2] = 0.5 * (state[0] + state[1]);
     state[3] = kT;
     state[4] = n_elec;
+    const bool warm = guess == guess;  // not NaN
+    state[5] = warm ? guess : 0.0;
+    state[6] = warm ? 1.0 : 0.0;
   }
 }
 
-__device__ __forceinline__ double mu_point(double lo, double hi, int j) {
+// Point j of a pass over the bracket [lo, hi]: evenly spaced, or in the
+// warm-start pass guess -+ kT 4^k (k = 7 .. -8 below the guess, -8 .. 7 above),
+// clipped to the bracket; ascending in j either way.
+__device__ __forceinline__ double mu_point(const double* state, double lo, double hi, int j) {
+  if (state[6] != 0.0) {
+    const double g = state[5], kT = state[3];
+    const double off = j < kMuPoints / 2 ? -kT * ldexp(1.0, 2 * (7 - j))
+                                         : kT * ldexp(1.0, 2 * (j - kMuPoints / 2 - 8));
+    return fmin(hi, fmax(lo, g + off));
+  }
   return lo + (hi - lo) * ((double)(j + 1) / (double)(kMuPoints + 1));
 }
+
+// true once the bracket holds no double strictly inside: later passes would
+// not change it
+__device__ __forceinline__ bool mu_done(double lo, double hi) { return !(nextafter(lo, hi) < hi); }
 
 __global__ __launch_bounds__(kThreads) void k_mu_eval(const double* __restrict__ eps,
                                                       const double* __restrict__ wts, int64_t count,
@@ -91,6 +110,8 @@ __global__ __launch_bounds__(kThreads) void k_mu_eval(const double* __restrict__
   constexpr int kH = kThreads / kMuPoints;  // threads per point
   __shared__ double se[kMuChunk], sw[kMuChunk];
   __shared__ double hp[kH][kMuPoints];
+  const double lo = state[0], hi = state[1], beta = 1.0 / state[3];
+  if (mu_done(lo, hi)) return;
   const int64_t base = (int64_t)blockIdx.x * kMuChunk;
   const int cnt = (int)min<int64_t>(kMuChunk, count - base);
   for (int i = threadIdx.x; i < cnt; i += kThreads) {
@@ -98,10 +119,9 @@ __global__ __launch_bounds__(kThreads) void k_mu_eval(const double* __restrict__
     sw[i] = wts[base + i];
   }
   __syncthreads();
-  const double lo = state[0], hi = state[1], beta = 1.0 / state[3];
   const int j = threadIdx.x % kMuPoints;
   const int h = threadIdx.x / kMuPoints;
-  const double mu = mu_point(lo, hi, j);
+  const double mu = mu_point(state, lo, hi, j);
   double acc = 0.0;
   for (int p = h; p < cnt; p += kH) {
     double f, f1f;
@@ -127,6 +147,7 @@ __global__ __launch_bounds__(kMuPoints * kMuGroups) void k_mu_update(
   __shared__ double G[kMuGroups][kMuPoints];
   __shared__ double F[kMuPoints];
   const int j = threadIdx.x % kMuPoints, g = threadIdx.x / kMuPoints;
+  if (mu_done(state[0], state[1])) return;
   double acc = 0.0;
   // unrolled so that the loads are in flight together; the adds keep their order
 #pragma unroll 8
@@ -147,11 +168,12 @@ __global__ __launch_bounds__(kMuPoints * kMuGroups) void k_mu_update(
         first = q;
         break;
       }
-    const double nlo = first == 0 ? lo : mu_point(lo, hi, first - 1);
-    const double nhi = first == kMuPoints ? hi : mu_point(lo, hi, first);
+    const double nlo = first == 0 ? lo : mu_point(state, lo, hi, first - 1);
+    const double nhi = first == kMuPoints ? hi : mu_point(state, lo, hi, first);
     state[0] = nlo;
     state[1] = nhi;
     state[2] = 0.5 * (nlo + nhi);
+    state[6] = 0.0;
   }
 }
 
@@ -327,14 +349,17 @@ __global__ __launch_bounds__(kThreads) void k_divided_differences(
 
 }  // namespace
 
-void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
+void launch_mu(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double guess) {
   const int64_t count = g->info.sum_n;
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_mu");
   hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(kThreads), 0, st, e->eps, g->dev.sub_orb_ptr,
-                     g->n_sub, e->mu_state, e->kT, e->n_elec);
+                     g->n_sub, e->mu_state, e->kT, e->n_elec, guess);
   const int nblk = (int)((count + kMuChunk - 1) / kMuChunk);
-  for (int pass = 0; pass < kMuPasses; ++pass) {
+  // the warm pass narrows the bracket to the two points around the root, at
+  // worst the whole span: one pass more keeps the cold-start resolution
+  const int passes = kMuPasses + (guess == guess ? 1 : 0);
+  for (int pass = 0; pass < passes; ++pass) {
     hipLaunchKernelGGL(k_mu_eval, dim3(nblk), dim3(kThreads), 0, st, e->eps, e->wts, count,
                        e->mu_state, e->mu_part);
     hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(kMuPoints * kMuGroups), 0, st, e->mu_part, nblk,

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kGaThreads) void k_gather(
     int32_t* __restrict__ status) {
   extern __shared__ int32_t si[];
   const int s = order[blockIdx.x];
-  if (threadIdx.x == 0) status[s] = 0;
+  if (status && threadIdx.x == 0) status[s] = 0;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   int32_t* so = si;
@@ -419,11 +419,12 @@ void eig_set_attributes() {
                             (int)tridiag_lds(kLdsPanelN));
 }
 
-void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status) {
+void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status,
+                   const char* label) {
   const gq_graph_dev& dv = g->dev;
   const int maxn = g->info.max_n;
   hipStream_t st = ctx->stream;
-  prof_begin(ctx, "k_gather");
+  prof_begin(ctx, label);
   hipLaunchKernelGGL(k_gather, dim3(g->n_sub), dim3(kGaThreads), 2 * maxn * sizeof(int32_t), st,
                      H->row_ptr, H->col, H->val, A, dv.off2, dv.sub_orb_ptr, dv.sub_orbs,
                      dv.sorted_orbs, dv.sorted_local, dv.order, status);

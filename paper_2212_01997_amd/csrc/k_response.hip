@@ -91,8 +91,14 @@ __device__ __forceinline__ double mfma4b(double a, double b, double c) {
 // 8-byte bank pairs in the staging writes (16 consecutive m) and in the B reads
 // (16 consecutive columns), and 4 broadcast addresses in the A reads.  h(m) is
 // applied to the B side while staging.
-template <int TM>
-__device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
+//
+// In general the block is sum_m A(m, k) h(m) B(m, l) with A and B column-major
+// n x n: A = B = Q for a diagonal perturbation (H = true), or without h for
+// the general kind, where W = h1_s Q is formed as G^T Q (G = h1_s, symmetric)
+// and X as Q^T W.
+template <int TM, bool H>
+__device__ __forceinline__ void xy_block_4b(const double* __restrict__ Am,
+                                            const double* __restrict__ Bm,
                                             const double* __restrict__ hl, int n, int k0, int l0,
                                             int kend, int lend, double (&acc)[TM / 16][TM / 16]) {
   constexpr int kXK = 16;  // FP64 K chunk: 16 rows keep four workgroups per CU
@@ -110,12 +116,12 @@ __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
   double ph = 0.0;
   auto fetch = [&](int m0) {
     const int mc = min(m0 + mm_t, n - 1);
-    ph = hl[mc];
+    if constexpr (H) ph = hl[mc];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int c = c_t + u * (kNT / kXK);
-      pa[u] = Q[mc + (size_t)n * min(k0 + c, n - 1)];
-      pb[u] = Q[mc + (size_t)n * min(l0 + c, n - 1)];
+      pa[u] = Am[mc + (size_t)n * min(k0 + c, n - 1)];
+      pb[u] = Bm[mc + (size_t)n * min(l0 + c, n - 1)];
     }
   };
 #pragma unroll
@@ -130,7 +136,8 @@ __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Q,
     for (int u = 0; u < kPer; ++u) {
       const int c = c_t + u * (kNT / kXK);
       As[mm_t][c] = (okm && k0 + c < kend) ? pa[u] : 0.0;
-      Bs[mm_t][c] = (okm && l0 + c < lend) ? ph * pb[u] : 0.0;
+      if constexpr (H) Bs[mm_t][c] = (okm && l0 + c < lend) ? ph * pb[u] : 0.0;
+      else Bs[mm_t][c] = (okm && l0 + c < lend) ? pb[u] : 0.0;
     }
     __syncthreads();
     if (m0 + kXK < n) fetch(m0 + kXK);
@@ -225,10 +232,13 @@ __device__ __forceinline__ void xy_block_4b_kq(const double* __restrict__ Q,
 // The same block from the FP32 leading parts: each kXK-deep chunk is summed by
 // FP32 MFMA in FP32 and the chunk sums are added in FP64.  acc[x][y][r] holds
 // row 4*(lane/16) + r of the 16x16 block (x, y).
-template <int TM>
+// The B side is the FP32 part of Q scaled by h (diagonal kind, TB = float)
+// or W = h1_s Q rounded to FP32 as it is staged (general kind, TB = double,
+// no h).
+template <int TM, typename TB, bool H>
 __device__ __forceinline__ void xy_block_f32(
-    const float* __restrict__ Q, const double* __restrict__ hl, int n, int k0, int l0,
-    double (&acc)[XyShape<TM>::kWB][XyShape<TM>::kWB][4]) {
+    const float* __restrict__ Q, const TB* __restrict__ Bm, const double* __restrict__ hl, int n,
+    int k0, int l0, double (&acc)[XyShape<TM>::kWB][XyShape<TM>::kWB][4]) {
   using S = XyShape<TM>;
   constexpr int WB = S::kWB;
   __shared__ float As[kXK][TM + 1];
@@ -247,9 +257,9 @@ __device__ __forceinline__ void xy_block_f32(
       const int mm = idx % kXK, kk = idx / kXK;
       const int mc = min(m0 + mm, n - 1);
       pa[u] = Q[mc + (size_t)n * min(k0 + kk, n - 1)];
-      pb[u] = Q[mc + (size_t)n * min(l0 + kk, n - 1)];
+      pb[u] = (float)Bm[mc + (size_t)n * min(l0 + kk, n - 1)];
     }
-    ph = (float)hl[min(m0 + (tid & (kXK - 1)), n - 1)];
+    if constexpr (H) ph = (float)hl[min(m0 + (tid & (kXK - 1)), n - 1)];
   };
 #pragma unroll
   for (int x = 0; x < WB; ++x)
@@ -268,7 +278,9 @@ __device__ __forceinline__ void xy_block_f32(
       As[mm][kk] = (okm && k0 + kk < n) ? pa[u] : 0.f;
       Bs[mm][kk] = (okm && l0 + kk < n) ? pb[u] : 0.f;
     }
-    if (tid < kXK) hs[tid] = (m0 + tid < n) ? ph : 0.f;
+    if constexpr (H) {
+      if (tid < kXK) hs[tid] = (m0 + tid < n) ? ph : 0.f;
+    }
     __syncthreads();
     if (m0 + kXK < n) fetch(m0 + kXK);
     v4f c[WB][WB];
@@ -279,12 +291,12 @@ __device__ __forceinline__ void xy_block_f32(
 #pragma unroll
     for (int ks = 0; ks < kXK / 4; ++ks) {
       const int row = 4 * ks + lk;
-      const float hr = hs[row];
       float a[WB], bb[WB];
 #pragma unroll
       for (int x = 0; x < WB; ++x) {
         a[x] = As[row][wr + 16 * x + li];
-        bb[x] = hr * Bs[row][wc + 16 * x + li];
+        if constexpr (H) bb[x] = hs[row] * Bs[row][wc + 16 * x + li];
+        else bb[x] = Bs[row][wc + 16 * x + li];
       }
 #pragma unroll
       for (int x = 0; x < WB; ++x)
@@ -394,13 +406,15 @@ __device__ __forceinline__ void xy_block_f32_kq(
 // parent is on or below the diagonal, so every value of the symmetric Y sits at
 // the position whose row tile is not above its column tile, written coalesced.
 // Workgroup b serves XCD b % 8 and walks that XCD's range of the list with
-// stride gridDim.x / 8 (one tile per workgroup, or persistent).
-template <int TM, bool SPLIT>
+// stride gridDim.x / 8 (one tile per workgroup, or persistent).  GEN: the
+// general kind, X = Q^T W with W = h1_s Q of perturbation q in wbuf.
+template <int TM, bool SPLIT, bool GEN>
 __global__ __launch_bounds__(256, 4) void k_xy(
     const double* __restrict__ qbuf, const float* __restrict__ q32,
     const double* __restrict__ dfbuf, double* __restrict__ ybuf, const double* __restrict__ hloc,
-    const int32_t* __restrict__ tiles, XcdSplit split, const int64_t* __restrict__ off2,
-    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n) {
+    const double* __restrict__ wbuf, const int32_t* __restrict__ tiles, XcdSplit split,
+    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2,
+    int64_t sum_n) {
   constexpr int WB = XyShape<TM>::kWB;
   const int q = blockIdx.y;
   const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
@@ -413,11 +427,13 @@ __global__ __launch_bounds__(256, 4) void k_xy(
     const int n = sub_orb_ptr[s + 1] - b;
     const int k0 = ti * TM, l0 = tj * TM;
     const double* hl = hloc + (size_t)q * sum_n + b;
+    const double* W = GEN ? wbuf + (size_t)q * sum_n2 + off2[s] : nullptr;
     const double* dF = dfbuf + off2[s];
     double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
     if constexpr (SPLIT) {
       double acc[WB][WB][4];
-      xy_block_f32<TM>(q32 + off2[s], hl, n, k0, l0, acc);
+      if constexpr (GEN) xy_block_f32<TM, double, false>(q32 + off2[s], W, hl, n, k0, l0, acc);
+      else xy_block_f32<TM, float, true>(q32 + off2[s], q32 + off2[s], hl, n, k0, l0, acc);
       // all dF loads first (clamped addresses), then the stores
       double dfv[WB][WB][4];
 #pragma unroll
@@ -442,7 +458,8 @@ __global__ __launch_bounds__(256, 4) void k_xy(
           }
     } else {
       double acc[TM / 16][TM / 16];
-      xy_block_4b<TM>(qbuf + off2[s], hl, n, k0, l0, n, n, acc);
+      if constexpr (GEN) xy_block_4b<TM, false>(qbuf + off2[s], W, hl, n, k0, l0, n, n, acc);
+      else xy_block_4b<TM, true>(qbuf + off2[s], qbuf + off2[s], hl, n, k0, l0, n, n, acc);
       double dfv[TM / 16][TM / 16];
 #pragma unroll
       for (int r = 0; r < TM / 16; ++r)
@@ -459,6 +476,41 @@ __global__ __launch_bounds__(256, 4) void k_xy(
           const int k = k0 + w * (TM / 4) + 4 * r + (lane >> 4);
           const int l = l0 + 16 * c + (lane & 15);
           if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[r][c] * dfv[r][c];
+        }
+    }
+  }
+}
+
+// W = h1_s Q for the general kind, perturbation q = blockIdx.y: the gathered
+// h1_s (symmetric, so its column r is its row r) is the A side and Q the B
+// side.  The 64x64 tile list holds (ti, tj) with tj <= ti; a workgroup forms
+// the W tiles (ti, tj) and, off the diagonal, (tj, ti), so every tile of the
+// full n x n W is written once, column-major like Q.
+__global__ __launch_bounds__(256, 4) void k_wq(
+    const double* __restrict__ gbuf, const double* __restrict__ qbuf, double* __restrict__ wbuf,
+    const int32_t* __restrict__ tiles, XcdSplit split, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2) {
+  constexpr int TM = kTile;
+  const int q = blockIdx.y;
+  const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int t = split.off[xcd] + (int)(blockIdx.x >> 3); t < split.off[xcd + 1]; t += stride) {
+    const int s = tiles[3 * t], ti = tiles[3 * t + 1], tj = tiles[3 * t + 2];
+    const int n = sub_orb_ptr[s + 1] - sub_orb_ptr[s];
+    const double* Gs = gbuf + (size_t)q * sum_n2 + off2[s];
+    const double* Q = qbuf + off2[s];
+    double* W = wbuf + (size_t)q * sum_n2 + off2[s];
+    for (int side = 0; side < (ti == tj ? 1 : 2); ++side) {
+      const int r0 = (side == 0 ? ti : tj) * TM, c0 = (side == 0 ? tj : ti) * TM;
+      double acc[TM / 16][TM / 16];
+      xy_block_4b<TM, false>(Gs, Q, nullptr, n, r0, c0, n, n, acc);
+#pragma unroll
+      for (int r = 0; r < TM / 16; ++r)
+#pragma unroll
+        for (int c = 0; c < TM / 16; ++c) {
+          const int row = r0 + w * (TM / 4) + 4 * r + (lane >> 4);
+          const int col = c0 + 16 * c + (lane & 15);
+          if (row < n && col < n) W[(size_t)row + (size_t)n * col] = acc[r][c];
         }
     }
   }
@@ -574,11 +626,13 @@ __device__ __forceinline__ int lower_index(const double* v, int n, double x) {
 // X would be amplified most.  Workgroup (subgraph, perturbation, z) recomputes
 // the 64x64 sub-block z = 2 bi + bj of the window block X[lo..hi, lo..hi]
 // (hi - lo <= kWinMax) on FP64 MFMA and overwrites those entries of Y.
+template <bool GEN>
 __global__ __launch_bounds__(kThreads) void k_win(
     const double* __restrict__ qbuf, const double* __restrict__ dfbuf, double* __restrict__ ybuf,
-    const double* __restrict__ hloc, const double* __restrict__ eps,
-    const double* __restrict__ mu_state, const int64_t* __restrict__ off2,
-    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n) {
+    const double* __restrict__ hloc, const double* __restrict__ wbuf,
+    const double* __restrict__ eps, const double* __restrict__ mu_state,
+    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2,
+    int64_t sum_n) {
   const int s = blockIdx.x, q = blockIdx.y;
   const int bi = blockIdx.z >> 1, bj = blockIdx.z & 1;
   const int b = sub_orb_ptr[s];
@@ -596,7 +650,12 @@ __global__ __launch_bounds__(kThreads) void k_win(
   const int k0 = lo + kTile * bi, l0 = lo + kTile * bj;
   if (k0 >= hi || l0 >= hi) return;
   double acc[kTile / 16][kTile / 16];
-  xy_block_4b<kTile>(qbuf + off2[s], hloc + (size_t)q * sum_n + b, n, k0, l0, hi, hi, acc);
+  if constexpr (GEN)
+    xy_block_4b<kTile, false>(qbuf + off2[s], wbuf + (size_t)q * sum_n2 + off2[s], nullptr, n, k0,
+                              l0, hi, hi, acc);
+  else
+    xy_block_4b<kTile, true>(qbuf + off2[s], qbuf + off2[s], hloc + (size_t)q * sum_n + b, n, k0,
+                             l0, hi, hi, acc);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* dF = dfbuf + off2[s];
   double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
@@ -875,15 +934,20 @@ __global__ __launch_bounds__(kThreads) void k_assemble(
 
 // ------------------------------------------------------------ xy launches
 using XyKernel = void (*)(const double*, const float*, const double*, double*, const double*,
-                          const int32_t*, XcdSplit, const int64_t*, const int32_t*, int64_t,
-                          int64_t);
+                          const double*, const int32_t*, XcdSplit, const int64_t*,
+                          const int32_t*, int64_t, int64_t);
 using XyKqKernel = void (*)(const double*, const float*, const double*, double*, const double*,
                             const int32_t*, XcdSplit, const int64_t*, const int32_t*, int64_t,
                             int64_t, int);
 
-XyKernel xy_kernel(int shape, bool split) {
-  if (shape == 0) return split ? k_xy<64, true> : k_xy<64, false>;
-  return split ? k_xy<32, true> : k_xy<32, false>;
+template <bool GEN>
+XyKernel xy_kernel_t(int shape, bool split) {
+  if (shape == 0) return split ? k_xy<64, true, GEN> : k_xy<64, false, GEN>;
+  return split ? k_xy<32, true, GEN> : k_xy<32, false, GEN>;
+}
+
+XyKernel xy_kernel(int shape, bool split, bool gen) {
+  return gen ? xy_kernel_t<true>(shape, split) : xy_kernel_t<false>(shape, split);
 }
 
 XyKqKernel xy_kq_kernel(int shape, bool split) {
@@ -901,7 +965,7 @@ int xy_resident_per_xcd(int shape, int variant) {
   int v = c.load(std::memory_order_relaxed);
   if (v == 0) {
     const void* fn = variant >= 2 ? (const void*)xy_kq_kernel(shape, variant == 3)
-                                  : (const void*)xy_kernel(shape, variant == 1);
+                                  : (const void*)xy_kernel(shape, variant == 1, false);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, xy_threads(shape), 0) !=
             hipSuccess ||
@@ -916,12 +980,14 @@ int xy_resident_per_xcd(int shape, int variant) {
 }
 
 // Launch of one bin with variant `choice` (bit 0: 32x32 tiles, bit 1: persistent).
-// Launches with K > 1 take kXyKq perturbations per workgroup.
-void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int bin, int choice, bool split,
-                   int K) {
+// Diagonal launches with K > 1 take kXyKq perturbations per workgroup; the
+// general kind (gen) takes one perturbation per workgroup, X = Q^T W with W in
+// rb.Y, written to rb.G.
+void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb, int bin,
+                   int choice, bool split, bool gen, int K) {
   const int shape = choice & 1;
   const bool persistent = (choice & 2) != 0;
-  const bool kq = K > 1;
+  const bool kq = K > 1 && !gen;
   const XcdSplit& sp = g->xy_split[shape][bin];
   int longest = 0;
   for (int x = 0; x < 8; ++x) longest = std::max(longest, sp.off[x + 1] - sp.off[x]);
@@ -932,14 +998,15 @@ void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int bin, int choi
   const gq_graph_dev& dv = g->dev;
   if (kq) {
     hipLaunchKernelGGL(xy_kq_kernel(shape, split), dim3(8 * per_xcd, (K + kXyKq - 1) / kXyKq),
-                       dim3(xy_threads(shape)), 0, ctx->stream, e->Q, e->Q32, e->A, e->Y, e->hloc,
-                       dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr, g->info.sum_n2,
+                       dim3(xy_threads(shape)), 0, ctx->stream, e->Q, e->Q32, e->A, rb.Y,
+                       rb.hloc, dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr, g->info.sum_n2,
                        g->info.sum_n, K);
     return;
   }
-  hipLaunchKernelGGL(xy_kernel(shape, split), dim3(8 * per_xcd, K), dim3(xy_threads(shape)), 0,
-                     ctx->stream, e->Q, e->Q32, e->A, e->Y, e->hloc, dv.xy_tiles[shape], sp,
-                     dv.off2, dv.sub_orb_ptr, g->info.sum_n2, g->info.sum_n);
+  hipLaunchKernelGGL(xy_kernel(shape, split, gen), dim3(8 * per_xcd, K), dim3(xy_threads(shape)),
+                     0, ctx->stream, e->Q, e->Q32, e->A, gen ? rb.G : rb.Y, rb.hloc,
+                     gen ? rb.Y : nullptr, dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr,
+                     g->info.sum_n2, g->info.sum_n);
 }
 
 void launch_split32(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
@@ -999,47 +1066,67 @@ void build_xy_tiles(gq_graph* g) {
     for (int bin = 0; bin < kXyBins; ++bin) g->xy_choice[p][bin] = 0;
 }
 
-void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const double* h1, int32_t K,
-                     uint32_t precision, double* p_blocks) {
+void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb,
+                     const H1Spec& h1, int32_t K, uint32_t precision, double* p_blocks) {
   hipStream_t st = ctx->stream;
   const gq_graph_dev& dv = g->dev;
   const int64_t nnz = g->info.nnz;
   const int64_t sum_n = g->info.sum_n, sum_n2 = g->info.sum_n2;
   const int sum_c = g->offcd[g->n_sub];
   const bool split = precision == GQ_PREC_SPLIT32;
+  const bool gen = h1.kind == GQ_H1_CSR;
   // a captured sequence must not depend on the host-side validity flag
   if (split && (!e->q32_valid || ctx->capturing)) {
     launch_split32(ctx, g, e);
     e->q32_valid = true;
   }
+  if (gen) {
+    // h1_s of every subgraph and perturbation into G, then W = h1_s Q into Y
+    for (int q = 0; q < K; ++q)
+      launch_gather(ctx, g, &h1.csr[q], rb.G + (size_t)q * sum_n2, nullptr, "k_h1_gather");
+    prof_begin(ctx, "k_wq");
+    const XcdSplit* sp = g->xy_split[0];
+    for (int bin = 0; bin < kXyBins; ++bin) {
+      int longest = 0;
+      for (int x = 0; x < 8; ++x) longest = std::max(longest, sp[bin].off[x + 1] - sp[bin].off[x]);
+      if (longest == 0) continue;
+      hipLaunchKernelGGL(k_wq, dim3(8 * longest, K), dim3(kThreads), 0, st, rb.G, e->Q, rb.Y,
+                         dv.xy_tiles[0], sp[bin], dv.off2, dv.sub_orb_ptr, sum_n2);
+    }
+    prof_end(ctx);
+  }
   prof_begin(ctx, split ? "k_xy32" : "k_xy");
-  hipLaunchKernelGGL(k_h1_gather,
-                     dim3((unsigned)std::min<int64_t>(1024, (sum_n + kThreads - 1) / kThreads), K),
-                     dim3(kThreads), 0, st, h1, g->N, dv.sub_orbs, sum_n, e->hloc);
+  if (!gen)
+    hipLaunchKernelGGL(k_h1_gather,
+                       dim3((unsigned)std::min<int64_t>(1024, (sum_n + kThreads - 1) / kThreads), K),
+                       dim3(kThreads), 0, st, h1.diag, g->N, dv.sub_orbs, sum_n, rb.hloc);
   for (int bin = 0; bin < kXyBins; ++bin)
-    launch_xy_bin(ctx, g, e, bin, g->xy_choice[split ? 1 : 0][bin], split, K);
+    launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[split ? 1 : 0][bin], split, gen, K);
   prof_end(ctx);
+  // X o dF of perturbation q is in ybuf: Y for the diagonal kind, G for the general
+  double* ybuf = gen ? rb.G : rb.Y;
   if (split) {
     prof_begin(ctx, "k_win");
-    hipLaunchKernelGGL(k_win, dim3(g->n_sub, K, 4), dim3(kThreads), 0, st, e->Q, e->A, e->Y, e->hloc,
-                       e->eps, e->mu_state, dv.off2, dv.sub_orb_ptr, sum_n2, sum_n);
+    hipLaunchKernelGGL(gen ? k_win<true> : k_win<false>, dim3(g->n_sub, K, 4), dim3(kThreads), 0,
+                       st, e->Q, e->A, ybuf, rb.hloc, rb.Y, e->eps, e->mu_state, dv.off2,
+                       dv.sub_orb_ptr, sum_n2, sum_n);
     prof_end(ctx);
   }
   prof_begin(ctx, "k_rows");
   dim3 grid_cols(g->n_sub, (g->info.max_n + kTC - 1) / kTC, K);
-  hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, e->Y, e->T, dv.off2,
+  hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, ybuf, rb.T, dv.off2,
                      dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
   const int ncb = (g->info.max_n + kTC - 1) / kTC;
   const int groups_per_xcd = (g->n_sub * ncb + 7) / 8;
-  hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, e->T, e->Q,
-                     p_blocks, e->pdiag, dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core,
+  hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, rb.T, e->Q,
+                     p_blocks, rb.pdiag, dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core,
                      dv.order, sum_n, nnz, sum_c, g->n_sub, ncb, K);
   prof_end(ctx);
   prof_begin(ctx, "k_mu1_combine");
-  hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, e->pdiag, sum_c, e->tmu, g->n_sub,
-                     e->mu1);
+  hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, rb.pdiag, sum_c, e->tmu, g->n_sub,
+                     rb.mu1);
   const int blocks = (int)std::min<int64_t>(4096, (nnz + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_combine, dim3(blocks, K), dim3(kThreads), 0, st, p_blocks, e->M, e->mu1,
+  hipLaunchKernelGGL(k_combine, dim3(blocks, K), dim3(kThreads), 0, st, p_blocks, e->M, rb.mu1,
                      nnz);
   prof_end(ctx);
 }
@@ -1052,6 +1139,7 @@ gq_status autotune_xy(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, uint32_t preci
     e->q32_valid = true;
   }
   hipStream_t st = ctx->stream;
+  const RespBufs rb{e->hloc, e->Y, e->G, e->T, e->pdiag, e->mu1};
   // the tuning launches read whatever h1 the workspace holds; only their time matters
   GQ_HIP(hipMemsetAsync(e->hloc, 0, g->info.sum_n * sizeof(double), st));
   hipEvent_t t0, t1;
@@ -1068,11 +1156,11 @@ gq_status autotune_xy(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, uint32_t preci
     float best = 1e30f;
     int best_c = 0;
     for (int choice = 0; choice < 4; ++choice) {
-      launch_xy_bin(ctx, g, e, bin, choice, split, 1);  // warm-up
+      launch_xy_bin(ctx, g, e, rb, bin, choice, split, false, 1);  // warm-up
       float ms_min = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {
         if (hipEventRecord(t0, st) != hipSuccess) rc = GQ_EDEVICE;
-        launch_xy_bin(ctx, g, e, bin, choice, split, 1);
+        launch_xy_bin(ctx, g, e, rb, bin, choice, split, false, 1);
         if (hipEventRecord(t1, st) != hipSuccess || hipEventSynchronize(t1) != hipSuccess)
           rc = GQ_EDEVICE;
         float ms = 0.f;

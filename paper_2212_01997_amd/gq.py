@@ -19,6 +19,9 @@ PATHS2 = 1
 COMPLETE = 2
 PREC_FP64 = 0
 PREC_SPLIT32 = 1
+EIGS_GENERAL_H1 = 1
+H1_DIAG = 0
+H1_CSR = 1
 
 _STATUS = {0: "GQ_OK", -1: "GQ_EINVAL", -2: "GQ_ENOMEM", -3: "GQ_ENOCONV", -4: "GQ_EDEVICE",
            -5: "GQ_EBUSY"}
@@ -60,7 +63,8 @@ _VP = C.c_void_p
 _SIGS = {
     "gq_last_error": ([], C.c_char_p),
     "gq_version": ([], C.c_char_p),
-    "gq_ctx_create": ([C.c_int32, _VP, C.POINTER(_VP)], C.c_int32),
+    "gq_ctx_create": ([C.c_int32, _VP, C.c_int64, C.POINTER(_VP)], C.c_int32),
+    "gq_ctx_arena_used": ([_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int32),
     "gq_ctx_destroy": ([_VP], None),
     "gq_graph_build": ([C.c_int32, _VP, C.POINTER(_Csr), C.POINTER(_Csr), _VP, C.c_double,
                         C.c_uint32, C.POINTER(_VP)], C.c_int32),
@@ -68,13 +72,15 @@ _SIGS = {
     "gq_graph_export": ([_VP] + [_VP] * 8, C.c_int32),
     "gq_graph_block_offsets": ([_VP, _VP], C.c_int32),
     "gq_graph_destroy": ([_VP], None),
-    "gq_eigs_create": ([_VP, _VP, C.c_int32, C.POINTER(_VP)], C.c_int32),
-    "gq_eigs_create_in": ([_VP, _VP, C.c_int32, _VP, C.c_int64, C.POINTER(_VP)], C.c_int32),
-    "gq_eigs_footprint": ([_VP, C.c_int32, C.POINTER(C.c_int64)], C.c_int32),
+    "gq_eigs_create": ([_VP, _VP, C.c_int32, C.c_uint32, C.POINTER(_VP)], C.c_int32),
+    "gq_eigs_create_in": ([_VP, _VP, C.c_int32, C.c_uint32, _VP, C.c_int64, C.POINTER(_VP)],
+                          C.c_int32),
+    "gq_eigs_footprint": ([_VP, C.c_int32, C.c_uint32, C.POINTER(C.c_int64)], C.c_int32),
     "gq_eigs_destroy": ([_VP], None),
     "gq_submatrix_solve": ([_VP, _VP, C.POINTER(_Csr), C.c_uint32, _VP], C.c_int32),
     "gq_density": ([_VP, _VP, C.c_double, C.c_double, _VP, _VP], C.c_int32),
-    "gq_response": ([_VP, _VP, _VP, C.c_int32, C.c_uint32, _VP, _VP, _VP], C.c_int32),
+    "gq_response": ([_VP, _VP, _VP, C.c_uint32, C.c_int32, C.c_uint32, _VP, _VP, _VP],
+                    C.c_int32),
     "gq_assemble": ([_VP, _VP, _VP, C.c_int32, _VP], C.c_int32),
     "gq_eigs_export": ([_VP, _VP, _VP, _VP], C.c_int32),
     "gq_eigs_vectors": ([_VP, C.c_int32, C.POINTER(_VP), C.POINTER(C.c_int32)], C.c_int32),
@@ -151,15 +157,24 @@ def _release(obj, fn):
 
 
 class Context:
-    def __init__(self, device=0, stream=None):
+    """gq_ctx_create: a device, a stream and, with arena_bytes > 0, one device
+    arena that every workspace made on this context takes its memory from."""
+
+    def __init__(self, device=0, stream=None, arena_bytes=0):
         import torch
         if not torch.cuda.is_available():
             raise GQError(-4, "no GPU visible")
         self.device = device
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         h = _VP()
-        _check(lib().gq_ctx_create(device, _VP(self.stream.cuda_stream), C.byref(h)))
+        _check(lib().gq_ctx_create(device, _VP(self.stream.cuda_stream), int(arena_bytes),
+                                   C.byref(h)))
         self.h = h
+
+    def arena_used(self):
+        used, size = C.c_int64(), C.c_int64()
+        _check(lib().gq_ctx_arena_used(self.h, C.byref(used), C.byref(size)))
+        return used.value, size.value
 
     def set_profiling(self, enable=True):
         _check(lib().gq_ctx_set_profiling(self.h, 1 if enable else 0))
@@ -264,9 +279,9 @@ class Graph:
         """Force the X-kernel launch variant of one size bin (gq_graph_set_launch)."""
         _check(lib().gq_graph_set_launch(self.h, int(precision), int(bin_index), int(variant)))
 
-    def footprint(self, max_k):
+    def footprint(self, max_k, flags=0):
         b = C.c_int64()
-        _check(lib().gq_eigs_footprint(self.h, int(max_k), C.byref(b)))
+        _check(lib().gq_eigs_footprint(self.h, int(max_k), int(flags), C.byref(b)))
         return b.value
 
     def __del__(self, _rel=_release):
@@ -291,26 +306,39 @@ class DeviceCsr:
 class Eigs:
     """Device-resident eigen workspace of one graph (gq_eigs_create)."""
 
-    def __init__(self, ctx: Context, graph: Graph, max_k=1):
+    def __init__(self, ctx: Context, graph: Graph, max_k=1, general_h1=False):
         self.ctx, self.graph, self.max_k = ctx, graph, max_k
         h = _VP()
-        _check(lib().gq_eigs_create(ctx.h, graph.h, int(max_k), C.byref(h)))
+        _check(lib().gq_eigs_create(ctx.h, graph.h, int(max_k),
+                                    EIGS_GENERAL_H1 if general_h1 else 0, C.byref(h)))
         self.h = h
 
     def solve(self, H: DeviceCsr):
         s = H.cstruct()
         _check(lib().gq_submatrix_solve(self.ctx.h, self.graph.h, C.byref(s), 0, self.h))
 
-    def density(self, kT, n_elec, rho_blocks=None, want_mu=True):
-        mu = C.c_double()
+    def density(self, kT, n_elec, rho_blocks=None, want_mu=True, mu_guess=None):
+        """gq_density; mu_guess (or None) is the warm start.  Returns mu when
+        want_mu (which waits for the stream)."""
+        if mu_guess is not None and not want_mu:
+            raise ValueError("a warm start returns mu: want_mu must be True")
+        mu = C.c_double(float("nan") if mu_guess is None else float(mu_guess))
         _check(lib().gq_density(self.ctx.h, self.h, float(kT), float(n_elec),
                                 C.byref(mu) if want_mu else None, _ptr(rho_blocks)))
         return mu.value if want_mu else None
 
     def response(self, h1, p_blocks, precision=PREC_FP64, mu1_dev=None, want_mu1=True):
-        K = int(h1.shape[0])
+        """gq_response.  h1: a [K, N] device tensor of diagonals, or a list of
+        K DeviceCsr perturbations (needs general_h1=True)."""
+        if isinstance(h1, (list, tuple)):
+            K = len(h1)
+            arr = (_Csr * K)(*[m.cstruct() for m in h1])
+            arg, kind = C.cast(arr, _VP), H1_CSR
+        else:
+            K = int(h1.shape[0])
+            arg, kind = _ptr(h1), H1_DIAG
         host = (C.c_double * K)()
-        _check(lib().gq_response(self.ctx.h, self.h, _ptr(h1), K, int(precision),
+        _check(lib().gq_response(self.ctx.h, self.h, arg, kind, K, int(precision),
                                  _ptr(p_blocks), _ptr(mu1_dev), host if want_mu1 else None))
         return np.array(host[:]) if want_mu1 else None
 

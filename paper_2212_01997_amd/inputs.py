@@ -396,6 +396,37 @@ def h1_diagonal(system, k, seed, sigma=0.05):
     return np.repeat(shifts, norb, axis=1).astype(np.float64)
 
 
+def h1_on_pattern(system, k, seed, sigma=0.05):
+    """K symmetric perturbations on the sparsity pattern of H (every stored
+    entry of H, diagonal included, gets an N(0, sigma) value; entry (b, a)
+    mirrors (a, b)).  Returns a list of K host CSR triples (row_ptr, col, val)."""
+    rng = np.random.default_rng(seed)
+    n = system.n_orb
+    rows = np.repeat(np.arange(n), np.diff(system.h_row_ptr))
+    col = system.h_col
+    out = []
+    for _ in range(k):
+        dense = np.zeros((n, n))
+        dense[rows, col] = rng.normal(0.0, sigma, size=len(col))
+        dense = np.triu(dense) + np.triu(dense, 1).T
+        out.append((system.h_row_ptr.copy(), col.copy(), dense[rows, col].copy()))
+    return out
+
+
+def h1_dense(system, k, seed, sigma=0.05):
+    """K fully dense symmetric N x N perturbations with N(0, sigma) entries,
+    as host CSR triples with every entry stored."""
+    rng = np.random.default_rng(seed)
+    n = system.n_orb
+    out = []
+    for _ in range(k):
+        a = rng.normal(0.0, sigma, size=(n, n))
+        a = np.triu(a) + np.triu(a, 1).T
+        out.append((np.arange(0, n * n + 1, n, dtype=np.int32),
+                    np.tile(np.arange(n, dtype=np.int32), n), a.ravel().copy()))
+    return out
+
+
 # -------------------------------------------------------------- partitions
 
 def single_atom_cores(system):

@@ -16,13 +16,14 @@ class GraphPath:
     """Device state of one system on one graph, reusable across perturbations."""
 
     def __init__(self, ctx: gq.Context, system, core_of_atom, tau, rho_prev=None, flags=0,
-                 max_k=1, graph: gq.Graph | None = None, H: gq.DeviceCsr | None = None):
+                 max_k=1, graph: gq.Graph | None = None, H: gq.DeviceCsr | None = None,
+                 general_h1=False):
         import torch
         self.ctx = ctx
         self.system = system
         self.graph = graph or gq.Graph.for_system(system, core_of_atom, tau, rho_prev, flags)
         self.H = H or gq.DeviceCsr(system.h_row_ptr, system.h_col, system.h_val, ctx.device)
-        self.eigs = gq.Eigs(ctx, self.graph, max_k)
+        self.eigs = gq.Eigs(ctx, self.graph, max_k, general_h1=general_h1)
         nnz = self.graph.info.nnz
         dev = torch.device("cuda", ctx.device)
         self.max_k = max_k
@@ -39,17 +40,19 @@ class GraphPath:
     def nnz(self):
         return self.graph.info.nnz
 
-    def ground_state(self, kT, n_elec=None, want_mu=True):
-        """submatrix_solve + density + assemble(rho)."""
+    def ground_state(self, kT, n_elec=None, want_mu=True, mu_guess=None):
+        """submatrix_solve + density (warm-started from mu_guess, if given) +
+        assemble(rho)."""
         ne = self.system.n_elec if n_elec is None else n_elec
         self.eigs.solve(self.H)
-        mu = self.eigs.density(kT, ne, self.rho_blocks, want_mu=want_mu)
+        mu = self.eigs.density(kT, ne, self.rho_blocks, want_mu=want_mu, mu_guess=mu_guess)
         gq.assemble(self.ctx, self.graph, self.rho_blocks, self.rho, 1)
         return mu
 
     def respond(self, h1, precision=gq.PREC_FP64, want_mu1=True):
-        """response + assemble(rho1) for K = h1.shape[0] perturbations."""
-        K = int(h1.shape[0])
+        """response + assemble(rho1) for K perturbations: a [K, N] tensor of
+        diagonals or a list of K DeviceCsr matrices."""
+        K = len(h1) if isinstance(h1, (list, tuple)) else int(h1.shape[0])
         mu1 = self.eigs.response(h1, self.p_blocks[:K * self.nnz], precision,
                                  mu1_dev=self.mu1_dev[:K], want_mu1=want_mu1)
         gq.assemble(self.ctx, self.graph, self.p_blocks[:K * self.nnz], self.rho1[:K * self.nnz], K)
