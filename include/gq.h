@@ -221,6 +221,28 @@ gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t h1_kind,
                       uint32_t precision, double* p_blocks_dev, double* mu1_dev,
                       double* mu1_host);
 
+/* ------------------------------------------------- response, no allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and the same results, bit for bit, as gq_response, with the
+ * response's per-call buffers (perturbations gathered per subgraph,
+ * X o dF, general-kind h1_s and W = h1_s Q, Q_c (X o dF), the core diagonals
+ * of P, mu1) in the library's static device scratch of 2^25 doubles
+ * (256 MiB) per device instead of the workspace, so K is not bounded by
+ * max_k.  The perturbations run in chunks of as many as fit the scratch
+ * (sum n_i^2 + 33 sum n_i + sum c_i doubles each, twice the n^2 term for
+ * GQ_H1_CSR); GQ_ENOMEM with a message if one does not fit (sum n_i^2 above
+ * about 3.2e7).  The scratch keeps the last call's contents and nothing in it
+ * needs to start at zero.  It is shared by every context on the device:
+ * calls that overlap in time on one GPU (concurrent streams or threads) race
+ * on it and must be serialised by the caller.  Calls no hipMalloc, hipFree or
+ * allocating library routine and does not wait for the stream (allowed while
+ * capturing).  Arguments and errors as gq_response, without mu1_host; the
+ * workspace needs no max_k >= K. */
+gq_status gq_response_static(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t h1_kind,
+                             int32_t K, uint32_t precision, double* p_blocks_dev,
+                             double* mu1_dev);
+
 /* ------------------------------------------------------------- assemble
  * Scatters K block arrays (device, [K][nnz], block layout) into CSR value
  * arrays vals_dev[K][nnz] in the collected pattern of g (device). */

@@ -252,6 +252,7 @@ gq_status gq_ctx_create(int32_t device, void* hip_stream, int64_t arena_bytes, g
   }
   eig_set_attributes();
   dc_set_attributes();
+  if (gq_status st = scratch_init(device)) return st;
   gq_ctx* c = new (std::nothrow) gq_ctx;
   if (!c) {
     set_error("gq_ctx_create: out of host memory");
@@ -651,6 +652,61 @@ gq_status gq_response(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t h1_kind,
   if (mu1_host) {
     GQ_HIP(hipMemcpyAsync(mu1_host, e->mu1, K * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     if (gq_status st = check_status(ctx, e)) return st;
+  }
+  return GQ_OK;
+}
+
+gq_status gq_response_static(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t h1_kind,
+                             int32_t K, uint32_t precision, double* p_blocks_dev,
+                             double* mu1_dev) {
+  H1Spec spec;
+  if (gq_status st = response_check(ctx, e, h1, h1_kind, K, precision, p_blocks_dev,
+                                    "gq_response_static", &spec))
+    return st;
+  double* base = scratch_ptr(ctx->device);
+  if (!base) {
+    set_error("gq_response_static: no static scratch on device %d", ctx->device);
+    return GQ_EDEVICE;
+  }
+  const gq_graph* g = e->g;
+  const int64_t per_k = resp_doubles_per_k(g, h1_kind);
+  const int64_t cap = scratch_doubles();
+  if (per_k > cap) {
+    set_error("gq_response_static: one perturbation needs %lld doubles of scratch, the static "
+              "scratch holds %lld (sum n_i^2 = %lld)",
+              (long long)per_k, (long long)cap, (long long)g->info.sum_n2);
+    return GQ_ENOMEM;
+  }
+  GQ_HIP(hipSetDevice(ctx->device));
+  const int64_t sum_n = g->info.sum_n, sum_n2 = g->info.sum_n2, nnz = g->info.nnz;
+  const int64_t sum_c = std::max<int64_t>(g->offcd[g->n_sub], 1);
+  auto up = [](int64_t x) { return (x + 31) & ~int64_t(31); };
+  const int32_t kc = (int32_t)std::min<int64_t>(K, cap / per_k);
+  for (int32_t q0 = 0; q0 < K; q0 += kc) {
+    const int32_t nq = std::min(kc, K - q0);
+    // carve nq perturbations' buffers out of the scratch (the layout that
+    // resp_doubles_per_k counts, for nq at once)
+    double* at = base;
+    auto take = [&](int64_t count) {
+      double* p = at;
+      at += up(count);
+      return p;
+    };
+    RespBufs rb;
+    rb.hloc = take(nq * sum_n);
+    rb.Y = take(nq * sum_n2);
+    rb.G = h1_kind == GQ_H1_CSR ? take(nq * sum_n2) : nullptr;
+    rb.T = take(nq * sum_n * 32);
+    rb.pdiag = take(nq * sum_c);
+    rb.mu1 = take(nq);
+    H1Spec sub = spec;
+    if (h1_kind == GQ_H1_DIAG) sub.diag = spec.diag + (size_t)q0 * g->N;
+    else sub.csr = spec.csr + q0;
+    launch_response(ctx, g, e, rb, sub, nq, precision, p_blocks_dev + (size_t)q0 * nnz);
+    GQ_HIP(hipGetLastError());
+    if (mu1_dev)
+      GQ_HIP(hipMemcpyAsync(mu1_dev + q0, rb.mu1, nq * sizeof(double), hipMemcpyDeviceToDevice,
+                            ctx->stream));
   }
   return GQ_OK;
 }

@@ -266,6 +266,13 @@ struct H1Spec {
 };
 void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb,
                      const H1Spec& h1, int32_t K, uint32_t precision, double* p_blocks);
+// Doubles of response scratch one perturbation needs (RespBufs layout).
+int64_t resp_doubles_per_k(const gq_graph* g, uint32_t kind);
+// Device address of the library's static response scratch on the current
+// device (taken once per device with hipGetSymbolAddress), and its size.
+gq_status scratch_init(int device);
+double* scratch_ptr(int device);
+int64_t scratch_doubles();
 void launch_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks, int32_t K,
                      double* vals);
 void build_xy_tiles(gq_graph* g);

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdio>
+#include <mutex>
 
 #include "gq_internal.hpp"
 
@@ -1064,6 +1065,56 @@ void build_xy_tiles(gq_graph* g) {
   }
   for (int p = 0; p < 2; ++p)
     for (int bin = 0; bin < kXyBins; ++bin) g->xy_choice[p][bin] = 0;
+}
+
+// ----------------------------------------------------- static scratch
+// Response scratch of gq_response_static, for callers that cannot allocate
+// device memory: 2^25 doubles (256 MiB) per device, held from the library's
+// first context on that device until the process ends.  Host code never uses
+// this name as an address: scratch_init takes the device address once per
+// device with hipGetSymbolAddress, and everything else uses that pointer.
+constexpr int64_t kScratchDoubles = int64_t(1) << 25;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+gq_status scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("static scratch: device %d beyond %d", device, kMaxDevices);
+    return GQ_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return GQ_OK;
+  // the caller has made `device` current
+  void* ptr = nullptr;
+  const hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (rc != hipSuccess || !ptr) {
+    set_error("static scratch: hipGetSymbolAddress failed on device %d: %s", device,
+              hipGetErrorString(rc));
+    return GQ_EDEVICE;
+  }
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return GQ_OK;
+}
+
+double* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+int64_t scratch_doubles() { return kScratchDoubles; }
+
+int64_t resp_doubles_per_k(const gq_graph* g, uint32_t kind) {
+  // hloc, Y, G (general kind), T, pdiag, mu1, each rounded up to 32 doubles
+  auto up = [](int64_t x) { return (x + 31) & ~int64_t(31); };
+  const int64_t sum_c = g->offcd[g->n_sub];
+  return up(g->info.sum_n) + up(g->info.sum_n2) * (kind == GQ_H1_CSR ? 2 : 1) +
+         up(g->info.sum_n * 32) + up(std::max<int64_t>(sum_c, 1)) + up(1);
 }
 
 void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb,

@@ -81,6 +81,8 @@ _SIGS = {
     "gq_density": ([_VP, _VP, C.c_double, C.c_double, _VP, _VP], C.c_int32),
     "gq_response": ([_VP, _VP, _VP, C.c_uint32, C.c_int32, C.c_uint32, _VP, _VP, _VP],
                     C.c_int32),
+    "gq_response_static": ([_VP, _VP, _VP, C.c_uint32, C.c_int32, C.c_uint32, _VP, _VP],
+                           C.c_int32),
     "gq_assemble": ([_VP, _VP, _VP, C.c_int32, _VP], C.c_int32),
     "gq_eigs_export": ([_VP, _VP, _VP, _VP], C.c_int32),
     "gq_eigs_vectors": ([_VP, C.c_int32, C.POINTER(_VP), C.POINTER(C.c_int32)], C.c_int32),
@@ -341,6 +343,19 @@ class Eigs:
         _check(lib().gq_response(self.ctx.h, self.h, arg, kind, K, int(precision),
                                  _ptr(p_blocks), _ptr(mu1_dev), host if want_mu1 else None))
         return np.array(host[:]) if want_mu1 else None
+
+    def response_static(self, h1, p_blocks, precision=PREC_FP64, mu1_dev=None):
+        """gq_response_static: as response, with the per-call buffers in the
+        library's static device scratch (no allocation, no host wait)."""
+        if isinstance(h1, (list, tuple)):
+            K = len(h1)
+            arr = (_Csr * K)(*[m.cstruct() for m in h1])
+            arg, kind = C.cast(arr, _VP), H1_CSR
+        else:
+            K = int(h1.shape[0])
+            arg, kind = _ptr(h1), H1_DIAG
+        _check(lib().gq_response_static(self.ctx.h, self.h, arg, kind, K, int(precision),
+                                        _ptr(p_blocks), _ptr(mu1_dev)))
 
     def export(self):
         n = self.graph.info.sum_n
