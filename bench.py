@@ -1,17 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the graph-based density + canonical response path on one MI355X.
 
-A step is one pass of the whole path over the 1,000-water system (3,000 atoms,
-6,000 orbitals, 8-atom spatial cores, graph = paths of two of the thresholded
-previous density and Hamiltonian at tau = 0.07, kT = 0.01 Ha):
+Metric: response solves per second, mixed (split-FP32 congruences) and served,
+against the plain FP64 path, with p50/p99 latency of the served form.
+
+A step is one pass of the whole device path over one structure of the
+30,000-atom chain-in-water system (6,000-atom C/N/O/S chain in water at 0.1
+atoms / A^3, 72,000 orbitals, 8-atom spatial cores, graph = paths of two of
+the thresholded previous density and Hamiltonian at tau = 0.07, kT = 0.01 Ha):
 gather + FP64 eigensolve of every subgraph, shared mu, density core rows,
-mu-response rows, divided differences, the response to one diagonal H1 with
-its canonical mu1, and the collect of rho and rho1.  The graph estimate is
-built on the host from the previous-step density before the timed region and
-timed on its own (graph_build_ms).
+mu-response rows, divided differences, K = 6 perturbations sharing the
+eigenbasis (split-FP32 congruences with FP64 window refinement) with their
+canonical mu1, and the collect of rho and of the six rho1.  `value` is
+response solves per second over the timed steps (six per step, each carrying
+a sixth of the structure's ground state).  The graph estimate (host) is built
+before the timed region and timed on its own.  The same steps with FP64
+congruences, the response alone, the served form (config 5), the batched
+form, two more temperatures and the oracle on the host cores are reported in
+the same line.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus N (1 only)
---no-cpu-baseline.
+--no-cpu-baseline --no-forms.
 """
 import argparse
 import json
@@ -25,7 +34,9 @@ sys.path.insert(0, ROOT)
 METRIC = "response solves/s, mixed & served vs FP64 at ‖Δρ1‖≤1e-6; p50/p99 latency"
 KT = 0.01
 TAU = 0.07
+K_H1 = 6
 PEAK_FP64 = 78.6e12     # MI355X FP64 (vector = MFMA), FLOP/s
+PEAK_FP32 = 157.3e12    # MI355X FP32 MFMA, FLOP/s
 PEAK_HBM = 8.0e12       # B/s
 
 
@@ -33,14 +44,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# ------------------------------------------------------- algorithmic work
 def algorithmic_work(sizes, cores):
-    """Algorithmic flops of each kernel per step (sum over subgraphs)."""
+    """Algorithmic flops of each kernel per step and per perturbation (sum
+    over subgraphs; counts of the method, not of the kernels' own schedule)."""
     n = sizes.astype(float)
     c = cores.astype(float)
     return {
         "k_tridiag": (4.0 / 3.0 * n ** 3).sum(),
-        "k_formq": (4.0 / 3.0 * n ** 3).sum(),
-        "k_ql": (6.0 * n ** 3).sum(),
         "k_density_rows": (4.0 * c * n ** 2).sum(),
         "k_xy": (n ** 3 + n ** 2).sum(),
         "k_rows": (4.0 * c * n ** 2).sum(),
@@ -48,12 +59,27 @@ def algorithmic_work(sizes, cores):
     }
 
 
+def eigensolve_min_bytes(sizes):
+    """The eigensolve's minimum HBM bytes per subgraph: the matrix read and the
+    eigenvectors written, 16 n^2 bytes."""
+    n = sizes.astype(float)
+    return float((16.0 * n ** 2).sum())
+
+
+def congruence_min_bytes(sizes, cores):
+    """The congruence unit's minimum bytes per subgraph and perturbation: Q and
+    dF read, h1 and the core block: 16 n^2 + 8 n + 8 c n."""
+    n = sizes.astype(float)
+    c = cores.astype(float)
+    return float((16.0 * n ** 2 + 8.0 * n + 8.0 * c * n).sum())
+
+
 def tridiag_bytes(sizes):
-    """Algorithmic HBM bytes of k_tridiag per step (Sec. II.D eigensolve,
-    one-stage Householder reduction): for every column c the symmetric product
-    reads the trailing matrix (rows and columns > c) once, and every panel of
-    16 reflectors reads and writes the trailing matrix once in its rank-2x16
-    update; 8 bytes per FP64 element."""
+    """Bytes the one-stage Householder reduction itself moves per step: for
+    every column c the symmetric product reads the trailing matrix (rows and
+    columns > c) once, and every panel of 16 reflectors reads and writes the
+    trailing matrix once in its rank-2x16 update; 8 bytes per element.  This
+    is the kernel's own schedule, reported beside the minimum of 16 n^2."""
     total = 0.0
     for n in sizes.astype(int):
         m = n - 1
@@ -68,12 +94,12 @@ def tridiag_bytes(sizes):
     return total
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+def measured_traffic(kernel, profile="pmc_traffic_chain30000.txt"):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel factor), or None
-    when the kernel's source changed since the counters were taken."""
+    when the summary is missing or the kernel's source changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_water1000.txt")
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     rec = None
@@ -91,62 +117,148 @@ def measured_traffic(kernel):
     return k["bytes_per_launch"]
 
 
-def cpu_baseline(system, core, h1, budget_s=12.0):
-    """The oracle as it stands, single-threaded, on a size-stratified sample of
-    subgraphs of its own graph (its own bootstrap density); extrapolated to the
-    whole step by sum n^3."""
+def _pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q))
+
+
+# ------------------------------------------------------------- CPU oracle
+_OW = {}
+
+
+def _ow_init(h_arrays, orbs_list, cores, h1, mu, kT, cpu):
+    if cpu is not None:
+        os.sched_setaffinity(0, {cpu})
+    from oracle import oracle as O
+    _OW["O"] = O
+    _OW["H"] = O.Csr(*h_arrays)
+    _OW["orbs"] = orbs_list
+    _OW["cores"] = cores
+    _OW["h1"] = h1
+    _OW["mu"] = mu
+    _OW["kT"] = kT
+
+
+def _ow_subgraph(i):
+    """The oracle's whole per-subgraph work of one step: gather, eigensolve,
+    density rows, mu-response rows, divided differences and the response rows
+    of every perturbation (the oracle as written: a dense diag(h1))."""
+    import numpy as np
+    O = _OW["O"]
+    orbs = _OW["orbs"][i]
+    c = int(_OW["cores"][i])
+    mu, kT = _OW["mu"], _OW["kT"]
+    t0 = time.perf_counter()
+    e, z = O.eigh(O.gather(_OW["H"], orbs))
+    O.core_rows(z, e, c, mu, kT)
+    O.mu_response_rows(z, e, c, mu, kT)
+    dF = O.divided_differences(e, mu, kT)
+    for q in range(_OW["h1"].shape[0]):
+        O.lambda_response_rows(z, dF, np.diag(_OW["h1"][q, orbs]), c)
+    return time.perf_counter() - t0
+
+
+def _ow_chunk(idx):
+    return [(_ow_subgraph(i), i) for i in idx]
+
+
+def cpu_baseline(system, graph_export, h1, mu, budget_s=12.0):
+    """The oracle as it stands on a bounded, size-stratified sample of the
+    step's subgraphs (its own gather, eigensolve, rows and K response rows per
+    subgraph), timed (a) in one process pinned to CPU 0 and (b) by a pool of
+    one process per host core; each rate is extrapolated to the whole step by
+    sum n^3 and converted to response solves per second."""
+    import multiprocessing as mp
     import numpy as np
     from oracle import oracle as O
-    prev = O.bootstrap_prev(system, core, KT, pool=True)
-    g = O.graph_build(system, core, TAU, rho_prev=prev, flags=O.PATHS2)
-    sizes = g.sizes()
-    H = O.Csr(system.h_row_ptr, system.h_col, system.h_val)
-    # size-stratified order: quantiles first, then the rest, until the budget is spent
-    order = np.argsort(sizes)
-    first = [int(order[min(len(order) - 1, int(f * len(order)))])
-             for f in (0.5, 0.95, 0.05, 0.75, 0.25, 0.99, 0.01, 0.6, 0.4, 0.85, 0.15)]
-    rest = [int(x) for x in np.random.default_rng(0).permutation(g.n_sub)]
+    O.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
+    sop = graph_export["sub_orb_ptr"]
+    orbs = [graph_export["sub_orbs"][sop[i]:sop[i + 1]].copy() for i in range(len(sop) - 1)]
+    cores = graph_export["n_core_orbs"]
+    sizes = np.diff(sop).astype(float)
+    total_n3 = float((sizes ** 3).sum())
+    order = np.argsort(sizes, kind="stable")
+    # size-stratified order: spread quantiles first, then a seeded shuffle
+    fr = (0.5, 0.95, 0.05, 0.75, 0.25, 0.99, 0.01, 0.6, 0.4, 0.85, 0.15, 0.9, 0.1, 0.7, 0.3)
+    first = [int(order[min(len(order) - 1, int(f * len(order)))]) for f in fr]
+    rest = [int(x) for x in np.random.default_rng(0).permutation(len(sizes))]
     picks = list(dict.fromkeys(first + rest))
-    t_used, n3_used, done = 0.0, 0.0, 0
-    mu = -0.22
-    for s in picks:
-        t0 = time.perf_counter()
-        orbs = g.orbs(s)
-        c = int(g.n_core_orbs[s])
-        e, z = O.eigh(O.gather(H, orbs))
-        O.core_rows(z, e, c, mu, KT)
-        O.mu_response_rows(z, e, c, mu, KT)
-        dF = O.divided_differences(e, mu, KT)
-        O.lambda_response_rows(z, dF, np.diag(h1[0, orbs]), c)
-        t_used += time.perf_counter() - t0
-        n3_used += float(len(orbs)) ** 3
-        done += 1
-        if t_used > budget_s and done >= 3:
+    h_arrays = (system.h_row_ptr, system.h_col, system.h_val)
+    ctx = mp.get_context("spawn")
+    try:
+        cpu_model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                         if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        cpu_model = "unknown"
+    avail = sorted(os.sched_getaffinity(0))
+    nproc = os.cpu_count() or len(avail)
+    # (a) one process pinned to the first available CPU
+    with ctx.Pool(1, initializer=_ow_init,
+                  initargs=(h_arrays, orbs, cores, h1, mu, KT, avail[0])) as pool:
+        done, t_used, n3_used = [], 0.0, 0.0
+        for i in picks:
+            (t, _), = pool.apply(_ow_chunk, ([i],))
+            done.append(i)
+            t_used += t
+            n3_used += sizes[i] ** 3
+            if t_used > budget_s and len(done) >= 3:
+                break
+    t_step_1 = t_used / n3_used * total_n3
+    # (b) one process per available core (at most 16), each on its own share of
+    # a sample sized for about budget_s of wall time
+    threads = min(len(avail), 16)
+    per_n3 = t_used / n3_used
+    sample, est = [], 0.0
+    for i in picks:
+        sample.append(i)
+        est += per_n3 * sizes[i] ** 3
+        if est > budget_s * threads and len(sample) >= threads:
             break
-    total = t_used / n3_used * float((sizes.astype(float) ** 3).sum())
+    chunks = [sample[w::threads] for w in range(threads)]
+    with ctx.Pool(threads, initializer=_ow_init,
+                  initargs=(h_arrays, orbs, cores, h1, mu, KT, None)) as pool:
+        pool.map(_ow_chunk, [[picks[0]]] * threads, chunksize=1)  # workers up and warm
+        t0 = time.perf_counter()
+        pool.map(_ow_chunk, chunks, chunksize=1)
+        wall = time.perf_counter() - t0
+    n3_sample = float((sizes[sample] ** 3).sum())
+    t_step_all = wall / n3_sample * total_n3
+    K = h1.shape[0]
     return {
-        "value": 1.0 / total,
+        "value": K / t_step_all,
         "unit": "solves/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"{done} of {g.n_sub} subgraphs (size-stratified, n {int(min(sizes[p] for p in picks[:done]))}"
-                   f"..{int(max(sizes[p] for p in picks[:done]))}), single thread, {t_used:.1f} s of"
-                   f" gather + eigensolve + density rows + response rows; whole-step time"
-                   f" extrapolated by sum n^3 to {total:.1f} s"),
+        "sample": (f"{len(sample)} of {len(sizes)} subgraphs (size-stratified, n "
+                   f"{int(sizes[sample].min())}..{int(sizes[sample].max())}) of the benchmark "
+                   f"step, each: gather + eigensolve + density rows + mu rows + divided "
+                   f"differences + {K} response rows; {threads} processes, {wall:.1f} s wall; "
+                   f"whole step extrapolated by sum n^3 to {t_step_all:.0f} s"),
+        "extrapolated": True,
+        "nproc": nproc,
+        "cpu_model": cpu_model,
+        "single_core": {"value": K / t_step_1, "unit": "solves/s", "pinned_cpu": avail[0],
+                        "sample": f"{len(done)} subgraphs, {t_used:.1f} s",
+                        "step_s_extrapolated": t_step_1},
     }
 
 
-# ------------------------------------------------------------ the three forms
-def _time_ms(fn, sync, reps=3):
-    """Best of `reps` wall-clock runs of fn, bracketed by `sync`."""
-    best = 1e30
-    for _ in range(reps):
-        sync()
-        t0 = time.perf_counter()
+# ------------------------------------------------------------- timing helpers
+def _time_steps(fn, stream, n):
+    """Per-call durations (ms) of n calls of fn, from event pairs on `stream`."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n)]
+    for a, b in evs:
+        a.record(stream)
         fn()
-        sync()
-        best = min(best, time.perf_counter() - t0)
-    return best * 1e3
+        b.record(stream)
+    stream.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def _dist(ms):
+    return {"median_ms": _pct(ms, 50), "p10_ms": _pct(ms, 10), "p90_ms": _pct(ms, 90), "n": len(ms)}
 
 
 def _golden3():
@@ -163,93 +275,50 @@ def _digest(a):
     return hashlib.sha256(np.ascontiguousarray(a, np.int32).tobytes()).hexdigest()[:16]
 
 
-def form_batched_and_mixed(ctx, side):
-    """Config 3 (30,000-atom chain in water, K = 6 perturbations per
-    eigenbasis): the plain batched FP64 path against the autotuned,
-    size-binned, graph-captured one; then the split-FP32 congruences at
-    kT = 0.003, 0.01, 0.03 with their errors against the FP64 path (whole
-    system) and against the stored oracle values (sampled positions)."""
-    import numpy as np
-    import torch
-    from paper_2212_01997_amd import gq, inputs as I
-    from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
-    K = 6
-    log("config 3: generating the 30,000-atom system")
-    s = I.config_system(3)
-    core = I.spatial_cores(s, 8)
-    prev = bootstrap_prev(ctx, s, core, KT)
-    graph = gq.Graph.for_system(s, core, TAU, prev, gq.PATHS2)
-    info = graph.info
-    path = GraphPath(ctx, s, core, TAU, graph=graph, max_k=K)
-    h1 = torch.as_tensor(I.h1_diagonal(s, K, seed=3002), device="cuda")
-    torch.cuda.synchronize()
-    sync = side.synchronize
-    out = {"workload": "config 3: 30,000 atoms (6,000-atom C/N/O/S chain in water), 72,000 "
-                       "orbitals, 8-atom cores, paths of two at tau 0.07, K = 6 diagonal H1",
-           "n_sub": info.n_sub, "n_min": info.min_n, "n_max": info.max_n, "nnz": info.nnz}
-    # plain: default launch variant, eager launches
+# ---------------------------------------------------------------- forms
+def form_batched(path, graph, h1, side):
+    """Batched form at the step's workload: autotuned X-kernel launches per
+    size bin and the K responses replayed as one captured HIP graph, against
+    the plain launches."""
+    from paper_2212_01997_amd import gq
     for b in range(5):
         graph.set_launch(0, b, 0)
-        graph.set_launch(1, b, 0)
-    path.ground_state(KT, want_mu=False)
-    g_ms = _time_ms(lambda: path.ground_state(KT, want_mu=False), sync)
-    r_ms = _time_ms(lambda: path.respond(h1, want_mu1=False), sync)
-    out["plain"] = {"ground_state_ms": g_ms, "response_ms_K6": r_ms,
-                    "response_solves_per_s": K * 1e3 / r_ms,
-                    "step_ms": g_ms + r_ms, "step_solves_per_s": K * 1e3 / (g_ms + r_ms)}
-    # the congruence kernel at K = 6 (two perturbations per workgroup), timed
-    # with the library's hipEvent pairs on its own stream
-    ctx.set_profiling(True)
-    for _ in range(3):
-        path.respond(h1, want_mu1=False)
-    sync()
-    kt = ctx.kernel_times()
-    ctx.set_profiling(False)
-    if "k_xy" in kt:
-        n3 = np.diff(graph.export()["sub_orb_ptr"]).astype(float)
-        flops = K * float((n3 ** 3 + n3 ** 2).sum())
-        xy_ms = kt["k_xy"][1] / kt["k_xy"][0]
-        out["congruence_roofline_K6"] = {
-            "bound": "mfma", "kernel": "k_xy", "achieved": flops / (xy_ms * 1e-3) / 1e12,
-            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-            "frac": flops / (xy_ms * 1e-3) / PEAK_FP64,
-            "algorithmic_flops_per_launch": flops, "launch_ms": xy_ms}
-    # batched: autotuned bins + one captured graph per step
+    plain = _time_steps(lambda: path.respond(h1, want_mu1=False), side, 5)
     report = path.eigs.autotune(gq.PREC_FP64)
-    ctx.capture_begin()
+    path.ctx.capture_begin()
     path.respond(h1, want_mu1=False)
-    x_resp = ctx.capture_end()
-    ctx.capture_begin()
-    path.ground_state(KT, want_mu=False)
-    path.respond(h1, want_mu1=False)
-    x_step = ctx.capture_end()
-    rb_ms = _time_ms(x_resp.launch, sync)
-    sb_ms = _time_ms(x_step.launch, sync)
-    out["batched"] = {"response_ms_K6": rb_ms, "response_solves_per_s": K * 1e3 / rb_ms,
-                      "step_ms": sb_ms, "step_solves_per_s": K * 1e3 / sb_ms,
-                      "speedup_response_vs_plain": r_ms / rb_ms,
-                      "speedup_step_vs_plain": (g_ms + r_ms) / sb_ms,
-                      "autotune": [ln for ln in report.splitlines() if "->" in ln]}
-    del x_resp, x_step
-    # mixed precision at three temperatures
-    gold = _golden3()
-    ex = graph.export()
-    gold_ok = gold is not None and all(
-        gold["graph"][k] == _digest(ex[k]) for k in ("sub_orb_ptr", "sub_orbs", "rho_row_ptr", "rho_col"))
-    path.eigs.autotune(gq.PREC_SPLIT32)
-    mixed = []
-    for kT in (0.003, 0.01, 0.03):
+    x = path.ctx.capture_end()
+    x.launch()
+    side.synchronize()
+    batched = _time_steps(x.launch, side, 5)
+    del x
+    for b in range(5):
+        graph.set_launch(0, b, 0)
+    return {"plain_response_ms_K6": _pct(plain, 50), "batched_response_ms_K6": _pct(batched, 50),
+            "speedup": _pct(plain, 50) / _pct(batched, 50),
+            "autotune": [ln for ln in report.splitlines() if "->" in ln]}
+
+
+def form_mixed_temperatures(path, h1, side, gold, gold_ok):
+    """Split-FP32 against FP64 at kT = 0.003 and 0.03 (0.01 is the headline):
+    response times and the errors of the split path against the FP64 path
+    (whole system) and against stored oracle values (sampled positions)."""
+    import numpy as np
+    import torch
+    from paper_2212_01997_amd import gq
+    K = h1.shape[0]
+    rows = []
+    for kT in (0.003, 0.03):
         mu = path.ground_state(kT)
-        path.sync()
         mu1_64 = path.respond(h1)
         path.sync()
-        rho = path.rho.clone()
         rho1_64 = path.rho1_view(K).clone()
-        t64 = _time_ms(lambda: path.respond(h1, want_mu1=False), sync)
+        t64 = _pct(_time_steps(lambda: path.respond(h1, want_mu1=False), side, 5), 50)
         mu1_32 = path.respond(h1, precision=gq.PREC_SPLIT32)
         path.sync()
         rho1_32 = path.rho1_view(K).clone()
-        t32 = _time_ms(lambda: path.respond(h1, precision=gq.PREC_SPLIT32, want_mu1=False), sync)
+        t32 = _pct(_time_steps(lambda: path.respond(h1, precision=gq.PREC_SPLIT32,
+                                                    want_mu1=False), side, 5), 50)
         row = {"kT": kT, "fp64_response_ms_K6": t64, "split32_response_ms_K6": t32,
                "speedup": t64 / t32,
                "split32_vs_fp64_path": {"rho1": float((rho1_32 - rho1_64).abs().max()),
@@ -259,27 +328,55 @@ def form_batched_and_mixed(ctx, side):
             idx = torch.as_tensor(np.array(gold["idx"]), device="cuda")
             r_or = np.array(g["rho1"])
             row["vs_oracle_sampled"] = {
-                "positions": len(gold["idx"]),
                 "mu": abs(mu - g["mu"]),
-                "rho": float(np.abs(rho[idx].cpu().numpy() - np.array(g["rho"])).max()),
-                "fp64": {"rho1": float(np.abs(rho1_64[:, idx].cpu().numpy() - r_or).max()),
-                         "mu1": float(np.abs(mu1_64 - np.array(g["mu1"])).max())},
-                "split32": {"rho1": float(np.abs(rho1_32[:, idx].cpu().numpy() - r_or).max()),
-                            "mu1": float(np.abs(mu1_32 - np.array(g["mu1"])).max())}}
-        mixed.append(row)
+                "fp64_rho1": float(np.abs(rho1_64[:, idx].cpu().numpy() - r_or).max()),
+                "split32_rho1": float(np.abs(rho1_32[:, idx].cpu().numpy() - r_or).max()),
+                "split32_mu1": float(np.abs(mu1_32 - np.array(g["mu1"])).max())}
+        rows.append(row)
         log(f"mixed kT={kT}: fp64 {t64:.2f} ms, split32 {t32:.2f} ms, "
             f"|drho1| {row['split32_vs_fp64_path']['rho1']:.2e}")
-    out["mixed"] = mixed
-    out["oracle_values"] = ("stored oracle values at 4,096 sampled positions (tests/golden)"
-                            if gold_ok else "not compared (stored oracle values missing or for another graph)")
-    return out
+    path.ground_state(KT, want_mu=False)
+    return rows
+
+
+def _serve_trace(srv, tr, systems, cores, prevs, h1s, scale, precision):
+    import threading
+    import numpy as np
+    from paper_2212_01997_amd import gq
+    n = len(tr.arrival)
+    ids = [None] * n
+    start = srv.clock()
+    arrival = tr.arrival / scale
+
+    def feeder():
+        for j in range(n):
+            now = srv.clock() - start
+            if now < arrival[j]:
+                time.sleep(arrival[j] - now)
+            i = int(tr.system[j])
+            ids[j] = srv.submit(systems[i], cores[i], TAU, prevs[i], gq.PATHS2, KT, h1s[j],
+                                precision=precision)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    infos = [srv.wait(rid) for rid in ids]
+    for rid in ids:
+        srv.release(rid)
+    lat = np.array([inf["t_done"] - (start + arrival[j]) for j, inf in enumerate(infos)])
+    span = max(inf["t_done"] for inf in infos) - start
+    solves = int(tr.K.sum())
+    return {"rate_req_per_s": 20.0 * scale, "p50_ms": _pct(lat, 50) * 1e3,
+            "p99_ms": _pct(lat, 99) * 1e3, "solves_per_s": solves / span, "makespan_s": span}
 
 
 def form_served(ctx, side, n_slots=4):
     """Config 5: a Poisson trace (20 requests/s, 200 requests, 500..20,000
-    atoms, K = 1..8) served by the runtime, against the same trace run one
-    request after another on the plain path (FIFO, same arrival times)."""
-    import threading
+    atoms, K = 1..8) served by the runtime (split-FP32 and FP64 congruences),
+    against the same trace run one request after another on the plain FP64
+    path on a context with an arena (no allocation per request); then the
+    served trace at 2x and 4x the rate, up to the first rate whose p99 latency
+    exceeds one second."""
     import numpy as np
     import torch
     from paper_2212_01997_amd import gq, inputs as I
@@ -288,15 +385,15 @@ def form_served(ctx, side, n_slots=4):
     systems = []
     for k, spec in enumerate(tr.pool):
         systems.append(I.pool_system(*spec))
-        log(f"config 5: pool system {k + 1}/{len(tr.pool)}: {spec[0]}, {systems[-1].n_atoms} atoms")
+    log(f"config 5: {len(systems)} pool systems generated")
     cores = [I.spatial_cores(s, 8) for s in systems]
     prevs = [bootstrap_prev(ctx, s, c, KT) for s, c in zip(systems, cores)]
     h1s = [I.h1_diagonal(systems[i], int(k), seed=int(sd))
            for i, k, sd in zip(tr.system, tr.K, tr.h1_seed)]
     n = len(tr.arrival)
     solves = int(tr.K.sum())
-    # sequential plain path
     log("config 5: sequential plain path")
+    seq_ctx = gq.Context(0, stream=side, arena_bytes=96 << 30)
     lat_seq = np.zeros(n)
     t0 = time.perf_counter()
     for j in range(n):
@@ -304,7 +401,7 @@ def form_served(ctx, side, n_slots=4):
         if now < tr.arrival[j]:
             time.sleep(tr.arrival[j] - now)
         i = int(tr.system[j])
-        p = GraphPath(ctx, systems[i], cores[i], TAU, prevs[i], gq.PATHS2, max_k=int(tr.K[j]))
+        p = GraphPath(seq_ctx, systems[i], cores[i], TAU, prevs[i], gq.PATHS2, max_k=int(tr.K[j]))
         p.ground_state(KT, want_mu=False)
         p.respond(torch.as_tensor(h1s[j], device="cuda"), want_mu1=False)
         side.synchronize()
@@ -312,45 +409,59 @@ def form_served(ctx, side, n_slots=4):
         del rho1
         lat_seq[j] = time.perf_counter() - t0 - tr.arrival[j]
         del p
-        if (j + 1) % 50 == 0:
-            log(f"config 5: sequential {j + 1}/{n}")
     span_seq = time.perf_counter() - t0
+    del seq_ctx
     torch.cuda.empty_cache()
-    # served
     log("config 5: served")
     srv = gq.Server(0, n_slots=n_slots, arena_bytes=96 << 30)
-    ids = [None] * n
-    start = srv.clock()
-
-    def feeder():
-        for j in range(n):
-            now = srv.clock() - start
-            if now < tr.arrival[j]:
-                time.sleep(tr.arrival[j] - now)
-            i = int(tr.system[j])
-            ids[j] = srv.submit(systems[i], cores[i], TAU, prevs[i], gq.PATHS2, KT, h1s[j])
-
-    th = threading.Thread(target=feeder)
-    th.start()
-    th.join()
-    log("config 5: all requests submitted")
-    infos = [srv.wait(rid) for rid in ids]
-    log("config 5: all requests served")
-    lat_srv = np.array([inf["t_done"] - (start + tr.arrival[j]) for j, inf in enumerate(infos)])
-    span_srv = max(inf["t_done"] for inf in infos) - start
+    served = {"split32": _serve_trace(srv, tr, systems, cores, prevs, h1s, 1.0, gq.PREC_SPLIT32),
+              "fp64": _serve_trace(srv, tr, systems, cores, prevs, h1s, 1.0, gq.PREC_FP64)}
+    capacity = []
+    for scale in (2.0, 4.0):
+        r = _serve_trace(srv, tr, systems, cores, prevs, h1s, scale, gq.PREC_SPLIT32)
+        capacity.append(r)
+        log(f"config 5: {r['rate_req_per_s']:.0f} req/s -> p99 {r['p99_ms']:.0f} ms, "
+            f"{r['solves_per_s']:.0f} solves/s")
+        if r["p99_ms"] > 1000.0:
+            break
     srv.close()
+    sustained = max([served["split32"]] + capacity,
+                    key=lambda r: r["rate_req_per_s"] if r["p99_ms"] <= 1000.0 else -1)
     return {"workload": f"config 5: {n} requests, Poisson 20/s, {len(tr.pool)} seeded pool systems "
                         f"of 500..20,000 atoms (log-uniform; water or chain-in-water), K = 1..8 "
                         f"({solves} solves), kT 0.01, paths of two at tau 0.07",
-            "served": {"slots": n_slots, "p50_ms": float(np.percentile(lat_srv, 50) * 1e3),
-                       "p99_ms": float(np.percentile(lat_srv, 99) * 1e3),
-                       "solves_per_s": solves / span_srv, "makespan_s": span_srv},
-            "sequential_plain": {"p50_ms": float(np.percentile(lat_seq, 50) * 1e3),
-                                 "p99_ms": float(np.percentile(lat_seq, 99) * 1e3),
-                                 "solves_per_s": solves / span_seq, "makespan_s": span_seq}}
+            "slots": n_slots, "served": served,
+            "sequential_plain_fp64": {"p50_ms": _pct(lat_seq, 50) * 1e3,
+                                      "p99_ms": _pct(lat_seq, 99) * 1e3,
+                                      "solves_per_s": solves / span_seq, "makespan_s": span_seq},
+            "capacity_split32": capacity,
+            "highest_rate_with_p99_under_1s": sustained["rate_req_per_s"]}
 
 
+def config2_step(ctx, side, steps):
+    """The 1,000-water FP64 step (ground state + one perturbation)."""
+    import torch
+    from paper_2212_01997_amd import gq, inputs as I
+    from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
+    s = I.config_system(2)
+    core = I.spatial_cores(s, 8)
+    prev = bootstrap_prev(ctx, s, core, KT)
+    graph = gq.Graph.for_system(s, core, TAU, prev, gq.PATHS2)
+    p = GraphPath(ctx, s, core, TAU, graph=graph, max_k=1)
+    h1 = torch.as_tensor(I.h1_diagonal(s, 1, seed=2002), device="cuda")
 
+    def step():
+        p.ground_state(KT, want_mu=False)
+        p.respond(h1, want_mu1=False)
+
+    for _ in range(2):
+        step()
+    ms = _time_steps(step, side, steps)
+    return {"workload": "1,000 waters (3,000 atoms, 6,000 orbitals), 8-atom cores, K = 1, FP64",
+            **_dist(ms), "solves_per_s": 1000.0 / _pct(ms, 50)}
+
+
+# ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,7 +469,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched (config 3), mixed (config 4) and served (config 5) forms")
+                    help="skip the served, batched and temperature forms and the 1,000-water step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 256 MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -372,11 +483,11 @@ def main():
     from paper_2212_01997_amd import gq, inputs as I
     from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
 
-    log("building the 1,000-water system")
-    system = I.config_system(2)
+    log("generating the 30,000-atom chain-in-water system")
+    system = I.config_system(3)
     core = I.spatial_cores(system, 8)
-    h1_host = I.h1_diagonal(system, 1, seed=2002)
-    side = torch.cuda.Stream()  # a stream of its own, so that whole steps can be captured
+    h1_host = I.h1_diagonal(system, K_H1, seed=3002)
+    side = torch.cuda.Stream()  # a stream of its own, so that steps can be captured
     ctx = gq.Context(0, stream=side)
     log("previous-step density on the Hamiltonian graph")
     prev = bootstrap_prev(ctx, system, core, KT)
@@ -390,25 +501,71 @@ def main():
     sizes = np.diff(ex["sub_orb_ptr"])
     cores_n = ex["n_core_orbs"]
     log(f"graph: {info.n_sub} subgraphs, n {info.min_n}..{info.max_n}, nnz {info.nnz}")
-    path = GraphPath(ctx, system, core, TAU, graph=graph, max_k=1)
+    path = GraphPath(ctx, system, core, TAU, graph=graph, max_k=K_H1)
     h1 = torch.as_tensor(h1_host, device="cuda")
+    torch.cuda.synchronize()
 
-    def step():
+    def step(precision=gq.PREC_SPLIT32):
         path.ground_state(KT, want_mu=False)
-        path.respond(h1, want_mu1=False)
+        path.respond(h1, precision=precision, want_mu1=False)
 
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
+    # ------------------------------------------------ the timed steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for a, b in ev:
+        a.record(side)
         step()
+        b.record(side)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt * 1e3 / args.steps
+    step_ms = [a.elapsed_time(b) for a, b in ev]
     log(f"timed {args.steps} steps: {ms:.3f} ms/step")
+
+    # ----------------------------------- FP64 congruences, same steps
+    step(gq.PREC_FP64)
+    torch.cuda.synchronize()
+    fp64_ms = _time_steps(lambda: step(gq.PREC_FP64), side, args.steps)
+    log(f"fp64 steps: median {_pct(fp64_ms, 50):.3f} ms")
+    # ----------------------------------- phases: ground state, responses alone
+    ground_ms = _time_steps(lambda: path.ground_state(KT, want_mu=False), side, 5)
+    resp32_ms = _time_steps(lambda: path.respond(h1, precision=gq.PREC_SPLIT32, want_mu1=False),
+                            side, 10)
+    resp64_ms = _time_steps(lambda: path.respond(h1, precision=gq.PREC_FP64, want_mu1=False),
+                            side, 10)
+    # ----------------------------------- errors of the mixed path
+    mu = path.ground_state(KT)
+    mu1_64 = path.respond(h1)
+    path.sync()
+    rho = path.rho.clone()
+    rho1_64 = path.rho1_view(K_H1).clone()
+    mu1_32 = path.respond(h1, precision=gq.PREC_SPLIT32)
+    path.sync()
+    rho1_32 = path.rho1_view(K_H1).clone()
+    errors = {"split32_vs_fp64_path": {"rho1": float((rho1_32 - rho1_64).abs().max()),
+                                       "mu1": float(np.abs(mu1_32 - mu1_64).max()),
+                                       "positions": int(K_H1 * info.nnz)}}
+    gold = _golden3()
+    gold_ok = gold is not None and all(
+        gold["graph"][k] == _digest(ex[k]) for k in ("sub_orb_ptr", "sub_orbs", "rho_row_ptr", "rho_col"))
+    if gold_ok:
+        g = gold["kT"][repr(KT)]
+        idx = torch.as_tensor(np.array(gold["idx"]), device="cuda")
+        r_or = np.array(g["rho1"])
+        errors["vs_oracle_sampled"] = {
+            "positions": len(gold["idx"]), "mu": abs(mu - g["mu"]),
+            "rho": float(np.abs(rho[idx].cpu().numpy() - np.array(g["rho"])).max()),
+            "fp64_rho1": float(np.abs(rho1_64[:, idx].cpu().numpy() - r_or).max()),
+            "fp64_mu1": float(np.abs(mu1_64 - np.array(g["mu1"])).max()),
+            "split32_rho1": float(np.abs(rho1_32[:, idx].cpu().numpy() - r_or).max()),
+            "split32_mu1": float(np.abs(mu1_32 - np.array(g["mu1"])).max())}
+    del rho1_64, rho1_32, rho
 
     if args.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -418,9 +575,9 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 268435456 bytes read, 268435456 bytes written")
 
-    # per-kernel durations, measured with hipEvents on the library stream
+    # ----------------------------------- per-kernel durations and rooflines
     ctx.set_profiling(True)
-    nprof = max(2, min(5, args.steps))
+    nprof = 3
     for _ in range(nprof):
         step()
     kt = ctx.kernel_times()
@@ -429,47 +586,62 @@ def main():
     per_launch = {k: v[1] / v[0] for k, v in kt.items()}
     work = algorithmic_work(sizes, cores_n)
     dominant = max(per_step, key=per_step.get)
-    # work per step over the kernel's summed launch durations per step, which
-    # is work per launch over the average launch duration when the launches
-    # share the work evenly (the eigensolve launches k_tridiag once per size
-    # class, on two streams, so their durations overlap and this understates)
-    launches_per_step = kt[dominant][0] / nprof
-    flops = work.get(dominant, 0.0) / launches_per_step
-    launch_s = per_launch[dominant] * 1e-3
-    achieved = flops / launch_s if flops else 0.0
+    launches = kt[dominant][0] / nprof
+    launch_ms = per_launch[dominant]
     if dominant == "k_tridiag":
-        # BLAS-2 bound: the symmetric product streams the trailing matrix once
-        # per column, so the roofline is HBM with the algorithm's own bytes
-        nbytes = tridiag_bytes(sizes) / launches_per_step
-        roofline = {"bound": "hbm", "kernel": dominant, "achieved": nbytes / launch_s / 1e9,
-                    "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": nbytes / launch_s / PEAK_HBM,
-                    "traffic": measured_traffic(dominant),
-                    "algorithmic_bytes_per_launch": nbytes,
-                    "algorithmic_flops_per_launch": flops, "achieved_tflops": achieved / 1e12,
-                    "launch_ms": per_launch[dominant], "launches_per_step": launches_per_step}
-    else:
-        bound = "alu" if dominant in ("k_dc_prep", "k_dc_leaves") else "mfma"
-        roofline = {"bound": bound, "kernel": dominant, "achieved": achieved / 1e12,
+        # the eigensolve's reduction half: 4/3 n^3 of the 9 n^3, on at least
+        # the 16 n^2 bytes of the whole eigensolve; its intensity (n/12 flop/B)
+        # is above the FP64 ridge, so its bound is the FP64 peak
+        flops = work["k_tridiag"] / launches
+        nbytes = eigensolve_min_bytes(sizes) / launches
+        achieved = flops / (launch_ms * 1e-3)
+        roofline = {"bound": "mfma", "kernel": dominant, "achieved": achieved / 1e12,
                     "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
                     "traffic": measured_traffic(dominant),
-                    "algorithmic_flops_per_launch": flops, "launch_ms": per_launch[dominant],
-                    "launches_per_step": launches_per_step}
-    xy_flops = work["k_xy"]
-    xy_ms = per_launch.get("k_xy", 0.0)
-    roofline_congruence = None
-    if xy_ms:
-        a = xy_flops / (xy_ms * 1e-3)
-        roofline_congruence = {"bound": "mfma", "kernel": "k_xy", "achieved": a / 1e12,
-                               "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": a / PEAK_FP64,
-                               "traffic": measured_traffic("k_xy"),
-                               "algorithmic_flops_per_launch": xy_flops, "launch_ms": xy_ms}
+                    "algorithmic_flops_per_launch": flops,
+                    "algorithmic_bytes_per_launch": nbytes,
+                    "bytes_frac": nbytes / (launch_ms * 1e-3) / PEAK_HBM,
+                    "schedule_bytes_per_launch": tridiag_bytes(sizes) / launches,
+                    "launch_ms": launch_ms, "launches_per_step": launches}
+    else:
+        flops = work.get(dominant, 0.0) * (K_H1 if dominant in ("k_xy", "k_xy32", "k_rows") else 1)
+        flops = flops / launches
+        peak = PEAK_FP32 if dominant == "k_xy32" else PEAK_FP64
+        achieved = flops / (launch_ms * 1e-3)
+        roofline = {"bound": "mfma", "kernel": dominant, "achieved": achieved / 1e12,
+                    "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                    "traffic": measured_traffic(dominant),
+                    "algorithmic_flops_per_launch": flops, "launch_ms": launch_ms,
+                    "launches_per_step": launches}
+    # the congruence kernels: FP64 X tiles (K = 6, three perturbations per
+    # workgroup) and the whole a7 unit n^3 + n^2 + 4 c n^2 per perturbation
+    ctx.set_profiling(True)
+    for _ in range(nprof):
+        path.respond(h1, precision=gq.PREC_FP64, want_mu1=False)
+    kt64 = ctx.kernel_times()
+    ctx.set_profiling(False)
+    xy_ms = kt64["k_xy"][1] / kt64["k_xy"][0]
+    rows_ms = kt64["k_rows"][1] / nprof
+    xy_flops = K_H1 * work["k_xy"]
+    unit_flops = K_H1 * (work["k_xy"] + work["k_rows"])
+    roofline_congruence = {
+        "bound": "mfma", "kernel": "k_xy (FP64, K = 6)", "achieved": xy_flops / (xy_ms * 1e-3) / 1e12,
+        "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": xy_flops / (xy_ms * 1e-3) / PEAK_FP64,
+        "traffic": measured_traffic("k_xy"), "algorithmic_flops_per_launch": xy_flops,
+        "launch_ms": xy_ms,
+        "a7_unit": {"flops": unit_flops, "ms": xy_ms + rows_ms,
+                    "achieved": unit_flops / ((xy_ms + rows_ms) * 1e-3) / 1e12,
+                    "frac": unit_flops / ((xy_ms + rows_ms) * 1e-3) / PEAK_FP64,
+                    "min_bytes": K_H1 * congruence_min_bytes(sizes, cores_n)}}
+    if "k_xy32" in per_launch:
+        x32 = per_launch["k_xy32"]
+        roofline_congruence["split32_xy"] = {
+            "achieved": xy_flops / (x32 * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s", "frac": xy_flops / (x32 * 1e-3) / PEAK_FP32, "launch_ms": x32}
     phases = {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda x: -x[1])}
-    eig_ms = sum(v for k, v in per_step.items() if k in ("k_gather", "k_tridiag") or k.startswith(("k_dc", "k_back")))
-    resp_ms = sum(per_step.get(k, 0) for k in ("k_xy", "k_rows", "k_mu1_combine"))
-    dens_ms = sum(per_step.get(k, 0) for k in ("k_mu", "k_density_rows", "k_divided_differences"))
     line = {
         "metric": METRIC,
-        "value": 1000.0 / ms,
+        "value": K_H1 * 1000.0 / ms,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -478,38 +650,49 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64, congruences split-f32",
         "data": "synthetic",
         "config": {
-            "workload": "1,000 waters (3,000 atoms, 6,000 orbitals, 31 A box, seed 2001); "
-                        "8-atom Morton cores; graph = paths of two of thr(rho_prev) u thr(H), "
-                        "tau 0.07; kT 0.01 Ha; one diagonal H1 per solve",
+            "workload": "30,000-atom chain in water (6,000-atom C/N/O/S chain, 72,000 orbitals, "
+                        "67 A box, seed 3001); 8-atom Morton cores; graph = paths of two of "
+                        "thr(rho_prev) u thr(H), tau 0.07; kT 0.01 Ha; K = 6 diagonal H1 per "
+                        "structure sharing one eigenbasis; split-FP32 congruences",
             "n_sub": info.n_sub, "n_min": info.min_n, "n_max": info.max_n,
-            "n_mean": float(sizes.mean()), "nnz": info.nnz, "K": 1,
-            "precision": "fp64",
+            "n_mean": float(sizes.mean()), "nnz": info.nnz, "K": K_H1,
+            "precision": "split32",
         },
-        "phase_ms": {"eigensolve": eig_ms, "density": dens_ms, "response": resp_ms,
-                     "assemble": per_step.get("k_assemble", 0.0),
-                     "graph_build_host": float(np.median(gb)),
-                     "note": "device phases are summed kernel durations; the eigensolve's two "
-                             "streams overlap, so its sum exceeds its share of ms_per_step"},
+        "step_ms": _dist(step_ms),
+        "fp64": {"step_ms": _dist(fp64_ms), "solves_per_s": K_H1 * 1000.0 / _pct(fp64_ms, 50),
+                 "mixed_speedup": _pct(fp64_ms, 50) / _pct(step_ms, 50)},
+        "response_only": {
+            "split32": {**_dist(resp32_ms), "solves_per_s": K_H1 * 1000.0 / _pct(resp32_ms, 50)},
+            "fp64": {**_dist(resp64_ms), "solves_per_s": K_H1 * 1000.0 / _pct(resp64_ms, 50)},
+            "note": "K = 6 responses on the resident eigenbasis, mu and dF (a7 + a8 + a9)"},
+        "ground_state_ms": _dist(ground_ms),
+        "graph_build_host_ms": float(np.median(gb)),
+        "md_step_ms": float(np.median(gb)) + _pct(step_ms, 50),
+        "errors": errors,
         "kernel_ms_per_step": phases,
-        "elements_per_s": info.nnz * 1000.0 / ms,
-        "response_only_solves_per_s": 1000.0 / resp_ms if resp_ms else None,
+        "elements_per_s": K_H1 * info.nnz * 1000.0 / ms,
         "roofline": roofline,
         "roofline_congruence": roofline_congruence,
     }
     if not args.no_forms:
         forms = {}
-        forms["batched_and_mixed"] = form_batched_and_mixed(ctx, side)
+        log("batched form")
+        forms["batched"] = form_batched(path, graph, h1, side)
+        log("mixed form at kT 0.003 and 0.03")
+        forms["mixed_temperatures"] = form_mixed_temperatures(path, h1, side, gold, gold_ok)
+        del path
+        torch.cuda.empty_cache()
+        log("1,000-water FP64 step")
+        forms["config2_fp64_step"] = config2_step(ctx, side, args.steps)
         torch.cuda.empty_cache()
         forms["served"] = form_served(ctx, side)
         line["forms"] = forms
     if not args.no_cpu_baseline:
-        log("oracle CPU baseline on a sample of subgraphs")
-        from oracle import oracle as O
-        O.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
-        line["cpu_baseline"] = cpu_baseline(system, core, h1_host)
+        log("oracle CPU baseline")
+        line["cpu_baseline"] = cpu_baseline(system, ex, h1_host, mu)
     print(json.dumps(line), flush=True)
 
 

@@ -349,6 +349,15 @@ gq_status gq_ctx_kernel_times(gq_ctx* ctx, const char** names, int64_t* launches
                               double* total_ms, int32_t cap, int32_t* count);
 
 /* ---------------------------------------------------------- diagnostics
+ * Most QL iterations per eigenvalue in the divide-and-conquer leaves of the
+ * eigensolves launched later on ctx (default 60; >= 0, else GQ_EINVAL).  A
+ * leaf that needs more marks its subgraph as not converged, every kernel
+ * still runs to its end, and the next call that synchronises (gq_density with
+ * mu_inout, gq_response with mu1_host, gq_eigs_export) returns GQ_ENOCONV.
+ * A small cap exercises that path from the host. */
+gq_status gq_ctx_set_iteration_cap(gq_ctx* ctx, int32_t leaf_iterations);
+
+/* Diagnostics (continued).
  * Copies eigenvalues eps[sum_n] (subgraph by subgraph, ascending) and core
  * weights w[sum_n] to host arrays (either may be NULL); waits for the stream.
  * Returns GQ_ENOCONV if any eigensolve failed to converge. */

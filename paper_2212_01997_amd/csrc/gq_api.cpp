@@ -915,6 +915,15 @@ void gq_exec_destroy(gq_exec* x) {
   delete x;
 }
 
+gq_status gq_ctx_set_iteration_cap(gq_ctx* ctx, int32_t leaf_iterations) {
+  if (!ctx || leaf_iterations < 0) {
+    set_error("gq_ctx_set_iteration_cap: bad argument");
+    return GQ_EINVAL;
+  }
+  ctx->leaf_iter_cap = leaf_iterations;
+  return GQ_OK;
+}
+
 gq_status gq_ctx_set_profiling(gq_ctx* ctx, int32_t enable) {
   if (!ctx) {
     set_error("gq_ctx_set_profiling: NULL context");

@@ -119,6 +119,7 @@ struct gq_ctx {
   hipEvent_t ev_fork_dd = nullptr, ev_join_dd = nullptr;
   bool profiling = false;
   bool capturing = false;
+  int32_t leaf_iter_cap = 60;  // QL iterations per eigenvalue in the leaves
   // optional device arena (gq_ctx_create with arena_bytes > 0): workspaces and
   // graph maps created on this context take pieces of it
   char* arena_mem = nullptr;

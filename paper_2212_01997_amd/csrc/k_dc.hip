@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64) void k_dc_leaves(
     const int32_t* __restrict__ leaves, int n_leaves, const int32_t* __restrict__ sub_orb_ptr,
     const int64_t* __restrict__ off2, const double* __restrict__ D, const double* __restrict__ E,
     double* __restrict__ qbuf, double* __restrict__ sbuf, double* __restrict__ lam,
-    int32_t* __restrict__ status) {
+    int32_t* __restrict__ status, int iter_cap) {
   // four leaves per wave: lanes 16 gi .. 16 gi + 15 take leaf 4 blockIdx.x + gi
   // with arrays of their own (the QL loop below has no barrier, so the groups
   // may diverge)
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(64) void k_dc_leaves(
         ++mm;
       }
       if (mm == l) break;
-      if (++iter > 60) {
+      if (++iter > iter_cap) {
         failed = 1;
         break;
       }
@@ -1043,7 +1043,8 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t 
   const int l0 = g->dc_leaf_off[cls], nleaf = g->dc_leaf_off[cls + 1] - l0;
   prof_begin_on(ctx, "k_dc_leaves", st);
   hipLaunchKernelGGL(k_dc_leaves, dim3((nleaf + 3) / 4), dim3(64), 0, st, dv.dc_leaves + 4 * l0,
-                     nleaf, dv.sub_orb_ptr, dv.off2, e->dd, e->ee, e->Q, e->Y, e->eps, e->status);
+                     nleaf, dv.sub_orb_ptr, dv.off2, e->dd, e->ee, e->Q, e->Y, e->eps, e->status,
+                     ctx->leaf_iter_cap);
   prof_end(ctx);
   const auto& mo = g->dc_level_merge_off[cls];
   const auto& to = g->dc_level_tile_off[cls];

@@ -604,12 +604,11 @@ __global__ __launch_bounds__(kThreads) void k_split32(const double* __restrict__
     q32[i] = (float)q[i];
 }
 
-// The FP64 refinement window: the states with |eps - mu| <= kWinKT kT, at most
-// kWinMax of them (the ones nearest mu).  The cap is wide enough that a dense
-// or degenerate level next to mu is not cut in two: pairs inside such a level
-// carry dF = f'(eps), up to beta/4, and must not be left in FP32.
+// The FP64 refinement window: the states with |eps - mu| <= kWinKT kT, all of
+// them.  Pairs inside a dense or degenerate level next to mu carry
+// dF = f'(eps), up to beta/4, and none of them is left in FP32.
 constexpr double kWinKT = 8.0;
-constexpr int kWinMax = 128;
+constexpr int kWinGroups = 4;  // workgroups per (subgraph, perturbation)
 
 // first index i in [0, n) with v[i] >= x (n if none)
 __device__ __forceinline__ int lower_index(const double* v, int n, double x) {
@@ -624,9 +623,12 @@ __device__ __forceinline__ int lower_index(const double* v, int n, double x) {
 
 // FP64 refinement of the thermal window: the dF weights are largest, up to
 // beta/4, between states within a few kT of mu, and there the FP32 rounding of
-// X would be amplified most.  Workgroup (subgraph, perturbation, z) recomputes
-// the 64x64 sub-block z = 2 bi + bj of the window block X[lo..hi, lo..hi]
-// (hi - lo <= kWinMax) on FP64 MFMA and overwrites those entries of Y.
+// X would be amplified most.  The window block X[lo..hi, lo..hi] is covered by
+// 64x64 sub-blocks (bi, bj) of rows lo + 64 bi.., columns lo + 64 bj..; only
+// those with bi >= bj - 1 hold positions of the stored half of Y (row tile not
+// above column tile).  Workgroup (subgraph, perturbation, z) recomputes the
+// sub-blocks z, z + kWinGroups, ... of that list on FP64 MFMA and overwrites
+// those entries of Y.
 template <bool GEN>
 __global__ __launch_bounds__(kThreads) void k_win(
     const double* __restrict__ qbuf, const double* __restrict__ dfbuf, double* __restrict__ ybuf,
@@ -635,43 +637,42 @@ __global__ __launch_bounds__(kThreads) void k_win(
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2,
     int64_t sum_n) {
   const int s = blockIdx.x, q = blockIdx.y;
-  const int bi = blockIdx.z >> 1, bj = blockIdx.z & 1;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   const double mu = mu_state[2], half = kWinKT * mu_state[3];
   const double* e = eps + b;  // ascending
-  int lo = lower_index(e, n, mu - half);
+  const int lo = lower_index(e, n, mu - half);
   int hi = lower_index(e, n, mu + half);
   while (hi < n && e[hi] <= mu + half) ++hi;
-  if (hi - lo > kWinMax) {
-    const int mid = lower_index(e, n, mu);
-    lo = max(lo, min(mid - kWinMax / 2, hi - kWinMax));
-    hi = lo + kWinMax;
-  }
-  const int k0 = lo + kTile * bi, l0 = lo + kTile * bj;
-  if (k0 >= hi || l0 >= hi) return;
-  double acc[kTile / 16][kTile / 16];
-  if constexpr (GEN)
-    xy_block_4b<kTile, false>(qbuf + off2[s], wbuf + (size_t)q * sum_n2 + off2[s], nullptr, n, k0,
-                              l0, hi, hi, acc);
-  else
-    xy_block_4b<kTile, true>(qbuf + off2[s], qbuf + off2[s], hloc + (size_t)q * sum_n + b, n, k0,
-                             l0, hi, hi, acc);
+  if (hi <= lo) return;
+  const int nb = (hi - lo + kTile - 1) / kTile;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* dF = dfbuf + off2[s];
   double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
+  for (int z = blockIdx.z; z < nb * nb; z += kWinGroups) {
+    const int bi = z / nb, bj = z % nb;
+    if (bi < bj - 1) continue;  // no stored position (uniform over the workgroup)
+    const int k0 = lo + kTile * bi, l0 = lo + kTile * bj;
+    double acc[kTile / 16][kTile / 16];
+    if constexpr (GEN)
+      xy_block_4b<kTile, false>(qbuf + off2[s], wbuf + (size_t)q * sum_n2 + off2[s], nullptr, n,
+                                k0, l0, hi, hi, acc);
+    else
+      xy_block_4b<kTile, true>(qbuf + off2[s], qbuf + off2[s], hloc + (size_t)q * sum_n + b, n,
+                               k0, l0, hi, hi, acc);
 #pragma unroll
-  for (int r = 0; r < kTile / 16; ++r)
+    for (int r = 0; r < kTile / 16; ++r)
 #pragma unroll
-    for (int c = 0; c < kTile / 16; ++c) {
-      const int k = k0 + w * (kTile / 4) + 4 * r + (lane >> 4);
-      const int l = l0 + 16 * c + (lane & 15);
-      // each stored position is written by the one (k, l) that owns it
-      if (k < hi && l < hi && k / kTile >= l / kTile) {
-        const size_t at = (size_t)l + (size_t)n * k;
-        Y[at] = acc[r][c] * dF[at];
+      for (int c = 0; c < kTile / 16; ++c) {
+        const int k = k0 + w * (kTile / 4) + 4 * r + (lane >> 4);
+        const int l = l0 + 16 * c + (lane & 15);
+        // each stored position is written by the one (k, l) that owns it
+        if (k < hi && l < hi && k / kTile >= l / kTile) {
+          const size_t at = (size_t)l + (size_t)n * k;
+          Y[at] = acc[r][c] * dF[at];
+        }
       }
-    }
+  }
 }
 
 // h1 restricted to every subgraph, in subgraph order, for K perturbations:
@@ -1158,7 +1159,8 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
   double* ybuf = gen ? rb.G : rb.Y;
   if (split) {
     prof_begin(ctx, "k_win");
-    hipLaunchKernelGGL(gen ? k_win<true> : k_win<false>, dim3(g->n_sub, K, 4), dim3(kThreads), 0,
+    hipLaunchKernelGGL(gen ? k_win<true> : k_win<false>, dim3(g->n_sub, K, kWinGroups),
+                       dim3(kThreads), 0,
                        st, e->Q, e->A, ybuf, rb.hloc, rb.Y, e->eps, e->mu_state, dv.off2,
                        dv.sub_orb_ptr, sum_n2, sum_n);
     prof_end(ctx);

@@ -101,6 +101,7 @@ _SIGS = {
     "gq_server_clock": ([_VP], C.c_double),
     "gq_server_destroy": ([_VP], None),
     "gq_ctx_set_profiling": ([_VP, C.c_int32], C.c_int32),
+    "gq_ctx_set_iteration_cap": ([_VP, C.c_int32], C.c_int32),
     "gq_ctx_kernel_times": ([_VP, _VP, _VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int32),
 }
 
@@ -177,6 +178,10 @@ class Context:
         used, size = C.c_int64(), C.c_int64()
         _check(lib().gq_ctx_arena_used(self.h, C.byref(used), C.byref(size)))
         return used.value, size.value
+
+    def set_iteration_cap(self, leaf_iterations=60):
+        """Diagnostics: QL iterations per eigenvalue allowed in the leaves."""
+        _check(lib().gq_ctx_set_iteration_cap(self.h, int(leaf_iterations)))
 
     def set_profiling(self, enable=True):
         _check(lib().gq_ctx_set_profiling(self.h, 1 if enable else 0))

@@ -40,3 +40,10 @@ def test_algorithmic_flops_by_hand():
     assert w["k_xy"] == (8 + 4) + (27 + 9)          # n^3 + n^2 per subgraph
     assert w["k_density_rows"] == 4 * 1 * 4 + 4 * 2 * 9  # 4 c n^2
     assert np.isclose(w["k_tridiag"], 4.0 / 3.0 * (8 + 27))
+
+
+def test_minimum_bytes_by_hand():
+    # eigensolve: the matrix in, the vectors out, 16 n^2 bytes
+    assert bench.eigensolve_min_bytes(np.array([2, 3])) == 16 * 4 + 16 * 9
+    # congruence per perturbation: 16 n^2 + 8 n + 8 c n
+    assert bench.congruence_min_bytes(np.array([3]), np.array([2])) == 16 * 9 + 8 * 3 + 8 * 6

@@ -267,6 +267,25 @@ def test_split32_tile_edges(ctx, oracle_lib):
     compare(gpu, g, r, tol1=TOL_MIXED)
 
 
+def test_split32_wide_window(ctx, oracle_lib):
+    """A 300-atom hydrogen chain (a metallic band) at kT = 0.03: each subgraph
+    has about 200 states within 8 kT of mu, all refined in FP64."""
+    O = oracle_lib
+    s = _h_line(300)
+    core = (np.arange(300) // 25).astype(np.int32)
+    h1 = I.h1_diagonal(s, 2, seed=7)
+    g, r = run_oracle(O, s, core, 0.0, None, 2, 0.03, h1)
+    sizes = g.sizes()
+    start = np.concatenate([[0], np.cumsum(sizes)])
+    wide = [int((np.abs(r.eps[start[i]:start[i + 1]] - r.mu) <= 8 * 0.03).sum())
+            for i in range(g.n_sub)]
+    assert min(wide) > 128, wide
+    gpu = run_gpu(ctx, s, core, 0.0, None, 2, 0.03, h1, precision=1)
+    err = compare(gpu, g, r, tol1=TOL_MIXED)
+    _say(f"split32 wide window ({min(wide)}..{max(wide)} states): |dmu1| {err[0]:.2e} "
+         f"|drho1| {err[1]:.2e}")
+
+
 def test_error_paths(ctx):
     import torch
     from paper_2212_01997_amd import gq
@@ -284,6 +303,45 @@ def test_error_paths(ctx):
     p.eigs.density(0.01, s.n_elec)
     with pytest.raises(gq.GQError, match="max_k"):
         p.eigs.response(torch.zeros((2, s.n_orb), dtype=torch.float64, device="cuda"), p.p_blocks)
+
+
+def test_enoconv_from_iteration_cap(ctx):
+    """A leaf iteration cap of zero, set from the host, makes the eigensolver
+    report non-convergence: every kernel ends normally and the next
+    synchronising call returns GQ_ENOCONV; the default cap then succeeds."""
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath
+    s = I.config_system(1)
+    p = GraphPath(ctx, s, I.single_atom_cores(s), 1e-3, max_k=1)
+    ctx.set_iteration_cap(0)
+    try:
+        with pytest.raises(gq.GQError, match="did not converge") as ei:
+            p.ground_state(KT)
+        assert ei.value.status == -3
+    finally:
+        ctx.set_iteration_cap(60)
+    mu = p.ground_state(KT)
+    assert np.isfinite(mu)
+    with pytest.raises(gq.GQError):
+        ctx.set_iteration_cap(-1)
+
+
+def test_size_limits_rejected(ctx):
+    """Subgraphs above 1,024 orbitals and cores above 32 orbitals are refused
+    when the workspace is created, with the limit in the message."""
+    from paper_2212_01997_amd import gq
+    s = I.water_system(180, 18.0, seed=181)  # 1,080 orbitals
+    g = gq.Graph.for_system(s, (np.arange(s.n_atoms) // 15).astype(np.int32), 0.0, None,
+                            gq.COMPLETE)
+    assert g.info.max_n == 1080
+    with pytest.raises(gq.GQError, match="exceeds the limit 1024"):
+        gq.Eigs(ctx, g, 1)
+    w = I.config_system(1)
+    core = (np.arange(w.n_atoms) // 27).astype(np.int32)  # nine waters: 54 core orbitals
+    g2 = gq.Graph.for_system(w, core, 1e-3)
+    assert g2.info.max_c > 32
+    with pytest.raises(gq.GQError, match="exceeds the limit 32"):
+        gq.Eigs(ctx, g2, 1)
 
 
 # ------------------------------------------------ config 3 at full size
