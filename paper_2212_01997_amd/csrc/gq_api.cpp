@@ -208,6 +208,7 @@ static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, uint32_t f
   x.G = (flags & GQ_EIGS_GENERAL_H1) ? c.take<double>(kk * in.sum_n2) : nullptr;
   x.Q32 = c.take<float>(in.sum_n2);
   x.status = c.take<int32_t>(g->n_sub);
+  x.wflag = c.take<int32_t>(g->n_sub);
   x.md_k = c.take<int32_t>((int64_t)(g->dc_merges.size() / 4));
   x.md_cols = c.take<int32_t>(in.sum_n);
   x.md_org = c.take<int32_t>(in.sum_n);
@@ -361,7 +362,7 @@ gq_status gq_graph_export(const gq_graph* g, int32_t* sub_ptr, int32_t* sub_atom
     set_error("gq_graph_export: NULL graph");
     return GQ_EINVAL;
   }
-  auto cp = [](int32_t* dst, const std::vector<int32_t>& v) {
+  auto cp = [](int32_t* dst, const auto& v) {
     if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(int32_t));
   };
   cp(sub_ptr, g->sub_ptr);

@@ -8,8 +8,10 @@
 // keeps the core rows of each subgraph, so the collected pattern of orbital a
 // is the orbital set of the subgraph owning a.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 #include "gq_internal.hpp"
 
@@ -17,7 +19,52 @@ namespace gq {
 
 namespace {
 
-gq_status check_csr(const gq_csr* X, int32_t n, const char* name) {
+// Host threads for the graph build: every task writes only its own output
+// region, so the result does not depend on the thread count.
+int build_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::min(16u, std::max(1u, hc));
+}
+
+// fn(tid, i) for i in [0, n), items dealt in blocks of `grain` from a shared
+// counter; tid in [0, threads) names the calling thread's scratch.
+template <class F>
+void parallel_for(int64_t n, int64_t grain, int threads, F&& fn) {
+  if (threads <= 1 || n <= grain) {
+    for (int64_t i = 0; i < n; ++i) fn(0, i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  auto work = [&](int tid) {
+    for (;;) {
+      const int64_t b = next.fetch_add(grain);
+      if (b >= n) break;
+      const int64_t e = std::min(n, b + grain);
+      for (int64_t i = b; i < e; ++i) fn(tid, i);
+    }
+  };
+  std::vector<std::thread> pool;
+  const int nt = (int)std::min<int64_t>(threads, (n + grain - 1) / grain);
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& t : pool) t.join();
+}
+
+// first row for which bad(row) holds, or -1
+template <class F>
+int32_t first_bad_row(int32_t n, int threads, F&& bad) {
+  std::atomic<int32_t> first{INT32_MAX};
+  parallel_for(n, 512, threads, [&](int, int64_t a) {
+    if (a < first.load(std::memory_order_relaxed) && bad((int32_t)a)) {
+      int32_t cur = first.load();
+      while (a < cur && !first.compare_exchange_weak(cur, (int32_t)a)) {
+      }
+    }
+  });
+  return first.load() == INT32_MAX ? -1 : first.load();
+}
+
+gq_status check_csr(const gq_csr* X, int32_t n, const char* name, int threads) {
   if (!X || X->n_rows != n || !X->row_ptr || (X->nnz > 0 && (!X->col || !X->val))) {
     set_error("%s: CSR header does not match N = %d", name, n);
     return GQ_EINVAL;
@@ -26,34 +73,38 @@ gq_status check_csr(const gq_csr* X, int32_t n, const char* name) {
     set_error("%s: row_ptr must run from 0 to nnz", name);
     return GQ_EINVAL;
   }
-  for (int32_t a = 0; a < n; ++a) {
+  const int32_t bad_ptr = first_bad_row(n, threads, [&](int32_t a) {
+    return X->row_ptr[a + 1] < X->row_ptr[a];
+  });
+  if (bad_ptr >= 0) {
+    set_error("%s: row_ptr decreases at row %d", name, bad_ptr);
+    return GQ_EINVAL;
+  }
+  const int32_t bad_col = first_bad_row(n, threads, [&](int32_t a) {
     const int32_t b0 = X->row_ptr[a], b1 = X->row_ptr[a + 1];
-    if (b1 < b0) {
-      set_error("%s: row_ptr decreases at row %d", name, a);
-      return GQ_EINVAL;
-    }
     for (int32_t p = b0; p < b1; ++p) {
       const int32_t c = X->col[p];
-      if (c < 0 || c >= n || (p > b0 && c <= X->col[p - 1])) {
-        set_error("%s: row %d has columns out of range or not ascending", name, a);
-        return GQ_EINVAL;
-      }
+      if (c < 0 || c >= n || (p > b0 && c <= X->col[p - 1])) return true;
     }
+    return false;
+  });
+  if (bad_col >= 0) {
+    set_error("%s: row %d has columns out of range or not ascending", name, bad_col);
+    return GQ_EINVAL;
   }
   return GQ_OK;
 }
 
-bool pattern_symmetric(const gq_csr* X) {
-  const int32_t n = X->n_rows;
-  for (int32_t a = 0; a < n; ++a) {
-    for (int32_t p = X->row_ptr[a]; p < X->row_ptr[a + 1]; ++p) {
-      const int32_t b = X->col[p];
-      const int32_t* first = X->col + X->row_ptr[b];
-      const int32_t* last = X->col + X->row_ptr[b + 1];
-      if (!std::binary_search(first, last, a)) return false;
-    }
-  }
-  return true;
+bool pattern_symmetric(const gq_csr* X, int threads) {
+  return first_bad_row(X->n_rows, threads, [&](int32_t a) {
+           for (int32_t p = X->row_ptr[a]; p < X->row_ptr[a + 1]; ++p) {
+             const int32_t b = X->col[p];
+             const int32_t* first = X->col + X->row_ptr[b];
+             const int32_t* last = X->col + X->row_ptr[b + 1];
+             if (!std::binary_search(first, last, a)) return true;
+           }
+           return false;
+         }) < 0;
 }
 
 }  // namespace
@@ -80,10 +131,11 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
     }
   }
   const int32_t N = atom_orb_ptr[n_atoms];
-  if (gq_status st = check_csr(H, N, "H")) return st;
+  const int threads = build_threads();
+  if (gq_status st = check_csr(H, N, "H", threads)) return st;
   if (rho_prev)
-    if (gq_status st = check_csr(rho_prev, N, "rho_prev")) return st;
-  if (!pattern_symmetric(H)) {
+    if (gq_status st = check_csr(rho_prev, N, "rho_prev", threads)) return st;
+  if (!pattern_symmetric(H, threads)) {
     set_error("graph_build: the pattern of H is not symmetric");
     return GQ_EINVAL;
   }
@@ -109,40 +161,87 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   for (int32_t I = 0; I < n_atoms; ++I)
     std::fill(atom_of.begin() + atom_orb_ptr[I], atom_of.begin() + atom_orb_ptr[I + 1], I);
 
-  // atom adjacency: every thresholded element joins its two atoms (both ways)
-  std::vector<std::vector<int32_t>> nbr(n_atoms);
-  auto scan = [&](const gq_csr* X) {
-    for (int32_t a = 0; a < N; ++a) {
-      const int32_t I = atom_of[a];
-      for (int32_t p = X->row_ptr[a]; p < X->row_ptr[a + 1]; ++p) {
-        if (!(std::fabs(X->val[p]) >= tau)) continue;
-        const int32_t J = atom_of[X->col[p]];
-        if (I == J) continue;
-        nbr[I].push_back(J);
-        nbr[J].push_back(I);
+  // atom adjacency: every thresholded element joins its two atoms (both ways).
+  // fwd[I]: atoms J != I holding a thresholded element of a row of atom I
+  // (ascending); the graph is fwd united with its transpose.
+  std::vector<std::vector<int32_t>> stamp_t(threads, std::vector<int32_t>(n_atoms, -1));
+  std::vector<std::vector<int32_t>> fwd(n_atoms);
+  parallel_for(n_atoms, 64, threads, [&](int tid, int64_t Ii) {
+    const int32_t I = (int32_t)Ii;
+    std::vector<int32_t>& stamp = stamp_t[tid];
+    std::vector<int32_t>& out = fwd[I];
+    auto rows = [&](const gq_csr* X) {
+      for (int32_t a = atom_orb_ptr[I]; a < atom_orb_ptr[I + 1]; ++a)
+        for (int32_t p = X->row_ptr[a]; p < X->row_ptr[a + 1]; ++p) {
+          if (!(std::fabs(X->val[p]) >= tau)) continue;
+          const int32_t J = atom_of[X->col[p]];
+          if (J != I && stamp[J] != I) {
+            stamp[J] = I;
+            out.push_back(J);
+          }
+        }
+    };
+    rows(H);
+    if (rho_prev) rows(rho_prev);
+    std::sort(out.begin(), out.end());
+  });
+  // transpose of fwd: rev[J] lists the I with J in fwd[I], ascending (each
+  // thread owns a contiguous range of I and fills its own slots of every rev[J])
+  std::vector<int32_t> rev_ptr(n_atoms + 1, 0), rev;
+  {
+    const int nt = threads;
+    const int64_t span = (n_atoms + nt - 1) / nt;
+    std::vector<std::vector<int32_t>> cnt(nt, std::vector<int32_t>(n_atoms, 0));
+    parallel_for(nt, 1, nt, [&](int, int64_t t) {
+      const int32_t i0 = (int32_t)std::min<int64_t>(n_atoms, t * span);
+      const int32_t i1 = (int32_t)std::min<int64_t>(n_atoms, (t + 1) * span);
+      for (int32_t I = i0; I < i1; ++I)
+        for (int32_t J : fwd[I]) ++cnt[t][J];
+    });
+    // slot of thread t in rev[J]: after the entries of rev[J] from threads < t
+    for (int32_t J = 0; J < n_atoms; ++J) {
+      int32_t c = 0;
+      for (int t = 0; t < nt; ++t) {
+        const int32_t k = cnt[t][J];
+        cnt[t][J] = c;
+        c += k;
       }
+      rev_ptr[J + 1] = rev_ptr[J] + c;
     }
-  };
-  scan(H);
-  if (rho_prev) scan(rho_prev);
-  for (auto& v : nbr) {
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
+    rev.resize(rev_ptr[n_atoms]);
+    parallel_for(nt, 1, nt, [&](int, int64_t t) {
+      const int32_t i0 = (int32_t)std::min<int64_t>(n_atoms, t * span);
+      const int32_t i1 = (int32_t)std::min<int64_t>(n_atoms, (t + 1) * span);
+      for (int32_t I = i0; I < i1; ++I)
+        for (int32_t J : fwd[I]) rev[rev_ptr[J] + cnt[t][J]++] = I;
+    });
   }
+  std::vector<std::vector<int32_t>> nbr(n_atoms);
+  parallel_for(n_atoms, 64, threads, [&](int, int64_t Ii) {
+    const int32_t I = (int32_t)Ii;
+    const auto& f = fwd[I];
+    std::vector<int32_t>& out = nbr[I];
+    out.resize(f.size() + (rev_ptr[I + 1] - rev_ptr[I]));
+    auto end = std::set_union(f.begin(), f.end(), rev.begin() + rev_ptr[I],
+                              rev.begin() + rev_ptr[I + 1], out.begin());
+    out.resize(end - out.begin());
+  });
+  fwd.clear();
 
   if (flags & GQ_PATHS2) {
     std::vector<std::vector<int32_t>> two(n_atoms);
-    std::vector<int32_t> stamp(n_atoms, -1);
-    for (int32_t I = 0; I < n_atoms; ++I) {
-      stamp[I] = I;
+    parallel_for(n_atoms, 64, threads, [&](int tid, int64_t Ii) {
+      const int32_t I = (int32_t)Ii;
+      std::vector<int32_t>& stamp = stamp_t[tid];
       auto& out = two[I];
+      stamp[I] = I;
       for (int32_t J : nbr[I]) {
         if (stamp[J] != I) { stamp[J] = I; out.push_back(J); }
         for (int32_t L : nbr[J])
           if (stamp[L] != I) { stamp[L] = I; out.push_back(L); }
       }
       std::sort(out.begin(), out.end());
-    }
+    });
     nbr.swap(two);
   }
 
@@ -150,25 +249,30 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   g->n_atoms = n_atoms;
   g->N = N;
   g->n_sub = n_sub;
+  g->atom_orb_ptr.assign(atom_orb_ptr, atom_orb_ptr + n_atoms + 1);
   g->sub_ptr.assign(n_sub + 1, 0);
   g->n_core_atoms.resize(n_sub);
   g->sub_atoms.clear();
-  std::vector<int32_t> owner_mark(n_atoms, -1);
-  std::vector<int32_t> halo;
-  for (int32_t s = 0; s < n_sub; ++s) {
-    for (int32_t I : cores[s]) owner_mark[I] = s;
-    halo.clear();
+  std::vector<std::vector<int32_t>> halos(n_sub);
+  for (auto& st : stamp_t) std::fill(st.begin(), st.end(), -1);
+  parallel_for(n_sub, 16, threads, [&](int tid, int64_t si) {
+    const int32_t s = (int32_t)si;
+    std::vector<int32_t>& mark = stamp_t[tid];
+    std::vector<int32_t>& halo = halos[s];
     if (flags & GQ_COMPLETE) {
       for (int32_t I = 0; I < n_atoms; ++I)
         if (core_of_atom[I] != s) halo.push_back(I);
-    } else {
-      for (int32_t I : cores[s])
-        for (int32_t J : nbr[I])
-          if (owner_mark[J] != s) { owner_mark[J] = s; halo.push_back(J); }
-      std::sort(halo.begin(), halo.end());
+      return;
     }
+    for (int32_t I : cores[s]) mark[I] = s;
+    for (int32_t I : cores[s])
+      for (int32_t J : nbr[I])
+        if (mark[J] != s) { mark[J] = s; halo.push_back(J); }
+    std::sort(halo.begin(), halo.end());
+  });
+  for (int32_t s = 0; s < n_sub; ++s) {
     g->sub_atoms.insert(g->sub_atoms.end(), cores[s].begin(), cores[s].end());
-    g->sub_atoms.insert(g->sub_atoms.end(), halo.begin(), halo.end());
+    g->sub_atoms.insert(g->sub_atoms.end(), halos[s].begin(), halos[s].end());
     g->n_core_atoms[s] = (int32_t)cores[s].size();
     if (g->sub_atoms.size() > (size_t)INT32_MAX) {
       set_error("graph_build: subgraph vertex lists exceed int32");
@@ -176,6 +280,7 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
     }
     g->sub_ptr[s + 1] = (int32_t)g->sub_atoms.size();
   }
+  halos.clear();
 
   // orbital maps
   g->sub_orb_ptr.assign(n_sub + 1, 0);
@@ -201,7 +306,8 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   g->sorted_orbs.resize(sum_n);
   g->sorted_local.resize(sum_n);
   g->slot.resize(sum_n);
-  for (int32_t s = 0; s < n_sub; ++s) {
+  parallel_for(n_sub, 16, threads, [&](int, int64_t si) {
+    const int32_t s = (int32_t)si;
     const int32_t b = g->sub_orb_ptr[s], n = g->sub_orb_ptr[s + 1] - b;
     int32_t* loc = g->sorted_local.data() + b;
     std::iota(loc, loc + n, 0);
@@ -211,7 +317,7 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
       g->sorted_orbs[b + r] = orbs[loc[r]];
       g->slot[b + loc[r]] = r;
     }
-  }
+  });
 
   // collected pattern
   g->rho_row_ptr.assign(N + 1, 0);
@@ -226,14 +332,15 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
     g->rho_row_ptr[a + 1] = (int32_t)nnz;
   }
   g->rho_col.resize(nnz);
-  for (int32_t s = 0; s < n_sub; ++s) {
+  parallel_for(n_sub, 16, threads, [&](int, int64_t si) {
+    const int32_t s = (int32_t)si;
     const int32_t b = g->sub_orb_ptr[s], n = g->sub_orb_ptr[s + 1] - b;
     for (int32_t j = 0; j < g->n_core_orbs[s]; ++j) {
       const int32_t a = g->sub_orbs[b + j];
       std::copy(g->sorted_orbs.begin() + b, g->sorted_orbs.begin() + b + n,
                 g->rho_col.begin() + g->rho_row_ptr[a]);
     }
-  }
+  });
 
   // per-subgraph offsets and a largest-first order
   g->off2.assign(n_sub + 1, 0);

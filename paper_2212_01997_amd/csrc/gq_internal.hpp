@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
+#include <utility>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -31,6 +33,27 @@ constexpr int kXyBinMax[kXyBins] = {128, 256, 384, 512, 1024};
 // Tile-list ranges [off[x], off[x+1]) served by the workgroups of XCD x.
 struct XcdSplit {
   int32_t off[9];
+};
+
+// Allocator whose value-initialisation leaves trivial elements uninitialised:
+// large index arrays that are filled right after resize() skip the zero pass.
+template <class T>
+struct DefaultInitAllocator : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = DefaultInitAllocator<U>;
+  };
+  DefaultInitAllocator() = default;
+  template <class U>
+  DefaultInitAllocator(const DefaultInitAllocator<U>&) {}
+  template <class U>
+  void construct(U* p) {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
 };
 
 constexpr size_t kArenaAlign = 256;
@@ -156,9 +179,11 @@ struct gq_graph_dev {
 
 struct gq_graph {
   int32_t n_atoms = 0, N = 0, n_sub = 0;
+  std::vector<int32_t> atom_orb_ptr;  // [n_atoms+1] orbitals of each atom
   std::vector<int32_t> sub_ptr, sub_atoms, n_core_atoms;
   std::vector<int32_t> sub_orb_ptr, sub_orbs, n_core_orbs;
-  std::vector<int32_t> rho_row_ptr, rho_col;
+  std::vector<int32_t> rho_row_ptr;
+  std::vector<int32_t, gq::DefaultInitAllocator<int32_t>> rho_col;
   std::vector<int32_t> sorted_orbs, sorted_local, slot;
   std::vector<int64_t> off2, offc;
   std::vector<int32_t> offcd;
@@ -208,6 +233,7 @@ struct gq_eigs {
   double* mu_part = nullptr;   // [blocks][kMuPoints]
   int32_t mu_blocks = 0;
   int32_t* status = nullptr;   // [n_sub] eigensolver status (0 ok)
+  int32_t* wflag = nullptr;    // [n_sub] split response: 1 = window too wide, X in FP64
   // merge metadata of the divide-and-conquer levels
   int32_t *md_k = nullptr, *md_cols = nullptr, *md_org = nullptr, *md_pos = nullptr;
   int32_t *md_dsrc = nullptr, *md_dpos = nullptr;

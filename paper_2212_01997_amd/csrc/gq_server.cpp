@@ -195,7 +195,7 @@ void gq_server::run(Request& r, gq_ctx* ctx) {
          "download rho1");
   hip_ok(hipStreamSynchronize(st), "request stream");
   r.rho_row_ptr = g->rho_row_ptr;
-  r.rho_col = g->rho_col;
+  r.rho_col.assign(g->rho_col.begin(), g->rho_col.end());
   r.t_done = now();  // before the arena piece is released below
 }
 

@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256, 4) void k_xy(
     const double* __restrict__ dfbuf, double* __restrict__ ybuf, const double* __restrict__ hloc,
     const double* __restrict__ wbuf, const int32_t* __restrict__ tiles, XcdSplit split,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2,
-    int64_t sum_n) {
+    int64_t sum_n, const int32_t* __restrict__ wflag, int mode) {
   constexpr int WB = XyShape<TM>::kWB;
   const int q = blockIdx.y;
   const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
@@ -424,6 +424,8 @@ __global__ __launch_bounds__(256, 4) void k_xy(
   const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
   for (int t = split.off[xcd] + (int)(blockIdx.x >> 3); t < split.off[xcd + 1]; t += stride) {
     const int s = tiles[3 * t], ti = tiles[3 * t + 1], tj = tiles[3 * t + 2];
+    // mode 1: subgraphs refined by window only; mode 2: the others (FP64 X)
+    if (mode != 0 && (wflag[s] != 0) != (mode == 2)) continue;
     const int b = sub_orb_ptr[s];
     const int n = sub_orb_ptr[s + 1] - b;
     const int k0 = ti * TM, l0 = tj * TM;
@@ -524,12 +526,14 @@ __global__ __launch_bounds__(256, 2) void k_xy_kq(
     const double* __restrict__ qbuf, const float* __restrict__ q32,
     const double* __restrict__ dfbuf, double* __restrict__ ybuf, const double* __restrict__ hloc,
     const int32_t* __restrict__ tiles, XcdSplit split, const int64_t* __restrict__ off2,
-    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n, int K) {
+    const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2, int64_t sum_n, int K,
+    const int32_t* __restrict__ wflag, int mode) {
   const int q0 = blockIdx.y * KQ, nq = min(KQ, K - q0);
   const int xcd = blockIdx.x & 7, stride = gridDim.x >> 3;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int t = split.off[xcd] + (int)(blockIdx.x >> 3); t < split.off[xcd + 1]; t += stride) {
     const int s = tiles[3 * t], ti = tiles[3 * t + 1], tj = tiles[3 * t + 2];
+    if (mode != 0 && (wflag[s] != 0) != (mode == 2)) continue;
     const int b = sub_orb_ptr[s];
     const int n = sub_orb_ptr[s + 1] - b;
     const int k0 = ti * TM, l0 = tj * TM;
@@ -606,8 +610,11 @@ __global__ __launch_bounds__(kThreads) void k_split32(const double* __restrict__
 
 // The FP64 refinement window: the states with |eps - mu| <= kWinKT kT, all of
 // them.  Pairs inside a dense or degenerate level next to mu carry
-// dF = f'(eps), up to beta/4, and none of them is left in FP32.
+// dF = f'(eps), up to beta/4, and none of them is left in FP32.  A subgraph
+// whose window holds more than kWinCap states gets its whole X in FP64
+// instead (refining a larger window would cost about as much as X itself).
 constexpr double kWinKT = 8.0;
+constexpr int kWinCap = 128;
 constexpr int kWinGroups = 4;  // workgroups per (subgraph, perturbation)
 
 // first index i in [0, n) with v[i] >= x (n if none)
@@ -619,6 +626,28 @@ __device__ __forceinline__ int lower_index(const double* v, int n, double x) {
     else hi = mid;
   }
   return lo;
+}
+
+// window [lo, hi) of a subgraph's ascending eigenvalues e[0..n)
+__device__ __forceinline__ void win_range(const double* e, int n, double mu, double half, int& lo,
+                                          int& hi) {
+  lo = lower_index(e, n, mu - half);
+  hi = lower_index(e, n, mu + half);
+  while (hi < n && e[hi] <= mu + half) ++hi;
+}
+
+// wflag[s] = 1 when subgraph s's window exceeds kWinCap states (its X is then
+// formed in FP64), else 0.
+__global__ __launch_bounds__(kThreads) void k_win_size(const double* __restrict__ eps,
+                                                       const double* __restrict__ mu_state,
+                                                       const int32_t* __restrict__ sub_orb_ptr,
+                                                       int n_sub, int32_t* __restrict__ wflag) {
+  const int s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= n_sub) return;
+  const int b = sub_orb_ptr[s];
+  int lo, hi;
+  win_range(eps + b, sub_orb_ptr[s + 1] - b, mu_state[2], kWinKT * mu_state[3], lo, hi);
+  wflag[s] = hi - lo > kWinCap ? 1 : 0;
 }
 
 // FP64 refinement of the thermal window: the dF weights are largest, up to
@@ -639,12 +668,10 @@ __global__ __launch_bounds__(kThreads) void k_win(
   const int s = blockIdx.x, q = blockIdx.y;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
-  const double mu = mu_state[2], half = kWinKT * mu_state[3];
-  const double* e = eps + b;  // ascending
-  const int lo = lower_index(e, n, mu - half);
-  int hi = lower_index(e, n, mu + half);
-  while (hi < n && e[hi] <= mu + half) ++hi;
-  if (hi <= lo) return;
+  int lo, hi;
+  win_range(eps + b, n, mu_state[2], kWinKT * mu_state[3], lo, hi);
+  // empty window, or X of this subgraph already in FP64
+  if (hi <= lo || hi - lo > kWinCap) return;
   const int nb = (hi - lo + kTile - 1) / kTile;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* dF = dfbuf + off2[s];
@@ -937,10 +964,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble(
 // ------------------------------------------------------------ xy launches
 using XyKernel = void (*)(const double*, const float*, const double*, double*, const double*,
                           const double*, const int32_t*, XcdSplit, const int64_t*,
-                          const int32_t*, int64_t, int64_t);
+                          const int32_t*, int64_t, int64_t, const int32_t*, int);
 using XyKqKernel = void (*)(const double*, const float*, const double*, double*, const double*,
                             const int32_t*, XcdSplit, const int64_t*, const int32_t*, int64_t,
-                            int64_t, int);
+                            int64_t, int, const int32_t*, int);
 
 template <bool GEN>
 XyKernel xy_kernel_t(int shape, bool split) {
@@ -986,7 +1013,7 @@ int xy_resident_per_xcd(int shape, int variant) {
 // general kind (gen) takes one perturbation per workgroup, X = Q^T W with W in
 // rb.Y, written to rb.G.
 void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb, int bin,
-                   int choice, bool split, bool gen, int K) {
+                   int choice, bool split, bool gen, int K, int mode = 0) {
   const int shape = choice & 1;
   const bool persistent = (choice & 2) != 0;
   const bool kq = K > 1 && !gen;
@@ -1002,13 +1029,13 @@ void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& r
     hipLaunchKernelGGL(xy_kq_kernel(shape, split), dim3(8 * per_xcd, (K + kXyKq - 1) / kXyKq),
                        dim3(xy_threads(shape)), 0, ctx->stream, e->Q, e->Q32, e->A, rb.Y,
                        rb.hloc, dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr, g->info.sum_n2,
-                       g->info.sum_n, K);
+                       g->info.sum_n, K, e->wflag, mode);
     return;
   }
   hipLaunchKernelGGL(xy_kernel(shape, split, gen), dim3(8 * per_xcd, K), dim3(xy_threads(shape)),
                      0, ctx->stream, e->Q, e->Q32, e->A, gen ? rb.G : rb.Y, rb.hloc,
                      gen ? rb.Y : nullptr, dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr,
-                     g->info.sum_n2, g->info.sum_n);
+                     g->info.sum_n2, g->info.sum_n, e->wflag, mode);
 }
 
 void launch_split32(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
@@ -1152,8 +1179,18 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
     hipLaunchKernelGGL(k_h1_gather,
                        dim3((unsigned)std::min<int64_t>(1024, (sum_n + kThreads - 1) / kThreads), K),
                        dim3(kThreads), 0, st, h1.diag, g->N, dv.sub_orbs, sum_n, rb.hloc);
-  for (int bin = 0; bin < kXyBins; ++bin)
-    launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[split ? 1 : 0][bin], split, gen, K);
+  if (split) {
+    // subgraphs whose window is too wide for the refinement get FP64 X
+    hipLaunchKernelGGL(k_win_size, dim3((g->n_sub + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       st, e->eps, e->mu_state, dv.sub_orb_ptr, g->n_sub, e->wflag);
+    for (int bin = 0; bin < kXyBins; ++bin)
+      launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[1][bin], true, gen, K, 1);
+    for (int bin = 0; bin < kXyBins; ++bin)
+      launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[0][bin], false, gen, K, 2);
+  } else {
+    for (int bin = 0; bin < kXyBins; ++bin)
+      launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[0][bin], false, gen, K);
+  }
   prof_end(ctx);
   // X o dF of perturbation q is in ybuf: Y for the diagonal kind, G for the general
   double* ybuf = gen ? rb.G : rb.Y;

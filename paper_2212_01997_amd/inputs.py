@@ -427,6 +427,53 @@ def h1_dense(system, k, seed, sigma=0.05):
     return out
 
 
+# ------------------------------------------------- charge model (Sec. V)
+# A stand-in for the charge-dependent potential of SCC-DFTB: atomic charges n
+# act on every orbital of atom I through the potential (gamma n)_I, so the
+# perturbation from a charge vector v is H1[v] = diag over orbitals of
+# (gamma v).  gamma_II = U_I (on-site interaction per element, Ha), and for
+# I != J within the cutoff (minimum image) a screened Coulomb form
+# exp(-r/s) / sqrt(r^2 + (2/(U_I + U_J))^2) with r and s in bohr.  The values
+# are chosen by this build (free-atom-like magnitudes), not taken from a
+# parameter set.
+HUBBARD_U = {"H": 0.42, "C": 0.36, "N": 0.43, "O": 0.50, "S": 0.33}
+BOHR = 0.529177210903  # Angstrom per bohr
+COULOMB_SCREEN = 6.0   # bohr
+COULOMB_CUTOFF = 8.0   # Angstrom (at most half the box)
+
+
+def coulomb_kernel(system, cutoff=COULOMB_CUTOFF):
+    """Symmetric atom-by-atom kernel gamma as a host CSR triple (row_ptr, col,
+    val), ascending columns, diagonal included."""
+    n = system.n_atoms
+    cut = min(cutoff, 0.5 * system.box - 1e-9)
+    U = np.array([HUBBARD_U[s] for s in system.species])
+    pos = np.mod(system.pos, system.box)
+    tree = cKDTree(pos, boxsize=system.box)
+    pairs = tree.query_pairs(cut, output_type="ndarray")
+    ii, jj = pairs[:, 0], pairs[:, 1]
+    d = pos[ii] - pos[jj]
+    d -= system.box * np.round(d / system.box)
+    r = np.sqrt((d * d).sum(axis=1)) / BOHR
+    a = 2.0 / (U[ii] + U[jj])
+    g = np.exp(-r / COULOMB_SCREEN) / np.sqrt(r * r + a * a)
+    rows = np.concatenate([ii, jj, np.arange(n)])
+    cols = np.concatenate([jj, ii, np.arange(n)])
+    vals = np.concatenate([g, g, U])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    np.cumsum(rp, out=rp)
+    return rp.astype(np.int32), cols.astype(np.int32), vals.astype(np.float64)
+
+
+def charge_vectors(system, k, seed, sigma=0.05):
+    """K seeded charge vectors over the atoms, N(0, sigma) per atom."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, sigma, size=(k, system.n_atoms))
+
+
 # -------------------------------------------------------------- partitions
 
 def single_atom_cores(system):
