@@ -230,6 +230,8 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
 
   if (flags & GQ_PATHS2) {
     std::vector<std::vector<int32_t>> two(n_atoms);
+    // the forward lists left atom ids in the marks: start from none
+    for (auto& st : stamp_t) std::fill(st.begin(), st.end(), -1);
     parallel_for(n_atoms, 64, threads, [&](int tid, int64_t Ii) {
       const int32_t I = (int32_t)Ii;
       std::vector<int32_t>& stamp = stamp_t[tid];

@@ -57,13 +57,26 @@ def _compare_graph(G, O, system, core, tau, prev=None, flags=0):
 
 
 @pytest.mark.parametrize("tau,flags,cores", [(1e-5, 0, 1), (0.07, 1, 1), (0.0, 2, 1),
-                                             (0.02, 0, 8), (0.07, 1, 8)])
+                                             (0.02, 0, 8), (0.07, 1, 8), (0.2, 1, 1),
+                                             (0.15, 1, 3), (0.3, 1, 1)])
 def test_graph_build_matches_oracle(gq, oracle_lib, tau, flags, cores):
     O = oracle_lib
     s = I.config_system(1)
     core = I.single_atom_cores(s) if cores == 1 else I.spatial_cores(s, cores)
     prev = O.bootstrap_prev(s, core, 0.01)
     _compare_graph(gq, O, s, core, tau, prev, flags)
+
+
+def test_graph_build_matches_oracle_chain(gq, oracle_lib):
+    """Mixed elements (4-orbital heavy atoms), sparse thresholds, paths of two:
+    the many-threaded host build against the oracle."""
+    O = oracle_lib
+    s = I.chain_water_system(900, 180, seed=3001)
+    for cores, tau in ((1, 0.2), (8, 0.07), (3, 0.12)):
+        core = I.single_atom_cores(s) if cores == 1 else I.spatial_cores(s, cores)
+        g0 = O.graph_build(s, core, 0.0)
+        prev = (g0.rho_row_ptr, g0.rho_col, np.linspace(0.5, 1e-4, g0.nnz))
+        _compare_graph(gq, O, s, core, tau, prev, 1)
 
 
 def test_graph_build_matches_oracle_config2(gq, oracle_lib):
