@@ -249,6 +249,68 @@ gq_status gq_response_static(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_t h
 gq_status gq_assemble(gq_ctx* ctx, const gq_graph* g, const double* blocks_dev, int32_t K,
                       double* vals_dev);
 
+/* -------------------------------------------------------------- charges
+ * Sec. V: the charge response that the preconditioned Krylov kernel of the
+ * electronic equations of motion needs.  Atomic charges n act on every
+ * orbital of atom I through the potential (gamma n)_I, so a charge vector v
+ * perturbs the Hamiltonian by H1[v] = diag(gamma v) over the orbitals; gamma
+ * is an n_atoms x n_atoms symmetric kernel (the charge-charge interaction, a
+ * Coulomb-type sum in SCC-DFTB).  Core charges of a density are the diagonal
+ * entries of its collected core rows summed per atom (Eq. (assemble_rho0)).
+ * Charge vectors are device arrays of n_atoms doubles; K of them are [K][n_atoms].
+ *
+ * gq_charge_create: device state of the charge model on graph g: gamma (host
+ * CSR, ascending columns) and each atom's core subgraph, with work buffers
+ * for up to kmax charge vectors per call (a piece of ctx's arena when it has
+ * one).  GQ_EINVAL for a malformed gamma; GQ_ENOMEM.  The graph must outlive
+ * the handle; the handle is destroyed before ctx.
+ *
+ * gq_charge_core: q[n_atoms] = per-atom core charges of the core-row blocks
+ * `blocks_dev` (nnz, block layout, e.g. the rho blocks of gq_density).
+ *
+ * gq_charge_response: for each v_q, the derivative of the core charges along
+ * H1[v_q] (Eq. (dfdv), first term): the canonical graph response (Eqs. (D1),
+ * (dmu_1)) on the workspace's eigenbasis, of which only the diagonal of the
+ * core rows is formed.  q1_dev [K][n_atoms]; mu1_dev [K] or NULL.
+ * 1 <= K <= min(max_k of e, kmax).  Requires gq_density on e.
+ *
+ * gq_preconditioner: Sec. V.A, Eq. (PreCond).  For every subgraph k and each
+ * of its m_k core atoms J, the fixed-mu response of the core charges to a
+ * unit charge on J (H1 = gamma[., J] on every orbital, restricted to the
+ * subgraph, Eq. (TwoDer)) and the core charges of the mu response; each
+ * column's mu1 is set so that the column sums over the core are -1, giving
+ * j^(k), and k0^(k) = (j^(k) - alpha I)^-1 (Gauss-Jordan, partial pivoting).
+ * k0_dev receives the blocks subgraph after subgraph, each m_k x m_k
+ * column-major over the subgraph's core atoms in ascending order (offsets
+ * sum_{j<k} m_j^2).  *singular_dev (device int32) is set to 1 if a block is
+ * singular (its entries are NaN then).  alpha >= 0; cores of at most 32 atoms.
+ * The unit-charge perturbations run min(max_k, largest m_k) at a time.
+ *
+ * gq_krylov_kernel: Sec. V.B, Eqs. (v1_prim), (v1), (dfdv), (LowRankEEOM),
+ * (ElEOM).  From the ground-state core rows rho_blocks_dev and the charges
+ * n_dev: f = rho_0 - n, v_1 = K0 f / |K0 f|; for i = 1..m the charge response
+ * along v_i and f_{v_i} = K0 (d rho_0 / d lambda - v_i) (F_dev row i), then
+ * v_{i+1} = f_{v_i} orthogonalised against v_1..v_i by two passes of modified
+ * Gram-Schmidt and normalised (V_dev row i+1); O_ij = f_{v_i} . f_{v_j}
+ * (O_dev, m x m), M = O^-1 (M_dev) and the charge acceleration
+ * ndd = -omega^2 sum_ij v_i M_ij (f_{v_j} . K0 f) (ndd_dev, n_atoms).  All
+ * sums over the atoms run in a fixed order.  1 <= m <= 32; *singular_dev is
+ * set to 1 if O is singular.  Requires gq_density on e; K0 from
+ * gq_preconditioner. */
+typedef struct gq_charge gq_charge;
+gq_status gq_charge_create(gq_ctx* ctx, const gq_graph* g, const gq_csr* gamma, int32_t kmax,
+                           gq_charge** out);
+void gq_charge_destroy(gq_charge* c);
+gq_status gq_charge_core(gq_ctx* ctx, gq_charge* c, const double* blocks_dev, double* q_dev);
+gq_status gq_charge_response(gq_ctx* ctx, gq_charge* c, gq_eigs* e, const double* v_dev,
+                             int32_t K, uint32_t precision, double* q1_dev, double* mu1_dev);
+gq_status gq_preconditioner(gq_ctx* ctx, gq_charge* c, gq_eigs* e, double alpha, double* k0_dev,
+                            int32_t* singular_dev);
+gq_status gq_krylov_kernel(gq_ctx* ctx, gq_charge* c, gq_eigs* e, const double* k0_dev,
+                           const double* rho_blocks_dev, const double* n_dev, int32_t m,
+                           double omega, uint32_t precision, double* ndd_dev, double* V_dev,
+                           double* F_dev, double* O_dev, double* M_dev, int32_t* singular_dev);
+
 /* ------------------------------------------------------------ batching
  * Launch tuning and whole-step capture for batches of uneven subgraphs
  * (Sec. II.G: the subgraph problems are independent and are run as one

@@ -291,8 +291,16 @@ struct H1Spec {
   const double* diag;
   const gq_csr* csr;
 };
+// local_h1: rb.hloc already holds the perturbations in subgraph order (the
+// kind in h1 is then ignored); charge_only: form only the diagonal of P (into
+// rb.pdiag) and mu1, not the core rows (p_blocks may be NULL).
+struct RespOpts {
+  bool local_h1 = false;
+  bool charge_only = false;
+};
 void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb,
-                     const H1Spec& h1, int32_t K, uint32_t precision, double* p_blocks);
+                     const H1Spec& h1, int32_t K, uint32_t precision, double* p_blocks,
+                     RespOpts opt = RespOpts{});
 // Doubles of response scratch one perturbation needs (RespBufs layout).
 int64_t resp_doubles_per_k(const gq_graph* g, uint32_t kind);
 // Device address of the library's static response scratch on the current

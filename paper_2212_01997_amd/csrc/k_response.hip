@@ -904,6 +904,43 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
   }
 }
 
+// Diagonal of P = 2 T Q^T only (the core charges of the response need no
+// more): P_jj = 2 sum_l T[j, l] Q[j, l] for j < c; workgroup (subgraph, q),
+// each thread sums its columns l in order, then a fixed-order reduction.
+__global__ __launch_bounds__(kThreads) void k_pdiag(
+    const double* __restrict__ tbuf, const double* __restrict__ qbuf, double* __restrict__ pdiag,
+    const int64_t* __restrict__ off2, const int32_t* __restrict__ offcd,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core, int64_t sum_n,
+    int sum_c) {
+  __shared__ double red[kThreads / 64][32];
+  const int s = blockIdx.x, q = blockIdx.y;
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const int c = n_core[s];
+  const double* Q = qbuf + off2[s];
+  const double* Tq = tbuf + (size_t)q * sum_n * 32;
+  double acc[32];
+#pragma unroll
+  for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+  for (int l = threadIdx.x; l < n; l += kThreads) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      if (j < c) acc[j] += Tq[(size_t)(b + l) * 32 + j] * Q[j + (size_t)n * l];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const double t = wave_sum(acc[j]);
+    if (lane == 0) red[w][j] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < c) {
+    double t = 0.0;
+    for (int x = 0; x < kThreads / 64; ++x) t += red[x][threadIdx.x];
+    pdiag[(size_t)q * sum_c + offcd[s] + threadIdx.x] = 2.0 * t;
+  }
+}
+
 // mu1_q = -sum_i sum_{j<c_i} P_i[j,j] / sum_i tmu_i, fixed order; one block per q
 __global__ __launch_bounds__(kThreads) void k_mu1(const double* __restrict__ pdiag, int sum_c,
                                                   const double* __restrict__ tmu, int n_sub,
@@ -1146,14 +1183,15 @@ int64_t resp_doubles_per_k(const gq_graph* g, uint32_t kind) {
 }
 
 void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb,
-                     const H1Spec& h1, int32_t K, uint32_t precision, double* p_blocks) {
+                     const H1Spec& h1, int32_t K, uint32_t precision, double* p_blocks,
+                     RespOpts opt) {
   hipStream_t st = ctx->stream;
   const gq_graph_dev& dv = g->dev;
   const int64_t nnz = g->info.nnz;
   const int64_t sum_n = g->info.sum_n, sum_n2 = g->info.sum_n2;
   const int sum_c = g->offcd[g->n_sub];
   const bool split = precision == GQ_PREC_SPLIT32;
-  const bool gen = h1.kind == GQ_H1_CSR;
+  const bool gen = !opt.local_h1 && h1.kind == GQ_H1_CSR;
   // a captured sequence must not depend on the host-side validity flag
   if (split && (!e->q32_valid || ctx->capturing)) {
     launch_split32(ctx, g, e);
@@ -1175,7 +1213,7 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
     prof_end(ctx);
   }
   prof_begin(ctx, split ? "k_xy32" : "k_xy");
-  if (!gen)
+  if (!gen && !opt.local_h1)
     hipLaunchKernelGGL(k_h1_gather,
                        dim3((unsigned)std::min<int64_t>(1024, (sum_n + kThreads - 1) / kThreads), K),
                        dim3(kThreads), 0, st, h1.diag, g->N, dv.sub_orbs, sum_n, rb.hloc);
@@ -1206,6 +1244,16 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
   dim3 grid_cols(g->n_sub, (g->info.max_n + kTC - 1) / kTC, K);
   hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, ybuf, rb.T, dv.off2,
                      dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
+  if (opt.charge_only) {
+    hipLaunchKernelGGL(k_pdiag, dim3(g->n_sub, K), dim3(kThreads), 0, st, rb.T, e->Q, rb.pdiag,
+                       dv.off2, dv.offcd, dv.sub_orb_ptr, dv.n_core, sum_n, sum_c);
+    prof_end(ctx);
+    prof_begin(ctx, "k_mu1_combine");
+    hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, rb.pdiag, sum_c, e->tmu, g->n_sub,
+                       rb.mu1);
+    prof_end(ctx);
+    return;
+  }
   const int ncb = (g->info.max_n + kTC - 1) / kTC;
   const int groups_per_xcd = (g->n_sub * ncb + 7) / 8;
   hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, rb.T, e->Q,

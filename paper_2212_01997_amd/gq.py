@@ -92,6 +92,13 @@ _SIGS = {
     "gq_capture_end": ([_VP, C.POINTER(_VP)], C.c_int32),
     "gq_exec_launch": ([_VP, _VP], C.c_int32),
     "gq_exec_destroy": ([_VP], None),
+    "gq_charge_create": ([_VP, _VP, C.POINTER(_Csr), C.c_int32, C.POINTER(_VP)], C.c_int32),
+    "gq_charge_destroy": ([_VP], None),
+    "gq_charge_core": ([_VP, _VP, _VP, _VP], C.c_int32),
+    "gq_charge_response": ([_VP, _VP, _VP, _VP, C.c_int32, C.c_uint32, _VP, _VP], C.c_int32),
+    "gq_preconditioner": ([_VP, _VP, _VP, C.c_double, _VP, _VP], C.c_int32),
+    "gq_krylov_kernel": ([_VP, _VP, _VP, _VP, _VP, _VP, C.c_int32, C.c_double, C.c_uint32,
+                          _VP, _VP, _VP, _VP, _VP, _VP], C.c_int32),
     "gq_server_create": ([C.c_int32, C.c_int32, C.c_int64, C.POINTER(_VP)], C.c_int32),
     "gq_server_submit": ([_VP, C.POINTER(_Request), C.POINTER(C.c_int64)], C.c_int32),
     "gq_server_wait": ([_VP, C.c_int64, C.POINTER(_ReqInfo)], C.c_int32),
@@ -383,6 +390,83 @@ class Eigs:
 
     def __del__(self, _rel=_release):
         _rel(self, "gq_eigs_destroy")
+
+
+class ChargeModel:
+    """gq_charge_*: the charge response, the subgraph preconditioner and the
+    preconditioned Krylov kernel (Sec. V) on one graph; gamma is the host CSR
+    triple of the atom-by-atom charge kernel."""
+
+    def __init__(self, ctx: Context, graph: Graph, gamma, kmax=8):
+        import torch
+        self.ctx, self.graph = ctx, graph
+        keep = []
+        gs = _host_csr(*gamma, keep)
+        h = _VP()
+        _check(lib().gq_charge_create(ctx.h, graph.h, C.byref(gs), int(kmax), C.byref(h)))
+        self.h = h
+        self.n_atoms = graph.info.n_atoms
+        ex = graph.export()
+        m = ex["n_core_atoms"].astype(np.int64)
+        self.k0_offsets = np.concatenate([[0], np.cumsum(m * m)])
+        self.dev = torch.device("cuda", ctx.device)
+
+    def _empty(self, *shape, dtype=None):
+        import torch
+        return torch.empty(*shape, dtype=dtype or torch.float64, device=self.dev)
+
+    def core(self, blocks):
+        """Per-atom core charges of core-row blocks (gq_charge_core)."""
+        q = self._empty(self.n_atoms)
+        _check(lib().gq_charge_core(self.ctx.h, self.h, _ptr(blocks), _ptr(q)))
+        return q
+
+    def response(self, eigs: Eigs, v, precision=PREC_FP64):
+        """(q1 [K, n_atoms], mu1 [K]) along the charge vectors v [K, n_atoms]."""
+        K = int(v.shape[0])
+        q1 = self._empty(K, self.n_atoms)
+        mu1 = self._empty(K)
+        _check(lib().gq_charge_response(self.ctx.h, self.h, eigs.h, _ptr(v.contiguous()), K,
+                                        int(precision), _ptr(q1), _ptr(mu1)))
+        return q1, mu1
+
+    def preconditioner(self, eigs: Eigs, alpha):
+        """k0 blocks (gq_preconditioner) as one device vector; raises if a
+        block is singular."""
+        import torch
+        k0 = self._empty(int(self.k0_offsets[-1]))
+        bad = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        _check(lib().gq_preconditioner(self.ctx.h, self.h, eigs.h, float(alpha), _ptr(k0),
+                                       _ptr(bad)))
+        self.ctx.stream.synchronize()
+        if int(bad.item()):
+            raise GQError(-3, "gq_preconditioner: a core Jacobian block is singular")
+        return k0
+
+    def blocks(self, k0):
+        """The k0 vector split into its m_k x m_k blocks (host arrays)."""
+        ex = self.graph.export()
+        m = ex["n_core_atoms"]
+        h = k0.cpu().numpy()
+        return [h[self.k0_offsets[s]:self.k0_offsets[s + 1]].reshape(m[s], m[s], order="F")
+                for s in range(len(m))]
+
+    def krylov(self, eigs: Eigs, k0, rho_blocks, n, m, omega=1.0, precision=PREC_FP64):
+        """gq_krylov_kernel; returns the device tensors ndd, V, F, O, M."""
+        import torch
+        out = {"ndd": self._empty(self.n_atoms), "V": self._empty(m, self.n_atoms),
+               "F": self._empty(m, self.n_atoms), "O": self._empty(m, m), "M": self._empty(m, m)}
+        bad = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        _check(lib().gq_krylov_kernel(self.ctx.h, self.h, eigs.h, _ptr(k0), _ptr(rho_blocks),
+                                      _ptr(n.contiguous()), int(m), float(omega), int(precision),
+                                      _ptr(out["ndd"]), _ptr(out["V"]), _ptr(out["F"]),
+                                      _ptr(out["O"]), _ptr(out["M"]), _ptr(bad)))
+        self.ctx.stream.synchronize()
+        out["singular"] = bool(bad.item())
+        return out
+
+    def __del__(self, _rel=_release):
+        _rel(self, "gq_charge_destroy")
 
 
 def assemble(ctx: Context, graph: Graph, blocks, vals, K=1):

@@ -1,0 +1,165 @@
+"""Parity of the charge response, the subgraph preconditioner and the
+preconditioned Krylov kernel (Sec. V) on the GPU with the oracle
+(oracle/krylov.py), through the C ABI.
+
+Bar: core charges and charge responses within 1e-10 (FP64 path) and 1e-6
+(split-FP32 congruences); preconditioner blocks, Krylov vectors, O, M and the
+acceleration within 1e-9 relative to their largest entry (the blocks are
+inverses of matrices of norm about one, the Krylov quantities chain up to six
+responses and a small matrix inverse).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2212_01997_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+KT = 0.01
+ALPHA = 0.2
+
+
+def _say(msg):
+    print(f"[gpu-charge] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2212_01997_amd import gq
+    return gq.Context(0)
+
+
+@pytest.fixture(scope="module")
+def K():
+    from oracle import krylov
+    return krylov
+
+
+def _case(name, O):
+    if name == "config1":
+        s = I.config_system(1)
+        core = I.spatial_cores(s, 3)
+    elif name == "water60":
+        s = I.water_system(60, 12.2, seed=61)
+        core = I.spatial_cores(s, 8)
+    else:
+        s = I.chain_water_system(900, 180, seed=3001)
+        core = I.spatial_cores(s, 8)
+    prev = O.bootstrap_prev(s, core, KT, pool=name == "chain900")
+    g = O.graph_build(s, core, 0.07, rho_prev=prev, flags=O.PATHS2)
+    return s, core, prev, g, I.coulomb_kernel(s)
+
+
+def _gpu(ctx, s, core, prev, gamma, max_k):
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath
+    p = GraphPath(ctx, s, core, 0.07, prev, gq.PATHS2, max_k=max_k)
+    mu = p.ground_state(KT)
+    cm = gq.ChargeModel(ctx, p.graph, gamma, kmax=max_k)
+    return p, mu, cm
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("name", ["config1", "water60"])
+def test_core_charges_and_response(ctx, oracle_lib, K, name):
+    import torch
+    O = oracle_lib
+    s, core, prev, g, gamma = _case(name, O)
+    v = I.charge_vectors(s, 3, seed=74)
+    q1_ref, r = K.charge_response(s, g, KT, gamma, v)
+    q0_ref = K.core_charges(s, g, r.rho)
+    p, mu, cm = _gpu(ctx, s, core, prev, gamma, 3)
+    assert abs(mu - r.mu) <= 1e-12
+    q0 = cm.core(p.rho_blocks).cpu().numpy()
+    assert np.abs(q0 - q0_ref).max() <= 1e-10
+    vd = torch.as_tensor(v, device="cuda")
+    for precision, tol in ((0, 1e-10), (1, 1e-6)):
+        q1, mu1 = cm.response(p.eigs, vd, precision)
+        q1 = q1.cpu().numpy()
+        err = (np.abs(q1 - q1_ref).max(), np.abs(mu1.cpu().numpy() - r.mu1).max())
+        _say(f"{name} charge response precision={precision}: |dq1| {err[0]:.2e} |dmu1| {err[1]:.2e}")
+        assert err[0] <= tol and err[1] <= tol
+        assert np.abs(q1.sum(axis=1)).max() <= 1e-10  # no net charge moves
+
+
+@pytest.mark.parametrize("name", ["config1", "water60", "chain900"])
+def test_preconditioner(ctx, oracle_lib, K, name):
+    O = oracle_lib
+    s, core, prev, g, gamma = _case(name, O)
+    r = O.solve(s, g, KT) if name != "chain900" else O.solve_pool(s, g, KT)
+    k0_ref, j_ref = K.preconditioner(s, g, KT, gamma, ALPHA, r.mu)
+    # three unit charges at a time: the blocks of up to eight core atoms take
+    # several passes of the response
+    p, mu, cm = _gpu(ctx, s, core, prev, gamma, 3)
+    k0 = cm.blocks(cm.preconditioner(p.eigs, ALPHA))
+    err = max(_rel(a, b) for a, b in zip(k0, k0_ref))
+    _say(f"{name} preconditioner: {len(k0)} blocks, max relative error {err:.2e}")
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("name,m", [("config1", 3), ("water60", 6), ("chain900", 3)])
+def test_krylov_kernel(ctx, oracle_lib, K, name, m):
+    import torch
+    O = oracle_lib
+    s, core, prev, g, gamma = _case(name, O)
+    r = O.solve(s, g, KT) if name != "chain900" else O.solve_pool(s, g, KT)
+    k0_ref, _ = K.preconditioner(s, g, KT, gamma, ALPHA, r.mu)
+    n = K.core_charges(s, g, r.rho) + I.charge_vectors(s, 1, seed=75)[0]
+    ref = K.krylov_kernel(s, g, KT, gamma, k0_ref, n, m, omega=1.3)
+    p, mu, cm = _gpu(ctx, s, core, prev, gamma, 1)
+    k0 = cm.preconditioner(p.eigs, ALPHA)
+    out = cm.krylov(p.eigs, k0, p.rho_blocks, torch.as_tensor(n, device="cuda"), m, omega=1.3)
+    assert not out["singular"]
+    errs = {k: _rel(out[k].cpu().numpy(), ref[k]) for k in ("V", "F", "O", "M", "ndd")}
+    _say(f"{name} krylov m={m}: " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    assert max(errs.values()) <= 1e-9, errs
+    V = out["V"].cpu().numpy()
+    assert np.abs(V @ V.T - np.eye(m)).max() <= 1e-12
+
+
+def test_krylov_split32(ctx, oracle_lib, K):
+    """The Krylov kernel with split-FP32 congruences stays within 1e-6 of the
+    FP64 oracle in the acceleration."""
+    import torch
+    O = oracle_lib
+    s, core, prev, g, gamma = _case("water60", O)
+    r = O.solve(s, g, KT)
+    k0_ref, _ = K.preconditioner(s, g, KT, gamma, ALPHA, r.mu)
+    n = K.core_charges(s, g, r.rho) + I.charge_vectors(s, 1, seed=75)[0]
+    ref = K.krylov_kernel(s, g, KT, gamma, k0_ref, n, 4, omega=1.0)
+    p, mu, cm = _gpu(ctx, s, core, prev, gamma, 1)
+    k0 = cm.preconditioner(p.eigs, ALPHA)
+    out = cm.krylov(p.eigs, k0, p.rho_blocks, torch.as_tensor(n, device="cuda"), 4,
+                    precision=1)
+    err = np.abs(out["ndd"].cpu().numpy() - ref["ndd"]).max()
+    _say(f"krylov split32: |dndd| {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_charge_errors(ctx):
+    import torch
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath
+    s = I.config_system(1)
+    core = I.single_atom_cores(s)
+    p = GraphPath(ctx, s, core, 1e-3, max_k=1)
+    gamma = I.coulomb_kernel(s)
+    bad = (gamma[0][:-1], gamma[1], gamma[2])
+    with pytest.raises(gq.GQError, match="n_atoms"):
+        gq.ChargeModel(ctx, p.graph, bad)
+    cm = gq.ChargeModel(ctx, p.graph, gamma, kmax=1)
+    v = torch.zeros((1, s.n_atoms), dtype=torch.float64, device="cuda")
+    with pytest.raises(gq.GQError, match="gq_density"):
+        cm.response(p.eigs, v)
+    p.ground_state(KT)
+    with pytest.raises(gq.GQError, match="K = 2"):
+        cm.response(p.eigs, torch.zeros((2, s.n_atoms), dtype=torch.float64, device="cuda"))
+    with pytest.raises(gq.GQError, match="rank"):
+        cm.krylov(p.eigs, torch.zeros(1, dtype=torch.float64, device="cuda"), p.rho_blocks,
+                  torch.zeros(s.n_atoms, dtype=torch.float64, device="cuda"), 33)
