@@ -438,6 +438,40 @@ def form_served(ctx, side, n_slots=4):
             "highest_rate_with_p99_under_1s": sustained["rate_req_per_s"]}
 
 
+def form_krylov(path, system, side):
+    """Sec. V at the step's workload: the subgraph preconditioner (unit
+    charges on every core atom, six per pass) and the preconditioned
+    low-rank Krylov kernel with m = 3 and 6 rank-1 updates per structure (m
+    sequential charge responses on the resident eigenbasis), FP64 and
+    split-FP32 congruences."""
+    import numpy as np
+    import torch
+    from paper_2212_01997_amd import gq, inputs as I
+    gamma = I.coulomb_kernel(system)
+    cm = gq.ChargeModel(path.ctx, path.graph, gamma, kmax=path.max_k)
+    path.ground_state(KT, want_mu=False)
+    k0 = cm.preconditioner(path.eigs, 0.2)
+    pre_ms = _time_steps(lambda: cm.preconditioner(path.eigs, 0.2), side, 3)
+    q0 = cm.core(path.rho_blocks)
+    n = q0 + torch.as_tensor(I.charge_vectors(system, 1, seed=3003)[0], device="cuda")
+    out = {"workload": "charge kernel gamma: screened Coulomb within 8 A "
+                       f"({len(gamma[1])} entries over {system.n_atoms} atoms); alpha 0.2; "
+                       "n = rho_0 + N(0, 0.05) per atom",
+           "preconditioner_ms": _dist(pre_ms),
+           "unit_charge_responses": int(system.n_atoms)}
+    for m in (3, 6):
+        row = {}
+        for name, prec in (("fp64", gq.PREC_FP64), ("split32", gq.PREC_SPLIT32)):
+            cm.krylov(path.eigs, k0, path.rho_blocks, n, m, precision=prec)
+            ms = _time_steps(lambda: cm.krylov(path.eigs, k0, path.rho_blocks, n, m,
+                                               precision=prec), side, 3)
+            row[name] = {**_dist(ms), "responses_per_s": m * 1000.0 / _pct(ms, 50)}
+        out[f"m{m}"] = row
+        log(f"krylov m={m}: fp64 {row['fp64']['median_ms']:.1f} ms, "
+            f"split32 {row['split32']['median_ms']:.1f} ms")
+    return out
+
+
 def config2_step(ctx, side, steps):
     """The 1,000-water FP64 step (ground state + one perturbation)."""
     import torch
@@ -683,6 +717,8 @@ def main():
         forms["batched"] = form_batched(path, graph, h1, side)
         log("mixed form at kT 0.003 and 0.03")
         forms["mixed_temperatures"] = form_mixed_temperatures(path, h1, side, gold, gold_ok)
+        log("preconditioner and Krylov kernel (Sec. V)")
+        forms["krylov"] = form_krylov(path, system, side)
         del path
         torch.cuda.empty_cache()
         log("1,000-water FP64 step")

@@ -65,6 +65,14 @@ typedef int32_t gq_status;
 /* response precision */
 #define GQ_PREC_FP64 0u       /* congruences in FP64 */
 #define GQ_PREC_SPLIT32 1u    /* split-FP32 congruences + one FP64 refinement */
+/* With GQ_PREC_SPLIT32, X = Q^T h1 Q is formed from the FP32 leading part of
+ * Q on FP32 MFMA (FP64 sums of 32-deep FP32 chunks); X o dF amplifies its
+ * rounding by dF, which is f'(eps) <= beta/4 for a pair of equal energies.
+ * Every pair of states whose f' exceeds tau_F, i.e. with
+ * |eps - mu| <= 2 acosh(sqrt(beta / (4 tau_F))) kT (none when
+ * beta/4 <= tau_F), is recomputed on FP64 MFMA; a subgraph with more than
+ * `cap` such states gets its whole X in FP64.  Defaults tau_F = 10 / Ha,
+ * cap = 128 (gq_ctx_set_split_window). */
 
 typedef struct gq_ctx gq_ctx;
 typedef struct gq_graph gq_graph;
@@ -418,6 +426,12 @@ gq_status gq_ctx_kernel_times(gq_ctx* ctx, const char** names, int64_t* launches
  * mu_inout, gq_response with mu1_host, gq_eigs_export) returns GQ_ENOCONV.
  * A small cap exercises that path from the host. */
 gq_status gq_ctx_set_iteration_cap(gq_ctx* ctx, int32_t leaf_iterations);
+
+/* Refinement window of the split-FP32 response on ctx: the divided-difference
+ * threshold tau_F > 0 (1/Ha) and the largest window refined by itself
+ * (cap >= 0; wider windows put the subgraph's X in FP64).  GQ_EINVAL
+ * otherwise. */
+gq_status gq_ctx_set_split_window(gq_ctx* ctx, double dF_threshold, int32_t max_states);
 
 /* Diagnostics (continued).
  * Copies eigenvalues eps[sum_n] (subgraph by subgraph, ascending) and core

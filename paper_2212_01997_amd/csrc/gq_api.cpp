@@ -925,6 +925,16 @@ gq_status gq_ctx_set_iteration_cap(gq_ctx* ctx, int32_t leaf_iterations) {
   return GQ_OK;
 }
 
+gq_status gq_ctx_set_split_window(gq_ctx* ctx, double dF_threshold, int32_t max_states) {
+  if (!ctx || !(dF_threshold > 0.0) || max_states < 0) {
+    set_error("gq_ctx_set_split_window: bad argument");
+    return GQ_EINVAL;
+  }
+  ctx->win_dF = dF_threshold;
+  ctx->win_cap = max_states;
+  return GQ_OK;
+}
+
 gq_status gq_ctx_set_profiling(gq_ctx* ctx, int32_t enable) {
   if (!ctx) {
     set_error("gq_ctx_set_profiling: NULL context");

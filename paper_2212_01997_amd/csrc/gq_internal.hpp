@@ -143,6 +143,10 @@ struct gq_ctx {
   bool profiling = false;
   bool capturing = false;
   int32_t leaf_iter_cap = 60;  // QL iterations per eigenvalue in the leaves
+  // split-FP32 response: states with f'(eps) above win_dF (1/Ha) are refined
+  // in FP64; windows above win_cap states put the subgraph's X in FP64
+  double win_dF = 10.0;
+  int32_t win_cap = 128;
   // optional device arena (gq_ctx_create with arena_bytes > 0): workspaces and
   // graph maps created on this context take pieces of it
   char* arena_mem = nullptr;

@@ -608,13 +608,19 @@ __global__ __launch_bounds__(kThreads) void k_split32(const double* __restrict__
     q32[i] = (float)q[i];
 }
 
-// The FP64 refinement window: the states with |eps - mu| <= kWinKT kT, all of
-// them.  Pairs inside a dense or degenerate level next to mu carry
-// dF = f'(eps), up to beta/4, and none of them is left in FP32.  A subgraph
-// whose window holds more than kWinCap states gets its whole X in FP64
+// The FP64 refinement window.  X o dF amplifies the FP32 rounding of X by dF,
+// which for a pair of states at the same energy eps is f'(eps) =
+// (beta/4) sech^2(beta (eps - mu)/2): pairs in a dense or degenerate level
+// next to mu carry up to beta/4.  Every state with f'(eps) > tau_F (tau_F per
+// context, gq_ctx_set_split_window) is in the window, i.e.
+// |eps - mu| <= w kT with w = 2 acosh(sqrt(beta / (4 tau_F))), and none when
+// beta/4 <= tau_F; all pairs of window states are recomputed in FP64.  A
+// subgraph whose window holds more than `cap` states gets its whole X in FP64
 // instead (refining a larger window would cost about as much as X itself).
-constexpr double kWinKT = 8.0;
-constexpr int kWinCap = 128;
+__device__ __forceinline__ double win_half_width(double kT, double tau_F) {
+  const double r = 1.0 / (4.0 * kT * tau_F);
+  return r > 1.0 ? 2.0 * acosh(sqrt(r)) * kT : -1.0;  // negative: no window
+}
 constexpr int kWinGroups = 4;  // workgroups per (subgraph, perturbation)
 
 // first index i in [0, n) with v[i] >= x (n if none)
@@ -636,18 +642,20 @@ __device__ __forceinline__ void win_range(const double* e, int n, double mu, dou
   while (hi < n && e[hi] <= mu + half) ++hi;
 }
 
-// wflag[s] = 1 when subgraph s's window exceeds kWinCap states (its X is then
+// wflag[s] = 1 when subgraph s's window exceeds win_cap states (its X is then
 // formed in FP64), else 0.
 __global__ __launch_bounds__(kThreads) void k_win_size(const double* __restrict__ eps,
                                                        const double* __restrict__ mu_state,
                                                        const int32_t* __restrict__ sub_orb_ptr,
-                                                       int n_sub, int32_t* __restrict__ wflag) {
+                                                       int n_sub, double win_dF, int win_cap,
+                                                       int32_t* __restrict__ wflag) {
   const int s = blockIdx.x * kThreads + threadIdx.x;
   if (s >= n_sub) return;
   const int b = sub_orb_ptr[s];
-  int lo, hi;
-  win_range(eps + b, sub_orb_ptr[s + 1] - b, mu_state[2], kWinKT * mu_state[3], lo, hi);
-  wflag[s] = hi - lo > kWinCap ? 1 : 0;
+  int lo = 0, hi = 0;
+  const double half = win_half_width(mu_state[3], win_dF);
+  if (half >= 0.0) win_range(eps + b, sub_orb_ptr[s + 1] - b, mu_state[2], half, lo, hi);
+  wflag[s] = hi - lo > win_cap ? 1 : 0;
 }
 
 // FP64 refinement of the thermal window: the dF weights are largest, up to
@@ -664,14 +672,16 @@ __global__ __launch_bounds__(kThreads) void k_win(
     const double* __restrict__ hloc, const double* __restrict__ wbuf,
     const double* __restrict__ eps, const double* __restrict__ mu_state,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr, int64_t sum_n2,
-    int64_t sum_n) {
+    int64_t sum_n, double win_dF, int win_cap) {
   const int s = blockIdx.x, q = blockIdx.y;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
+  const double half = win_half_width(mu_state[3], win_dF);
+  if (half < 0.0) return;
   int lo, hi;
-  win_range(eps + b, n, mu_state[2], kWinKT * mu_state[3], lo, hi);
+  win_range(eps + b, n, mu_state[2], half, lo, hi);
   // empty window, or X of this subgraph already in FP64
-  if (hi <= lo || hi - lo > kWinCap) return;
+  if (hi <= lo || hi - lo > win_cap) return;
   const int nb = (hi - lo + kTile - 1) / kTile;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double* dF = dfbuf + off2[s];
@@ -1220,11 +1230,14 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
   if (split) {
     // subgraphs whose window is too wide for the refinement get FP64 X
     hipLaunchKernelGGL(k_win_size, dim3((g->n_sub + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       st, e->eps, e->mu_state, dv.sub_orb_ptr, g->n_sub, e->wflag);
+                       st, e->eps, e->mu_state, dv.sub_orb_ptr, g->n_sub, ctx->win_dF,
+                       ctx->win_cap, e->wflag);
     for (int bin = 0; bin < kXyBins; ++bin)
       launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[1][bin], true, gen, K, 1);
+    // the FP64 pass serves the few subgraphs with wide windows: a persistent
+    // grid walks the tile list and skips the others cheaply
     for (int bin = 0; bin < kXyBins; ++bin)
-      launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[0][bin], false, gen, K, 2);
+      launch_xy_bin(ctx, g, e, rb, bin, (g->xy_choice[0][bin] & 1) | 2, false, gen, K, 2);
   } else {
     for (int bin = 0; bin < kXyBins; ++bin)
       launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[0][bin], false, gen, K);
@@ -1237,7 +1250,7 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
     hipLaunchKernelGGL(gen ? k_win<true> : k_win<false>, dim3(g->n_sub, K, kWinGroups),
                        dim3(kThreads), 0,
                        st, e->Q, e->A, ybuf, rb.hloc, rb.Y, e->eps, e->mu_state, dv.off2,
-                       dv.sub_orb_ptr, sum_n2, sum_n);
+                       dv.sub_orb_ptr, sum_n2, sum_n, ctx->win_dF, ctx->win_cap);
     prof_end(ctx);
   }
   prof_begin(ctx, "k_rows");

@@ -109,6 +109,7 @@ _SIGS = {
     "gq_server_destroy": ([_VP], None),
     "gq_ctx_set_profiling": ([_VP, C.c_int32], C.c_int32),
     "gq_ctx_set_iteration_cap": ([_VP, C.c_int32], C.c_int32),
+    "gq_ctx_set_split_window": ([_VP, C.c_double, C.c_int32], C.c_int32),
     "gq_ctx_kernel_times": ([_VP, _VP, _VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int32),
 }
 
@@ -189,6 +190,10 @@ class Context:
     def set_iteration_cap(self, leaf_iterations=60):
         """Diagnostics: QL iterations per eigenvalue allowed in the leaves."""
         _check(lib().gq_ctx_set_iteration_cap(self.h, int(leaf_iterations)))
+
+    def set_split_window(self, dF_threshold=10.0, max_states=128):
+        """Refinement window of the split-FP32 response (gq_ctx_set_split_window)."""
+        _check(lib().gq_ctx_set_split_window(self.h, float(dF_threshold), int(max_states)))
 
     def set_profiling(self, enable=True):
         _check(lib().gq_ctx_set_profiling(self.h, 1 if enable else 0))
