@@ -206,6 +206,27 @@ gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev
 gq_status gq_density(gq_ctx* ctx, gq_eigs* e, double kT, double n_elec, double* mu_inout,
                      double* rho_blocks_dev);
 
+/* ---------------------------------------------------------------- purify
+ * The zero-temperature density of every subgraph by recursive expansion
+ * (Sec. II.D, Eqs. (Step), (Recur), (dCollect)), on matrix products only,
+ * without an eigensolve: gathers h_i = H[orbs_i, orbs_i] from the device CSR
+ * H_dev, maps it to X_0 = I/2 - (h_i - mu I)/(2 R_i) with R_i the Gershgorin
+ * bound of |eig(h_i - mu I)|, and iterates X <- 3 X^2 - 2 X^3 (McWeeny),
+ * which sends the eigenvalues of h_i below mu to 1 and above mu to 0.  A
+ * subgraph stops once max |X_{k+1} - X_k| <= tol.  Writes the core rows
+ * 2 X_i[0:c_i, :] (2 Theta(mu - h_i), spin included, as gq_density) into
+ * rho_blocks_dev (device, nnz doubles, block layout).  mu (host) is given:
+ * the grand-canonical form, as in Eq. (Step).  1 <= max_iter; tol > 0.
+ * The workspace's eigenvectors and density are overwritten (a following
+ * gq_response needs gq_submatrix_solve and gq_density again).  Waits for the
+ * stream every fourth iteration to test convergence; not while capturing.
+ * iterations (host, may be NULL): the iterations run.  GQ_ENOCONV (the rows
+ * are still written) if a subgraph has not converged after max_iter, which
+ * happens when an eigenvalue of h_i lies at or very close to mu: the step
+ * function is then not defined or not reached at that precision. */
+gq_status gq_purify(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev, gq_eigs* e, double mu,
+                    int32_t max_iter, double tol, double* rho_blocks_dev, int32_t* iterations);
+
 /* ------------------------------------------------------------- response
  * K perturbations H1_q of the Hamiltonian, H(lambda) = H + lambda H1
  * (Sec. IV.A, Eq. (ddlambda)), each symmetric N x N, as

@@ -68,6 +68,7 @@ static gq_status graph_maps(const gq_graph* g, gq_graph_dev& d, Carve& c, bool u
   put(d.bt_toff, g->bt_toff);
   put(d.xy_tiles[0], g->xy_tiles[0]);
   put(d.xy_tiles[1], g->xy_tiles[1]);
+  put(d.tri_tiles, g->tri_tiles);
   d.n_leaves = (int32_t)(g->dc_leaves.size() / 4);  // both size classes
   return st;
 }

@@ -179,6 +179,7 @@ struct gq_graph_dev {
   int32_t n_leaves = 0;
   int32_t* bt_toff = nullptr;      // [n_sub] first compact-WY block of each subgraph
   int32_t* xy_tiles[2] = {nullptr, nullptr};  // X tiles (subgraph, ti, tj): 64x64, 32x32
+  int32_t* tri_tiles = nullptr;   // lower 64x64 tiles (subgraph, ti >= tj), by XCD range
 };
 
 struct gq_graph {
@@ -206,6 +207,10 @@ struct gq_graph {
   // response X tiles per shape (0: 64x64, 1: 32x32), binned by size, XCD ranges
   std::vector<int32_t> xy_tiles[2];
   gq::XcdSplit xy_split[2][gq::kXyBins];
+  // every lower-triangular 64x64 tile of every subgraph (batched products of
+  // symmetric results), cut into eight XCD ranges at subgraph boundaries
+  std::vector<int32_t> tri_tiles;
+  gq::XcdSplit tri_split;
   // launch variant per [precision][bin] (bit 0: 32x32 tiles, bit 1: persistent)
   mutable int8_t xy_choice[2][gq::kXyBins];
   gq_graph_info info{};
@@ -271,6 +276,15 @@ void prof_end(gq_ctx* ctx);
 // status is not NULL.
 void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status,
                    const char* label = "k_gather");
+// C = alpha A^T B + beta D + gamma I on every subgraph (n x n column-major at
+// off2): SYM for a symmetric result (A symmetric, commuting with B; lower
+// tiles computed and mirrored), else general.  Subgraphs with
+// conv[s] >= skip_level are skipped (B copied to C when copy_b); errbits
+// (SYM only) gets max |C - B| per subgraph.  conv and errbits may be NULL.
+template <bool SYM>
+void launch_bgemm(gq_ctx* ctx, const gq_graph* g, const double* A, const double* B,
+                  const double* D, double* C, double alpha, double beta, double gamma,
+                  const int32_t* conv, int skip_level, int copy_b, unsigned long long* errbits);
 void eig_set_attributes();
 void dc_set_attributes();
 void build_dc_plan(gq_graph* g);

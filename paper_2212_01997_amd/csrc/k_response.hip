@@ -31,6 +31,7 @@
 #include <mutex>
 
 #include "gq_internal.hpp"
+#include "tile_f64.hpp"
 
 namespace gq {
 
@@ -73,90 +74,6 @@ struct XyShape {
   static constexpr int kWB = TM / 32;
   static constexpr int kPer = kXK * TM / kNT;  // operand values per thread per chunk
 };
-
-// v_mfma_f64_4x4x4f64 on gfx950 (four blocks per instruction): lane l supplies
-// A_b(l%4, l/16) and B_b(l/16, l%4) of block b = (l/4)%4 and receives
-// D_b(l/16, l%4).  With the four blocks side by side along the columns, one
-// instruction yields a 4x16 strip: A (4 rows x 4 deep) is shared by the four
-// blocks, B is the 4 x 16 slice, and lane l holds row l/16, column l%16.
-__device__ __forceinline__ double mfma4b(double a, double b, double c) {
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
-
-// The TMxTM block X(k0.., l0..) of one subgraph (columns k >= kend or l >= lend
-// read as zero) on the four-block 4x4x4 FP64 MFMA.  Wave w owns rows [w TM/4, (w+1) TM/4) and
-// all TM columns: TM/16 x TM/16 independent accumulators, lane l holding row
-// w TM/4 + 4 r + l/16, column 16 c + l%16 in acc[r][c].  The K dimension is
-// staged through LDS in chunks of kXK rows, stored [m][column] with a row
-// stride of TM + 1 doubles: each group of 16 lanes then touches 16 distinct
-// 8-byte bank pairs in the staging writes (16 consecutive m) and in the B reads
-// (16 consecutive columns), and 4 broadcast addresses in the A reads.  h(m) is
-// applied to the B side while staging.
-//
-// In general the block is sum_m A(m, k) h(m) B(m, l) with A and B column-major
-// n x n: A = B = Q for a diagonal perturbation (H = true), or without h for
-// the general kind, where W = h1_s Q is formed as G^T Q (G = h1_s, symmetric)
-// and X as Q^T W.
-template <int TM, bool H>
-__device__ __forceinline__ void xy_block_4b(const double* __restrict__ Am,
-                                            const double* __restrict__ Bm,
-                                            const double* __restrict__ hl, int n, int k0, int l0,
-                                            int kend, int lend, double (&acc)[TM / 16][TM / 16]) {
-  constexpr int kXK = 16;  // FP64 K chunk: 16 rows keep four workgroups per CU
-  constexpr int kNT = 256, LD = TM + 1, R4 = TM / 16, C16 = TM / 16;
-  constexpr int kPer = kXK * TM / kNT;
-  __shared__ double As[kXK][LD];
-  __shared__ double Bs[kXK][LD];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int lq = lane & 3, lr = lane >> 4, l15 = lane & 15;
-  const int mm_t = tid & (kXK - 1), c_t = tid / kXK;
-  double pa[kPer], pb[kPer];
-  // out-of-range elements load a clamped (valid) address; the zeroing and the
-  // h factor are applied when the registers are written to LDS, after the
-  // MFMAs of the current chunk, so the loads stay in flight across them
-  double ph = 0.0;
-  auto fetch = [&](int m0) {
-    const int mc = min(m0 + mm_t, n - 1);
-    if constexpr (H) ph = hl[mc];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int c = c_t + u * (kNT / kXK);
-      pa[u] = Am[mc + (size_t)n * min(k0 + c, n - 1)];
-      pb[u] = Bm[mc + (size_t)n * min(l0 + c, n - 1)];
-    }
-  };
-#pragma unroll
-  for (int r = 0; r < R4; ++r)
-#pragma unroll
-    for (int c = 0; c < C16; ++c) acc[r][c] = 0.0;
-  fetch(0);
-  for (int m0 = 0; m0 < n; m0 += kXK) {
-    __syncthreads();
-    const bool okm = m0 + mm_t < n;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int c = c_t + u * (kNT / kXK);
-      As[mm_t][c] = (okm && k0 + c < kend) ? pa[u] : 0.0;
-      if constexpr (H) Bs[mm_t][c] = (okm && l0 + c < lend) ? ph * pb[u] : 0.0;
-      else Bs[mm_t][c] = (okm && l0 + c < lend) ? pb[u] : 0.0;
-    }
-    __syncthreads();
-    if (m0 + kXK < n) fetch(m0 + kXK);
-#pragma unroll
-    for (int ks = 0; ks < kXK / 4; ++ks) {
-      const int mm = 4 * ks + lr;
-      double a[R4], bb[C16];
-#pragma unroll
-      for (int r = 0; r < R4; ++r) a[r] = As[mm][w * (TM / 4) + 4 * r + lq];
-#pragma unroll
-      for (int c = 0; c < C16; ++c) bb[c] = Bs[mm][16 * c + l15];
-#pragma unroll
-      for (int r = 0; r < R4; ++r)
-#pragma unroll
-        for (int c = 0; c < C16; ++c) acc[r][c] = mfma4b(a[r], bb[c], acc[r][c]);
-    }
-  }
-}
 
 // The same TMxTM block for nq <= KQ perturbations at once: the Q columns are
 // staged once, and each perturbation's h(m) multiplies the B operand in
@@ -1140,6 +1057,28 @@ void build_xy_tiles(gq_graph* g) {
   }
   for (int p = 0; p < 2; ++p)
     for (int bin = 0; bin < kXyBins; ++bin) g->xy_choice[p][bin] = 0;
+  // every lower-triangular 64x64 tile (ti >= tj) of every subgraph, subgraphs
+  // in decreasing size, the tiles of a subgraph together on one XCD
+  std::vector<int32_t>& ft = g->tri_tiles;
+  ft.clear();
+  std::vector<int32_t> sub_start;
+  for (int32_t s : g->order) {
+    const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
+    const int32_t nt = (n + 63) / 64;
+    sub_start.push_back((int32_t)(ft.size() / 3));
+    for (int32_t ti = 0; ti < nt; ++ti)
+      for (int32_t tj = 0; tj <= ti; ++tj) ft.insert(ft.end(), {s, ti, tj});
+  }
+  const int64_t total = (int64_t)(ft.size() / 3);
+  size_t next = 0;
+  g->tri_split.off[0] = 0;
+  for (int x = 1; x < 8; ++x) {
+    const int64_t target = (total * x + 7) / 8;
+    while (next < sub_start.size() && sub_start[next] < target) ++next;
+    g->tri_split.off[x] = next < sub_start.size() ? sub_start[next] : (int32_t)total;
+    g->tri_split.off[x] = std::max(g->tri_split.off[x], g->tri_split.off[x - 1]);
+  }
+  g->tri_split.off[8] = (int32_t)total;
 }
 
 // ----------------------------------------------------- static scratch

@@ -79,6 +79,8 @@ _SIGS = {
     "gq_eigs_destroy": ([_VP], None),
     "gq_submatrix_solve": ([_VP, _VP, C.POINTER(_Csr), C.c_uint32, _VP], C.c_int32),
     "gq_density": ([_VP, _VP, C.c_double, C.c_double, _VP, _VP], C.c_int32),
+    "gq_purify": ([_VP, _VP, C.POINTER(_Csr), _VP, C.c_double, C.c_int32, C.c_double, _VP,
+                   C.POINTER(C.c_int32)], C.c_int32),
     "gq_response": ([_VP, _VP, _VP, C.c_uint32, C.c_int32, C.c_uint32, _VP, _VP, _VP],
                     C.c_int32),
     "gq_response_static": ([_VP, _VP, _VP, C.c_uint32, C.c_int32, C.c_uint32, _VP, _VP],
@@ -345,6 +347,16 @@ class Eigs:
         _check(lib().gq_density(self.ctx.h, self.h, float(kT), float(n_elec),
                                 C.byref(mu) if want_mu else None, _ptr(rho_blocks)))
         return mu.value if want_mu else None
+
+    def purify(self, H: DeviceCsr, mu, rho_blocks, max_iter=60, tol=1e-11):
+        """gq_purify: zero-temperature core rows 2 Theta(mu - h_i) by McWeeny
+        purification into rho_blocks; returns the iterations run.  Raises
+        GQError (GQ_ENOCONV) if a subgraph did not converge."""
+        s = H.cstruct()
+        it = C.c_int32(0)
+        _check(lib().gq_purify(self.ctx.h, self.graph.h, C.byref(s), self.h, float(mu),
+                               int(max_iter), float(tol), _ptr(rho_blocks), C.byref(it)))
+        return it.value
 
     def response(self, h1, p_blocks, precision=PREC_FP64, mu1_dev=None, want_mu1=True):
         """gq_response.  h1: a [K, N] device tensor of diagonals, or a list of

@@ -49,6 +49,14 @@ class GraphPath:
         gq.assemble(self.ctx, self.graph, self.rho_blocks, self.rho, 1)
         return mu
 
+    def purified_state(self, mu, max_iter=60, tol=1e-11):
+        """Zero-temperature density by recursive expansion (purify +
+        assemble(rho)) at the given mu; returns the iterations run.  The
+        eigenbasis is overwritten: ground_state again before a response."""
+        it = self.eigs.purify(self.H, mu, self.rho_blocks, max_iter=max_iter, tol=tol)
+        gq.assemble(self.ctx, self.graph, self.rho_blocks, self.rho, 1)
+        return it
+
     def respond(self, h1, precision=gq.PREC_FP64, want_mu1=True):
         """response + assemble(rho1) for K perturbations: a [K, N] tensor of
         diagonals or a list of K DeviceCsr matrices."""
