@@ -427,6 +427,26 @@ def h1_dense(system, k, seed, sigma=0.05):
     return out
 
 
+# ------------------------------------------------- overlap (non-orthogonal basis)
+def overlap_matrix(system, decay=0.6, min_eig=0.3):
+    """A synthetic overlap S for a non-orthogonal basis on the pattern of H:
+    unit diagonal, zero between distinct orbitals of one atom, and between
+    orbitals of atoms at distance r (< 4 A) a value t exp(-r/decay), with
+    t = (1 - min_eig) / (largest off-diagonal row sum), so that Gershgorin
+    bounds every eigenvalue of S (and of every principal submatrix) below by
+    min_eig: S is symmetric positive definite.  r is recovered from the hopping
+    -0.5 exp(-r/1.2) stored in H.  Returns a host CSR triple."""
+    n = system.n_orb
+    rows = np.repeat(np.arange(n), np.diff(system.h_row_ptr))
+    off = rows != system.h_col
+    v = np.zeros(len(system.h_col))
+    v[off] = (system.h_val[off] / HOP_PREFACTOR) ** (HOP_DECAY / decay)
+    t = (1.0 - min_eig) / np.bincount(rows, weights=v, minlength=n).max()
+    val = t * v
+    val[~off] = 1.0
+    return system.h_row_ptr.copy(), system.h_col.copy(), val
+
+
 # ------------------------------------------------- charge model (Sec. V)
 # A stand-in for the charge-dependent potential of SCC-DFTB: atomic charges n
 # act on every orbital of atom I through the potential (gamma n)_I, so the
