@@ -48,11 +48,17 @@ class Result:
 
 def solve(system, S, graph, kT, h1=None, n_elec=None) -> Result:
     """The whole path in a non-orthogonal basis.  S is a host CSR triple
-    (row_ptr, col, val); h1 a [K, N] array of atomic-orbital diagonals or None."""
+    (row_ptr, col, val); h1 the atomic-orbital perturbations: a [K, N] array of
+    diagonals, a list of K host CSR triples, or None."""
     H = O.Csr(system.h_row_ptr, system.h_col, system.h_val)
     Sc = O.Csr(*S)
-    h1 = np.zeros((0, system.n_orb)) if h1 is None else np.atleast_2d(h1)
-    K = h1.shape[0]
+    if h1 is None:
+        pert = []
+    elif isinstance(h1, np.ndarray):
+        pert = [O.Csr.diagonal(row) for row in np.atleast_2d(h1)]
+    else:
+        pert = [O.Csr(*m) for m in h1]
+    K = len(pert)
     ne = system.n_elec if n_elec is None else n_elec
     subs = []
     for s in range(graph.n_sub):
@@ -81,8 +87,9 @@ def solve(system, S, graph, kT, h1=None, n_elec=None) -> Result:
             for k in range(K):
                 # the orthogonalized perturbation fixes the trace (mu1); the
                 # same X = Q^T h1 Q = C^T h1_ao C gives the atomic-orbital rows
-                _, tlam[k, s] = O.lambda_response_rows(q, dF, z.T @ np.diag(h1[k, orbs]) @ z, c)
-                rows_ao, _ = O.lambda_response_rows(C, dF, np.diag(h1[k, orbs]), c)
+                h1_ao = O.gather(pert[k], orbs)
+                _, tlam[k, s] = O.lambda_response_rows(q, dF, z.T @ h1_ao @ z, c)
+                rows_ao, _ = O.lambda_response_rows(C, dF, h1_ao, c)
                 O.collect(graph, s, rows_ao, lam_ao[k])
     mu1 = np.array([O.mu1(tlam[k], tmu) for k in range(K)])
     rho1_ao = lam_ao + mu1[:, None] * mur_ao[None, :]

@@ -65,6 +65,18 @@ def test_identity_overlap_is_orthogonal_case(oracle_lib, V, small):
     assert np.abs(r.mu1 - ref.mu1).max() <= 1e-11
 
 
+def test_identity_overlap_general_perturbation(oracle_lib, V, small):
+    O = oracle_lib
+    s, g, _, _ = small
+    n = s.n_orb
+    eye = (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    h1 = I.h1_on_pattern(s, 2, seed=75)
+    r = V.solve(s, eye, g, KT, h1)
+    ref = O.solve(s, g, KT, h1)
+    assert np.abs(r.rho1_ao - ref.rho1).max() <= 1e-11
+    assert np.abs(r.mu1 - ref.mu1).max() <= 1e-11
+
+
 def test_lowdin_factor(oracle_lib, V, small):
     O = oracle_lib
     s, g, S, _ = small
@@ -120,3 +132,18 @@ def test_response_is_finite_difference(oracle_lib, V, small):
         q = {j: V.solve(_shift(s, h1[k], j * lam), S, g, KT).rho_ao for j in (-2, -1, 1, 2)}
         fd = (8 * (q[1] - q[-1]) - (q[2] - q[-2])) / (12 * lam)
         assert np.abs(fd - r.rho1_ao[k]).max() <= 1e-8
+
+
+def test_general_response_is_finite_difference(oracle_lib, V, small):
+    """A perturbation on the whole pattern of H (off-diagonal entries too)."""
+    s, g, S, _ = small
+    h1 = I.h1_on_pattern(s, 1, seed=76)
+    r = V.solve(s, S, g, KT, h1)
+    lam = 1e-4
+    q = {}
+    for j in (-2, -1, 1, 2):
+        sj = copy.copy(s)
+        sj.h_val = s.h_val + j * lam * h1[0][2]
+        q[j] = V.solve(sj, S, g, KT).rho_ao
+    fd = (8 * (q[1] - q[-1]) - (q[2] - q[-2])) / (12 * lam)
+    assert np.abs(fd - r.rho1_ao[0]).max() <= 1e-8
