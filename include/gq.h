@@ -15,9 +15,16 @@
  *   response         Sec. IV.A, Eqs. (D1_a), (D1_b), (ddlambda), (dddmu),
  *                    (dmu_1) (canonical first-order response in the eigenbasis)
  *   assemble         Eqs. (sub_f), (dCollect), (D1) (collect core rows)
+ *   purify           Sec. II.D, Eqs. (Step), (Recur) (zero-temperature density
+ *                    of every subgraph by purification, products only)
+ *   overlap          Sec. II.D, Eqs. (SmallKS), (ksSmall) (non-orthogonal basis:
+ *                    inverse factor of each overlap submatrix, congruences)
+ *   charges          Sec. V (charge response, subgraph preconditioner,
+ *                    preconditioned Krylov kernel)
  *
  * Conventions
- *   - Orthogonal basis; energies in Hartree.  Densities carry the closed-shell
+ *   - Orthogonal basis unless a workspace is solved with
+ *     gq_submatrix_solve_overlap; energies in Hartree.  Densities carry the closed-shell
  *     spin factor 2: Tr rho = N_e.  beta = 1/kT.
  *   - A "subgraph" i has n_i orbitals, of which the first c_i are its core.
  *   - "Blocks" are ragged per-subgraph arrays of c_i x n_i doubles, row-major,
@@ -159,10 +166,13 @@ void gq_graph_destroy(gq_graph* g);
  * perturbations per response call.  flags: GQ_EIGS_GENERAL_H1 also reserves
  * the buffer (max_k x sum n_i^2 doubles) that perturbations given as CSR
  * matrices need (GQ_H1_CSR); diagonal perturbations do not need it.
- * Allocates device memory, or takes a piece of the context's arena
+ * GQ_EIGS_OVERLAP reserves the non-orthogonal basis's inverse factors z_i
+ * and atomic-orbital eigenvectors C_i = z_i Q_i (2 sum n_i^2 doubles), needed
+ * by gq_submatrix_solve_overlap.  Allocates device memory, or takes a piece of the context's arena
  * (GQ_ENOMEM when neither is available); GQ_EINVAL for unknown flags, a
  * subgraph above 1024 orbitals or a core above 32 orbitals. */
 #define GQ_EIGS_GENERAL_H1 1u
+#define GQ_EIGS_OVERLAP 2u
 gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
                          gq_eigs** out);
 /* Device bytes held by an eigen workspace for graph g, max_k and flags, plus
@@ -187,6 +197,33 @@ void gq_eigs_destroy(gq_eigs* e);
  * if an eigensolve hit its iteration cap. */
 gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev,
                              uint32_t flags, gq_eigs* e);
+
+/* ------------------------------------------------ non-orthogonal basis
+ * The same for a non-orthogonal (atomic-orbital) basis with overlap matrix S
+ * (Sec. II.D, Eqs. (SmallKS), (ksSmall) and the atomic-orbital congruence
+ * after them): for every subgraph, s_i = S[orbs_i, orbs_i] is solved as
+ * s_i = U diag(sigma) U^T, z_i = s_i^(-1/2) = U diag(sigma^(-1/2)) U^T (the
+ * Lowdin inverse factor, z^T s z = I), h_ao = H[orbs_i, orbs_i] is carried to
+ * h_i = z_i h_ao z_i and solved as h_i = Q_i diag(eps_i) Q_i^T, and the
+ * atomic-orbital eigenvectors C_i = z_i Q_i are kept.  All products run on
+ * the batched FP64 MFMA kernel.  After this call, on this workspace:
+ *   gq_density fixes mu on the orthogonalized core weights (Eq. (DD)) and
+ *     writes the atomic-orbital core rows 2 C_c diag(f) C^T, the core rows of
+ *     z d z^T (its mu-response rows likewise);
+ *   gq_response and gq_response_static take h1 in the atomic-orbital basis
+ *     (X = C^T h1 C = Q^T z h1 z Q), fix mu1 on the orthogonalized traces, and
+ *     write the atomic-orbital response rows (the core rows of z d1 z^T),
+ *     FP64 only (GQ_PREC_SPLIT32: GQ_EINVAL);
+ *   the charge entry points return GQ_EINVAL.
+ * A later gq_submatrix_solve returns the workspace to the orthogonal case.
+ * S_dev: device CSR, N rows, symmetric, its pattern contained in the one
+ * given to graph_build.  Needs a workspace created with GQ_EIGS_OVERLAP.
+ * Waits for the stream once (after the overlap eigensolves): GQ_EINVAL if an
+ * s_i is not positive definite (the message names the subgraph and its
+ * smallest eigenvalue), GQ_ENOCONV if one of those eigensolves did not
+ * converge.  Not while capturing. */
+gq_status gq_submatrix_solve_overlap(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev,
+                                     const gq_csr* S_dev, uint32_t flags, gq_eigs* e);
 
 /* -------------------------------------------------------------- density
  * Shared chemical potential: the root of 2 sum_{i,k} w_ik f(eps_ik; mu) = n_elec

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libgq.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["gq_api.cpp", "gq_graph.cpp", "gq_server.cpp", "k_eig.hip", "k_dc.hip", "k_density.hip",
-           "k_response.hip", "k_charge.hip", "k_foe.hip"]
+           "k_response.hip", "k_charge.hip", "k_foe.hip",
+           "k_overlap.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -207,6 +207,8 @@ static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, uint32_t f
   x.wsc = c.take<double>(in.sum_n * 16);
   x.hloc = c.take<double>(kk * in.sum_n);
   x.G = (flags & GQ_EIGS_GENERAL_H1) ? c.take<double>(kk * in.sum_n2) : nullptr;
+  x.Z = (flags & GQ_EIGS_OVERLAP) ? c.take<double>(in.sum_n2) : nullptr;
+  x.C = (flags & GQ_EIGS_OVERLAP) ? c.take<double>(in.sum_n2) : nullptr;
   x.Q32 = c.take<float>(in.sum_n2);
   x.status = c.take<int32_t>(g->n_sub);
   x.wflag = c.take<int32_t>(g->n_sub);
@@ -398,7 +400,7 @@ static int64_t footprint(const gq_graph* g, int32_t max_k, uint32_t flags) {
 }
 
 gq_status gq_eigs_footprint(const gq_graph* g, int32_t max_k, uint32_t flags, int64_t* bytes) {
-  if (!g || !bytes || max_k < 0 || (flags & ~GQ_EIGS_GENERAL_H1)) {
+  if (!g || !bytes || max_k < 0 || (flags & ~(GQ_EIGS_GENERAL_H1 | GQ_EIGS_OVERLAP))) {
     set_error("gq_eigs_footprint: bad argument");
     return GQ_EINVAL;
   }
@@ -422,7 +424,7 @@ static gq_status eigs_check(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint3
     set_error("%s: bad argument", who);
     return GQ_EINVAL;
   }
-  if (flags & ~GQ_EIGS_GENERAL_H1) {
+  if (flags & ~(GQ_EIGS_GENERAL_H1 | GQ_EIGS_OVERLAP)) {
     set_error("%s: unknown flags 0x%x", who, flags);
     return GQ_EINVAL;
   }
@@ -528,6 +530,7 @@ gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev
   GQ_HIP(hipGetLastError());
   e->have_density = false;
   e->q32_valid = false;
+  e->overlap_solved = false;
   return GQ_OK;
 }
 
@@ -541,6 +544,60 @@ static gq_status check_status(gq_ctx* ctx, const gq_eigs* e) {
       set_error("eigensolver did not converge on subgraph %zu", i);
       return GQ_ENOCONV;
     }
+  return GQ_OK;
+}
+
+gq_status gq_submatrix_solve_overlap(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev,
+                                     const gq_csr* S_dev, uint32_t flags, gq_eigs* e) {
+  if (!ctx || !g || !H_dev || !S_dev || !e || e->g != g) {
+    set_error("gq_submatrix_solve_overlap: bad argument (workspace must belong to this graph)");
+    return GQ_EINVAL;
+  }
+  if (flags != GQ_SOLVE_DEFAULT) {
+    set_error("gq_submatrix_solve_overlap: unknown flags 0x%x", flags);
+    return GQ_EINVAL;
+  }
+  if (!e->Z) {
+    set_error("gq_submatrix_solve_overlap: the workspace was created without GQ_EIGS_OVERLAP");
+    return GQ_EINVAL;
+  }
+  for (const gq_csr* m : {H_dev, S_dev})
+    if (m->n_rows != g->N || !m->row_ptr || !m->col || !m->val) {
+      set_error("gq_submatrix_solve_overlap: %s has %d rows, graph has N = %d",
+                m == H_dev ? "H" : "S", m->n_rows, g->N);
+      return GQ_EINVAL;
+    }
+  if (ctx->capturing) {
+    set_error("gq_submatrix_solve_overlap: not available while capturing (it waits for the "
+              "stream to check the overlap)");
+    return GQ_EINVAL;
+  }
+  GQ_HIP(hipSetDevice(ctx->device));
+  e->have_density = false;
+  e->q32_valid = false;
+  e->overlap_solved = false;
+  // the overlap submatrices: eigenpairs, then their smallest eigenvalues
+  launch_gather(ctx, g, S_dev, e->A, e->status, "k_s_gather");
+  launch_eigensolve(ctx, g, e);
+  launch_overlap_min(ctx, g, e, e->tmu);
+  GQ_HIP(hipGetLastError());
+  gq_status rc = check_status(ctx, e);
+  if (rc != GQ_OK) return rc;
+  std::vector<double> smin(g->n_sub);
+  GQ_HIP(hipMemcpy(smin.data(), e->tmu, smin.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < g->n_sub; ++i)
+    if (!(smin[i] > 0.0)) {
+      set_error("gq_submatrix_solve_overlap: overlap submatrix of subgraph %d is not positive "
+                "definite (smallest eigenvalue %g)", i, smin[i]);
+      return GQ_EINVAL;
+    }
+  launch_overlap_factor(ctx, g, e);
+  launch_gather(ctx, g, H_dev, e->A, e->status);
+  launch_overlap_congruence(ctx, g, e);
+  launch_eigensolve(ctx, g, e);
+  launch_overlap_vectors(ctx, g, e);
+  GQ_HIP(hipGetLastError());
+  e->overlap_solved = true;
   return GQ_OK;
 }
 
@@ -600,6 +657,10 @@ static gq_status response_check(gq_ctx* ctx, gq_eigs* e, const void* h1, uint32_
   }
   if (precision != GQ_PREC_FP64 && precision != GQ_PREC_SPLIT32) {
     set_error("%s: precision %u not available", who, precision);
+    return GQ_EINVAL;
+  }
+  if (e->overlap_solved && precision != GQ_PREC_FP64) {
+    set_error("%s: a non-orthogonal basis takes FP64 congruences only", who);
     return GQ_EINVAL;
   }
   if (K < 1) {

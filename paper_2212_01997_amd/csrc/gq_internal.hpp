@@ -251,6 +251,9 @@ struct gq_eigs {
   double* wsc = nullptr;   // [sum_n * 16] panel scratch of the tridiagonalisation
   double* hloc = nullptr;  // [max_k][sum_n] perturbations gathered into subgraph order
   double* G = nullptr;     // [max_k][sum n^2] general perturbations (GQ_EIGS_GENERAL_H1 only)
+  double* Z = nullptr;     // [sum n^2] Lowdin factors s_i^(-1/2) (GQ_EIGS_OVERLAP only)
+  double* C = nullptr;     // [sum n^2] atomic-orbital eigenvectors z_i Q_i (GQ_EIGS_OVERLAP only)
+  bool overlap_solved = false;  // the last solve was gq_submatrix_solve_overlap
   float* Q32 = nullptr;    // [sum n^2] FP32 leading part of Q (split-FP32 congruences)
   bool q32_valid = false;  // Q32 matches the current Q
   bool have_density = false;
@@ -277,10 +280,17 @@ void prof_end(gq_ctx* ctx);
 void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status,
                    const char* label = "k_gather");
 // C = alpha A^T B + beta D + gamma I on every subgraph (n x n column-major at
-// off2): SYM for a symmetric result (A symmetric, commuting with B; lower
-// tiles computed and mirrored), else general.  Subgraphs with
+// off2): SYM when A^T B is symmetric (lower tiles computed and mirrored),
+// else general.  Subgraphs with
 // conv[s] >= skip_level are skipped (B copied to C when copy_b); errbits
 // (SYM only) gets max |C - B| per subgraph.  conv and errbits may be NULL.
+// Non-orthogonal basis: smallest eigenvalue per subgraph of the solved
+// overlap (into out[n_sub]); z = s^(-1/2) into Z from the eigenpairs in
+// (Q, eps); A = z A z; C = z Q.
+void launch_overlap_min(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* out);
+void launch_overlap_factor(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+void launch_overlap_congruence(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
+void launch_overlap_vectors(gq_ctx* ctx, const gq_graph* g, gq_eigs* e);
 template <bool SYM>
 void launch_bgemm(gq_ctx* ctx, const gq_graph* g, const double* A, const double* B,
                   const double* D, double* C, double alpha, double beta, double gamma,

@@ -439,6 +439,11 @@ gq_status check_ready(gq_ctx* ctx, gq_charge* c, gq_eigs* e, const char* who) {
     set_error("%s: call gq_density on this workspace first", who);
     return GQ_EINVAL;
   }
+  if (e->overlap_solved) {
+    set_error("%s: charges are defined for an orthogonal basis only (the workspace was "
+              "solved with an overlap)", who);
+    return GQ_EINVAL;
+  }
   return GQ_OK;
 }
 

@@ -375,7 +375,10 @@ void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_bloc
   hipStream_t st = ctx->stream;
   prof_begin(ctx, "k_density_rows");
   const int ncb = (g->info.max_n + kDC - 1) / kDC;
-  hipLaunchKernelGGL(k_density_rows, dim3(g->n_sub * ncb), dim3(kThreads), 0, st, e->Q, e->eps,
+  // in a non-orthogonal basis the rows are the atomic-orbital ones, from
+  // C = z Q; mu and tmu stay on the orthogonalized weights
+  const double* qrows = e->overlap_solved ? e->C : e->Q;
+  hipLaunchKernelGGL(k_density_rows, dim3(g->n_sub * ncb), dim3(kThreads), 0, st, qrows, e->eps,
                      e->wts, dv.off2, dv.offc, dv.sub_orb_ptr, dv.n_core, dv.order, e->mu_state,
                      rho_blocks, e->M, e->tmu, ncb);
   prof_end(ctx);

@@ -31,10 +31,10 @@ constexpr int kTM = 64;
 
 // C = alpha A^T B + beta D + gamma I per subgraph, all n x n column-major at
 // off2[s], over the lower tiles (ti >= tj) of every subgraph.
-//   SYM: the result is symmetric (A symmetric and commuting with B, so
-//        A^T B = A B = B A).  Each lower tile writes its block and the mirrored
-//        one (a diagonal tile its lower triangle and the mirror), so C is
-//        exactly symmetric and every element is written once.
+//   SYM: A^T B is symmetric (here: A symmetric and commuting with B, or
+//        A = B).  Each lower tile writes its block and the mirrored one (a
+//        diagonal tile its lower triangle and the mirror), so C is exactly
+//        symmetric and every element is written once.
 //   else: a general product; the workgroup of tile (ti, tj) also computes
 //        block (tj, ti).
 // conv (when given): subgraphs with conv[s] >= skip_level are skipped, and
@@ -228,6 +228,7 @@ extern "C" gq_status gq_purify(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_d
   int32_t* open = e->md_org;                                      // [1]
   e->have_density = false;
   e->q32_valid = false;
+  e->overlap_solved = false;
   launch_gather(ctx, g, H_dev, X[0], e->status, "k_gather");
   prof_begin(ctx, "k_purify");
   hipLaunchKernelGGL(k_purify_init, dim3(g->n_sub), dim3(kNT), 0, st, X[0], dv.off2,

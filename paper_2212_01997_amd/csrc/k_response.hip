@@ -977,7 +977,9 @@ int xy_resident_per_xcd(int shape, int variant) {
 // general kind (gen) takes one perturbation per workgroup, X = Q^T W with W in
 // rb.Y, written to rb.G.
 void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& rb, int bin,
-                   int choice, bool split, bool gen, int K, int mode = 0) {
+                   int choice, bool split, bool gen, int K, int mode = 0,
+                   const double* qx = nullptr) {
+  if (!qx) qx = e->Q;
   const int shape = choice & 1;
   const bool persistent = (choice & 2) != 0;
   const bool kq = K > 1 && !gen;
@@ -991,13 +993,13 @@ void launch_xy_bin(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs& r
   const gq_graph_dev& dv = g->dev;
   if (kq) {
     hipLaunchKernelGGL(xy_kq_kernel(shape, split), dim3(8 * per_xcd, (K + kXyKq - 1) / kXyKq),
-                       dim3(xy_threads(shape)), 0, ctx->stream, e->Q, e->Q32, e->A, rb.Y,
+                       dim3(xy_threads(shape)), 0, ctx->stream, qx, e->Q32, e->A, rb.Y,
                        rb.hloc, dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr, g->info.sum_n2,
                        g->info.sum_n, K, e->wflag, mode);
     return;
   }
   hipLaunchKernelGGL(xy_kernel(shape, split, gen), dim3(8 * per_xcd, K), dim3(xy_threads(shape)),
-                     0, ctx->stream, e->Q, e->Q32, e->A, gen ? rb.G : rb.Y, rb.hloc,
+                     0, ctx->stream, qx, e->Q32, e->A, gen ? rb.G : rb.Y, rb.hloc,
                      gen ? rb.Y : nullptr, dv.xy_tiles[shape], sp, dv.off2, dv.sub_orb_ptr,
                      g->info.sum_n2, g->info.sum_n, e->wflag, mode);
 }
@@ -1141,6 +1143,10 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
   const int sum_c = g->offcd[g->n_sub];
   const bool split = precision == GQ_PREC_SPLIT32;
   const bool gen = !opt.local_h1 && h1.kind == GQ_H1_CSR;
+  // non-orthogonal basis: X = C^T h1 C with C = z Q (h1 in the atomic-orbital
+  // basis); split precision is not offered there
+  const bool ao = e->overlap_solved;
+  const double* qx = ao ? e->C : e->Q;
   // a captured sequence must not depend on the host-side validity flag
   if (split && (!e->q32_valid || ctx->capturing)) {
     launch_split32(ctx, g, e);
@@ -1156,7 +1162,7 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
       int longest = 0;
       for (int x = 0; x < 8; ++x) longest = std::max(longest, sp[bin].off[x + 1] - sp[bin].off[x]);
       if (longest == 0) continue;
-      hipLaunchKernelGGL(k_wq, dim3(8 * longest, K), dim3(kThreads), 0, st, rb.G, e->Q, rb.Y,
+      hipLaunchKernelGGL(k_wq, dim3(8 * longest, K), dim3(kThreads), 0, st, rb.G, qx, rb.Y,
                          dv.xy_tiles[0], sp[bin], dv.off2, dv.sub_orb_ptr, sum_n2);
     }
     prof_end(ctx);
@@ -1179,7 +1185,7 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
       launch_xy_bin(ctx, g, e, rb, bin, (g->xy_choice[0][bin] & 1) | 2, false, gen, K, 2);
   } else {
     for (int bin = 0; bin < kXyBins; ++bin)
-      launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[0][bin], false, gen, K);
+      launch_xy_bin(ctx, g, e, rb, bin, g->xy_choice[0][bin], false, gen, K, 0, qx);
   }
   prof_end(ctx);
   // X o dF of perturbation q is in ybuf: Y for the diagonal kind, G for the general
@@ -1196,7 +1202,8 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
   dim3 grid_cols(g->n_sub, (g->info.max_n + kTC - 1) / kTC, K);
   hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, ybuf, rb.T, dv.off2,
                      dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
-  if (opt.charge_only) {
+  if (opt.charge_only || ao) {
+    // the orthogonalized core traces (the diagonal of P only) fix mu1
     hipLaunchKernelGGL(k_pdiag, dim3(g->n_sub, K), dim3(kThreads), 0, st, rb.T, e->Q, rb.pdiag,
                        dv.off2, dv.offcd, dv.sub_orb_ptr, dv.n_core, sum_n, sum_c);
     prof_end(ctx);
@@ -1204,17 +1211,23 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
     hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, rb.pdiag, sum_c, e->tmu, g->n_sub,
                        rb.mu1);
     prof_end(ctx);
-    return;
+    if (opt.charge_only) return;
+    // the atomic-orbital rows 2 C_c Y C^T (their diagonal overwrites pdiag,
+    // which k_mu1 has consumed)
+    prof_begin(ctx, "k_rows");
+    hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->C, ybuf, rb.T, dv.off2,
+                       dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
   }
   const int ncb = (g->info.max_n + kTC - 1) / kTC;
   const int groups_per_xcd = (g->n_sub * ncb + 7) / 8;
-  hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, rb.T, e->Q,
+  hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, rb.T, qx,
                      p_blocks, rb.pdiag, dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core,
                      dv.order, sum_n, nnz, sum_c, g->n_sub, ncb, K);
   prof_end(ctx);
   prof_begin(ctx, "k_mu1_combine");
-  hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, rb.pdiag, sum_c, e->tmu, g->n_sub,
-                     rb.mu1);
+  if (!ao)
+    hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, rb.pdiag, sum_c, e->tmu, g->n_sub,
+                       rb.mu1);
   const int blocks = (int)std::min<int64_t>(4096, (nnz + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_combine, dim3(blocks, K), dim3(kThreads), 0, st, p_blocks, e->M, rb.mu1,
                      nnz);

@@ -20,6 +20,7 @@ COMPLETE = 2
 PREC_FP64 = 0
 PREC_SPLIT32 = 1
 EIGS_GENERAL_H1 = 1
+EIGS_OVERLAP = 2
 H1_DIAG = 0
 H1_CSR = 1
 
@@ -78,6 +79,8 @@ _SIGS = {
     "gq_eigs_footprint": ([_VP, C.c_int32, C.c_uint32, C.POINTER(C.c_int64)], C.c_int32),
     "gq_eigs_destroy": ([_VP], None),
     "gq_submatrix_solve": ([_VP, _VP, C.POINTER(_Csr), C.c_uint32, _VP], C.c_int32),
+    "gq_submatrix_solve_overlap": ([_VP, _VP, C.POINTER(_Csr), C.POINTER(_Csr), C.c_uint32, _VP],
+                                   C.c_int32),
     "gq_density": ([_VP, _VP, C.c_double, C.c_double, _VP, _VP], C.c_int32),
     "gq_purify": ([_VP, _VP, C.POINTER(_Csr), _VP, C.c_double, C.c_int32, C.c_double, _VP,
                    C.POINTER(C.c_int32)], C.c_int32),
@@ -327,16 +330,24 @@ class DeviceCsr:
 class Eigs:
     """Device-resident eigen workspace of one graph (gq_eigs_create)."""
 
-    def __init__(self, ctx: Context, graph: Graph, max_k=1, general_h1=False):
+    def __init__(self, ctx: Context, graph: Graph, max_k=1, general_h1=False, overlap=False):
         self.ctx, self.graph, self.max_k = ctx, graph, max_k
         h = _VP()
-        _check(lib().gq_eigs_create(ctx.h, graph.h, int(max_k),
-                                    EIGS_GENERAL_H1 if general_h1 else 0, C.byref(h)))
+        flags = (EIGS_GENERAL_H1 if general_h1 else 0) | (EIGS_OVERLAP if overlap else 0)
+        _check(lib().gq_eigs_create(ctx.h, graph.h, int(max_k), flags, C.byref(h)))
         self.h = h
 
     def solve(self, H: DeviceCsr):
         s = H.cstruct()
         _check(lib().gq_submatrix_solve(self.ctx.h, self.graph.h, C.byref(s), 0, self.h))
+
+    def solve_overlap(self, H: DeviceCsr, S: DeviceCsr):
+        """gq_submatrix_solve_overlap: non-orthogonal basis with overlap S
+        (needs overlap=True); later densities and responses are in the
+        atomic-orbital basis."""
+        hs, ss = H.cstruct(), S.cstruct()
+        _check(lib().gq_submatrix_solve_overlap(self.ctx.h, self.graph.h, C.byref(hs),
+                                                C.byref(ss), 0, self.h))
 
     def density(self, kT, n_elec, rho_blocks=None, want_mu=True, mu_guess=None):
         """gq_density; mu_guess (or None) is the warm start.  Returns mu when

@@ -17,13 +17,16 @@ class GraphPath:
 
     def __init__(self, ctx: gq.Context, system, core_of_atom, tau, rho_prev=None, flags=0,
                  max_k=1, graph: gq.Graph | None = None, H: gq.DeviceCsr | None = None,
-                 general_h1=False):
+                 general_h1=False, S=None):
+        """S: an overlap matrix (host CSR triple) for a non-orthogonal basis, or
+        None; with it the densities and responses are atomic-orbital rows."""
         import torch
         self.ctx = ctx
         self.system = system
         self.graph = graph or gq.Graph.for_system(system, core_of_atom, tau, rho_prev, flags)
         self.H = H or gq.DeviceCsr(system.h_row_ptr, system.h_col, system.h_val, ctx.device)
-        self.eigs = gq.Eigs(ctx, self.graph, max_k, general_h1=general_h1)
+        self.S = None if S is None else gq.DeviceCsr(*S, device=ctx.device)
+        self.eigs = gq.Eigs(ctx, self.graph, max_k, general_h1=general_h1, overlap=S is not None)
         nnz = self.graph.info.nnz
         dev = torch.device("cuda", ctx.device)
         self.max_k = max_k
@@ -44,7 +47,10 @@ class GraphPath:
         """submatrix_solve + density (warm-started from mu_guess, if given) +
         assemble(rho)."""
         ne = self.system.n_elec if n_elec is None else n_elec
-        self.eigs.solve(self.H)
+        if self.S is None:
+            self.eigs.solve(self.H)
+        else:
+            self.eigs.solve_overlap(self.H, self.S)
         mu = self.eigs.density(kT, ne, self.rho_blocks, want_mu=want_mu, mu_guess=mu_guess)
         gq.assemble(self.ctx, self.graph, self.rho_blocks, self.rho, 1)
         return mu
