@@ -509,6 +509,37 @@ def form_purify(path, side, sizes):
                         "frac": achieved / PEAK_FP64}}
 
 
+def form_overlap(ctx, system, core, graph, h1, side):
+    """The non-orthogonal basis at the step's workload (synthetic overlap on
+    the pattern of H): overlap eigensolves, Lowdin factors, h = z h_ao z, the
+    eigensolve, C = z Q, atomic-orbital density rows, then K = 6 FP64
+    atomic-orbital responses; beside the orthogonal FP64 ground state."""
+    import numpy as np
+    from paper_2212_01997_amd import gq, inputs as I
+    from paper_2212_01997_amd.path import GraphPath
+    p = GraphPath(ctx, system, core, TAU, graph=graph, max_k=K_H1, S=I.overlap_matrix(system))
+    p.ground_state(KT, want_mu=False)
+    ground = _time_steps(lambda: p.ground_state(KT, want_mu=False), side, 3)
+    p.respond(h1, precision=gq.PREC_FP64, want_mu1=False)
+    resp = _time_steps(lambda: p.respond(h1, precision=gq.PREC_FP64, want_mu1=False), side, 3)
+    ctx.set_profiling(True)
+    p.ground_state(KT, want_mu=False)
+    kt = ctx.kernel_times()
+    ctx.set_profiling(False)
+    sizes = np.diff(graph.export()["sub_orb_ptr"]).astype(float)
+    # the four products of one solve: z (symmetric), h_ao z (general),
+    # z (h_ao z) (symmetric), z Q (general)
+    flops = (2.0 * (sizes ** 3 + sizes ** 2) + 2.0 * 2.0 * sizes ** 3).sum()
+    gemm_ms = kt["k_bgemm"][1]
+    log(f"overlap: ground state {_pct(ground, 50):.1f} ms, K = 6 responses {_pct(resp, 50):.1f} ms")
+    del p
+    return {"ground_state_ms": _dist(ground), "response_ms_K6": _dist(resp),
+            "k_bgemm": {"ms_per_solve": gemm_ms, "launches": kt["k_bgemm"][0],
+                        "flops": flops, "achieved": flops / (gemm_ms * 1e-3) / 1e12,
+                        "frac": flops / (gemm_ms * 1e-3) / PEAK_FP64},
+            "k_transpose_scale_ms": kt.get("k_transpose_scale", (0, 0.0))[1]}
+
+
 def config2_step(ctx, side, steps):
     """The 1,000-water FP64 step (ground state + one perturbation)."""
     import torch
@@ -759,6 +790,9 @@ def main():
         log("zero-temperature density by purification (Sec. II.D)")
         forms["purify"] = form_purify(path, side, sizes)
         del path
+        torch.cuda.empty_cache()
+        log("non-orthogonal basis")
+        forms["overlap"] = form_overlap(ctx, system, core, graph, h1, side)
         torch.cuda.empty_cache()
         log("1,000-water FP64 step")
         forms["config2_fp64_step"] = config2_step(ctx, side, args.steps)
