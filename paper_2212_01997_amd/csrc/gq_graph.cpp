@@ -10,6 +10,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -26,6 +29,68 @@ int build_threads() {
   return (int)std::min(16u, std::max(1u, hc));
 }
 
+// A pool of host worker threads kept for the life of the process, so that the
+// dozen parallel phases of a graph build do not each start and join threads.
+// One job at a time: a caller that finds the pool busy (graph builds on
+// several threads at once, as in the serving runtime) runs its job with
+// threads of its own instead.  Never destroyed: the workers wait on a
+// condition variable and end with the process.
+class BuildPool {
+ public:
+  static BuildPool& get() {
+    static BuildPool* p = new BuildPool;
+    return *p;
+  }
+  // work(tid) for tid in [0, nt), tid 0 on the calling thread; false (nothing
+  // run) if another job holds the pool
+  bool run(int nt, const std::function<void(int)>& work) {
+    std::unique_lock<std::mutex> own(run_mu_, std::try_to_lock);
+    if (!own.owns_lock()) return false;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      while ((int)workers_ < nt - 1) {
+        const int id = ++workers_;
+        std::thread([this, id] { loop(id); }).detach();
+      }
+      job_ = &work;
+      want_ = nt - 1;
+      done_ = 0;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work(0);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return done_ == want_; });
+    job_ = nullptr;
+    return true;
+  }
+
+ private:
+  void loop(int id) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int)>* job;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_ != seen && id <= want_; });
+        seen = gen_;
+        job = job_;
+      }
+      (*job)(id);
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        ++done_;
+      }
+      done_cv_.notify_one();
+    }
+  }
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* job_ = nullptr;
+  int workers_ = 0, want_ = 0, done_ = 0;
+  uint64_t gen_ = 0;
+};
+
 // fn(tid, i) for i in [0, n), items dealt in blocks of `grain` from a shared
 // counter; tid in [0, threads) names the calling thread's scratch.
 template <class F>
@@ -35,7 +100,7 @@ void parallel_for(int64_t n, int64_t grain, int threads, F&& fn) {
     return;
   }
   std::atomic<int64_t> next{0};
-  auto work = [&](int tid) {
+  const std::function<void(int)> work = [&](int tid) {
     for (;;) {
       const int64_t b = next.fetch_add(grain);
       if (b >= n) break;
@@ -43,28 +108,25 @@ void parallel_for(int64_t n, int64_t grain, int threads, F&& fn) {
       for (int64_t i = b; i < e; ++i) fn(tid, i);
     }
   };
-  std::vector<std::thread> pool;
   const int nt = (int)std::min<int64_t>(threads, (n + grain - 1) / grain);
+  if (BuildPool::get().run(nt, work)) return;
+  std::vector<std::thread> pool;
   for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
   work(0);
   for (auto& t : pool) t.join();
 }
 
-// first row for which bad(row) holds, or -1
-template <class F>
-int32_t first_bad_row(int32_t n, int threads, F&& bad) {
-  std::atomic<int32_t> first{INT32_MAX};
-  parallel_for(n, 512, threads, [&](int, int64_t a) {
-    if (a < first.load(std::memory_order_relaxed) && bad((int32_t)a)) {
-      int32_t cur = first.load();
-      while (a < cur && !first.compare_exchange_weak(cur, (int32_t)a)) {
-      }
-    }
-  });
-  return first.load() == INT32_MAX ? -1 : first.load();
-}
-
-gq_status check_csr(const gq_csr* X, int32_t n, const char* name, int threads) {
+// Structure checks of a host CSR matrix of n rows in one parallel pass: the
+// first row where row_ptr decreases, the first row with columns out of range
+// or not ascending, and (symmetric) the first row holding an entry (a, b)
+// whose mirror (b, a) is missing.  They are reported in that order, so each
+// is the first such row of a matrix that passed the checks before it.  Every
+// read is bounds-checked first: a row whose range lies outside [0, nnz] (only
+// possible where row_ptr decreases elsewhere) is not read, and another row's
+// search does not enter it.  The mirror search keeps one cursor per row b and
+// thread: a thread takes its rows a in ascending order, so the a it looks for
+// in row b only grow and each cursor only moves forward.
+gq_status check_csr(const gq_csr* X, int32_t n, const char* name, bool symmetric, int threads) {
   if (!X || X->n_rows != n || !X->row_ptr || (X->nnz > 0 && (!X->col || !X->val))) {
     set_error("%s: CSR header does not match N = %d", name, n);
     return GQ_EINVAL;
@@ -73,38 +135,62 @@ gq_status check_csr(const gq_csr* X, int32_t n, const char* name, int threads) {
     set_error("%s: row_ptr must run from 0 to nnz", name);
     return GQ_EINVAL;
   }
-  const int32_t bad_ptr = first_bad_row(n, threads, [&](int32_t a) {
-    return X->row_ptr[a + 1] < X->row_ptr[a];
+  const int32_t* rp = X->row_ptr;
+  const int32_t* col = X->col;
+  const int32_t nnz = X->nnz;
+  auto readable = [&](int32_t a) { return rp[a] >= 0 && rp[a] <= rp[a + 1] && rp[a + 1] <= nnz; };
+  std::atomic<int32_t> bad_ptr{INT32_MAX}, bad_col{INT32_MAX}, bad_sym{INT32_MAX};
+  auto lower = [](std::atomic<int32_t>& f, int32_t a) {
+    int32_t cur = f.load();
+    while (a < cur && !f.compare_exchange_weak(cur, a)) {
+    }
+  };
+  std::vector<std::vector<int32_t>> cursor(symmetric ? threads : 0);
+  parallel_for(n, 512, threads, [&](int tid, int64_t ai) {
+    const int32_t a = (int32_t)ai;
+    if (rp[a + 1] < rp[a]) {
+      lower(bad_ptr, a);
+      return;
+    }
+    if (!readable(a)) return;
+    for (int32_t p = rp[a]; p < rp[a + 1]; ++p) {
+      const int32_t c = col[p];
+      if (c < 0 || c >= n || (p > rp[a] && c <= col[p - 1])) {
+        lower(bad_col, a);
+        return;
+      }
+    }
+    if (!symmetric) return;
+    std::vector<int32_t>& cu = cursor[tid];
+    if (cu.empty()) cu.assign(rp, rp + n);
+    for (int32_t p = rp[a]; p < rp[a + 1]; ++p) {
+      const int32_t c = col[p];
+      if (!readable(c)) {
+        lower(bad_sym, a);
+        return;
+      }
+      int32_t q = std::max(cu[c], rp[c]);
+      while (q < rp[c + 1] && col[q] < a) ++q;
+      cu[c] = q;
+      if (q == rp[c + 1] || col[q] != a) {
+        lower(bad_sym, a);
+        return;
+      }
+    }
   });
-  if (bad_ptr >= 0) {
-    set_error("%s: row_ptr decreases at row %d", name, bad_ptr);
+  if (bad_ptr.load() != INT32_MAX) {
+    set_error("%s: row_ptr decreases at row %d", name, bad_ptr.load());
     return GQ_EINVAL;
   }
-  const int32_t bad_col = first_bad_row(n, threads, [&](int32_t a) {
-    const int32_t b0 = X->row_ptr[a], b1 = X->row_ptr[a + 1];
-    for (int32_t p = b0; p < b1; ++p) {
-      const int32_t c = X->col[p];
-      if (c < 0 || c >= n || (p > b0 && c <= X->col[p - 1])) return true;
-    }
-    return false;
-  });
-  if (bad_col >= 0) {
-    set_error("%s: row %d has columns out of range or not ascending", name, bad_col);
+  if (bad_col.load() != INT32_MAX) {
+    set_error("%s: row %d has columns out of range or not ascending", name, bad_col.load());
+    return GQ_EINVAL;
+  }
+  if (bad_sym.load() != INT32_MAX) {
+    set_error("graph_build: the pattern of %s is not symmetric", name);
     return GQ_EINVAL;
   }
   return GQ_OK;
-}
-
-bool pattern_symmetric(const gq_csr* X, int threads) {
-  return first_bad_row(X->n_rows, threads, [&](int32_t a) {
-           for (int32_t p = X->row_ptr[a]; p < X->row_ptr[a + 1]; ++p) {
-             const int32_t b = X->col[p];
-             const int32_t* first = X->col + X->row_ptr[b];
-             const int32_t* last = X->col + X->row_ptr[b + 1];
-             if (!std::binary_search(first, last, a)) return true;
-           }
-           return false;
-         }) < 0;
 }
 
 }  // namespace
@@ -132,13 +218,9 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   }
   const int32_t N = atom_orb_ptr[n_atoms];
   const int threads = build_threads();
-  if (gq_status st = check_csr(H, N, "H", threads)) return st;
+  if (gq_status st = check_csr(H, N, "H", true, threads)) return st;
   if (rho_prev)
-    if (gq_status st = check_csr(rho_prev, N, "rho_prev", threads)) return st;
-  if (!pattern_symmetric(H, threads)) {
-    set_error("graph_build: the pattern of H is not symmetric");
-    return GQ_EINVAL;
-  }
+    if (gq_status st = check_csr(rho_prev, N, "rho_prev", false, threads)) return st;
 
   int32_t n_sub = 0;
   for (int32_t I = 0; I < n_atoms; ++I) {
@@ -284,24 +366,41 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   }
   halos.clear();
 
-  // orbital maps
+  // orbital maps: counts per subgraph, offsets, then the lists in parallel
   g->sub_orb_ptr.assign(n_sub + 1, 0);
   g->n_core_orbs.resize(n_sub);
-  g->sub_orbs.clear();
-  for (int32_t s = 0; s < n_sub; ++s) {
+  std::vector<int64_t> norb(n_sub);
+  parallel_for(n_sub, 64, threads, [&](int, int64_t si) {
+    const int32_t s = (int32_t)si;
+    int64_t n = 0;
     int32_t c = 0;
     for (int32_t q = g->sub_ptr[s]; q < g->sub_ptr[s + 1]; ++q) {
       const int32_t I = g->sub_atoms[q];
-      for (int32_t a = atom_orb_ptr[I]; a < atom_orb_ptr[I + 1]; ++a) g->sub_orbs.push_back(a);
-      if (q - g->sub_ptr[s] < g->n_core_atoms[s]) c += atom_orb_ptr[I + 1] - atom_orb_ptr[I];
+      const int32_t k = atom_orb_ptr[I + 1] - atom_orb_ptr[I];
+      n += k;
+      if (q - g->sub_ptr[s] < g->n_core_atoms[s]) c += k;
     }
-    if (g->sub_orbs.size() > (size_t)INT32_MAX) {
+    norb[s] = n;
+    g->n_core_orbs[s] = c;
+  });
+  int64_t tot = 0;
+  for (int32_t s = 0; s < n_sub; ++s) {
+    tot += norb[s];
+    if (tot > INT32_MAX) {
       set_error("graph_build: orbital lists exceed int32");
       return GQ_ENOMEM;
     }
-    g->n_core_orbs[s] = c;
-    g->sub_orb_ptr[s + 1] = (int32_t)g->sub_orbs.size();
+    g->sub_orb_ptr[s + 1] = (int32_t)tot;
   }
+  g->sub_orbs.resize(tot);
+  parallel_for(n_sub, 64, threads, [&](int, int64_t si) {
+    const int32_t s = (int32_t)si;
+    int32_t* out = g->sub_orbs.data() + g->sub_orb_ptr[s];
+    for (int32_t q = g->sub_ptr[s]; q < g->sub_ptr[s + 1]; ++q) {
+      const int32_t I = g->sub_atoms[q];
+      for (int32_t a = atom_orb_ptr[I]; a < atom_orb_ptr[I + 1]; ++a) *out++ = a;
+    }
+  });
 
   // sorted orbital lists, their local indices, and the column slot of every local orbital
   const size_t sum_n = g->sub_orbs.size();
