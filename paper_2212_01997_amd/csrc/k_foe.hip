@@ -18,6 +18,7 @@
 //   k_purify_check  convergence flags from max |X_{k+1} - X_k| per subgraph
 //   k_purify_rows   2 X[0:c, :] into the core-row blocks
 #include <algorithm>
+#include <type_traits>
 
 #include "gq_internal.hpp"
 #include "tile_f64.hpp"
@@ -65,17 +66,17 @@ __global__ __launch_bounds__(kNT, 4) void k_bgemm(
         }
       continue;
     }
-    const int passes = (!SYM && ti != tj) ? 2 : 1;
-    for (int pass = 0; pass < passes; ++pass) {
-      const int k0 = (pass ? tj : ti) * kTM, l0 = (pass ? ti : tj) * kTM;
-      double acc[4][4];
-      xy_block_4b<kTM, false>(A + o, B + o, nullptr, n, k0, l0, n, n, acc);
+    // one block: C(k, l) = alpha acc + beta D + gamma delta_kl for the rows of
+    // the product's mode (DG: the diagonal mode, blocks c > r not formed)
+    auto put = [&](auto dg, const double (&acc)[4][4], int k0, int l0) {
+      constexpr bool DG = decltype(dg)::value;
       double emax = 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const int k = k0 + w * 16 + 4 * r + (lane >> 4);
+          if (DG && c > r) continue;
+          const int k = k0 + xy_row<kTM, DG>(r, w) + (lane >> 4);
           const int l = l0 + 16 * c + (lane & 15);
           if (k < n && l < n && (!SYM || ti != tj || k >= l)) {
             const size_t at = o + k + (size_t)n * l;
@@ -94,6 +95,20 @@ __global__ __launch_bounds__(kNT, 4) void k_bgemm(
         for (int o2 = 32; o2 > 0; o2 >>= 1) emax = fmax(emax, __shfl_xor(emax, o2, 64));
         if (lane == 0) atomicMax(errbits + s, (unsigned long long)__double_as_longlong(emax));
       }
+    };
+    if (SYM && ti == tj) {
+      // a diagonal tile of a symmetric result: its lower triangle only
+      double acc[4][4];
+      xy_block_4b<kTM, false, true>(A + o, B + o, nullptr, n, ti * kTM, tj * kTM, n, n, acc);
+      put(std::true_type{}, acc, ti * kTM, tj * kTM);
+      continue;
+    }
+    const int passes = (!SYM && ti != tj) ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int k0 = (pass ? tj : ti) * kTM, l0 = (pass ? ti : tj) * kTM;
+      double acc[4][4];
+      xy_block_4b<kTM, false>(A + o, B + o, nullptr, n, k0, l0, n, n, acc);
+      put(std::false_type{}, acc, k0, l0);
     }
   }
 }

@@ -79,7 +79,7 @@ struct XyShape {
 // staged once, and each perturbation's h(m) multiplies the B operand in
 // registers (the same double product h(m) Q(m, l) as in xy_block_4b, so each
 // perturbation's block is bit for bit what xy_block_4b gives).
-template <int TM, int KQ>
+template <int TM, int KQ, bool DIAG = false>
 __device__ __forceinline__ void xy_block_4b_kq(const double* __restrict__ Q,
                                                const double* __restrict__ hl, int64_t hstride,
                                                int nq, int n, int k0, int l0,
@@ -129,7 +129,7 @@ __device__ __forceinline__ void xy_block_4b_kq(const double* __restrict__ Q,
       const int mm = 4 * ks + lr;
       double a[R4], braw[C16];
 #pragma unroll
-      for (int r = 0; r < R4; ++r) a[r] = As[mm][w * (TM / 4) + 4 * r + lq];
+      for (int r = 0; r < R4; ++r) a[r] = As[mm][xy_row<TM, DIAG>(r, w) + lq];
 #pragma unroll
       for (int c = 0; c < C16; ++c) braw[c] = Bs[mm][16 * c + l15];
 #pragma unroll
@@ -141,7 +141,8 @@ __device__ __forceinline__ void xy_block_4b_kq(const double* __restrict__ Q,
 #pragma unroll
         for (int r = 0; r < R4; ++r)
 #pragma unroll
-          for (int c = 0; c < C16; ++c) acc[q][r][c] = mfma4b(a[r], bb[c], acc[q][r][c]);
+          for (int c = 0; c < C16; ++c)
+            if (!DIAG || c <= r) acc[q][r][c] = mfma4b(a[r], bb[c], acc[q][r][c]);
       }
     }
   }
@@ -326,6 +327,49 @@ __device__ __forceinline__ void xy_block_f32_kq(
 // Workgroup b serves XCD b % 8 and walks that XCD's range of the list with
 // stride gridDim.x / 8 (one tile per workgroup, or persistent).  GEN: the
 // general kind, X = Q^T W with W = h1_s Q of perturbation q in wbuf.
+// Stores of an FP64 X tile times dF into Y (element (k, l) at l + n k).
+// mirror: the tile lies in a diagonal 64x64 tile, whose upper triangle is
+// written from its lower one: elements with k < l are dropped and those with
+// k > l are also stored at (l, k), with dF(l, k).  DIAG: acc was formed in the
+// diagonal mode of xy_block_4b (rows by xy_row; blocks c > r not formed).
+// The dF values (and, with mirror, their mirrors) are loaded first, once per
+// tile, from clamped addresses.
+template <int TM, bool DIAG>
+struct XyDf {
+  double v[TM / 16][TM / 16], m[TM / 16][TM / 16];
+  __device__ __forceinline__ void load(const double* __restrict__ dF, int n, int k0, int l0,
+                                       int w, int lane, bool mirror) {
+#pragma unroll
+    for (int r = 0; r < TM / 16; ++r)
+#pragma unroll
+      for (int c = 0; c < TM / 16; ++c) {
+        const int k = min(k0 + xy_row<TM, DIAG>(r, w) + (lane >> 4), n - 1);
+        const int l = min(l0 + 16 * c + (lane & 15), n - 1);
+        v[r][c] = dF[(size_t)l + (size_t)n * k];
+        m[r][c] = mirror ? dF[(size_t)k + (size_t)n * l] : 0.0;
+      }
+  }
+  __device__ __forceinline__ void store(const double (&acc)[TM / 16][TM / 16],
+                                        double* __restrict__ Y, int n, int k0, int l0, int w,
+                                        int lane, bool mirror) const {
+#pragma unroll
+    for (int r = 0; r < TM / 16; ++r)
+#pragma unroll
+      for (int c = 0; c < TM / 16; ++c) {
+        if (DIAG && c > r) continue;
+        const int k = k0 + xy_row<TM, DIAG>(r, w) + (lane >> 4);
+        const int l = l0 + 16 * c + (lane & 15);
+        if (k >= n || l >= n) continue;
+        if (!mirror) {
+          Y[(size_t)l + (size_t)n * k] = acc[r][c] * v[r][c];
+        } else if (k >= l) {
+          Y[(size_t)l + (size_t)n * k] = acc[r][c] * v[r][c];
+          if (k > l) Y[(size_t)k + (size_t)n * l] = acc[r][c] * m[r][c];
+        }
+      }
+  }
+};
+
 template <int TM, bool SPLIT, bool GEN>
 __global__ __launch_bounds__(256, 4) void k_xy(
     const double* __restrict__ qbuf, const float* __restrict__ q32,
@@ -377,26 +421,25 @@ __global__ __launch_bounds__(256, 4) void k_xy(
             if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[x][y][r] * dfv[x][y][r];
           }
     } else {
+      // FP64: inside a diagonal 64x64 tile only the lower triangle is formed
+      // and each element is also stored at its mirror (X is symmetric); the
+      // upper 32x32 tile of a diagonal 64x64 tile is therefore skipped
+      const bool mirror = k0 / kTile == l0 / kTile;
+      if (mirror && ti < tj) continue;
       double acc[TM / 16][TM / 16];
-      if constexpr (GEN) xy_block_4b<TM, false>(qbuf + off2[s], W, hl, n, k0, l0, n, n, acc);
-      else xy_block_4b<TM, true>(qbuf + off2[s], qbuf + off2[s], hl, n, k0, l0, n, n, acc);
-      double dfv[TM / 16][TM / 16];
-#pragma unroll
-      for (int r = 0; r < TM / 16; ++r)
-#pragma unroll
-        for (int c = 0; c < TM / 16; ++c) {
-          const int k = min(k0 + w * (TM / 4) + 4 * r + (lane >> 4), n - 1);
-          const int l = min(l0 + 16 * c + (lane & 15), n - 1);
-          dfv[r][c] = dF[(size_t)l + (size_t)n * k];
-        }
-#pragma unroll
-      for (int r = 0; r < TM / 16; ++r)
-#pragma unroll
-        for (int c = 0; c < TM / 16; ++c) {
-          const int k = k0 + w * (TM / 4) + 4 * r + (lane >> 4);
-          const int l = l0 + 16 * c + (lane & 15);
-          if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[r][c] * dfv[r][c];
-        }
+      if (ti == tj) {
+        if constexpr (GEN) xy_block_4b<TM, false, true>(qbuf + off2[s], W, hl, n, k0, l0, n, n, acc);
+        else xy_block_4b<TM, true, true>(qbuf + off2[s], qbuf + off2[s], hl, n, k0, l0, n, n, acc);
+        XyDf<TM, true> df;
+        df.load(dF, n, k0, l0, w, lane, true);
+        df.store(acc, Y, n, k0, l0, w, lane, true);
+      } else {
+        if constexpr (GEN) xy_block_4b<TM, false>(qbuf + off2[s], W, hl, n, k0, l0, n, n, acc);
+        else xy_block_4b<TM, true>(qbuf + off2[s], qbuf + off2[s], hl, n, k0, l0, n, n, acc);
+        XyDf<TM, false> df;
+        df.load(dF, n, k0, l0, w, lane, mirror);
+        df.store(acc, Y, n, k0, l0, w, lane, mirror);
+      }
     }
   }
 }
@@ -489,29 +532,29 @@ __global__ __launch_bounds__(256, 2) void k_xy_kq(
             }
       }
     } else {
+      // FP64: diagonal 64x64 tiles formed on their lower triangle and stored
+      // with the mirror, as in k_xy
+      const bool mirror = k0 / kTile == l0 / kTile;
+      if (mirror && ti < tj) continue;
       double acc[KQ][TM / 16][TM / 16];
-      xy_block_4b_kq<TM, KQ>(qbuf + off2[s], hl, sum_n, nq, n, k0, l0, acc);
-      double dfv[TM / 16][TM / 16];
+      if (ti == tj) {
+        xy_block_4b_kq<TM, KQ, true>(qbuf + off2[s], hl, sum_n, nq, n, k0, l0, acc);
+        XyDf<TM, true> df;
+        df.load(dF, n, k0, l0, w, lane, true);
 #pragma unroll
-      for (int r = 0; r < TM / 16; ++r)
-#pragma unroll
-        for (int c = 0; c < TM / 16; ++c) {
-          const int k = min(k0 + w * (TM / 4) + 4 * r + (lane >> 4), n - 1);
-          const int l = min(l0 + 16 * c + (lane & 15), n - 1);
-          dfv[r][c] = dF[(size_t)l + (size_t)n * k];
+        for (int q = 0; q < KQ; ++q) {
+          if (q >= nq) break;
+          df.store(acc[q], ybuf + (size_t)(q0 + q) * sum_n2 + off2[s], n, k0, l0, w, lane, true);
         }
+      } else {
+        xy_block_4b_kq<TM, KQ, false>(qbuf + off2[s], hl, sum_n, nq, n, k0, l0, acc);
+        XyDf<TM, false> df;
+        df.load(dF, n, k0, l0, w, lane, mirror);
 #pragma unroll
-      for (int q = 0; q < KQ; ++q) {
-        if (q >= nq) break;
-        double* Y = ybuf + (size_t)(q0 + q) * sum_n2 + off2[s];
-#pragma unroll
-        for (int r = 0; r < TM / 16; ++r)
-#pragma unroll
-          for (int c = 0; c < TM / 16; ++c) {
-            const int k = k0 + w * (TM / 4) + 4 * r + (lane >> 4);
-            const int l = l0 + 16 * c + (lane & 15);
-            if (k < n && l < n) Y[(size_t)l + (size_t)n * k] = acc[q][r][c] * dfv[r][c];
-          }
+        for (int q = 0; q < KQ; ++q) {
+          if (q >= nq) break;
+          df.store(acc[q], ybuf + (size_t)(q0 + q) * sum_n2 + off2[s], n, k0, l0, w, lane, mirror);
+        }
       }
     }
   }

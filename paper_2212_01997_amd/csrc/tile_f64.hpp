@@ -21,7 +21,7 @@ __device__ __forceinline__ double mfma4b(double a, double b, double c) {
 // The TMxTM block X(k0.., l0..) of one subgraph (columns k >= kend or l >= lend
 // read as zero) on the four-block 4x4x4 FP64 MFMA.  Wave w owns rows [w TM/4, (w+1) TM/4) and
 // all TM columns: TM/16 x TM/16 independent accumulators, lane l holding row
-// w TM/4 + 4 r + l/16, column 16 c + l%16 in acc[r][c].  The K dimension is
+// w TM/4 + 4 r + l/16 (xy_row(r, w) + l/16), column 16 c + l%16 in acc[r][c].  The K dimension is
 // staged through LDS in chunks of kXK rows, stored [m][column] with a row
 // stride of TM + 1 doubles: each group of 16 lanes then touches 16 distinct
 // 8-byte bank pairs in the staging writes (16 consecutive m) and in the B reads
@@ -32,7 +32,22 @@ __device__ __forceinline__ double mfma4b(double a, double b, double c) {
 // n x n: A = B = Q for a diagonal perturbation (H = true), or without h for
 // the general kind, where W = h1_s Q is formed as G^T Q (G = h1_s, symmetric)
 // and X as Q^T W.
-template <int TM, bool H>
+//
+// DIAG: a block on the diagonal (k0 = l0) of which only the lower triangle
+// (k >= l) is wanted.  The TM rows are cut into strips of 4; strip s needs the
+// 16-column blocks c <= s/4.  Wave w takes the strips 8 (r/2) + (r odd ?
+// 7 - w : w) for r = 0 .. TM/16 - 1, which need exactly the blocks c <= r, so
+// every wave runs (R4 (R4 + 1) / 2) of the R4^2 products (10 of 16 for
+// TM = 64) and the waves stay balanced.  Each element is still the same sum
+// in the same order, so its bits do not depend on DIAG.  xy_row gives the
+// first row of sub-strip r in either mode.
+template <int TM, bool DIAG>
+__device__ __forceinline__ int xy_row(int r, int w) {
+  if constexpr (DIAG) return 4 * (8 * (r >> 1) + ((r & 1) ? 7 - w : w));
+  else return w * (TM / 4) + 4 * r;
+}
+
+template <int TM, bool H, bool DIAG = false>
 __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Am,
                                             const double* __restrict__ Bm,
                                             const double* __restrict__ hl, int n, int k0, int l0,
@@ -82,13 +97,14 @@ __device__ __forceinline__ void xy_block_4b(const double* __restrict__ Am,
       const int mm = 4 * ks + lr;
       double a[R4], bb[C16];
 #pragma unroll
-      for (int r = 0; r < R4; ++r) a[r] = As[mm][w * (TM / 4) + 4 * r + lq];
+      for (int r = 0; r < R4; ++r) a[r] = As[mm][xy_row<TM, DIAG>(r, w) + lq];
 #pragma unroll
       for (int c = 0; c < C16; ++c) bb[c] = Bs[mm][16 * c + l15];
 #pragma unroll
       for (int r = 0; r < R4; ++r)
 #pragma unroll
-        for (int c = 0; c < C16; ++c) acc[r][c] = mfma4b(a[r], bb[c], acc[r][c]);
+        for (int c = 0; c < C16; ++c)
+          if (!DIAG || c <= r) acc[r][c] = mfma4b(a[r], bb[c], acc[r][c]);
     }
   }
 }
