@@ -170,7 +170,7 @@ void gq_graph_destroy(gq_graph* g);
  * and atomic-orbital eigenvectors C_i = z_i Q_i (2 sum n_i^2 doubles), needed
  * by gq_submatrix_solve_overlap.  Allocates device memory, or takes a piece of the context's arena
  * (GQ_ENOMEM when neither is available); GQ_EINVAL for unknown flags, a
- * subgraph above 1024 orbitals or a core above 32 orbitals. */
+ * subgraph above 1024 orbitals or a core above 128 orbitals. */
 #define GQ_EIGS_GENERAL_H1 1u
 #define GQ_EIGS_OVERLAP 2u
 gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,

@@ -20,9 +20,10 @@ namespace gq {
 constexpr int kMaxN = 1024;
 // Largest tridiagonal block solved directly in the divide-and-conquer tree.
 constexpr int kLeaf = 16;
-// Largest core (orbitals): the response products keep two 16-row MFMA blocks.
-constexpr int kMaxCore = 32;
-// Core rows handled per workgroup in the core-row products.
+// Largest core (orbitals).  The core-row products (density rows, T = Q_c Y,
+// P = 2 T Q^T) run in blocks of 32 core rows, so the bound only caps the
+// number of those blocks (4); 128 orbitals hold cores of about 50 atoms.
+constexpr int kMaxCore = 128;
 // Points per multisection pass of the chemical-potential search.
 constexpr int kMuPoints = 32;  // chemical potentials per multisection pass
 constexpr int kMuPasses = 11;  // the bracket shrinks 33^11 = 5e16 fold

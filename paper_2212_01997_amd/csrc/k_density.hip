@@ -190,11 +190,13 @@ constexpr int kDU = 4;    // K steps of operands loaded ahead
 
 // Core rows of both products for kDC columns l of one subgraph:
 //   rho[j, l] = sum_m Q[j, m] 2 f_m Q[l, m],
-//   M[j, l]   = sum_m Q[j, m] 2 beta f_m (1 - f_m) Q[l, m],   j < c <= 32.
-// Wave w owns columns L0 + 32 w .. + 31 (two 16-column tiles) and both 16-row
-// tiles of core rows; the K steps run over m, the A operand Q[j, m] g(m) is
-// formed in registers and one load of Q[l, m] feeds both products.  The
-// workgroup of the first column block also forms tmu = 2 beta sum f(1-f) w.
+//   M[j, l]   = sum_m Q[j, m] 2 beta f_m (1 - f_m) Q[l, m],   j < c,
+// 32 core rows J0 .. J0 + 31 per workgroup (J0 = 32 blockIdx.y; blocks past
+// the core return).  Wave w owns columns L0 + 32 w .. + 31 (two 16-column
+// tiles) and both 16-row tiles of the block's core rows; the K steps run over
+// m, the A operand Q[j, m] g(m) is formed in registers and one load of
+// Q[l, m] feeds both products.  The workgroup of the first column and row
+// block also forms tmu = 2 beta sum f(1-f) w.
 __global__ __launch_bounds__(kThreads) void k_density_rows(
     const double* __restrict__ qbuf, const double* __restrict__ eps,
     const double* __restrict__ wts, const int64_t* __restrict__ off2,
@@ -205,15 +207,17 @@ __global__ __launch_bounds__(kThreads) void k_density_rows(
   __shared__ double red[kThreads / 64];
   const int s = order[blockIdx.x / ncb];
   const int L0 = (blockIdx.x % ncb) * kDC;
+  const int J0 = 32 * blockIdx.y;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   if (L0 >= n) return;
   const int c = n_core[s];
+  if (J0 >= c) return;
   const double mu = state[2], beta = 1.0 / state[3];
   const double* Q = qbuf + off2[s];
   const double* e = eps + b;
 
-  if (L0 == 0) {
+  if (L0 == 0 && J0 == 0) {
     double acc = 0.0;
     for (int k = threadIdx.x; k < n; k += kThreads) {
       double f, f1f;
@@ -233,9 +237,10 @@ __global__ __launch_bounds__(kThreads) void k_density_rows(
     lcol[y] = L0 + 32 * w + 16 * y + li;
     colok[y] = lcol[y] < n;
   }
-  // rows li and 16 + li of Q, clamped to valid rows (zeroed below when not core)
-  const int r0 = min(li, n - 1), r1 = min(16 + li, n - 1);
-  const bool ok0 = li < c, ok1 = 16 + li < c;
+  // rows J0 + li and J0 + 16 + li of Q, clamped to valid rows (zeroed below
+  // when not core)
+  const int r0 = min(J0 + li, n - 1), r1 = min(J0 + 16 + li, n - 1);
+  const bool ok0 = J0 + li < c, ok1 = J0 + 16 + li < c;
   v4d ar[2][2], am[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_density_rows(
     if (!colok[y]) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j0 = lk + 4 * r, j1 = 16 + lk + 4 * r;
+      const int j0 = J0 + lk + 4 * r, j1 = J0 + 16 + lk + 4 * r;
       if (j0 < c) {
         if (rho) rho[base + (size_t)j0 * n + lcol[y]] = ar[0][y][r];
         mrows[base + (size_t)j0 * n + lcol[y]] = am[0][y][r];
@@ -378,7 +383,8 @@ void launch_density(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, double* rho_bloc
   // in a non-orthogonal basis the rows are the atomic-orbital ones, from
   // C = z Q; mu and tmu stay on the orthogonalized weights
   const double* qrows = e->overlap_solved ? e->C : e->Q;
-  hipLaunchKernelGGL(k_density_rows, dim3(g->n_sub * ncb), dim3(kThreads), 0, st, qrows, e->eps,
+  hipLaunchKernelGGL(k_density_rows, dim3(g->n_sub * ncb, (g->info.max_c + 31) / 32),
+                     dim3(kThreads), 0, st, qrows, e->eps,
                      e->wts, dv.off2, dv.offc, dv.sub_orb_ptr, dv.n_core, dv.order, e->mu_state,
                      rho_blocks, e->M, e->tmu, ncb);
   prof_end(ctx);

@@ -684,7 +684,9 @@ __global__ __launch_bounds__(kThreads) void k_h1_gather(const double* __restrict
 }
 
 
-// T = Q_c Y for 128 columns of one subgraph; T stored as tbuf[(b + l) * 32 + j].
+// T = Q_c Y for 128 columns of one subgraph and the 32 core rows J0 .. J0 + 31
+// (one launch per block of 32 core rows; subgraphs whose core ends before J0
+// return); T stored as tbuf[(b + l) * 32 + (j - J0)].
 // K (the rows of Y) is staged through LDS 32 rows at a time, each half of the
 // 128 columns read along its stored direction (a 32-row stage lies inside one
 // 64-row tile of Y); the next stage is prefetched into registers meanwhile.
@@ -696,7 +698,7 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
     const double* __restrict__ qbuf, const double* __restrict__ ybuf, double* __restrict__ tbuf,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
     const int32_t* __restrict__ n_core, const int32_t* __restrict__ order, int64_t sum_n2,
-    int64_t sum_n) {
+    int64_t sum_n, int J0) {
   __shared__ double As[kTK][33];
   __shared__ double Bs[kTK][kTC + 1];
   const int s = order[blockIdx.x];
@@ -705,7 +707,7 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
   const int L0 = blockIdx.y * kTC;
-  if (L0 >= n) return;
+  if (L0 >= n || J0 >= c) return;
   const double* Q = qbuf + off2[s];
   const double* Y = ybuf + (size_t)q * sum_n2 + off2[s];
   double* Tq = tbuf + (size_t)q * sum_n * 32;
@@ -718,7 +720,7 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
     for (int u = 0; u < kPa; ++u) {
       const int idx = tid + u * kThreads;
       const int j = idx % 32, kk = idx / 32;
-      pa[u] = (j < c && k0 + kk < n) ? Q[j + (size_t)n * (k0 + kk)] : 0.0;
+      pa[u] = (J0 + j < c && k0 + kk < n) ? Q[J0 + j + (size_t)n * (k0 + kk)] : 0.0;
     }
 #pragma unroll
     for (int hlf = 0; hlf < 2; ++hlf) {
@@ -791,8 +793,8 @@ __global__ __launch_bounds__(kThreads) void k_t_mfma(
   }
 }
 
-// P = 2 T Q^T (c x n core rows, block layout) and its diagonal, 128 columns per
-// workgroup.  Each wave owns 32 columns; T and Q are read straight from memory
+// P = 2 T Q^T (c x n core rows, block layout) and its diagonal for the core
+// rows J0 .. J0 + 31 that T holds, 128 columns per workgroup.  Each wave owns 32 columns; T and Q are read straight from memory
 // along their stored directions, kPU steps of 4 rows loaded ahead of their MFMAs.
 constexpr int kPU = 8;
 
@@ -801,7 +803,7 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
     double* __restrict__ pdiag, const int64_t* __restrict__ off2, const int64_t* __restrict__ offc,
     const int32_t* __restrict__ offcd, const int32_t* __restrict__ sub_orb_ptr,
     const int32_t* __restrict__ n_core, const int32_t* __restrict__ order, int64_t sum_n,
-    int64_t nnz, int sum_c, int n_sub, int ncb, int K) {
+    int64_t nnz, int sum_c, int n_sub, int ncb, int K, int J0) {
   // group g = (subgraph in order, column block) holds the K perturbations that
   // read the same 128 rows of Q.  Groups go round-robin to the XCDs (workgroup
   // b runs on XCD b mod 8), and on each XCD a group's K workgroups are
@@ -815,7 +817,7 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
   const int n = sub_orb_ptr[s + 1] - b;
   const int c = n_core[s];
   const int L0 = (g % ncb) * kTC;
-  if (L0 >= n) return;
+  if (L0 >= n || J0 >= c) return;
   const double* Q = qbuf + off2[s];
   const double* Tq = tbuf + (size_t)q * sum_n * 32;
   double* outq = out + (size_t)q * nnz;
@@ -859,7 +861,7 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
     if (!colok[y]) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int j0 = lk + 4 * r, j1 = 16 + lk + 4 * r;
+      const int j0 = J0 + lk + 4 * r, j1 = J0 + 16 + lk + 4 * r;
       if (j0 < c) {
         const double v = 2.0 * acc[0][y][r];
         outq[base + (size_t)j0 * n + lcol[y]] = v;
@@ -875,19 +877,21 @@ __global__ __launch_bounds__(kThreads) void k_p_mfma(
 }
 
 // Diagonal of P = 2 T Q^T only (the core charges of the response need no
-// more): P_jj = 2 sum_l T[j, l] Q[j, l] for j < c; workgroup (subgraph, q),
-// each thread sums its columns l in order, then a fixed-order reduction.
+// more): P_jj = 2 sum_l T[j, l] Q[j, l] for the core rows J0 .. J0 + 31 that T
+// holds; workgroup (subgraph, q), each thread sums its columns l in order,
+// then a fixed-order reduction.
 __global__ __launch_bounds__(kThreads) void k_pdiag(
     const double* __restrict__ tbuf, const double* __restrict__ qbuf, double* __restrict__ pdiag,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ offcd,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core, int64_t sum_n,
-    int sum_c) {
+    int sum_c, int J0) {
   __shared__ double red[kThreads / 64][32];
   const int s = blockIdx.x, q = blockIdx.y;
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
-  const int c = n_core[s];
-  const double* Q = qbuf + off2[s];
+  const int c = n_core[s] - J0;  // core rows of this block: J0 .. J0 + min(c, 32) - 1
+  if (c <= 0) return;
+  const double* Q = qbuf + off2[s] + J0;
   const double* Tq = tbuf + (size_t)q * sum_n * 32;
   double acc[32];
 #pragma unroll
@@ -904,10 +908,10 @@ __global__ __launch_bounds__(kThreads) void k_pdiag(
     if (lane == 0) red[w][j] = t;
   }
   __syncthreads();
-  if (threadIdx.x < c) {
+  if (threadIdx.x < min(c, 32)) {
     double t = 0.0;
     for (int x = 0; x < kThreads / 64; ++x) t += red[x][threadIdx.x];
-    pdiag[(size_t)q * sum_c + offcd[s] + threadIdx.x] = 2.0 * t;
+    pdiag[(size_t)q * sum_c + offcd[s] + J0 + threadIdx.x] = 2.0 * t;
   }
 }
 
@@ -1241,14 +1245,21 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
                        dv.sub_orb_ptr, sum_n2, sum_n, ctx->win_dF, ctx->win_cap);
     prof_end(ctx);
   }
+  // the core rows in blocks of 32 (T holds one block at a time)
   prof_begin(ctx, "k_rows");
   dim3 grid_cols(g->n_sub, (g->info.max_n + kTC - 1) / kTC, K);
-  hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, ybuf, rb.T, dv.off2,
-                     dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
+  const int ncb = (g->info.max_n + kTC - 1) / kTC;
+  const int groups_per_xcd = (g->n_sub * ncb + 7) / 8;
+  const int n_jb = (g->info.max_c + 31) / 32;
   if (opt.charge_only || ao) {
     // the orthogonalized core traces (the diagonal of P only) fix mu1
-    hipLaunchKernelGGL(k_pdiag, dim3(g->n_sub, K), dim3(kThreads), 0, st, rb.T, e->Q, rb.pdiag,
-                       dv.off2, dv.offcd, dv.sub_orb_ptr, dv.n_core, sum_n, sum_c);
+    for (int jb = 0; jb < n_jb; ++jb) {
+      hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->Q, ybuf, rb.T, dv.off2,
+                         dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n, 32 * jb);
+      hipLaunchKernelGGL(k_pdiag, dim3(g->n_sub, K), dim3(kThreads), 0, st, rb.T, e->Q,
+                         rb.pdiag, dv.off2, dv.offcd, dv.sub_orb_ptr, dv.n_core, sum_n, sum_c,
+                         32 * jb);
+    }
     prof_end(ctx);
     prof_begin(ctx, "k_mu1_combine");
     hipLaunchKernelGGL(k_mu1, dim3(K), dim3(kThreads), 0, st, rb.pdiag, sum_c, e->tmu, g->n_sub,
@@ -1258,14 +1269,14 @@ void launch_response(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, const RespBufs&
     // the atomic-orbital rows 2 C_c Y C^T (their diagonal overwrites pdiag,
     // which k_mu1 has consumed)
     prof_begin(ctx, "k_rows");
-    hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, e->C, ybuf, rb.T, dv.off2,
-                       dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n);
   }
-  const int ncb = (g->info.max_n + kTC - 1) / kTC;
-  const int groups_per_xcd = (g->n_sub * ncb + 7) / 8;
-  hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, rb.T, qx,
-                     p_blocks, rb.pdiag, dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core,
-                     dv.order, sum_n, nnz, sum_c, g->n_sub, ncb, K);
+  for (int jb = 0; jb < n_jb; ++jb) {
+    hipLaunchKernelGGL(k_t_mfma, grid_cols, dim3(kThreads), 0, st, qx, ybuf, rb.T, dv.off2,
+                       dv.sub_orb_ptr, dv.n_core, dv.order, sum_n2, sum_n, 32 * jb);
+    hipLaunchKernelGGL(k_p_mfma, dim3(8 * groups_per_xcd * K), dim3(kThreads), 0, st, rb.T, qx,
+                       p_blocks, rb.pdiag, dv.off2, dv.offc, dv.offcd, dv.sub_orb_ptr, dv.n_core,
+                       dv.order, sum_n, nnz, sum_c, g->n_sub, ncb, K, 32 * jb);
+  }
   prof_end(ctx);
   prof_begin(ctx, "k_mu1_combine");
   if (!ao)

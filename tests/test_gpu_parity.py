@@ -327,7 +327,7 @@ def test_enoconv_from_iteration_cap(ctx):
 
 
 def test_size_limits_rejected(ctx):
-    """Subgraphs above 1,024 orbitals and cores above 32 orbitals are refused
+    """Subgraphs above 1,024 orbitals and cores above 128 orbitals are refused
     when the workspace is created, with the limit in the message."""
     from paper_2212_01997_amd import gq
     s = I.water_system(180, 18.0, seed=181)  # 1,080 orbitals
@@ -337,11 +337,57 @@ def test_size_limits_rejected(ctx):
     with pytest.raises(gq.GQError, match="exceeds the limit 1024"):
         gq.Eigs(ctx, g, 1)
     w = I.config_system(1)
-    core = (np.arange(w.n_atoms) // 27).astype(np.int32)  # nine waters: 54 core orbitals
+    core = (np.arange(w.n_atoms) // 66).astype(np.int32)  # 22 waters: 132 core orbitals
     g2 = gq.Graph.for_system(w, core, 1e-3)
-    assert g2.info.max_c > 32
-    with pytest.raises(gq.GQError, match="exceeds the limit 32"):
+    assert g2.info.max_c > 128
+    with pytest.raises(gq.GQError, match="exceeds the limit 128"):
         gq.Eigs(ctx, g2, 1)
+
+
+@pytest.mark.parametrize("atoms_per_core", [30, 45])
+def test_large_cores(ctx, oracle_lib, atoms_per_core):
+    """Cores of 30 and 45 atoms (60 and 90 core orbitals: two and three blocks
+    of the 32-row core products), the shape of the paper's largest runs: rho,
+    mu, rho1 and mu1 against the oracle (FP64 and split-FP32), the core-charge
+    response (the diagonal-only path) and the non-orthogonal rows."""
+    import torch
+    from oracle import krylov as Kr, overlap as Ov
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath
+    O = oracle_lib
+    s = I.water_system(60, 12.2, seed=61)
+    core = (np.arange(s.n_atoms) // atoms_per_core).astype(np.int32)
+    prev = O.bootstrap_prev(s, core, KT)
+    g = O.graph_build(s, core, 0.07, rho_prev=prev, flags=O.PATHS2)
+    assert int(g.n_core_orbs.max()) > 32 * (1 if atoms_per_core == 30 else 2)
+    h1 = I.h1_diagonal(s, 2, seed=182)
+    ref = O.solve(s, g, KT, h1)
+    p = GraphPath(ctx, s, core, 0.07, prev, gq.PATHS2, max_k=2)
+    mu = p.ground_state(KT)
+    assert abs(mu - ref.mu) <= TOL_MU
+    assert np.abs(p.rho.cpu().numpy() - ref.rho).max() <= TOL
+    h1d = torch.as_tensor(h1, device="cuda")
+    for precision, tol in ((gq.PREC_FP64, TOL), (gq.PREC_SPLIT32, 1e-6)):
+        mu1 = p.respond(h1d, precision=precision)
+        p.sync()
+        err = (np.abs(p.rho1_view(2).cpu().numpy() - ref.rho1).max(), np.abs(mu1 - ref.mu1).max())
+        _say(f"cores of {atoms_per_core} atoms precision={precision}: |drho1| {err[0]:.1e} "
+             f"|dmu1| {err[1]:.1e}")
+        assert max(err) <= tol
+    gamma = I.coulomb_kernel(s)
+    v = I.charge_vectors(s, 2, seed=183)
+    q1_ref, _ = Kr.charge_response(s, g, KT, gamma, v)
+    cm = gq.ChargeModel(ctx, p.graph, gamma, kmax=2)
+    q1, _ = cm.response(p.eigs, torch.as_tensor(v, device="cuda"))
+    assert np.abs(q1.cpu().numpy() - q1_ref).max() <= TOL
+    S = I.overlap_matrix(s)
+    ov = Ov.solve(s, S, g, KT, h1)
+    po = GraphPath(ctx, s, core, 0.07, prev, gq.PATHS2, max_k=2, S=S)
+    po.ground_state(KT)
+    po.respond(h1d)
+    po.sync()
+    assert np.abs(po.rho.cpu().numpy() - ov.rho_ao).max() <= TOL
+    assert np.abs(po.rho1_view(2).cpu().numpy() - ov.rho1_ao).max() <= TOL
 
 
 # ------------------------------------------------ config 3 at full size
