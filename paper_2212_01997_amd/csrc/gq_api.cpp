@@ -205,6 +205,10 @@ static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, uint32_t f
   x.md_inv = c.take<double>(in.sum_n);
   x.tfac = c.take<double>((int64_t)g->bt_nblocks * 256);
   x.wsc = c.take<double>(in.sum_n * 16);
+  x.huge = g->n_huge ? c.take<double>((int64_t)g->n_huge * kHugeSlot) : nullptr;
+  x.dcg = g->dc_nglob_max
+              ? c.take<double>((int64_t)g->dc_nglob_max * kMaxN * kDcGlobalStride)
+              : nullptr;
   x.hloc = c.take<double>(kk * in.sum_n);
   x.G = (flags & GQ_EIGS_GENERAL_H1) ? c.take<double>(kk * in.sum_n2) : nullptr;
   x.Z = (flags & GQ_EIGS_OVERLAP) ? c.take<double>(in.sum_n2) : nullptr;

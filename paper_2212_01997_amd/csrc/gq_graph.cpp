@@ -497,8 +497,16 @@ void build_dc_plan(gq_graph* g) {
   // first class leaves fewer small subgraphs to fill the CUs while the
   // largest are reduced, a smaller one puts more of them in its way)
   g->n_big = std::min(g->n_sub, std::max(1, (g->n_sub + 2) / 5));
+  // subgraphs above the one-workgroup reduction's limit lead the order and
+  // stay in class 0
+  g->n_huge = 0;
+  while (g->n_huge < g->n_sub &&
+         g->sub_orb_ptr[g->order[g->n_huge] + 1] - g->sub_orb_ptr[g->order[g->n_huge]] > kTdMaxN)
+    ++g->n_huge;
+  g->n_big = std::max(g->n_big, g->n_huge);
   g->dc_leaves.clear();
   g->dc_merges.clear();
+  g->dc_nglob_max = 0;
   g->dc_tiles.clear();
   for (int cls = 0; cls < 2; ++cls) {
     const int32_t i0 = cls == 0 ? 0 : g->n_big, i1 = cls == 0 ? g->n_big : g->n_sub;
@@ -532,17 +540,21 @@ void build_dc_plan(gq_graph* g) {
     auto& to = g->dc_level_tile_off[cls];
     mo.assign(1, (int32_t)(g->dc_merges.size() / 4));
     to.assign(1, (int32_t)(g->dc_tiles.size() / 3));
-    g->dc_level_maxm[cls].clear();
     g->dc_level_msum[cls].clear();
+    g->dc_level_nglob[cls].clear();
+    g->dc_level_maxm_lds[cls].clear();
     for (int d = (int)by_depth.size() - 1; d >= 0; --d) {
       const auto& v = by_depth[d];
-      int32_t maxm = 0;
+      int32_t maxm_lds = 0, nglob = 0;
       int64_t msum = 0;
       for (size_t q = 0; q < v.size(); q += 4) {
         const int32_t li = (int32_t)(q / 4);
         const int32_t m = v[q + 2] + v[q + 3];
-        maxm = std::max(maxm, m);
         msum += m;
+        // merges above the LDS bound come first in their level (subgraphs in
+        // decreasing size; only a top merge can exceed it)
+        if (m > kDcLdsMaxM) nglob = li + 1;
+        else maxm_lds = std::max(maxm_lds, m);
         const int32_t nt = (m + 63) / 64;
         for (int32_t tr = 0; tr < nt; ++tr)
           for (int32_t tc = 0; tc < nt; ++tc) g->dc_tiles.insert(g->dc_tiles.end(), {li, tr, tc});
@@ -550,8 +562,10 @@ void build_dc_plan(gq_graph* g) {
       g->dc_merges.insert(g->dc_merges.end(), v.begin(), v.end());
       mo.push_back((int32_t)(g->dc_merges.size() / 4));
       to.push_back((int32_t)(g->dc_tiles.size() / 3));
-      g->dc_level_maxm[cls].push_back(maxm);
       g->dc_level_msum[cls].push_back(msum);
+      g->dc_level_nglob[cls].push_back(nglob);
+      g->dc_nglob_max = std::max(g->dc_nglob_max, nglob);
+      g->dc_level_maxm_lds[cls].push_back(maxm_lds);
     }
   }
   g->dc_leaf_off[2] = (int32_t)(g->dc_leaves.size() / 4);

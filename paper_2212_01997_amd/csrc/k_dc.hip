@@ -367,14 +367,17 @@ __device__ int compact(int m, F flag, int* out, int base, int* wtot) {
   return total;
 }
 
-template <int NT>
+// GL: the merge's work arrays live in the device scratch gscr (kDcGlobalStride
+// doubles per eigenvalue and workgroup) instead of LDS, for merges above
+// kDcLdsMaxM eigenvalues.
+template <int NT, bool GL>
 __global__ __launch_bounds__(NT) void k_dc_prep(
     const int32_t* __restrict__ merges, const int32_t* __restrict__ sub_orb_ptr,
     const int64_t* __restrict__ off2, const double* __restrict__ E, double* __restrict__ zbuf,
     double* __restrict__ lam, int32_t* __restrict__ md_k, int32_t* __restrict__ md_cols,
     int32_t* __restrict__ md_org, int32_t* __restrict__ md_pos, int32_t* __restrict__ md_dsrc,
     int32_t* __restrict__ md_dpos, double* __restrict__ md_delta, double* __restrict__ md_tau,
-    double* __restrict__ md_zhat, double* __restrict__ md_inv) {
+    double* __restrict__ md_zhat, double* __restrict__ md_inv, double* __restrict__ gscr) {
   extern __shared__ double smem[];
   __shared__ double red[NT / 64];
   __shared__ int sh_k, sh_nrot, sh_rot;
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   double* Z = zbuf + off2[s];
-  PrepLds L = carve(smem, m);
+  PrepLds L = GL ? carve(gscr + (size_t)blockIdx.x * kMaxN * kDcGlobalStride, m) : carve(smem, m);
   const int tid = threadIdx.x;
 
   const double beta = E[b + lo + m1 - 1];
@@ -1010,17 +1013,177 @@ __global__ __launch_bounds__(kThreads, MRB <= 4 ? 4 : MRB <= 6 ? 3 : MRB <= 10 ?
   if (tid < 16 && c0 + tid < n) wts[b + c0 + tid] = csum[0][tid] + csum[1][tid] + csum[2][tid] + csum[3][tid];
 }
 
+// The back-transformation of subgraphs above kTdMaxN orbitals (up to kMaxN):
+// the products of k_bt_mfma on a 16-column panel held in registers by eight
+// waves (wave w holds row blocks w, w + 8, ...), with the reflector block staged
+// in LDS kBigHalf rows at a time: the first half, then the second for W =
+// V^T Z; the update Z -= V W2 on the second half (still staged), then on the
+// first, staged again.
+constexpr int kBigThreads = 512;
+constexpr int kBigHalf = 1024;
+constexpr int kBigMRB = kMaxN / (16 * (kBigThreads / 64));  // row blocks per wave
+static_assert(kBigMRB % 2 == 0 && 16 * (kBigThreads / 64) * (kBigMRB / 2) == kBigHalf,
+              "half of each wave's row blocks per staged half");
+
+__global__ __launch_bounds__(kBigThreads, 1) void k_bt_mfma_big(
+    const double* __restrict__ abuf, const double* __restrict__ tfac,
+    const int32_t* __restrict__ toff, double* __restrict__ zbuf, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ n_core,
+    const int32_t* __restrict__ list, double* __restrict__ wts, int count, int npanel) {
+  extern __shared__ double vb[];  // [kBigHalf][kLdv]: half of the reflector block
+  constexpr int NW = kBigThreads / 64;
+  constexpr int HB = kBigMRB / 2;  // a wave's row blocks in one half
+  __shared__ double Wp[NW][16][17];
+  __shared__ double Ts[16][17];
+  __shared__ double csum[NW][16];
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int si = 8 * (slot / npanel) + xcd;
+  if (si >= count) return;
+  const int s = list[si];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const int c0 = (slot % npanel) * 16;
+  if (c0 >= n) return;
+  const int nrb = (n + 15) / 16;
+  const double* A = abuf + off2[s];
+  double* Z = zbuf + off2[s];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int col = c0 + li;
+  v4d zt[kBigMRB];
+#pragma unroll
+  for (int i = 0; i < kBigMRB; ++i) {
+    const int rb = w + NW * i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + 4 * r + lk;
+      zt[i][r] = (rb < nrb && row < n && col < n) ? Z[row + (size_t)n * col] : 0.0;
+    }
+  }
+  const int nref = n - 2;
+  for (int kbi = (nref - 1) / kNb; nref > 0 && kbi >= 0; --kbi) {
+    const int kb = kbi * kNb;
+    const int nb = min(kNb, nref - kb);
+    const int rb0 = (kb + 1) / 16;  // first row block with a nonzero reflector row
+    // rows [max(16 rb0, h kBigHalf), min(16 nrb, (h+1) kBigHalf)) of the block
+    // into vb (row - h kBigHalf); thread (q, rl) takes reflector q, rows rl +
+    // 32 i, eight loads in flight before their stores
+    auto stage = [&](int h) {
+      const int lo = max(16 * rb0, h * kBigHalf), hi = min(16 * nrb, (h + 1) * kBigHalf);
+      const int q = tid >> 5, rl = tid & 31;
+      const int colq = kb + min(q, nb - 1);
+      const int top = kb + q + 1;
+      for (int i0 = lo; i0 < hi; i0 += 8 * 32) {
+        double vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vv[u] = A[min(i0 + rl + 32 * u, n - 1) + (size_t)n * colq];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = i0 + rl + 32 * u;
+          if (r < hi) {
+            const double v = (q < nb && r < n && r >= top) ? ((r == top) ? 1.0 : vv[u]) : 0.0;
+            vb[(r - h * kBigHalf) * kLdv + q] = v;
+          }
+        }
+      }
+    };
+    __syncthreads();
+    stage(0);
+    if (tid < kNb * kNb) Ts[tid / kNb][tid % kNb] = tfac[(size_t)(toff[s] + kbi) * kNb * kNb + tid];
+    __syncthreads();
+    // W = V^T Z over this wave's row blocks, first half then second
+    v4d W = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const int rb = w + NW * i;
+      if (rb < rb0 || rb >= nrb) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W = mfma16(vb[(16 * rb + 4 * r + lk) * kLdv + li], zt[i][r], W);
+    }
+    __syncthreads();
+    stage(1);
+    __syncthreads();
+#pragma unroll
+    for (int i = HB; i < kBigMRB; ++i) {
+      const int rb = w + NW * i;
+      if (rb < rb0 || rb >= nrb) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        W = mfma16(vb[(16 * rb - kBigHalf + 4 * r + lk) * kLdv + li], zt[i][r], W);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wp[w][4 * r + lk][li] = W[r];
+    __syncthreads();
+    // W2 = T W, the wave partials added in order
+    v4d W2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      const int q = 4 * kc + lk;
+      double bw = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) bw += Wp[ww][q][li];
+      W2 = mfma16(Ts[li][q], bw, W2);
+    }
+    // Z -= V W2: the second half (staged), then the first
+#pragma unroll
+    for (int i = HB; i < kBigMRB; ++i) {
+      const int rb = w + NW * i;
+      if (rb < rb0 || rb >= nrb) continue;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        zt[i] = mfma16(vb[(16 * rb - kBigHalf + li) * kLdv + 4 * kc + lk], -W2[kc], zt[i]);
+    }
+    __syncthreads();
+    stage(0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < HB; ++i) {
+      const int rb = w + NW * i;
+      if (rb < rb0 || rb >= nrb) continue;
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        zt[i] = mfma16(vb[(16 * rb + li) * kLdv + 4 * kc + lk], -W2[kc], zt[i]);
+    }
+  }
+  // write back and core weights of the panel's columns
+  const int c = n_core[s];
+  double cw = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBigMRB; ++i) {
+    const int rb = w + NW * i;
+    if (rb >= nrb) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + 4 * r + lk;
+      if (row < n && col < n) {
+        Z[row + (size_t)n * col] = zt[i][r];
+        if (row < c) cw += zt[i][r] * zt[i][r];
+      }
+    }
+  }
+  cw += __shfl_xor(cw, 16, 64);
+  cw += __shfl_xor(cw, 32, 64);
+  if (lk == 0) csum[w][li] = cw;
+  __syncthreads();
+  if (tid < 16 && c0 + tid < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) t += csum[ww][tid];
+    wts[b + c0 + tid] = t;
+  }
+}
+
 }  // namespace
 
 size_t dc_prep_lds(int m) { return (size_t)m * (13 * sizeof(double) + 7 * sizeof(int)); }
 
 void dc_set_attributes() {
-  (void)hipFuncSetAttribute((const void*)k_dc_prep<kThreads>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
-  (void)hipFuncSetAttribute((const void*)k_dc_prep<512>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
-  (void)hipFuncSetAttribute((const void*)k_dc_prep<1024>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kMaxN));
+  (void)hipFuncSetAttribute((const void*)k_dc_prep<kThreads, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kDcLdsMaxM));
+  (void)hipFuncSetAttribute((const void*)k_dc_prep<512, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kDcLdsMaxM));
+  (void)hipFuncSetAttribute((const void*)k_dc_prep<1024, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kDcLdsMaxM));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(256 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1030,7 +1193,9 @@ void dc_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<10>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(640 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(kMaxN * kLdv * sizeof(double)));
+                            (int)(kTdMaxN * kLdv * sizeof(double)));
+  (void)hipFuncSetAttribute((const void*)k_bt_mfma_big, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kBigHalf * kLdv * sizeof(double)));
 }
 
 void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t st) {
@@ -1056,17 +1221,29 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t 
     const int m0 = mo[lv], m1 = mo[lv + 1];
     const int t0 = to[lv], t1 = to[lv + 1];
     if (m1 == m0) continue;
-    const int maxm = g->dc_level_maxm[cls][lv];
     prof_begin_on(ctx, "k_dc_prep", st);
-    // levels whose merges average over 256 run on 1024 threads, over 128 on
-    // 512, the rest on 256, so that a merge's roots take one or two rounds
-    const int64_t msum = g->dc_level_msum[cls][lv], nm = m1 - m0;
-    const int ntl = msum > 256 * nm ? 1024 : msum > 128 * nm ? 512 : kThreads;
-    auto prep = ntl == 1024 ? k_dc_prep<1024> : ntl == 512 ? k_dc_prep<512> : k_dc_prep<kThreads>;
-    hipLaunchKernelGGL(prep, dim3(m1 - m0), dim3(ntl), dc_prep_lds(maxm), st,
-                       dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, zin, e->eps,
-                       e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
-                       e->md_delta, e->md_tau, e->md_zhat, e->md_inv);
+    // the level's leading merges above kDcLdsMaxM eigenvalues keep their work
+    // arrays in device scratch (one slot per workgroup)
+    const int nglob = g->dc_level_nglob[cls][lv];
+    if (nglob > 0)
+      hipLaunchKernelGGL((k_dc_prep<1024, true>), dim3(nglob), dim3(1024), 0, st,
+                         dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, zin, e->eps,
+                         e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
+                         e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->dcg);
+    if (m1 - m0 > nglob) {
+      // levels whose merges average over 256 run on 1024 threads, over 128 on
+      // 512, the rest on 256, so that a merge's roots take one or two rounds
+      const int maxm = g->dc_level_maxm_lds[cls][lv];
+      const int64_t msum = g->dc_level_msum[cls][lv], nm = m1 - m0;
+      const int ntl = msum > 256 * nm ? 1024 : msum > 128 * nm ? 512 : kThreads;
+      auto prep = ntl == 1024 ? k_dc_prep<1024, false>
+                  : ntl == 512 ? k_dc_prep<512, false> : k_dc_prep<kThreads, false>;
+      const int ms = m0 + nglob;
+      hipLaunchKernelGGL(prep, dim3(m1 - ms), dim3(ntl), dc_prep_lds(maxm), st,
+                         dv.dc_merges + 4 * ms, dv.sub_orb_ptr, dv.off2, e->ee, zin, e->eps,
+                         e->md_k + ms, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
+                         e->md_delta, e->md_tau, e->md_zhat, e->md_inv, nullptr);
+    }
     prof_end(ctx);
     prof_begin_on(ctx, "k_dc_gemm", st);
     hipLaunchKernelGGL(k_dc_gemm, dim3(t1 - t0), dim3(kThreads), 0, st, dv.dc_tiles + 3 * t0,
@@ -1082,11 +1259,12 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t 
   prof_end(ctx);
   prof_begin_on(ctx, "k_backtransform", st);
   // subgraphs are ordered by decreasing size: classes n <= 256, <= 384, <= 512,
-  // <= 640, <= 1024 are contiguous ranges of that order, each launched with
-  // its register panel (the smallest that holds its row blocks)
-  static constexpr int kClassN[5] = {256, 384, 512, 640, kMaxN};
+  // <= 640, <= 1024, <= kMaxN are contiguous ranges of that order, each
+  // launched with its register panel (the smallest that holds its row blocks)
+  static constexpr int kClassN[6] = {256, 384, 512, 640, kTdMaxN, kMaxN};
+  static_assert(kTdMaxN == 1024, "the k_bt_mfma<16> class holds 1024 rows");
   int lo = i0;
-  for (int c = 4; c >= 0; --c) {
+  for (int c = 5; c >= 0; --c) {
     const int floor_n = c == 0 ? 0 : kClassN[c - 1];
     int hi = lo;
     while (hi < i1 && g->sub_orb_ptr[g->order[hi] + 1] - g->sub_orb_ptr[g->order[hi]] > floor_n) ++hi;
@@ -1095,6 +1273,13 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t 
       const int nrb = (nmax + 15) / 16;
       const int npanel = (nmax + 15) / 16, count = hi - lo;
       dim3 grid(8 * npanel * ((count + 7) / 8));
+      if (c == 5) {
+        hipLaunchKernelGGL(k_bt_mfma_big, grid, dim3(kBigThreads), kBigHalf * kLdv * sizeof(double),
+                           st, e->A, e->tfac, dv.bt_toff, e->Q, dv.off2, dv.sub_orb_ptr,
+                           dv.n_core, dv.order + lo, e->wts, count, npanel);
+        lo = hi;
+        continue;
+      }
       const size_t lds = (size_t)16 * nrb * kLdv * sizeof(double);
       auto kern = c == 0 ? k_bt_mfma<4> : c == 1 ? k_bt_mfma<6> : c == 2 ? k_bt_mfma<8> : c == 3 ? k_bt_mfma<10> : k_bt_mfma<16>;
       hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, st, e->A, e->tfac, dv.bt_toff, e->Q,

@@ -315,8 +315,12 @@ __device__ __forceinline__ double sinhc_small(double x) {
 __global__ __launch_bounds__(kThreads) void k_divided_differences(
     const double* __restrict__ eps, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
-    const double* __restrict__ state, double* __restrict__ dfbuf) {
-  __shared__ double se[kMaxN], sa[kMaxN], sx[kMaxN], sd[kMaxN];
+    const double* __restrict__ state, double* __restrict__ dfbuf, int ldn) {
+  extern __shared__ double dd_lds[];  // four arrays of ldn (the largest n) doubles
+  double* se = dd_lds;
+  double* sa = se + ldn;
+  double* sx = sa + ldn;
+  double* sd = sx + ldn;
   const int s = order[blockIdx.x];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
@@ -394,8 +398,10 @@ void launch_divided_differences(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipS
   const gq_graph_dev& dv = g->dev;
   prof_begin_on(ctx, "k_divided_differences", st);
   dim3 grid(g->n_sub, (g->info.max_n + kDdCols - 1) / kDdCols);
-  hipLaunchKernelGGL(k_divided_differences, grid, dim3(kThreads), 0, st, e->eps, dv.off2,
-                     dv.sub_orb_ptr, dv.order, e->mu_state, e->A);
+  // 4 kMaxN doubles (64 KiB) at most: within the default LDS limit
+  const int ldn = g->info.max_n;
+  hipLaunchKernelGGL(k_divided_differences, grid, dim3(kThreads), 4 * ldn * sizeof(double), st,
+                     e->eps, dv.off2, dv.sub_orb_ptr, dv.order, e->mu_state, e->A, ldn);
   prof_end(ctx);
 }
 

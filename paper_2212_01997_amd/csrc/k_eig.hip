@@ -5,7 +5,9 @@
 //   k_gather    CSR rows of H -> dense column-major h (binary search of each
 //               column index in the subgraph's sorted orbital list, in LDS)
 //   k_tridiag   blocked Householder reduction to tridiagonal form, reflectors
-//               kept in the lower triangle
+//               kept in the lower triangle (subgraphs of up to kTdMaxN
+//               orbitals; larger ones take the multi-workgroup reduction
+//               k_td_col / k_td_symv / k_td_update below)
 //   then the tridiagonal eigenproblem by divide and conquer and the
 //   back-transformation (k_dc.hip).
 #include <algorithm>
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
   extern __shared__ double pan[];  // 2 kPanel min(max n, kLdsPanelN) doubles
-  __shared__ __align__(16) double vl[kMaxN + kUnroll];  // v, then kUnroll zeros
+  __shared__ __align__(16) double vl[kTdMaxN + kUnroll];  // v, then kUnroll zeros
   __shared__ double part[kTdThreads];
   __shared__ double red[2 * (kTdThreads / 64)];  // the two sums of a column
   __shared__ double yp[kTdThreads / 32][2 * kPanel + 1];
@@ -408,7 +410,308 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
     tridiag_body<false>(A, W, pan, n, b, D, E, TAU, vl, part, red, yp, yfin, rowc, &alpha_sh);
 }
 
+// ---------------------------------------------------------------------------
+// Multi-workgroup reduction of the subgraphs above kTdMaxN orbitals (up to
+// kMaxN): the blocked algorithm of k_tridiag (panels of kPanel reflectors
+// formed against the stale trailing matrix plus the panel corrections, then a
+// rank-2 kPanel update on MFMA), with each step spread over workgroups and the
+// kernel launches as the only synchronisation:
+//   k_td_col     one 1024-thread workgroup per subgraph (two rows per
+//                thread): completes w = p - (tau/2)(p.v) v of the previous
+//                column from the slab sums, then forms the current column,
+//                its reflector (v, tau, beta) and the panel products W^T v and
+//                V^T v;
+//   k_td_symv    row slabs of kSlabRows rows on separate workgroups: p = tau
+//                (A v - V (W^T v) - W (V^T v)) on the slab's rows, and the
+//                slab's share of p.v;
+//   k_td_update  64x64 blocks of the trailing matrix on separate workgroups:
+//                A -= V W^T + W V^T on MFMA;
+//   k_td_final   the last two diagonal entries and the last off-diagonal one.
+// Every listed subgraph takes part in each launch (one whose reduction has
+// ended returns at once).  Reflectors, d, e and tau are stored as k_tridiag
+// stores them, so the divide and conquer and the back-transformation are
+// shared.  Per subgraph the scratch slot holds v (kUnroll zeros after row n),
+// p, the panel products (W^T v, then V^T v) and the slab sums.
+constexpr int kSlabRows = 64;      // one wave's rows
+constexpr int kSlabThreads = 256;  // four threads per row
+constexpr int kTdRows = kMaxN / kTdThreads;
+
+struct HugeSlot {
+  double *v, *p, *y, *sums;
+  __device__ HugeSlot(double* base) {
+    v = base;
+    p = v + kMaxN + kUnroll;
+    y = p + kMaxN;
+    sums = y + 2 * kPanel;
+  }
+};
+static_assert(2 * kMaxN + kUnroll + 2 * kPanel + 64 <= kHugeSlot, "scratch slot too small");
+static_assert(kMaxN / kSlabRows <= 64, "slab sums");
+
+__global__ __launch_bounds__(kTdThreads) void k_td_col(
+    double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
+    double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU,
+    double* __restrict__ huge, int k0, int j) {
+  __shared__ __align__(16) double vl[kMaxN];
+  __shared__ double red[kTdThreads / 64];
+  __shared__ double yp[kTdThreads / 32][2 * kPanel + 1];
+  __shared__ double rowc[2 * kPanel];
+  __shared__ double alpha_sh;
+  const int s = order[blockIdx.x];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  if (k0 + 2 >= n) return;
+  const int nb = min(kPanel, n - 2 - k0);
+  if (j > nb) return;
+  double* A = abuf + off2[s];
+  double* Wg = wsc + (size_t)b * kPanel;  // W[q * n + r]
+  HugeSlot sl(huge + (size_t)blockIdx.x * kHugeSlot);
+  const int tid = threadIdx.x;
+  // w of the previous column: p and the slab sums come from k_td_symv
+  if (j >= 1) {
+    const int cp = k0 + j - 1;
+    const double tp = TAU[b + cp];
+    if (tp != 0.0) {
+      double S = 0.0;
+      for (int gg = (cp + 1) / kSlabRows; gg < (n + kSlabRows - 1) / kSlabRows; ++gg) S += sl.sums[gg];
+      const double K = 0.5 * tp * S;
+#pragma unroll
+      for (int u = 0; u < kTdRows; ++u) {
+        const int r = tid + u * kTdThreads;
+        if (r < n) Wg[(j - 1) * n + r] = r >= cp + 1 ? sl.p[r] - K * sl.v[r] : 0.0;
+      }
+    }
+  }
+  if (j == nb) return;
+  const int c = k0 + j;
+  __syncthreads();  // w_{j-1} of row c is read below by the threads < j
+  if (tid < j) {
+    rowc[tid] = A[c + (size_t)n * (k0 + tid)];
+    rowc[kPanel + tid] = Wg[tid * n + c];
+  }
+  __syncthreads();
+  // the current column: A[r, c] - sum_q (v_q[r] w_q[c] + w_q[r] v_q[c]), r >= c
+  double a[kTdRows];
+  double sq = 0.0;
+#pragma unroll
+  for (int u = 0; u < kTdRows; ++u) {
+    const int r = tid + u * kTdThreads;
+    a[u] = 0.0;
+    if (r < n && r >= c) {
+      double x = A[r + (size_t)n * c];
+      for (int q = 0; q < j; ++q)
+        x -= A[r + (size_t)n * (k0 + q)] * rowc[kPanel + q] + Wg[q * n + r] * rowc[q];
+      a[u] = x;
+      if (r == c) D[b + c] = x;
+      if (r == c + 1) alpha_sh = x;
+      if (r >= c + 2) sq += x * x;
+    }
+  }
+  const double sigma = tsum(sq, red);  // its barrier also publishes alpha_sh
+  const double alpha = alpha_sh;
+  double tau = 0.0, beta = alpha, scale = 0.0;
+  if (sigma != 0.0) {
+    const double nrm = sqrt(alpha * alpha + sigma);
+    beta = alpha >= 0.0 ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  // v (zero at rows <= c; all zero when H = I), into A's column c below the
+  // diagonal, LDS and the slot
+#pragma unroll
+  for (int u = 0; u < kTdRows; ++u) {
+    const int r = tid + u * kTdThreads;
+    if (r < n) {
+      const double v = tau == 0.0 ? 0.0 : (r == c + 1 ? 1.0 : (r >= c + 2 ? a[u] * scale : 0.0));
+      vl[r] = v;
+      sl.v[r] = v;
+      if (r >= c + 1) A[r + (size_t)n * c] = v;
+      if (tau == 0.0) Wg[j * n + r] = 0.0;
+    }
+  }
+  if (tid < kUnroll) sl.v[n + tid] = 0.0;
+  if (tid == 0) {
+    TAU[b + c] = tau;
+    E[b + c] = beta;
+  }
+  if (tau == 0.0) return;
+  __syncthreads();
+  // y = (W^T v, V^T v) over the panel so far, rows > c: thread t sums panel
+  // column t mod 32 (W for q < kPanel, V above) over rows c+1+seg, c+1+seg+32,
+  // ... of segment seg = t / 32; the segments are added in order
+  {
+    const int q = tid & 31, seg = tid >> 5;
+    const int qp = q & (kPanel - 1);
+    double t = 0.0;
+    if (qp < j) {
+      const bool isw = q < kPanel;
+      for (int row = c + 1 + seg; row < n; row += kTdThreads / 32)
+        t += (isw ? Wg[qp * n + row] : A[row + (size_t)n * (k0 + qp)]) * vl[row];
+    }
+    yp[seg][q] = t;
+  }
+  __syncthreads();
+  if (tid < 2 * kPanel) {
+    double t = 0.0;
+    if ((tid % kPanel) < j)
+      for (int sg = 0; sg < kTdThreads / 32; ++sg) t += yp[sg][tid];
+    sl.y[tid] = t;
+  }
+}
+
+__global__ __launch_bounds__(kSlabThreads) void k_td_symv(
+    const double* __restrict__ abuf, const double* __restrict__ wsc,
+    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
+    const int32_t* __restrict__ order, const double* __restrict__ TAU, double* __restrict__ huge,
+    int k0, int j) {
+  __shared__ __align__(16) double vl[kMaxN + kUnroll];
+  __shared__ double part[kSlabThreads];
+  __shared__ double ys[2 * kPanel];
+  const int s = order[blockIdx.y];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  if (k0 + 2 >= n) return;
+  const int nb = min(kPanel, n - 2 - k0);
+  if (j >= nb) return;
+  const int c = k0 + j;
+  const int r0 = blockIdx.x * kSlabRows;
+  if (r0 >= n || r0 + kSlabRows <= c + 1) return;
+  const double tau = TAU[b + c];
+  if (tau == 0.0) return;
+  const double* A = abuf + off2[s];
+  const double* Wg = wsc + (size_t)b * kPanel;
+  HugeSlot sl(huge + (size_t)blockIdx.y * kHugeSlot);
+  const int tid = threadIdx.x;
+  // v from the first chunk symv_row reads (columns below it are not read)
+  for (int i = (c + 1) / kUnroll * kUnroll + tid; i < n + kUnroll; i += kSlabThreads) vl[i] = sl.v[i];
+  if (tid < 2 * kPanel) ys[tid] = sl.y[tid];
+  __syncthreads();
+  constexpr int H = kSlabThreads / kSlabRows;
+  const int rl = tid % kSlabRows, h = tid / kSlabRows;
+  const int r = r0 + rl;
+  double unused = 0.0;
+  part[tid] = (r >= c + 1 && r < n) ? symv_row(A + r, vl, n, c, h, H, unused) : 0.0;
+  __syncthreads();
+  if (tid < kSlabRows) {  // the first wave, all lanes
+    double p = 0.0;
+    if (r >= c + 1 && r < n) {
+#pragma unroll
+      for (int hh = 0; hh < H; ++hh) p += part[hh * kSlabRows + rl];
+      for (int q = 0; q < j; ++q)
+        p -= A[r + (size_t)n * (k0 + q)] * ys[q] + Wg[q * n + r] * ys[kPanel + q];
+      p *= tau;
+      sl.p[r] = p;
+    }
+    const double pv = wave_total(r >= c + 1 && r < n ? p * vl[r] : 0.0);
+    if (tid == 0) sl.sums[blockIdx.x] = pv;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_td_update(
+    double* __restrict__ abuf, const double* __restrict__ wsc, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order, int k0) {
+  const int s = order[blockIdx.y];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  if (k0 + 2 >= n) return;
+  const int nb = min(kPanel, n - 2 - k0);
+  const int t0 = k0 + nb;
+  const int nt = (n - t0 + 63) / 64;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
+  double* A = abuf + off2[s];
+  const double* Wg = wsc + (size_t)b * kPanel;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // the block's sixteen 16x16 tiles, four per wave; tile element (row0 + j,
+  // col0 + i) in lane j + 16 (i % 4), register i / 4, as in k_tridiag
+#pragma unroll 1
+  for (int tile = wv; tile < 16; tile += 4) {
+    const int row0 = t0 + 64 * bi + 16 * (tile / 4), col0 = t0 + 64 * bj + 16 * (tile % 4);
+    const int row = row0 + li;
+    const bool rok = row < n;
+    const int cl = col0 + li;
+    const bool cok = cl < n;
+    const int rowc_ = min(row, n - 1), clc = min(cl, n - 1);
+    double a4[4], wcv[kPanel / 4], vcv[kPanel / 4], vrv[kPanel / 4], wrv[kPanel / 4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a4[i] = A[rowc_ + (size_t)n * min(col0 + 4 * i + lk, n - 1)];
+#pragma unroll
+    for (int kq = 0; kq < kPanel / 4; ++kq) {
+      const int qc = min(4 * kq + lk, nb - 1);
+      wcv[kq] = Wg[qc * n + clc];
+      vcv[kq] = A[clc + (size_t)n * (k0 + qc)];
+      vrv[kq] = A[rowc_ + (size_t)n * (k0 + qc)];
+      wrv[kq] = Wg[qc * n + rowc_];
+    }
+    v4d acc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = (rok && col0 + 4 * i + lk < n) ? a4[i] : 0.0;
+#pragma unroll
+    for (int kq = 0; kq < kPanel / 4; ++kq) {
+      const bool qok = 4 * kq + lk < nb;
+      const double wc = (qok && cok) ? wcv[kq] : 0.0;
+      const double vc = (qok && cok) ? vcv[kq] : 0.0;
+      const double vrr = (qok && rok) ? vrv[kq] : 0.0;
+      const double wr = (qok && rok) ? wrv[kq] : 0.0;
+      acc = mfma16(-wc, vrr, acc);
+      acc = mfma16(-vc, wr, acc);
+    }
+    if (rok) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int col = col0 + 4 * i + lk;
+        if (col < n) A[row + (size_t)n * col] = acc[i];
+      }
+    }
+  }
+}
+
+__global__ void k_td_final(const double* __restrict__ abuf, const int64_t* __restrict__ off2,
+                           const int32_t* __restrict__ sub_orb_ptr,
+                           const int32_t* __restrict__ order, double* __restrict__ D,
+                           double* __restrict__ E) {
+  const int s = order[blockIdx.x];
+  const int b = sub_orb_ptr[s];
+  const int n = sub_orb_ptr[s + 1] - b;
+  const double* A = abuf + off2[s];
+  if (threadIdx.x == 0 && n >= 2) {
+    D[b + n - 2] = A[(n - 2) + (size_t)n * (n - 2)];
+    E[b + n - 2] = A[(n - 1) + (size_t)n * (n - 2)];
+    D[b + n - 1] = A[(size_t)(n - 1) * (n + 1)];
+    E[b + n - 1] = 0.0;
+  }
+}
+
 }  // namespace
+
+// The multi-workgroup reduction of order[0..n_huge) on stream st: per panel,
+// kPanel column steps (k_td_col, k_td_symv) and one k_td_col that completes
+// the panel's last w, then the trailing update.
+static void launch_tridiag_huge(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st) {
+  const gq_graph_dev& dv = g->dev;
+  const int nh = g->n_huge;
+  const int maxn = g->sub_orb_ptr[g->order[0] + 1] - g->sub_orb_ptr[g->order[0]];
+  const int nslab = (maxn + kSlabRows - 1) / kSlabRows;
+  prof_begin_on(ctx, "k_tridiag_mwg", st);
+  for (int k0 = 0; k0 + 2 < maxn; k0 += kPanel) {
+    const int nbmax = std::min(kPanel, maxn - 2 - k0);
+    for (int j = 0; j <= nbmax; ++j) {
+      hipLaunchKernelGGL(k_td_col, dim3(nh), dim3(kTdThreads), 0, st, e->A, e->wsc, dv.off2,
+                         dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau, e->huge, k0, j);
+      if (j < nbmax)
+        hipLaunchKernelGGL(k_td_symv, dim3(nslab, nh), dim3(kSlabThreads), 0, st, e->A, e->wsc,
+                           dv.off2, dv.sub_orb_ptr, dv.order, e->tau, e->huge, k0, j);
+    }
+    const int nt = (maxn - k0 + 63) / 64;
+    hipLaunchKernelGGL(k_td_update, dim3(nt * nt, nh), dim3(256), 0, st, e->A, e->wsc, dv.off2,
+                       dv.sub_orb_ptr, dv.order, k0);
+  }
+  hipLaunchKernelGGL(k_td_final, dim3(nh), dim3(64), 0, st, e->A, dv.off2, dv.sub_orb_ptr,
+                     dv.order, e->dd, e->ee);
+  prof_end(ctx);
+}
 
 static size_t tridiag_lds(int maxn) {
   return (size_t)2 * kPanel * std::min(maxn, kLdsPanelN) * sizeof(double);
@@ -451,10 +754,15 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     launch_dc(ctx, g, e, 1, ctx->side);
   }
   if (nbig > 0) {
-    prof_begin(ctx, "k_tridiag");
-    hipLaunchKernelGGL(k_tridiag, dim3(nbig), dim3(kTdThreads), tridiag_lds(g->info.max_n), st,
-                       e->A, e->wsc, dv.off2, dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau);
-    prof_end(ctx);
+    const int nh = g->n_huge;
+    if (nh > 0) launch_tridiag_huge(ctx, g, e, st);
+    if (nbig > nh) {
+      const int n0 = g->sub_orb_ptr[g->order[nh] + 1] - g->sub_orb_ptr[g->order[nh]];
+      prof_begin(ctx, "k_tridiag");
+      hipLaunchKernelGGL(k_tridiag, dim3(nbig - nh), dim3(kTdThreads), tridiag_lds(n0), st, e->A,
+                         e->wsc, dv.off2, dv.sub_orb_ptr, dv.order + nh, e->dd, e->ee, e->tau);
+      prof_end(ctx);
+    }
     launch_dc(ctx, g, e, 0, st);
   }
   if (nsmall > 0) {

@@ -144,9 +144,9 @@ def test_tile_edges_complete(ctx, oracle_lib, n_atoms):
 
 def test_max_size_complete(ctx, oracle_lib):
     """170 waters, cores of five molecules, complete graph: 34 subgraphs of
-    1,020 orbitals, next to the size limit of 1,024 (global-memory
-    back-transform, the deepest divide-and-conquer tree, one
-    tridiagonalisation row per thread)."""
+    1,020 orbitals, next to the limit of the one-workgroup reduction (1,024:
+    one tridiagonalisation row per thread, panel in global memory, the
+    largest LDS divide-and-conquer merge and register back-transform)."""
     O = oracle_lib
     s = I.water_system(170, 17.2, seed=171)
     core = (np.arange(s.n_atoms) // 15).astype(np.int32)
@@ -327,14 +327,14 @@ def test_enoconv_from_iteration_cap(ctx):
 
 
 def test_size_limits_rejected(ctx):
-    """Subgraphs above 1,024 orbitals and cores above 128 orbitals are refused
+    """Subgraphs above 2,048 orbitals and cores above 128 orbitals are refused
     when the workspace is created, with the limit in the message."""
     from paper_2212_01997_amd import gq
-    s = I.water_system(180, 18.0, seed=181)  # 1,080 orbitals
+    s = I.water_system(350, 22.4, seed=181)  # 2,100 orbitals
     g = gq.Graph.for_system(s, (np.arange(s.n_atoms) // 15).astype(np.int32), 0.0, None,
                             gq.COMPLETE)
-    assert g.info.max_n == 1080
-    with pytest.raises(gq.GQError, match="exceeds the limit 1024"):
+    assert g.info.max_n == 2100
+    with pytest.raises(gq.GQError, match="exceeds the limit 2048"):
         gq.Eigs(ctx, g, 1)
     w = I.config_system(1)
     core = (np.arange(w.n_atoms) // 66).astype(np.int32)  # 22 waters: 132 core orbitals
