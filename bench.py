@@ -540,6 +540,56 @@ def form_overlap(ctx, system, core, graph, h1, side):
             "k_transpose_scale_ms": kt.get("k_transpose_scale", (0, 0.0))[1]}
 
 
+def form_large(ctx, side):
+    """Subgraphs of 768 to 2,048 orbitals: the multi-workgroup reduction to
+    tridiagonal form (row slabs on separate workgroups, two launches per
+    column), the device-memory top merges and the eight-wave
+    back-transformation.  Two seeded systems: 400 waters with 30-atom cores
+    at tau 0.02 (40 subgraphs of 870..1,213 orbitals), and 2,048 hydrogen
+    atoms on a jittered lattice with the complete graph and 128-atom cores
+    (16 subgraphs of 2,048).  Ground state (eigensolve, mu, density rows) and
+    K = 6 FP64 responses; the reduction priced on 4/3 n^3 flops and on the
+    (8/3) n^3 bytes its per-column products and panel updates stream."""
+    import numpy as np
+    from paper_2212_01997_amd import gq, inputs as I
+    from paper_2212_01997_amd.path import GraphPath
+    out = {}
+    for name, system, core, tau, flags in (
+            ("water400_cores30", I.water_system(400, 22.9, seed=401), None, 0.02, gq.PATHS2),
+            ("hlattice2048_complete", I.h_lattice_system(), "idx128", 0.0, gq.COMPLETE)):
+        core = (np.arange(system.n_atoms) // 128).astype(np.int32) if core == "idx128" \
+            else I.spatial_cores(system, 30)
+        p = GraphPath(ctx, system, core, tau, None, flags, max_k=K_H1)
+        sizes = np.diff(p.graph.export()["sub_orb_ptr"]).astype(float)
+        h1 = I.h1_diagonal(system, K_H1, seed=4002)
+        import torch
+        h1d = torch.as_tensor(h1, device="cuda")
+        p.ground_state(KT)
+        ground = _time_steps(lambda: p.ground_state(KT, want_mu=False), side, 3)
+        p.respond(h1d, want_mu1=False)
+        resp = _time_steps(lambda: p.respond(h1d, want_mu1=False), side, 3)
+        ctx.set_profiling(True)
+        p.ground_state(KT, want_mu=False)
+        kt = ctx.kernel_times()
+        ctx.set_profiling(False)
+        mwg = sizes[sizes >= 768]
+        red_ms = kt["k_tridiag_mwg"][1]
+        flops = (4.0 / 3.0) * (mwg ** 3).sum()
+        bytes_ = (8.0 / 3.0) * (mwg ** 3).sum()
+        log(f"large {name}: ground {_pct(ground, 50):.1f} ms, K = 6 responses "
+            f"{_pct(resp, 50):.1f} ms, multi-workgroup reduction {red_ms:.1f} ms")
+        out[name] = {
+            "n_sub": int(len(sizes)), "n_min": int(sizes.min()), "n_max": int(sizes.max()),
+            "multi_workgroup_subgraphs": int(len(mwg)),
+            "ground_state_ms": _dist(ground), "response_ms_K6": _dist(resp),
+            "kernel_ms": {k: v[1] for k, v in sorted(kt.items(), key=lambda kv: -kv[1][1])[:6]},
+            "reduction": {"ms": red_ms, "tflops": flops / (red_ms * 1e-3) / 1e12,
+                          "frac_fp64": flops / (red_ms * 1e-3) / PEAK_FP64,
+                          "schedule_tb_per_s": bytes_ / (red_ms * 1e-3) / 1e12}}
+        del p
+    return out
+
+
 def config2_step(ctx, side, steps):
     """The 1,000-water FP64 step (ground state + one perturbation)."""
     import torch
@@ -805,6 +855,9 @@ def main():
         torch.cuda.empty_cache()
         log("non-orthogonal basis")
         forms["overlap"] = form_overlap(ctx, system, core, graph, h1, side)
+        torch.cuda.empty_cache()
+        log("subgraphs of 768..2,048 orbitals")
+        forms["large"] = form_large(ctx, side)
         torch.cuda.empty_cache()
         log("1,000-water FP64 step")
         forms["config2_fp64_step"] = config2_step(ctx, side, args.steps)

@@ -205,7 +205,7 @@ static void eigs_layout(gq_eigs* e, const gq_graph* g, int32_t max_k, uint32_t f
   x.md_inv = c.take<double>(in.sum_n);
   x.tfac = c.take<double>((int64_t)g->bt_nblocks * 256);
   x.wsc = c.take<double>(in.sum_n * 16);
-  x.huge = g->n_huge ? c.take<double>((int64_t)g->n_huge * kHugeSlot) : nullptr;
+  x.mwg = g->n_mwg ? c.take<double>((int64_t)g->n_mwg * kMwgSlot) : nullptr;
   x.dcg = g->dc_nglob_max
               ? c.take<double>((int64_t)g->dc_nglob_max * kMaxN * kDcGlobalStride)
               : nullptr;

@@ -497,13 +497,13 @@ void build_dc_plan(gq_graph* g) {
   // first class leaves fewer small subgraphs to fill the CUs while the
   // largest are reduced, a smaller one puts more of them in its way)
   g->n_big = std::min(g->n_sub, std::max(1, (g->n_sub + 2) / 5));
-  // subgraphs above the one-workgroup reduction's limit lead the order and
-  // stay in class 0
-  g->n_huge = 0;
-  while (g->n_huge < g->n_sub &&
-         g->sub_orb_ptr[g->order[g->n_huge] + 1] - g->sub_orb_ptr[g->order[g->n_huge]] > kTdMaxN)
-    ++g->n_huge;
-  g->n_big = std::max(g->n_big, g->n_huge);
+  // the subgraphs of the multi-workgroup reduction lead the order and stay in
+  // class 0
+  g->n_mwg = 0;
+  while (g->n_mwg < g->n_sub &&
+         g->sub_orb_ptr[g->order[g->n_mwg] + 1] - g->sub_orb_ptr[g->order[g->n_mwg]] >= kMwgMinN)
+    ++g->n_mwg;
+  g->n_big = std::max(g->n_big, g->n_mwg);
   g->dc_leaves.clear();
   g->dc_merges.clear();
   g->dc_nglob_max = 0;

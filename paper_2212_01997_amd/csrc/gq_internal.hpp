@@ -15,21 +15,25 @@
 
 namespace gq {
 
-// Largest subgraph the kernels accept (orbitals).  Subgraphs of up to kTdMaxN
-// orbitals are reduced to tridiagonal form by one workgroup each (a row per
-// thread of a 1024-thread workgroup); larger ones take the multi-workgroup
-// reduction (row slabs of a subgraph on separate workgroups, one launch per
-// column step), whose register and LDS budgets end at kMaxN.
+// Largest subgraph the kernels accept (orbitals).  The one-workgroup
+// reduction to tridiagonal form (a row per thread of a 1024-thread workgroup)
+// takes subgraphs of up to kTdMaxN orbitals; subgraphs of kMwgMinN orbitals
+// and more take the multi-workgroup reduction instead (row slabs of a
+// subgraph on separate workgroups, one launch per column step), whose
+// register and LDS budgets end at kMaxN.  From about 700 orbitals one
+// subgraph's reduction on one CU takes longer than the multi-workgroup one's
+// two launches per column.
 constexpr int kMaxN = 2048;
 constexpr int kTdMaxN = 1024;
+constexpr int kMwgMinN = 768;
 // Divide-and-conquer merges of up to kDcLdsMaxM eigenvalues keep their work
 // arrays in LDS; larger merges (the top merge of a subgraph above kTdMaxN)
 // keep them in a device scratch of kDcGlobalStride doubles per eigenvalue.
 constexpr int kDcLdsMaxM = 1024;
 constexpr int kDcGlobalStride = 17;
-// Device scratch of the multi-workgroup reduction per large subgraph (doubles):
+// Device scratch of the multi-workgroup reduction per subgraph (doubles):
 // v (kMaxN + 8 padded), p (kMaxN), the panel products (32), slab sums (64).
-constexpr int kHugeSlot = 2 * kMaxN + 8 + 32 + 64;
+constexpr int kMwgSlot = 2 * kMaxN + 8 + 32 + 64;
 // Largest tridiagonal block solved directly in the divide-and-conquer tree.
 constexpr int kLeaf = 16;
 // Largest core (orbitals).  The core-row products (density rows, T = Q_c Y,
@@ -212,10 +216,9 @@ struct gq_graph {
   // class 1 = the rest; each has its own leaves and merge levels, stored one
   // after the other in dc_leaves / dc_merges / dc_tiles
   int32_t n_big = 0;
-  // subgraphs above kTdMaxN orbitals (order[0..n_huge), all in class 0): the
-  // multi-workgroup reduction; their top merges (the leading dc_level_nglob
-  // merges of a level) keep the merge work arrays in device memory
-  int32_t n_huge = 0;
+  // subgraphs of kMwgMinN orbitals and more (order[0..n_mwg), all in class
+  // 0): the multi-workgroup reduction
+  int32_t n_mwg = 0;
   int32_t dc_leaf_off[3] = {0, 0, 0};
   std::vector<int32_t> dc_level_merge_off[2], dc_level_tile_off[2];
   // per level: leading merges with device-memory work arrays, and the largest
@@ -270,7 +273,7 @@ struct gq_eigs {
   double *md_delta = nullptr, *md_tau = nullptr, *md_zhat = nullptr, *md_inv = nullptr;
   double* tfac = nullptr;  // [bt_nblocks][16*16] compact-WY T factors
   double* wsc = nullptr;   // [sum_n * 16] panel scratch of the tridiagonalisation
-  double* huge = nullptr;  // [n_huge][kHugeSlot] multi-workgroup reduction scratch
+  double* mwg = nullptr;  // [n_mwg][kMwgSlot] multi-workgroup reduction scratch
   double* dcg = nullptr;   // [dc_nglob_max][kMaxN * kDcGlobalStride] large-merge work arrays
   double* hloc = nullptr;  // [max_k][sum_n] perturbations gathered into subgraph order
   double* G = nullptr;     // [max_k][sum n^2] general perturbations (GQ_EIGS_GENERAL_H1 only)

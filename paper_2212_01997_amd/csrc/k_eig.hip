@@ -5,7 +5,7 @@
 //   k_gather    CSR rows of H -> dense column-major h (binary search of each
 //               column index in the subgraph's sorted orbital list, in LDS)
 //   k_tridiag   blocked Householder reduction to tridiagonal form, reflectors
-//               kept in the lower triangle (subgraphs of up to kTdMaxN
+//               kept in the lower triangle (subgraphs below kMwgMinN
 //               orbitals; larger ones take the multi-workgroup reduction
 //               k_td_col / k_td_symv / k_td_update below)
 //   then the tridiagonal eigenproblem by divide and conquer and the
@@ -411,8 +411,8 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
 }
 
 // ---------------------------------------------------------------------------
-// Multi-workgroup reduction of the subgraphs above kTdMaxN orbitals (up to
-// kMaxN): the blocked algorithm of k_tridiag (panels of kPanel reflectors
+// Multi-workgroup reduction of the subgraphs of kMwgMinN orbitals and more
+// (up to kMaxN): the blocked algorithm of k_tridiag (panels of kPanel reflectors
 // formed against the stale trailing matrix plus the panel corrections, then a
 // rank-2 kPanel update on MFMA), with each step spread over workgroups and the
 // kernel launches as the only synchronisation:
@@ -436,23 +436,23 @@ constexpr int kSlabRows = 64;      // one wave's rows
 constexpr int kSlabThreads = 256;  // four threads per row
 constexpr int kTdRows = kMaxN / kTdThreads;
 
-struct HugeSlot {
+struct MwgSlot {
   double *v, *p, *y, *sums;
-  __device__ HugeSlot(double* base) {
+  __device__ MwgSlot(double* base) {
     v = base;
     p = v + kMaxN + kUnroll;
     y = p + kMaxN;
     sums = y + 2 * kPanel;
   }
 };
-static_assert(2 * kMaxN + kUnroll + 2 * kPanel + 64 <= kHugeSlot, "scratch slot too small");
+static_assert(2 * kMaxN + kUnroll + 2 * kPanel + 64 <= kMwgSlot, "scratch slot too small");
 static_assert(kMaxN / kSlabRows <= 64, "slab sums");
 
 __global__ __launch_bounds__(kTdThreads) void k_td_col(
     double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU,
-    double* __restrict__ huge, int k0, int j) {
+    double* __restrict__ mwg, int k0, int j) {
   __shared__ __align__(16) double vl[kMaxN];
   __shared__ double red[kTdThreads / 64];
   __shared__ double yp[kTdThreads / 32][2 * kPanel + 1];
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(kTdThreads) void k_td_col(
   if (j > nb) return;
   double* A = abuf + off2[s];
   double* Wg = wsc + (size_t)b * kPanel;  // W[q * n + r]
-  HugeSlot sl(huge + (size_t)blockIdx.x * kHugeSlot);
+  MwgSlot sl(mwg + (size_t)blockIdx.x * kMwgSlot);
   const int tid = threadIdx.x;
   // w of the previous column: p and the slab sums come from k_td_symv
   if (j >= 1) {
@@ -563,7 +563,7 @@ __global__ __launch_bounds__(kTdThreads) void k_td_col(
 __global__ __launch_bounds__(kSlabThreads) void k_td_symv(
     const double* __restrict__ abuf, const double* __restrict__ wsc,
     const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
-    const int32_t* __restrict__ order, const double* __restrict__ TAU, double* __restrict__ huge,
+    const int32_t* __restrict__ order, const double* __restrict__ TAU, double* __restrict__ mwg,
     int k0, int j) {
   __shared__ __align__(16) double vl[kMaxN + kUnroll];
   __shared__ double part[kSlabThreads];
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(kSlabThreads) void k_td_symv(
   if (tau == 0.0) return;
   const double* A = abuf + off2[s];
   const double* Wg = wsc + (size_t)b * kPanel;
-  HugeSlot sl(huge + (size_t)blockIdx.y * kHugeSlot);
+  MwgSlot sl(mwg + (size_t)blockIdx.y * kMwgSlot);
   const int tid = threadIdx.x;
   // v from the first chunk symv_row reads (columns below it are not read)
   for (int i = (c + 1) / kUnroll * kUnroll + tid; i < n + kUnroll; i += kSlabThreads) vl[i] = sl.v[i];
@@ -686,12 +686,12 @@ __global__ void k_td_final(const double* __restrict__ abuf, const int64_t* __res
 
 }  // namespace
 
-// The multi-workgroup reduction of order[0..n_huge) on stream st: per panel,
+// The multi-workgroup reduction of order[0..n_mwg) on stream st: per panel,
 // kPanel column steps (k_td_col, k_td_symv) and one k_td_col that completes
 // the panel's last w, then the trailing update.
-static void launch_tridiag_huge(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st) {
+static void launch_tridiag_mwg(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st) {
   const gq_graph_dev& dv = g->dev;
-  const int nh = g->n_huge;
+  const int nh = g->n_mwg;
   const int maxn = g->sub_orb_ptr[g->order[0] + 1] - g->sub_orb_ptr[g->order[0]];
   const int nslab = (maxn + kSlabRows - 1) / kSlabRows;
   prof_begin_on(ctx, "k_tridiag_mwg", st);
@@ -699,10 +699,10 @@ static void launch_tridiag_huge(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipS
     const int nbmax = std::min(kPanel, maxn - 2 - k0);
     for (int j = 0; j <= nbmax; ++j) {
       hipLaunchKernelGGL(k_td_col, dim3(nh), dim3(kTdThreads), 0, st, e->A, e->wsc, dv.off2,
-                         dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau, e->huge, k0, j);
+                         dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau, e->mwg, k0, j);
       if (j < nbmax)
         hipLaunchKernelGGL(k_td_symv, dim3(nslab, nh), dim3(kSlabThreads), 0, st, e->A, e->wsc,
-                           dv.off2, dv.sub_orb_ptr, dv.order, e->tau, e->huge, k0, j);
+                           dv.off2, dv.sub_orb_ptr, dv.order, e->tau, e->mwg, k0, j);
     }
     const int nt = (maxn - k0 + 63) / 64;
     hipLaunchKernelGGL(k_td_update, dim3(nt * nt, nh), dim3(256), 0, st, e->A, e->wsc, dv.off2,
@@ -754,8 +754,8 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     launch_dc(ctx, g, e, 1, ctx->side);
   }
   if (nbig > 0) {
-    const int nh = g->n_huge;
-    if (nh > 0) launch_tridiag_huge(ctx, g, e, st);
+    const int nh = g->n_mwg;
+    if (nh > 0) launch_tridiag_mwg(ctx, g, e, st);
     if (nbig > nh) {
       const int n0 = g->sub_orb_ptr[g->order[nh] + 1] - g->sub_orb_ptr[g->order[nh]];
       prof_begin(ctx, "k_tridiag");

@@ -361,6 +361,19 @@ def chain_water_system(n_atoms, n_chain, seed, density=0.1, name=None):
                          "seed": seed})
 
 
+def h_lattice_system(shape=(16, 16, 8), spacing=(1.5, 1.5, 3.0), box=24.0, jitter=0.15,
+                     seed=2048):
+    """Hydrogen atoms on a rectangular lattice (one s orbital each) in a cubic
+    periodic box, each moved by up to `jitter` A per axis: a system whose
+    complete-graph subgraphs have exactly prod(shape) orbitals."""
+    rng = np.random.default_rng(seed)
+    g = np.stack(np.meshgrid(*[np.arange(k) for k in shape], indexing="ij"),
+                 axis=-1).reshape(-1, 3).astype(np.float64)
+    pos = g * np.asarray(spacing) + 0.5 + rng.uniform(-jitter, jitter, size=g.shape)
+    return make_system(f"hlattice{len(pos)}", box, pos, ["H"] * len(pos),
+                       {"kind": "h_lattice", "shape": list(shape), "seed": seed})
+
+
 def isolated_molecules_system(n_mol, spacing, seed):
     """Waters on a cubic lattice `spacing` apart: H is block diagonal when
     spacing - 2 A > 4 A (used to check the disconnected case)."""

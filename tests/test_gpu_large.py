@@ -1,7 +1,7 @@
-"""Parity of the subgraphs above 1,024 orbitals (the multi-workgroup
-reduction to tridiagonal form, the divide-and-conquer top merge with its work
-arrays in device memory, the eight-wave back-transformation) with the oracle,
-through the C ABI.
+"""Parity of large subgraphs with the oracle, through the C ABI: the
+multi-workgroup reduction to tridiagonal form (768 orbitals and more) and,
+above 1,024 orbitals, the divide-and-conquer top merge with its work arrays
+in device memory and the eight-wave back-transformation.
 
 Bar: the FP64 bar of the other parity tests (eigenvalues 1e-12, mu 1e-12,
 rho, rho1 and mu1 1e-10); split-FP32 responses 1e-6.
@@ -11,7 +11,7 @@ Cases:
   of 870..1,213 orbitals, 21 of them above 1,024 (the whole first size
   class);
 - the same system with 45-atom cores at tau 0.03: 27 subgraphs of
-  703..1,072, three above 1,024 beside two below it in the first class;
+  703..1,072, three above 1,024, the one-workgroup reduction below 768;
 - 2,048 hydrogen atoms on a jittered lattice, complete graph, cores of 128
   atoms: 16 subgraphs at both limits (2,048 orbitals, 128 core orbitals).
 """
@@ -39,19 +39,10 @@ def ctx():
     return gq.Context(0)
 
 
-def h_lattice(seed=2048):
-    """2,048 hydrogen atoms on a 16 x 16 x 8 lattice (1.5 A in x and y, 3 A in
-    z) in a 24 A periodic box, each moved by up to 0.15 A per axis."""
-    rng = np.random.default_rng(seed)
-    g = np.stack(np.meshgrid(np.arange(16), np.arange(16), np.arange(8), indexing="ij"),
-                 axis=-1).reshape(-1, 3).astype(np.float64)
-    pos = g * np.array([1.5, 1.5, 3.0]) + 0.5 + rng.uniform(-0.15, 0.15, size=g.shape)
-    return I.make_system("hlattice2048", 24.0, pos, ["H"] * len(pos), {"seed": seed})
-
-
 def _case(name, O):
     if name == "max2048":
-        s = h_lattice()
+        # 16 x 16 x 8 lattice (1.5 A in x and y, 3 A in z), 24 A box
+        s = I.h_lattice_system()
         core = (np.arange(s.n_atoms) // 128).astype(np.int32)
         return s, core, 0.0, O.COMPLETE
     s = I.water_system(400, 22.9, seed=401)

@@ -144,9 +144,9 @@ def test_tile_edges_complete(ctx, oracle_lib, n_atoms):
 
 def test_max_size_complete(ctx, oracle_lib):
     """170 waters, cores of five molecules, complete graph: 34 subgraphs of
-    1,020 orbitals, next to the limit of the one-workgroup reduction (1,024:
-    one tridiagonalisation row per thread, panel in global memory, the
-    largest LDS divide-and-conquer merge and register back-transform)."""
+    1,020 orbitals (the multi-workgroup reduction, the largest
+    divide-and-conquer merge kept in LDS, the largest four-wave register
+    back-transform)."""
     O = oracle_lib
     s = I.water_system(170, 17.2, seed=171)
     core = (np.arange(s.n_atoms) // 15).astype(np.int32)
