@@ -170,7 +170,7 @@ void gq_graph_destroy(gq_graph* g);
  * and atomic-orbital eigenvectors C_i = z_i Q_i (2 sum n_i^2 doubles), needed
  * by gq_submatrix_solve_overlap.  Allocates device memory, or takes a piece of the context's arena
  * (GQ_ENOMEM when neither is available); GQ_EINVAL for unknown flags, a
- * subgraph above 1024 orbitals or a core above 128 orbitals. */
+ * subgraph above 2048 orbitals or a core above 128 orbitals. */
 #define GQ_EIGS_GENERAL_H1 1u
 #define GQ_EIGS_OVERLAP 2u
 gq_status gq_eigs_create(gq_ctx* ctx, const gq_graph* g, int32_t max_k, uint32_t flags,
@@ -193,8 +193,11 @@ void gq_eigs_destroy(gq_eigs* e);
  * Gathers every principal submatrix h_i = H[orbs_i, orbs_i] from the device
  * CSR H (same N and a pattern containing the one given to graph_build) and
  * solves h_i = Q_i diag(eps_i) Q_i^T in FP64 (eps ascending), all on the
- * context stream.  Asynchronous; a later call that syncs reports GQ_ENOCONV
- * if an eigensolve hit its iteration cap. */
+ * context stream.  Subgraphs below 768 orbitals are reduced to tridiagonal
+ * form by one workgroup each; larger ones (up to 2048) by row slabs on
+ * separate workgroups, two launches per column, every such subgraph of the
+ * graph in the same launches.  Asynchronous; a later call that syncs reports
+ * GQ_ENOCONV if an eigensolve hit its iteration cap. */
 gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev,
                              uint32_t flags, gq_eigs* e);
 
@@ -385,7 +388,7 @@ gq_status gq_krylov_kernel(gq_ctx* ctx, gq_charge* c, gq_eigs* e, const double* 
  * gq_autotune: times, on this workspace and for precision GQ_PREC_FP64 or
  * GQ_PREC_SPLIT32, each launch variant of the response's X kernel (64x64 or
  * 32x32 tiles; one workgroup per tile or a persistent grid) on every size bin
- * of the subgraphs (n <= 128, 256, 384, 512, 1024) and keeps the fastest per
+ * of the subgraphs (n <= 128, 256, 384, 512, 2048) and keeps the fastest per
  * bin in the graph handle, where later gq_response calls on any workspace of
  * that graph use it.  Requires gq_density first.  Overwrites the workspace's
  * response scratch; waits for the stream.  report (host, may be NULL)
