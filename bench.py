@@ -638,8 +638,8 @@ def main():
                     help="also run one device copy of 256 MiB (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
-              "(the multi-GPU sharding is described, not run).", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures the single-GPU path "
+              "(the sharding over several GPUs is described, not run).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

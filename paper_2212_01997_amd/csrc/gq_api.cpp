@@ -255,7 +255,7 @@ gq_status gq_ctx_create(int32_t device, void* hip_stream, int64_t arena_bytes, g
   hipDeviceProp_t prop;
   GQ_HIP(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
-    set_error("gq_ctx_create: device %d is %s; this build targets gfx950", device, prop.gcnArchName);
+    set_error("gq_ctx_create: device %d is %s; libgq targets gfx950", device, prop.gcnArchName);
     return GQ_EDEVICE;
   }
   eig_set_attributes();

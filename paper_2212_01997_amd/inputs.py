@@ -467,8 +467,8 @@ def overlap_matrix(system, decay=0.6, min_eig=0.3):
 # (gamma v).  gamma_II = U_I (on-site interaction per element, Ha), and for
 # I != J within the cutoff (minimum image) a screened Coulomb form
 # exp(-r/s) / sqrt(r^2 + (2/(U_I + U_J))^2) with r and s in bohr.  The values
-# are chosen by this build (free-atom-like magnitudes), not taken from a
-# parameter set.
+# are chosen here (free-atom-like magnitudes), not taken from a parameter
+# set.
 HUBBARD_U = {"H": 0.42, "C": 0.36, "N": 0.43, "O": 0.50, "S": 0.33}
 BOHR = 0.529177210903  # Angstrom per bohr
 COULOMB_SCREEN = 6.0   # bohr

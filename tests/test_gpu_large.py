@@ -13,7 +13,10 @@ Cases:
 - the same system with 45-atom cores at tau 0.03: 27 subgraphs of
   703..1,072, three above 1,024, the one-workgroup reduction below 768;
 - 2,048 hydrogen atoms on a jittered lattice, complete graph, cores of 128
-  atoms: 16 subgraphs at both limits (2,048 orbitals, 128 core orbitals).
+  atoms: 16 subgraphs at both limits (2,048 orbitals, 128 core orbitals);
+- 768 hydrogen atoms likewise: six subgraphs of exactly 768 orbitals;
+- 200 isolated waters, complete graph: ten block-diagonal subgraphs of 1,200
+  orbitals, where most columns are already reduced (identity reflectors).
 """
 import os
 import sys
@@ -44,6 +47,18 @@ def _case(name, O):
         # 16 x 16 x 8 lattice (1.5 A in x and y, 3 A in z), 24 A box
         s = I.h_lattice_system()
         core = (np.arange(s.n_atoms) // 128).astype(np.int32)
+        return s, core, 0.0, O.COMPLETE
+    if name == "lattice768":
+        # 16 x 16 x 3 lattice: six subgraphs of exactly 768 orbitals, the
+        # smallest size the multi-workgroup reduction takes
+        s = I.h_lattice_system(shape=(16, 16, 3), spacing=(1.5, 1.5, 3.0), box=24.0, seed=768)
+        core = (np.arange(s.n_atoms) // 128).astype(np.int32)
+        return s, core, 0.0, O.COMPLETE
+    if name == "isolated1200":
+        # 200 waters 7 A apart: every subgraph (the whole system) is block
+        # diagonal, so most reflectors of the reduction are the identity
+        s = I.isolated_molecules_system(200, 7.0, seed=1200)
+        core = (np.arange(s.n_atoms) // 60).astype(np.int32)
         return s, core, 0.0, O.COMPLETE
     s = I.water_system(400, 22.9, seed=401)
     if name == "mixed21":
@@ -87,6 +102,14 @@ def test_large_subgraphs(ctx, oracle_lib, name):
     assert max(err["rho"], err["rho1"], err["mu1"]) <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["lattice768", "isolated1200"])
+def test_large_edge_cases(ctx, oracle_lib, name):
+    sizes, err = _run(ctx, oracle_lib, name, 1)
+    assert (sizes == (768 if name == "lattice768" else 1200)).all()
+    assert err["mu"] <= 1e-12 and err["eps"] <= 1e-12
+    assert max(err["rho"], err["rho1"], err["mu1"]) <= 1e-10
+
+
 def test_size_limits(ctx, oracle_lib):
     """16 subgraphs of 2,048 orbitals with cores of 128 orbitals."""
     sizes, err = _run(ctx, oracle_lib, "max2048", 1)
@@ -100,3 +123,44 @@ def test_large_split32(ctx, oracle_lib):
     _, err = _run(ctx, oracle_lib, "mixed3", 3, precision=gq.PREC_SPLIT32)
     assert err["mu"] <= 1e-12 and err["rho"] <= 1e-10
     assert max(err["rho1"], err["mu1"]) <= 1e-6
+
+
+def test_large_capture_replay(oracle_lib):
+    """A step on subgraphs of 703..1,072 orbitals (several thousand launches
+    of the multi-workgroup reduction) recorded once and replayed three times,
+    with eager work in between: every replay gives the eager bits."""
+    import torch
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath
+    s, core, tau, flags = _case("mixed3", oracle_lib)
+    side = torch.cuda.Stream()
+    cx = gq.Context(0, stream=side)
+    p = GraphPath(cx, s, core, tau, None, flags, max_k=2)
+    h1 = torch.as_tensor(I.h1_diagonal(s, 2, seed=4003), device="cuda")
+    h1b = torch.as_tensor(I.h1_diagonal(s, 2, seed=4004), device="cuda")
+    torch.cuda.synchronize()
+
+    def step(h):
+        p.ground_state(KT, want_mu=False)
+        p.respond(h, want_mu1=False)
+
+    p.ground_state(KT)  # mu on the host once; the captured steps reuse it
+    step(h1)
+    side.synchronize()
+    ref = (p.rho.clone(), p.rho1_view(2).clone())
+    cx.capture_begin()
+    step(h1)
+    x = cx.capture_end()
+    _say("large step captured")
+    for rep in range(3):
+        p.rho.zero_()
+        p.rho1.zero_()
+        torch.cuda.synchronize()
+        x.launch()
+        side.synchronize()
+        assert torch.equal(p.rho, ref[0]), rep
+        assert torch.equal(p.rho1_view(2), ref[1]), rep
+        step(h1b)
+        side.synchronize()
+        assert not torch.equal(p.rho1_view(2), ref[1])
+    del x
