@@ -636,11 +636,21 @@ def main():
                     help="skip the served, batched and temperature forms and the 1,000-water step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 256 MiB (reference for byte counters)")
+    ap.add_argument("--only-form", choices=["large", "config2"],
+                    help="run only this form (for profiling) and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: it measures the single-GPU path "
               "(the sharding over several GPUs is described, not run).", file=sys.stderr)
         sys.exit(2)
+    if args.only_form:
+        import torch
+        from paper_2212_01997_amd import gq
+        side = torch.cuda.Stream()
+        ctx = gq.Context(0, stream=side)
+        out = form_large(ctx, side) if args.only_form == "large" else config2_step(ctx, side, args.steps)
+        print(json.dumps({"form": args.only_form, **out}), flush=True)
+        return
 
     import numpy as np
     import torch
