@@ -143,7 +143,7 @@ void gq_ctx_destroy(gq_ctx* ctx);
  * All pointers are host memory.  atom_orb_ptr[n_atoms+1] strictly increasing
  * from 0; H: N x N with a symmetric pattern; rho_prev: N x N or NULL;
  * core_of_atom[n_atoms]: ids 0..n_sub-1, each used.  GQ_EINVAL on any
- * violation or tau < 0; GQ_ENOMEM if a count exceeds int32.  *out is owned by
+ * violation, n_atoms < 1 or tau < 0; GQ_ENOMEM if a count exceeds int32.  *out is owned by
  * the caller (gq_graph_destroy). */
 gq_status gq_graph_build(int32_t n_atoms, const int32_t* atom_orb_ptr, const gq_csr* H,
                          const gq_csr* rho_prev, const int32_t* core_of_atom, double tau,

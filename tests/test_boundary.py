@@ -110,6 +110,11 @@ def test_graph_build_errors(gq):
         gq.Graph(s.n_atoms, aop, H, core, 0.01)
     with pytest.raises(gq.GQError, match="flags"):
         gq.Graph(s.n_atoms, s.atom_orb_ptr, H, core, 0.01, flags=8)
+    # an empty system has no subgraph to solve
+    with pytest.raises(gq.GQError, match="empty system"):
+        gq.Graph(0, np.zeros(1, np.int32),
+                 (np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0)),
+                 np.zeros(0, np.int32), 0.01)
 
 
 def test_footprint_counts_buffers(gq):
