@@ -31,9 +31,10 @@ constexpr int kMwgMinN = 768;
 // keep them in a device scratch of kDcGlobalStride doubles per eigenvalue.
 constexpr int kDcLdsMaxM = 1024;
 constexpr int kDcGlobalStride = 17;
-// Device scratch of the multi-workgroup reduction per subgraph (doubles):
-// v (kMaxN + 8 padded), p (kMaxN), the panel products (32), slab sums (64).
-constexpr int kMwgSlot = 2 * kMaxN + 8 + 32 + 64;
+// Device scratch of the multi-workgroup reduction per subgraph (doubles): v
+// (kMaxN), the panel products (32), the row and column partials of the
+// (kMaxN/64)(kMaxN/64 + 1)/2 lower 64x64 tiles (64 each).
+constexpr int kMwgSlot = kMaxN + 32 + 2 * 64 * ((kMaxN / 64) * (kMaxN / 64 + 1) / 2);
 // Largest tridiagonal block solved directly in the divide-and-conquer tree.
 constexpr int kLeaf = 16;
 // Largest core (orbitals).  The core-row products (density rows, T = Q_c Y,

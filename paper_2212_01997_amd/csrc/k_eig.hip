@@ -412,41 +412,53 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
 
 // ---------------------------------------------------------------------------
 // Multi-workgroup reduction of the subgraphs of kMwgMinN orbitals and more
-// (up to kMaxN): the blocked algorithm of k_tridiag (panels of kPanel reflectors
-// formed against the stale trailing matrix plus the panel corrections, then a
-// rank-2 kPanel update on MFMA), with each step spread over workgroups and the
-// kernel launches as the only synchronisation:
+// (up to kMaxN): the blocked algorithm of k_tridiag (panels of kPanel
+// reflectors formed against the stale trailing matrix plus the panel
+// corrections, then a rank-2 kPanel update on MFMA), with each step spread
+// over workgroups and the kernel launches as the only synchronisation.  Only
+// the lower triangle of the trailing matrix, in absolute 64x64 tiles (I >= J),
+// is read and kept up to date; diagonal tiles are kept whole.
 //   k_td_col     one 1024-thread workgroup per subgraph (two rows per
-//                thread): completes w = p - (tau/2)(p.v) v of the previous
-//                column from the slab sums, then forms the current column,
-//                its reflector (v, tau, beta) and the panel products W^T v and
-//                V^T v;
-//   k_td_symv    row slabs of kSlabRows rows on separate workgroups: p = tau
-//                (A v - V (W^T v) - W (V^T v)) on the slab's rows, and the
-//                slab's share of p.v;
-//   k_td_update  64x64 blocks of the trailing matrix on separate workgroups:
-//                A -= V W^T + W V^T on MFMA;
+//                thread): completes the previous column's p from the tile
+//                partials (fixed order), its panel corrections and tau, then
+//                w = p - (tau/2)(p.v) v; forms the current column, its
+//                reflector (v, tau, beta) and the panel products W^T v, V^T v;
+//   k_td_symv    one workgroup per lower tile (I, J) of the trailing matrix:
+//                the row partials A_IJ v_J and, off the diagonal, the column
+//                partials A_IJ^T v_I (the upper tile's share by symmetry);
+//   k_td_update  one workgroup per lower tile: A -= V W^T + W V^T on MFMA for
+//                the rows and columns of the trailing matrix;
 //   k_td_final   the last two diagonal entries and the last off-diagonal one.
 // Every listed subgraph takes part in each launch (one whose reduction has
 // ended returns at once).  Reflectors, d, e and tau are stored as k_tridiag
 // stores them, so the divide and conquer and the back-transformation are
-// shared.  Per subgraph the scratch slot holds v (kUnroll zeros after row n),
-// p, the panel products (W^T v, then V^T v) and the slab sums.
-constexpr int kSlabRows = 64;      // one wave's rows
-constexpr int kSlabThreads = 256;  // four threads per row
+// shared.  Per subgraph the scratch slot holds v (zero from row n), the panel
+// products (W^T v, then V^T v) and the row and column partials of every lower
+// tile.
 constexpr int kTdRows = kMaxN / kTdThreads;
+constexpr int kTdBlocks = kMaxN / 64;
+constexpr int kTdTiles = kTdBlocks * (kTdBlocks + 1) / 2;
 
 struct MwgSlot {
-  double *v, *p, *y, *sums;
+  double *v, *y, *rowp, *colp;
   __device__ MwgSlot(double* base) {
-    v = base;
-    p = v + kMaxN + kUnroll;
-    y = p + kMaxN;
-    sums = y + 2 * kPanel;
+    v = base;               // [kMaxN]
+    y = v + kMaxN;          // [2 kPanel]
+    rowp = y + 2 * kPanel;  // [kTdTiles][64]
+    colp = rowp + (size_t)kTdTiles * 64;
   }
 };
-static_assert(2 * kMaxN + kUnroll + 2 * kPanel + 64 <= kMwgSlot, "scratch slot too small");
-static_assert(kMaxN / kSlabRows <= 64, "slab sums");
+static_assert(kMaxN + 2 * kPanel + 2 * kTdTiles * 64 <= kMwgSlot, "scratch slot too small");
+
+// Index of the lower tile (I, J), J <= I, and its inverse.
+__device__ __forceinline__ int tile_id(int I, int J) { return I * (I + 1) / 2 + J; }
+__device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i + 1) / 2;
+}
 
 __global__ __launch_bounds__(kTdThreads) void k_td_col(
     double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
@@ -454,8 +466,7 @@ __global__ __launch_bounds__(kTdThreads) void k_td_col(
     double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU,
     double* __restrict__ mwg, int k0, int j) {
   __shared__ __align__(16) double vl[kMaxN];
-  __shared__ double red[kTdThreads / 64];
-  __shared__ double yp[kTdThreads / 32][2 * kPanel + 1];
+  __shared__ double red[2][kTdThreads / 64];  // the two workgroup sums
   __shared__ double rowc[2 * kPanel];
   __shared__ double alpha_sh;
   const int s = order[blockIdx.x];
@@ -467,29 +478,49 @@ __global__ __launch_bounds__(kTdThreads) void k_td_col(
   double* A = abuf + off2[s];
   double* Wg = wsc + (size_t)b * kPanel;  // W[q * n + r]
   MwgSlot sl(mwg + (size_t)blockIdx.x * kMwgSlot);
-  const int tid = threadIdx.x;
-  // w of the previous column: p and the slab sums come from k_td_symv
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // the previous column cp: p from the tile partials and the panel
+  // corrections, then w; wprev keeps w of this thread's rows
+  double wprev[kTdRows];
+#pragma unroll
+  for (int u = 0; u < kTdRows; ++u) wprev[u] = 0.0;
   if (j >= 1) {
     const int cp = k0 + j - 1;
     const double tp = TAU[b + cp];
-    if (tp != 0.0) {
-      double S = 0.0;
-      for (int gg = (cp + 1) / kSlabRows; gg < (n + kSlabRows - 1) / kSlabRows; ++gg) S += sl.sums[gg];
-      const double K = 0.5 * tp * S;
+    const int B0 = (cp + 1) / 64, NB = (n + 63) / 64;
+    double pr[kTdRows], pv = 0.0;
 #pragma unroll
-      for (int u = 0; u < kTdRows; ++u) {
-        const int r = tid + u * kTdThreads;
-        if (r < n) Wg[(j - 1) * n + r] = r >= cp + 1 ? sl.p[r] - K * sl.v[r] : 0.0;
+    for (int u = 0; u < kTdRows; ++u) {
+      const int r = tid + u * kTdThreads;
+      pr[u] = 0.0;
+      if (tp != 0.0 && r < n && r >= cp + 1) {
+        const int I = r >> 6, i = r & 63;
+        double acc = 0.0;
+        for (int J = B0; J <= I; ++J) acc += sl.rowp[(size_t)tile_id(I, J) * 64 + i];
+        for (int Ip = I + 1; Ip < NB; ++Ip) acc += sl.colp[(size_t)tile_id(Ip, I) * 64 + i];
+        for (int q = 0; q < j - 1; ++q)
+          acc -= A[r + (size_t)n * (k0 + q)] * sl.y[q] + Wg[q * n + r] * sl.y[kPanel + q];
+        pr[u] = tp * acc;
+        pv += pr[u] * sl.v[r];
+      }
+    }
+    const double K = 0.5 * tp * tsum(pv, red[0]);
+#pragma unroll
+    for (int u = 0; u < kTdRows; ++u) {
+      const int r = tid + u * kTdThreads;
+      if (tp != 0.0 && r < n) {
+        wprev[u] = r >= cp + 1 ? pr[u] - K * sl.v[r] : 0.0;
+        Wg[(j - 1) * n + r] = wprev[u];
       }
     }
   }
   if (j == nb) return;
   const int c = k0 + j;
-  __syncthreads();  // w_{j-1} of row c is read below by the threads < j
-  if (tid < j) {
-    rowc[tid] = A[c + (size_t)n * (k0 + tid)];
-    rowc[kPanel + tid] = Wg[tid * n + c];
-  }
+  // row c's panel entries: earlier columns from memory, column j - 1's w from
+  // the thread that owns row c
+  if (tid < j) rowc[tid] = A[c + (size_t)n * (k0 + tid)];
+  if (tid + 1 < j) rowc[kPanel + tid] = Wg[tid * n + c];
+  if (j >= 1 && (c % kTdThreads) == tid) rowc[kPanel + j - 1] = wprev[c / kTdThreads];
   __syncthreads();
   // the current column: A[r, c] - sum_q (v_q[r] w_q[c] + w_q[r] v_q[c]), r >= c
   double a[kTdRows];
@@ -500,15 +531,17 @@ __global__ __launch_bounds__(kTdThreads) void k_td_col(
     a[u] = 0.0;
     if (r < n && r >= c) {
       double x = A[r + (size_t)n * c];
-      for (int q = 0; q < j; ++q)
+      for (int q = 0; q + 1 < j; ++q)
         x -= A[r + (size_t)n * (k0 + q)] * rowc[kPanel + q] + Wg[q * n + r] * rowc[q];
+      if (j >= 1)
+        x -= A[r + (size_t)n * (k0 + j - 1)] * rowc[kPanel + j - 1] + wprev[u] * rowc[j - 1];
       a[u] = x;
       if (r == c) D[b + c] = x;
       if (r == c + 1) alpha_sh = x;
       if (r >= c + 2) sq += x * x;
     }
   }
-  const double sigma = tsum(sq, red);  // its barrier also publishes alpha_sh
+  const double sigma = tsum(sq, red[1]);  // its barrier also publishes alpha_sh
   const double alpha = alpha_sh;
   double tau = 0.0, beta = alpha, scale = 0.0;
   if (sigma != 0.0) {
@@ -530,44 +563,41 @@ __global__ __launch_bounds__(kTdThreads) void k_td_col(
       if (tau == 0.0) Wg[j * n + r] = 0.0;
     }
   }
-  if (tid < kUnroll) sl.v[n + tid] = 0.0;
   if (tid == 0) {
     TAU[b + c] = tau;
     E[b + c] = beta;
   }
   if (tau == 0.0) return;
   __syncthreads();
-  // y = (W^T v, V^T v) over the panel so far, rows > c: thread t sums panel
-  // column t mod 32 (W for q < kPanel, V above) over rows c+1+seg, c+1+seg+32,
-  // ... of segment seg = t / 32; the segments are added in order
-  {
-    const int q = tid & 31, seg = tid >> 5;
-    const int qp = q & (kPanel - 1);
-    double t = 0.0;
-    if (qp < j) {
-      const bool isw = q < kPanel;
-      for (int row = c + 1 + seg; row < n; row += kTdThreads / 32)
-        t += (isw ? Wg[qp * n + row] : A[row + (size_t)n * (k0 + qp)]) * vl[row];
+  // y = (W^T v, V^T v) over the panel so far, rows > c: wave q takes panel
+  // column q, its lanes 64-row strides, then a wave sum
+  if (wv < j) {
+    double t1 = 0.0, t2 = 0.0;
+    for (int r = c + 1 + lane; r < n; r += 64) {
+      t1 += Wg[wv * n + r] * vl[r];
+      t2 += A[r + (size_t)n * (k0 + wv)] * vl[r];
     }
-    yp[seg][q] = t;
-  }
-  __syncthreads();
-  if (tid < 2 * kPanel) {
-    double t = 0.0;
-    if ((tid % kPanel) < j)
-      for (int sg = 0; sg < kTdThreads / 32; ++sg) t += yp[sg][tid];
-    sl.y[tid] = t;
+    t1 = wave_total(t1);
+    t2 = wave_total(t2);
+    if (lane == 0) {
+      sl.y[wv] = t1;
+      sl.y[kPanel + wv] = t2;
+    }
   }
 }
 
-__global__ __launch_bounds__(kSlabThreads) void k_td_symv(
-    const double* __restrict__ abuf, const double* __restrict__ wsc,
-    const int64_t* __restrict__ off2, const int32_t* __restrict__ sub_orb_ptr,
-    const int32_t* __restrict__ order, const double* __restrict__ TAU, double* __restrict__ mwg,
-    int k0, int j) {
-  __shared__ __align__(16) double vl[kMaxN + kUnroll];
-  __shared__ double part[kSlabThreads];
-  __shared__ double ys[2 * kPanel];
+// Tile (I, J) of the trailing matrix (absolute 64-row blocks, B0 <= J <= I,
+// B0 the block of row c + 1): wave w takes the tile's columns 16w .. 16w+15,
+// lane l its row 64 I + l.  Row partials: sum over the tile's columns of
+// A v; column partials (I > J): sum over the tile's rows of A^T v, reduced
+// across the lanes by halving exchanges (each step keeps half of the columns
+// and adds the partner's share), so lane l ends with column (l / 4) mod 16.
+__global__ __launch_bounds__(256) void k_td_symv(
+    const double* __restrict__ abuf, const int64_t* __restrict__ off2,
+    const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
+    const double* __restrict__ TAU, double* __restrict__ mwg, int k0, int j) {
+  __shared__ double vr[64], vc[64];
+  __shared__ double rp[4][64];
   const int s = order[blockIdx.y];
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
@@ -575,39 +605,62 @@ __global__ __launch_bounds__(kSlabThreads) void k_td_symv(
   const int nb = min(kPanel, n - 2 - k0);
   if (j >= nb) return;
   const int c = k0 + j;
-  const int r0 = blockIdx.x * kSlabRows;
-  if (r0 >= n || r0 + kSlabRows <= c + 1) return;
-  const double tau = TAU[b + c];
-  if (tau == 0.0) return;
-  const double* A = abuf + off2[s];
-  const double* Wg = wsc + (size_t)b * kPanel;
+  if (TAU[b + c] == 0.0) return;
+  const int B0 = (c + 1) / 64, NB = (n + 63) / 64, nt = NB - B0;
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  I += B0;
+  J += B0;
   MwgSlot sl(mwg + (size_t)blockIdx.y * kMwgSlot);
-  const int tid = threadIdx.x;
-  // v from the first chunk symv_row reads (columns below it are not read)
-  for (int i = (c + 1) / kUnroll * kUnroll + tid; i < n + kUnroll; i += kSlabThreads) vl[i] = sl.v[i];
-  if (tid < 2 * kPanel) ys[tid] = sl.y[tid];
-  __syncthreads();
-  constexpr int H = kSlabThreads / kSlabRows;
-  const int rl = tid % kSlabRows, h = tid / kSlabRows;
-  const int r = r0 + rl;
-  double unused = 0.0;
-  part[tid] = (r >= c + 1 && r < n) ? symv_row(A + r, vl, n, c, h, H, unused) : 0.0;
-  __syncthreads();
-  if (tid < kSlabRows) {  // the first wave, all lanes
-    double p = 0.0;
-    if (r >= c + 1 && r < n) {
-#pragma unroll
-      for (int hh = 0; hh < H; ++hh) p += part[hh * kSlabRows + rl];
-      for (int q = 0; q < j; ++q)
-        p -= A[r + (size_t)n * (k0 + q)] * ys[q] + Wg[q * n + r] * ys[kPanel + q];
-      p *= tau;
-      sl.p[r] = p;
-    }
-    const double pv = wave_total(r >= c + 1 && r < n ? p * vl[r] : 0.0);
-    if (tid == 0) sl.sums[blockIdx.x] = pv;
+  const double* A = abuf + off2[s];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid < 64) {
+    const int r = 64 * I + tid;
+    vr[tid] = r < n ? sl.v[r] : 0.0;
+  } else if (tid < 128) {
+    const int k = 64 * J + tid - 64;
+    vc[tid - 64] = k < n ? sl.v[k] : 0.0;
   }
+  __syncthreads();
+  const int rc = min(64 * I + lane, n - 1);
+  double x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = A[rc + (size_t)n * min(64 * J + 16 * wv + k, n - 1)];
+  double rs = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) rs += x[k] * vc[16 * wv + k];
+  rp[wv][lane] = rs;
+  const int t = tile_id(I, J);
+  if (I > J) {
+    const double vi = vr[lane];
+    double y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) y[k] = x[k] * vi;
+    double y8[8], y4[4], y2[2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      y8[k] = (b5 ? y[k + 8] : y[k]) + __shfl_xor(b5 ? y[k] : y[k + 8], 32, 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      y4[k] = (b4 ? y8[k + 4] : y8[k]) + __shfl_xor(b4 ? y8[k] : y8[k + 4], 16, 64);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      y2[k] = (b3 ? y4[k + 2] : y4[k]) + __shfl_xor(b3 ? y4[k] : y4[k + 2], 8, 64);
+    double z = (b2 ? y2[1] : y2[0]) + __shfl_xor(b2 ? y2[0] : y2[1], 4, 64);
+    z += __shfl_xor(z, 2, 64);
+    z += __shfl_xor(z, 1, 64);
+    if ((lane & 3) == 0) sl.colp[(size_t)t * 64 + 16 * wv + ((lane >> 2) & 15)] = z;
+  }
+  __syncthreads();
+  if (tid < 64) sl.rowp[(size_t)t * 64 + tid] = (rp[0][tid] + rp[1][tid]) + (rp[2][tid] + rp[3][tid]);
 }
 
+// Lower tile (BI, BJ), BT <= BJ <= BI with BT the block of row t0: the
+// rank-2 kPanel update of its elements in rows and columns >= t0, by its
+// sixteen 16x16 sub-tiles (four per wave); element (row0 + j, col0 + i) in
+// lane j + 16 (i % 4), register i / 4, as in k_tridiag.
 __global__ __launch_bounds__(256) void k_td_update(
     double* __restrict__ abuf, const double* __restrict__ wsc, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order, int k0) {
@@ -617,20 +670,21 @@ __global__ __launch_bounds__(256) void k_td_update(
   if (k0 + 2 >= n) return;
   const int nb = min(kPanel, n - 2 - k0);
   const int t0 = k0 + nb;
-  const int nt = (n - t0 + 63) / 64;
-  if ((int)blockIdx.x >= nt * nt) return;
-  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
+  const int BT = t0 / 64, NB = (n + 63) / 64, nt = NB - BT;
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int BI, BJ;
+  tile_ij(blockIdx.x, BI, BJ);
+  BI += BT;
+  BJ += BT;
   double* A = abuf + off2[s];
   const double* Wg = wsc + (size_t)b * kPanel;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  // the block's sixteen 16x16 tiles, four per wave; tile element (row0 + j,
-  // col0 + i) in lane j + 16 (i % 4), register i / 4, as in k_tridiag
 #pragma unroll 1
   for (int tile = wv; tile < 16; tile += 4) {
-    const int row0 = t0 + 64 * bi + 16 * (tile / 4), col0 = t0 + 64 * bj + 16 * (tile % 4);
+    const int row0 = 64 * BI + 16 * (tile / 4), col0 = 64 * BJ + 16 * (tile % 4);
     const int row = row0 + li;
-    const bool rok = row < n;
+    const bool rok = row >= t0 && row < n;
     const int cl = col0 + li;
     const bool cok = cl < n;
     const int rowc_ = min(row, n - 1), clc = min(cl, n - 1);
@@ -647,7 +701,7 @@ __global__ __launch_bounds__(256) void k_td_update(
     }
     v4d acc;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = (rok && col0 + 4 * i + lk < n) ? a4[i] : 0.0;
+    for (int i = 0; i < 4; ++i) acc[i] = a4[i];
 #pragma unroll
     for (int kq = 0; kq < kPanel / 4; ++kq) {
       const bool qok = 4 * kq + lk < nb;
@@ -662,7 +716,7 @@ __global__ __launch_bounds__(256) void k_td_update(
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int col = col0 + 4 * i + lk;
-        if (col < n) A[row + (size_t)n * col] = acc[i];
+        if (col >= t0 && col < n) A[row + (size_t)n * col] = acc[i];
       }
     }
   }
@@ -688,24 +742,26 @@ __global__ void k_td_final(const double* __restrict__ abuf, const int64_t* __res
 
 // The multi-workgroup reduction of order[0..n_mwg) on stream st: per panel,
 // kPanel column steps (k_td_col, k_td_symv) and one k_td_col that completes
-// the panel's last w, then the trailing update.
+// the panel's last w, then the trailing update of the lower tiles.
 static void launch_tridiag_mwg(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st) {
   const gq_graph_dev& dv = g->dev;
   const int nh = g->n_mwg;
   const int maxn = g->sub_orb_ptr[g->order[0] + 1] - g->sub_orb_ptr[g->order[0]];
-  const int nslab = (maxn + kSlabRows - 1) / kSlabRows;
+  const int NB = (maxn + 63) / 64;
   prof_begin_on(ctx, "k_tridiag_mwg", st);
   for (int k0 = 0; k0 + 2 < maxn; k0 += kPanel) {
     const int nbmax = std::min(kPanel, maxn - 2 - k0);
+    // lower tiles from the block of row k0 (an upper bound for every column
+    // of the panel and for the update from row t0 > k0)
+    const int nt = NB - k0 / 64, ntiles = nt * (nt + 1) / 2;
     for (int j = 0; j <= nbmax; ++j) {
       hipLaunchKernelGGL(k_td_col, dim3(nh), dim3(kTdThreads), 0, st, e->A, e->wsc, dv.off2,
                          dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau, e->mwg, k0, j);
       if (j < nbmax)
-        hipLaunchKernelGGL(k_td_symv, dim3(nslab, nh), dim3(kSlabThreads), 0, st, e->A, e->wsc,
-                           dv.off2, dv.sub_orb_ptr, dv.order, e->tau, e->mwg, k0, j);
+        hipLaunchKernelGGL(k_td_symv, dim3(ntiles, nh), dim3(256), 0, st, e->A, dv.off2,
+                           dv.sub_orb_ptr, dv.order, e->tau, e->mwg, k0, j);
     }
-    const int nt = (maxn - k0 + 63) / 64;
-    hipLaunchKernelGGL(k_td_update, dim3(nt * nt, nh), dim3(256), 0, st, e->A, e->wsc, dv.off2,
+    hipLaunchKernelGGL(k_td_update, dim3(ntiles, nh), dim3(256), 0, st, e->A, e->wsc, dv.off2,
                        dv.sub_orb_ptr, dv.order, k0);
   }
   hipLaunchKernelGGL(k_td_final, dim3(nh), dim3(64), 0, st, e->A, dv.off2, dv.sub_orb_ptr,
