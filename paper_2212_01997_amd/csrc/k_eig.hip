@@ -494,12 +494,31 @@ __global__ __launch_bounds__(kTdThreads) void k_td_col(
       const int r = tid + u * kTdThreads;
       pr[u] = 0.0;
       if (tp != 0.0 && r < n && r >= cp + 1) {
-        const int I = r >> 6, i = r & 63;
+        // the partials of blocks B0 + t, t ascending: row partials of tiles
+        // (I, B0 + t) up to the diagonal, column partials of tiles (B0 + t, I)
+        // below it; all loads issued before the sum (unused terms read a
+        // valid entry and are dropped)
+        const int I = r >> 6, i = r & 63, cnt = NB - B0;
+        double pt[kTdBlocks];
+#pragma unroll
+        for (int t = 0; t < kTdBlocks; ++t) {
+          const int K2 = min(B0 + t, NB - 1);
+          pt[t] = K2 <= I ? sl.rowp[(size_t)tile_id(I, K2) * 64 + i]
+                          : sl.colp[(size_t)tile_id(K2, I) * 64 + i];
+        }
         double acc = 0.0;
-        for (int J = B0; J <= I; ++J) acc += sl.rowp[(size_t)tile_id(I, J) * 64 + i];
-        for (int Ip = I + 1; Ip < NB; ++Ip) acc += sl.colp[(size_t)tile_id(Ip, I) * 64 + i];
-        for (int q = 0; q < j - 1; ++q)
-          acc -= A[r + (size_t)n * (k0 + q)] * sl.y[q] + Wg[q * n + r] * sl.y[kPanel + q];
+#pragma unroll
+        for (int t = 0; t < kTdBlocks; ++t) acc += t < cnt ? pt[t] : 0.0;
+        double cv[kPanel], cw[kPanel];
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q) {
+          const int qc = min(q, max(j - 2, 0));
+          cv[q] = A[r + (size_t)n * (k0 + qc)];
+          cw[q] = Wg[qc * n + r];
+        }
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q)
+          if (q < j - 1) acc -= cv[q] * sl.y[q] + cw[q] * sl.y[kPanel + q];
         pr[u] = tp * acc;
         pv += pr[u] * sl.v[r];
       }
