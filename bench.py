@@ -549,7 +549,8 @@ def form_large(ctx, side):
     atoms on a jittered lattice with the complete graph and 128-atom cores
     (16 subgraphs of 2,048).  Ground state (eigensolve, mu, density rows) and
     K = 6 FP64 responses; the reduction priced on 4/3 n^3 flops and on the
-    (8/3) n^3 bytes its per-column products and panel updates stream."""
+    (4/3) n^3 bytes its per-column products stream (the lower triangle of the
+    trailing matrix once per column)."""
     import numpy as np
     from paper_2212_01997_amd import gq, inputs as I
     from paper_2212_01997_amd.path import GraphPath
@@ -575,7 +576,7 @@ def form_large(ctx, side):
         mwg = sizes[sizes >= 768]
         red_ms = kt["k_tridiag_mwg"][1]
         flops = (4.0 / 3.0) * (mwg ** 3).sum()
-        bytes_ = (8.0 / 3.0) * (mwg ** 3).sum()
+        bytes_ = (4.0 / 3.0) * (mwg ** 3).sum()
         log(f"large {name}: ground {_pct(ground, 50):.1f} ms, K = 6 responses "
             f"{_pct(resp, 50):.1f} ms, multi-workgroup reduction {red_ms:.1f} ms")
         out[name] = {
