@@ -432,9 +432,9 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
 // Every listed subgraph takes part in each launch (one whose reduction has
 // ended returns at once).  Reflectors, d, e and tau are stored as k_tridiag
 // stores them, so the divide and conquer and the back-transformation are
-// shared.  Per subgraph the scratch slot holds v (zero from row n), the panel
-// products (W^T v, then V^T v) and the row and column partials of every lower
-// tile.
+// shared.  Per subgraph the scratch slot holds v (rows < n; readers mask the
+// rest), the panel products (W^T v, then V^T v) and the row and column
+// partials of every lower tile.
 constexpr int kTdRows = kMaxN / kTdThreads;
 constexpr int kTdBlocks = kMaxN / 64;
 constexpr int kTdTiles = kTdBlocks * (kTdBlocks + 1) / 2;
