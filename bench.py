@@ -637,7 +637,7 @@ def main():
                     help="skip the served, batched and temperature forms and the 1,000-water step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 256 MiB (reference for byte counters)")
-    ap.add_argument("--only-form", choices=["large", "config2"],
+    ap.add_argument("--only-form", choices=["large", "config2", "served"],
                     help="run only this form (for profiling) and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -649,7 +649,9 @@ def main():
         from paper_2212_01997_amd import gq
         side = torch.cuda.Stream()
         ctx = gq.Context(0, stream=side)
-        out = form_large(ctx, side) if args.only_form == "large" else config2_step(ctx, side, args.steps)
+        out = (form_large(ctx, side) if args.only_form == "large"
+               else form_served(ctx, side) if args.only_form == "served"
+               else config2_step(ctx, side, args.steps))
         print(json.dumps({"form": args.only_form, **out}), flush=True)
         return
 
