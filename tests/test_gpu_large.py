@@ -17,6 +17,8 @@ Cases:
 - 768 hydrogen atoms likewise: six subgraphs of exactly 768 orbitals;
 - 200 isolated waters, complete graph: ten block-diagonal subgraphs of 1,200
   orbitals, where most columns are already reduced (identity reflectors).
+Beside the eigensolve path: the zero-temperature density by purification
+(batched products) and the non-orthogonal basis on these sizes.
 """
 import os
 import sys
@@ -164,3 +166,86 @@ def test_large_capture_replay(oracle_lib):
         side.synchronize()
         assert not torch.equal(p.rho1_view(2), ref[1])
     del x
+
+
+def _gershgorin(O, s, g, mu):
+    H = O.Csr(s.h_row_ptr, s.h_col, s.h_val)
+    R = 0.0
+    for i in range(g.n_sub):
+        h = O.gather(H, g.orbs(i))
+        R = max(R, float(np.abs(h - mu * np.eye(h.shape[0])).sum(axis=1).max()))
+    return R
+
+
+@pytest.mark.parametrize("name", ["lattice768", "isolated1200"])
+def test_large_purify(ctx, oracle_lib, name):
+    """The zero-temperature density by purification (batched products over
+    the lower tiles of subgraphs of 768 and 1,200 orbitals) against the step
+    density of the oracle, within the bar of the purification tests
+    (64 n u R / gap: R the largest Gershgorin radius of h_i - mu I, gap the
+    distance of the nearest subgraph eigenvalue to mu); then the eigensolve
+    path again, unchanged."""
+    from oracle import foe as F
+    from paper_2212_01997_amd.path import GraphPath
+    O = oracle_lib
+    s, core, tau, flags = _case(name, O)
+    g = O.graph_build(s, core, tau, flags=flags)
+    r = O.solve_pool(s, g, KT, workers=min(16, os.cpu_count() or 1))
+    mu = F.mid_gap(r.eps, r.mu)
+    ref, gap = F.purified_density(s, g, mu)
+    tol = 64 * int(g.sizes().max()) * 2.0 ** -53 * _gershgorin(O, s, g, mu) / gap
+    p = GraphPath(ctx, s, core, tau, None, flags)
+    it = p.purified_state(mu, max_iter=80)
+    err = float(np.abs(p.rho.cpu().numpy() - ref).max())
+    _say(f"{name} purify: gap {gap:.2e} iterations {it} |drho| {err:.1e} (bar {tol:.1e})")
+    assert err <= tol and it < 80
+    assert abs(p.ground_state(KT) - r.mu) <= 1e-12
+    assert np.abs(p.rho.cpu().numpy() - r.rho).max() <= 1e-10
+
+
+def test_large_overlap(ctx, oracle_lib):
+    """The non-orthogonal basis on six subgraphs of 768 orbitals (Lowdin
+    factors by batched products, two eigensolves on the multi-workgroup path)
+    against the overlap oracle: mu 1e-12, atomic-orbital rho, rho1 and mu1
+    1e-10."""
+    import torch
+    from oracle import overlap as V
+    from paper_2212_01997_amd import gq
+    from paper_2212_01997_amd.path import GraphPath
+    O = oracle_lib
+    s, core, tau, flags = _case("lattice768", O)
+    g = O.graph_build(s, core, tau, flags=flags)
+    S = I.overlap_matrix(s)
+    h1 = I.h1_diagonal(s, 2, seed=4005)
+    ref = V.solve(s, S, g, KT, h1)
+    p = GraphPath(ctx, s, core, tau, None, flags, max_k=2, S=S)
+    mu = p.ground_state(KT)
+    mu1 = p.respond(torch.as_tensor(h1, device="cuda"))
+    p.sync()
+    err = {"mu": abs(mu - ref.mu), "rho": float(np.abs(p.rho.cpu().numpy() - ref.rho_ao).max()),
+           "rho1": float(np.abs(p.rho1_view(2).cpu().numpy() - ref.rho1_ao).max()),
+           "mu1": float(np.abs(mu1 - ref.mu1).max())}
+    _say("lattice768 overlap: " + " ".join(f"{k} {v:.1e}" for k, v in err.items()))
+    assert err["mu"] <= 1e-12
+    assert max(err["rho"], err["rho1"], err["mu1"]) <= 1e-10
+
+
+def test_large_identity_overlap(ctx, oracle_lib):
+    """S = I on subgraphs of 1,200 orbitals: the non-orthogonal path equals
+    the orthogonal one."""
+    import torch
+    from paper_2212_01997_amd.path import GraphPath
+    s, core, tau, flags = _case("isolated1200", oracle_lib)
+    n = s.n_orb
+    eye = (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    h1 = torch.as_tensor(I.h1_diagonal(s, 1, seed=4006), device="cuda")
+    a = GraphPath(ctx, s, core, tau, None, flags, max_k=1, S=eye)
+    b = GraphPath(ctx, s, core, tau, None, flags, max_k=1)
+    mus = (a.ground_state(KT), b.ground_state(KT))
+    mu1s = (a.respond(h1), b.respond(h1))
+    a.sync()
+    b.sync()
+    assert abs(mus[0] - mus[1]) <= 1e-13
+    assert (a.rho - b.rho).abs().max().item() <= 1e-12
+    assert (a.rho1_view(1) - b.rho1_view(1)).abs().max().item() <= 1e-12
+    assert np.abs(mu1s[0] - mu1s[1]).max() <= 1e-12
