@@ -213,6 +213,37 @@ struct PrepLds {
   int *perm, *defl, *nd, *rp, *ri, *org, *pos;
 };
 
+// Merges above kDcLdsMaxM: the arrays the O(k^2) loops read (delta, z2, tau,
+// zhat, vals, org) in LDS, the others in the device scratch.
+constexpr int kDcHotBytes = 5 * sizeof(double) + sizeof(int);  // per eigenvalue
+__device__ PrepLds carve_split(void* lds, double* glob, int m) {
+  PrepLds L;
+  double* hp = reinterpret_cast<double*>(lds);
+  L.delta = hp; hp += m;
+  L.z2 = hp; hp += m;
+  L.tau = hp; hp += m;
+  L.zhat = hp; hp += m;
+  L.vals = hp; hp += m;
+  L.org = reinterpret_cast<int*>(hp);
+  double* dp = glob;
+  L.D = dp; dp += m;
+  L.z = dp; dp += m;
+  L.dS = dp; dp += m;
+  L.zS = dp; dp += m;
+  L.rc = dp; dp += m;
+  L.rs = dp; dp += m;
+  L.zeta = dp; dp += m;
+  L.inv = dp; dp += m;
+  int* ip = reinterpret_cast<int*>(dp);
+  L.perm = ip; ip += m;
+  L.defl = ip; ip += m;
+  L.nd = ip; ip += m;
+  L.rp = ip; ip += m;
+  L.ri = ip; ip += m;
+  L.pos = ip; ip += m;
+  return L;
+}
+
 __device__ PrepLds carve(void* base, int m) {
   PrepLds L;
   double* dp = reinterpret_cast<double*>(base);
@@ -367,9 +398,9 @@ __device__ int compact(int m, F flag, int* out, int base, int* wtot) {
   return total;
 }
 
-// GL: the merge's work arrays live in the device scratch gscr (kDcGlobalStride
-// doubles per eigenvalue and workgroup) instead of LDS, for merges above
-// kDcLdsMaxM eigenvalues.
+// GL: for merges above kDcLdsMaxM eigenvalues, the work arrays of the O(m)
+// steps live in the device scratch gscr (kDcGlobalStride doubles per
+// eigenvalue and workgroup) and only those the O(k^2) loops read in LDS.
 template <int NT, bool GL>
 __global__ __launch_bounds__(NT) void k_dc_prep(
     const int32_t* __restrict__ merges, const int32_t* __restrict__ sub_orb_ptr,
@@ -389,7 +420,8 @@ __global__ __launch_bounds__(NT) void k_dc_prep(
   const int b = sub_orb_ptr[s];
   const int n = sub_orb_ptr[s + 1] - b;
   double* Z = zbuf + off2[s];
-  PrepLds L = GL ? carve(gscr + (size_t)blockIdx.x * kMaxN * kDcGlobalStride, m) : carve(smem, m);
+  PrepLds L = GL ? carve_split(smem, gscr + (size_t)blockIdx.x * kMaxN * kDcGlobalStride, m)
+                 : carve(smem, m);
   const int tid = threadIdx.x;
 
   const double beta = E[b + lo + m1 - 1];
@@ -1184,6 +1216,8 @@ void dc_set_attributes() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kDcLdsMaxM));
   (void)hipFuncSetAttribute((const void*)k_dc_prep<1024, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dc_prep_lds(kDcLdsMaxM));
+  (void)hipFuncSetAttribute((const void*)k_dc_prep<1024, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxN * kDcHotBytes));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(256 * kLdv * sizeof(double)));
   (void)hipFuncSetAttribute((const void*)k_bt_mfma<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1226,7 +1260,8 @@ void launch_dc(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, int cls, hipStream_t 
     // arrays in device scratch (one slot per workgroup)
     const int nglob = g->dc_level_nglob[cls][lv];
     if (nglob > 0)
-      hipLaunchKernelGGL((k_dc_prep<1024, true>), dim3(nglob), dim3(1024), 0, st,
+      hipLaunchKernelGGL((k_dc_prep<1024, true>), dim3(nglob), dim3(1024),
+                         (size_t)kMaxN * kDcHotBytes, st,
                          dv.dc_merges + 4 * m0, dv.sub_orb_ptr, dv.off2, e->ee, zin, e->eps,
                          e->md_k + m0, e->md_cols, e->md_org, e->md_pos, e->md_dsrc, e->md_dpos,
                          e->md_delta, e->md_tau, e->md_zhat, e->md_inv, e->dcg);
