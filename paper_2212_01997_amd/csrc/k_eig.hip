@@ -759,15 +759,19 @@ __global__ void k_td_final(const double* __restrict__ abuf, const int64_t* __res
 
 }  // namespace
 
-// The multi-workgroup reduction of order[0..n_mwg) on stream st: per panel,
+// The multi-workgroup reduction of order[first..first+count) (scratch slots
+// from `first`) on stream st: per panel,
 // kPanel column steps (k_td_col, k_td_symv) and one k_td_col that completes
 // the panel's last w, then the trailing update of the lower tiles.
-static void launch_tridiag_mwg(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st) {
+static void launch_tridiag_mwg(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipStream_t st,
+                               int first, int count, const char* label) {
   const gq_graph_dev& dv = g->dev;
-  const int nh = g->n_mwg;
-  const int maxn = g->sub_orb_ptr[g->order[0] + 1] - g->sub_orb_ptr[g->order[0]];
+  const int nh = count;
+  const int32_t* order = dv.order + first;
+  double* slots = e->mwg + (size_t)first * kMwgSlot;
+  const int maxn = g->sub_orb_ptr[g->order[first] + 1] - g->sub_orb_ptr[g->order[first]];
   const int NB = (maxn + 63) / 64;
-  prof_begin_on(ctx, "k_tridiag_mwg", st);
+  prof_begin_on(ctx, label, st);
   for (int k0 = 0; k0 + 2 < maxn; k0 += kPanel) {
     const int nbmax = std::min(kPanel, maxn - 2 - k0);
     // lower tiles from the block of row k0 (an upper bound for every column
@@ -775,16 +779,16 @@ static void launch_tridiag_mwg(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipSt
     const int nt = NB - k0 / 64, ntiles = nt * (nt + 1) / 2;
     for (int j = 0; j <= nbmax; ++j) {
       hipLaunchKernelGGL(k_td_col, dim3(nh), dim3(kTdThreads), 0, st, e->A, e->wsc, dv.off2,
-                         dv.sub_orb_ptr, dv.order, e->dd, e->ee, e->tau, e->mwg, k0, j);
+                         dv.sub_orb_ptr, order, e->dd, e->ee, e->tau, slots, k0, j);
       if (j < nbmax)
         hipLaunchKernelGGL(k_td_symv, dim3(ntiles, nh), dim3(256), 0, st, e->A, dv.off2,
-                           dv.sub_orb_ptr, dv.order, e->tau, e->mwg, k0, j);
+                           dv.sub_orb_ptr, order, e->tau, slots, k0, j);
     }
     hipLaunchKernelGGL(k_td_update, dim3(ntiles, nh), dim3(256), 0, st, e->A, e->wsc, dv.off2,
-                       dv.sub_orb_ptr, dv.order, k0);
+                       dv.sub_orb_ptr, order, k0);
   }
   hipLaunchKernelGGL(k_td_final, dim3(nh), dim3(64), 0, st, e->A, dv.off2, dv.sub_orb_ptr,
-                     dv.order, e->dd, e->ee);
+                     order, e->dd, e->ee);
   prof_end(ctx);
 }
 
@@ -828,9 +832,23 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
     prof_end(ctx);
     launch_dc(ctx, g, e, 1, ctx->side);
   }
+  // with no small class the side stream is free: the multi-workgroup
+  // subgraphs go in two halves, the larger on the caller's stream and the
+  // smaller on the side stream, so that one half's single-workgroup column
+  // steps overlap the other half's tile products
+  const bool mwg_split = nsmall == 0 && g->n_mwg >= 2;
   if (nbig > 0) {
     const int nh = g->n_mwg;
-    if (nh > 0) launch_tridiag_mwg(ctx, g, e, st);
+    if (mwg_split) {
+      const int na = (nh + 1) / 2;
+      (void)hipEventRecord(ctx->ev_fork, st);
+      (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+      launch_tridiag_mwg(ctx, g, e, ctx->side, na, nh - na, "k_tridiag_mwg_b");
+      (void)hipEventRecord(ctx->ev_join, ctx->side);
+      launch_tridiag_mwg(ctx, g, e, st, 0, na, "k_tridiag_mwg");
+    } else if (nh > 0) {
+      launch_tridiag_mwg(ctx, g, e, st, 0, nh, "k_tridiag_mwg");
+    }
     if (nbig > nh) {
       const int n0 = g->sub_orb_ptr[g->order[nh] + 1] - g->sub_orb_ptr[g->order[nh]];
       prof_begin(ctx, "k_tridiag");
@@ -838,6 +856,7 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
                          e->wsc, dv.off2, dv.sub_orb_ptr, dv.order + nh, e->dd, e->ee, e->tau);
       prof_end(ctx);
     }
+    if (mwg_split) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
     launch_dc(ctx, g, e, 0, st);
   }
   if (nsmall > 0) {

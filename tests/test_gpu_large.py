@@ -127,14 +127,16 @@ def test_large_split32(ctx, oracle_lib):
     assert max(err["rho1"], err["mu1"]) <= 1e-6
 
 
-def test_large_capture_replay(oracle_lib):
-    """A step on subgraphs of 703..1,072 orbitals (several thousand launches
-    of the multi-workgroup reduction) recorded once and replayed three times,
-    with eager work in between: every replay gives the eager bits."""
+@pytest.mark.parametrize("name", ["mixed3", "mixed21"])
+def test_large_capture_replay(oracle_lib, name):
+    """A step on subgraphs of 703..1,072 orbitals (both size classes), or of
+    870..1,213 (all on the multi-workgroup path, in two halves on two
+    streams), recorded once and replayed three times, with eager work in
+    between: every replay gives the eager bits."""
     import torch
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
-    s, core, tau, flags = _case("mixed3", oracle_lib)
+    s, core, tau, flags = _case(name, oracle_lib)
     side = torch.cuda.Stream()
     cx = gq.Context(0, stream=side)
     p = GraphPath(cx, s, core, tau, None, flags, max_k=2)
@@ -153,7 +155,7 @@ def test_large_capture_replay(oracle_lib):
     cx.capture_begin()
     step(h1)
     x = cx.capture_end()
-    _say("large step captured")
+    _say(f"{name}: large step captured")
     for rep in range(3):
         p.rho.zero_()
         p.rho1.zero_()
