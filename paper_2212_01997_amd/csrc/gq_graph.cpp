@@ -310,25 +310,6 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
   });
   fwd.clear();
 
-  if (flags & GQ_PATHS2) {
-    std::vector<std::vector<int32_t>> two(n_atoms);
-    // the forward lists left atom ids in the marks: start from none
-    for (auto& st : stamp_t) std::fill(st.begin(), st.end(), -1);
-    parallel_for(n_atoms, 64, threads, [&](int tid, int64_t Ii) {
-      const int32_t I = (int32_t)Ii;
-      std::vector<int32_t>& stamp = stamp_t[tid];
-      auto& out = two[I];
-      stamp[I] = I;
-      for (int32_t J : nbr[I]) {
-        if (stamp[J] != I) { stamp[J] = I; out.push_back(J); }
-        for (int32_t L : nbr[J])
-          if (stamp[L] != I) { stamp[L] = I; out.push_back(L); }
-      }
-      std::sort(out.begin(), out.end());
-    });
-    nbr.swap(two);
-  }
-
   // subgraphs: core ascending (already, atoms were visited in order) ++ halo ascending
   g->n_atoms = n_atoms;
   g->N = N;
@@ -348,10 +329,20 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
         if (core_of_atom[I] != s) halo.push_back(I);
       return;
     }
+    // the halo: every atom within one edge of a core atom, or within two
+    // with paths of length two (the neighbours J of a core atom and, with
+    // GQ_PATHS2, the neighbours of every such J), minus the core; gathered
+    // per subgraph with marks, so the two-step neighbour lists of single
+    // atoms are never formed
+    const bool two = flags & GQ_PATHS2;
     for (int32_t I : cores[s]) mark[I] = s;
     for (int32_t I : cores[s])
-      for (int32_t J : nbr[I])
+      for (int32_t J : nbr[I]) {
         if (mark[J] != s) { mark[J] = s; halo.push_back(J); }
+        if (two)
+          for (int32_t L : nbr[J])
+            if (mark[L] != s) { mark[L] = s; halo.push_back(L); }
+      }
     std::sort(halo.begin(), halo.end());
   });
   for (int32_t s = 0; s < n_sub; ++s) {
@@ -411,9 +402,14 @@ gq_status graph_build_host(int32_t n_atoms, const int32_t* atom_orb_ptr, const g
     const int32_t s = (int32_t)si;
     const int32_t b = g->sub_orb_ptr[s], n = g->sub_orb_ptr[s + 1] - b;
     int32_t* loc = g->sorted_local.data() + b;
-    std::iota(loc, loc + n, 0);
     const int32_t* orbs = g->sub_orbs.data() + b;
-    std::sort(loc, loc + n, [&](int32_t x, int32_t y) { return orbs[x] < orbs[y]; });
+    // the core orbitals (ascending) come first, then the halo's (ascending),
+    // and no orbital is in both: the sorted order is the merge of the two runs
+    const int32_t nc = g->n_core_orbs[s];
+    int32_t i = 0, j = nc, r = 0;
+    while (i < nc && j < n) loc[r++] = orbs[i] < orbs[j] ? i++ : j++;
+    while (i < nc) loc[r++] = i++;
+    while (j < n) loc[r++] = j++;
     for (int32_t r = 0; r < n; ++r) {
       g->sorted_orbs[b + r] = orbs[loc[r]];
       g->slot[b + loc[r]] = r;
