@@ -543,6 +543,7 @@ void build_dc_plan(gq_graph* g) {
       const auto& v = by_depth[d];
       int32_t maxm_lds = 0, nglob = 0;
       int64_t msum = 0;
+      int64_t ntiles = 0;
       for (size_t q = 0; q < v.size(); q += 4) {
         const int32_t li = (int32_t)(q / 4);
         const int32_t m = v[q + 2] + v[q + 3];
@@ -551,9 +552,21 @@ void build_dc_plan(gq_graph* g) {
         // decreasing size; only a top merge can exceed it)
         if (m > kDcLdsMaxM) nglob = li + 1;
         else maxm_lds = std::max(maxm_lds, m);
-        const int32_t nt = (m + 63) / 64;
+        const int64_t nt = (m + 63) / 64;
+        ntiles += nt * nt;
+      }
+      size_t at = g->dc_tiles.size();
+      g->dc_tiles.resize(at + 3 * (size_t)ntiles);
+      int32_t* t = g->dc_tiles.data();
+      for (size_t q = 0; q < v.size(); q += 4) {
+        const int32_t li = (int32_t)(q / 4);
+        const int32_t nt = (v[q + 2] + v[q + 3] + 63) / 64;
         for (int32_t tr = 0; tr < nt; ++tr)
-          for (int32_t tc = 0; tc < nt; ++tc) g->dc_tiles.insert(g->dc_tiles.end(), {li, tr, tc});
+          for (int32_t tc = 0; tc < nt; ++tc) {
+            t[at++] = li;
+            t[at++] = tr;
+            t[at++] = tc;
+          }
       }
       g->dc_merges.insert(g->dc_merges.end(), v.begin(), v.end());
       mo.push_back((int32_t)(g->dc_merges.size() / 4));

@@ -1070,27 +1070,38 @@ void build_xy_tiles(gq_graph* g) {
     const int tm = shape == 0 ? 64 : 32;
     std::vector<int32_t>& tl = g->xy_tiles[shape];
     tl.clear();
+    {
+      // an upper bound of the list's length: every tile of every subgraph
+      size_t cap = 0;
+      for (int32_t s = 0; s < g->n_sub; ++s) {
+        const size_t nt = (g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s] + tm - 1) / tm;
+        cap += 3 * nt * nt;
+      }
+      tl.resize(cap);
+    }
+    size_t at = 0;  // ints written so far
     for (int bin = 0; bin < kXyBins; ++bin) {
       const int lo = bin == 0 ? 0 : kXyBinMax[bin - 1];
       const int hi = kXyBinMax[bin];
-      const int32_t start = (int32_t)(tl.size() / 3);
+      const int32_t start = (int32_t)(at / 3);
       std::vector<int32_t> sub_start;  // first tile of each subgraph of the bin
       for (int32_t s : g->order) {
         const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
         if (n <= lo || n > hi) continue;
-        sub_start.push_back((int32_t)(tl.size() / 3));
+        sub_start.push_back((int32_t)(at / 3));
         const int32_t nt = (n + tm - 1) / tm;
+        int32_t* t = tl.data();
         for (int32_t ti = 0; ti < nt; ++ti)
           for (int32_t tj = 0; tj < nt; ++tj) {
             // parent 64x64 tile on or below the diagonal
             if ((ti * tm) / 64 < (tj * tm) / 64) continue;
             if (tm == 64 && tj > ti) continue;
-            tl.push_back(s);
-            tl.push_back(ti);
-            tl.push_back(tj);
+            t[at++] = s;
+            t[at++] = ti;
+            t[at++] = tj;
           }
       }
-      const int32_t end = (int32_t)(tl.size() / 3);
+      const int32_t end = (int32_t)(at / 3);
       XcdSplit& sp = g->xy_split[shape][bin];
       const int64_t total = end - start;
       size_t next = 0;
@@ -1103,6 +1114,7 @@ void build_xy_tiles(gq_graph* g) {
       }
       sp.off[8] = end;
     }
+    tl.resize(at);
   }
   for (int p = 0; p < 2; ++p)
     for (int bin = 0; bin < kXyBins; ++bin) g->xy_choice[p][bin] = 0;
@@ -1111,12 +1123,25 @@ void build_xy_tiles(gq_graph* g) {
   std::vector<int32_t>& ft = g->tri_tiles;
   ft.clear();
   std::vector<int32_t> sub_start;
+  sub_start.reserve(g->n_sub);
+  {
+    size_t cap = 0;
+    for (int32_t s = 0; s < g->n_sub; ++s) {
+      const size_t nt = (g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s] + 63) / 64;
+      cap += 3 * nt * (nt + 1) / 2;
+    }
+    ft.reserve(cap);
+  }
   for (int32_t s : g->order) {
     const int32_t n = g->sub_orb_ptr[s + 1] - g->sub_orb_ptr[s];
     const int32_t nt = (n + 63) / 64;
     sub_start.push_back((int32_t)(ft.size() / 3));
     for (int32_t ti = 0; ti < nt; ++ti)
-      for (int32_t tj = 0; tj <= ti; ++tj) ft.insert(ft.end(), {s, ti, tj});
+      for (int32_t tj = 0; tj <= ti; ++tj) {
+        ft.push_back(s);
+        ft.push_back(ti);
+        ft.push_back(tj);
+      }
   }
   const int64_t total = (int64_t)(ft.size() / 3);
   size_t next = 0;
