@@ -370,7 +370,7 @@ def _serve_trace(srv, tr, systems, cores, prevs, h1s, scale, precision):
             "p99_ms": _pct(lat, 99) * 1e3, "solves_per_s": solves / span, "makespan_s": span}
 
 
-def form_served(ctx, side, n_slots=4):
+def form_served(ctx, side, n_slots=6):
     """Config 5: a Poisson trace (20 requests/s, 200 requests, 500..20,000
     atoms, K = 1..8) served by the runtime (split-FP32 and FP64 congruences),
     against the same trace run one request after another on the plain FP64
