@@ -194,10 +194,12 @@ void gq_eigs_destroy(gq_eigs* e);
  * CSR H (same N and a pattern containing the one given to graph_build) and
  * solves h_i = Q_i diag(eps_i) Q_i^T in FP64 (eps ascending), all on the
  * context stream.  Subgraphs below 768 orbitals are reduced to tridiagonal
- * form by one workgroup each; larger ones (up to 2048) by row slabs on
- * separate workgroups, two launches per column, every such subgraph of the
- * graph in the same launches.  Asynchronous; a later call that syncs reports
- * GQ_ENOCONV if an eigensolve hit its iteration cap. */
+ * form by one workgroup each; larger ones (up to 2048) on the lower 64x64
+ * tiles of their trailing matrix, one workgroup per tile, two launches per
+ * column (the tile products, then the column step), every such subgraph of
+ * the graph in the same launches (in two halves on the context's two streams
+ * when the graph has no smaller subgraphs).  Asynchronous; a later call that
+ * syncs reports GQ_ENOCONV if an eigensolve hit its iteration cap. */
 gq_status gq_submatrix_solve(gq_ctx* ctx, const gq_graph* g, const gq_csr* H_dev,
                              uint32_t flags, gq_eigs* e);
 

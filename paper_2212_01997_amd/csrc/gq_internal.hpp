@@ -18,9 +18,9 @@ namespace gq {
 // Largest subgraph the kernels accept (orbitals).  The one-workgroup
 // reduction to tridiagonal form (a row per thread of a 1024-thread workgroup)
 // takes subgraphs of up to kTdMaxN orbitals; subgraphs of kMwgMinN orbitals
-// and more take the multi-workgroup reduction instead (row slabs of a
-// subgraph on separate workgroups, one launch per column step), whose
-// register and LDS budgets end at kMaxN.  From about 700 orbitals one
+// and more take the multi-workgroup reduction instead (the lower 64x64 tiles
+// of a subgraph's trailing matrix on separate workgroups, two launches per
+// column), whose scratch slot and register budgets end at kMaxN.  From about 700 orbitals one
 // subgraph's reduction on one CU takes longer than the multi-workgroup one's
 // two launches per column.
 constexpr int kMaxN = 2048;
