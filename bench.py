@@ -15,7 +15,7 @@ canonical mu1, and the collect of rho and of the six rho1.  `value` is
 response solves per second over the timed steps (six per step, each carrying
 a sixth of the structure's ground state).  The graph estimate (host) is built
 before the timed region and timed on its own.  The same steps with FP64
-congruences, the response alone, the served form (config 5), the batched
+congruences, the response alone, the served form (the serving trace), the batched
 form, two more temperatures and the oracle on the host cores are reported in
 the same line.
 
@@ -261,8 +261,8 @@ def _dist(ms):
     return {"median_ms": _pct(ms, 50), "p10_ms": _pct(ms, 10), "p90_ms": _pct(ms, 90), "n": len(ms)}
 
 
-def _golden3():
-    path = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
+def _golden_chain30000():
+    path = os.path.join(ROOT, "tests", "golden", "chain30000_oracle.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -371,7 +371,7 @@ def _serve_trace(srv, tr, systems, cores, prevs, h1s, scale, precision):
 
 
 def form_served(ctx, side, n_slots=6):
-    """Config 5: a Poisson trace (20 requests/s, 200 requests, 500..20,000
+    """The serving trace: a Poisson trace (20 requests/s, 200 requests, 500..20,000
     atoms, K = 1..8) served by the runtime (split-FP32 and FP64 congruences),
     against the same trace run one request after another on the plain FP64
     path on a context with an arena (no allocation per request); then the
@@ -385,14 +385,14 @@ def form_served(ctx, side, n_slots=6):
     systems = []
     for k, spec in enumerate(tr.pool):
         systems.append(I.pool_system(*spec))
-    log(f"config 5: {len(systems)} pool systems generated")
+    log(f"serving trace: {len(systems)} pool systems generated")
     cores = [I.spatial_cores(s, 8) for s in systems]
     prevs = [bootstrap_prev(ctx, s, c, KT) for s, c in zip(systems, cores)]
     h1s = [I.h1_diagonal(systems[i], int(k), seed=int(sd))
            for i, k, sd in zip(tr.system, tr.K, tr.h1_seed)]
     n = len(tr.arrival)
     solves = int(tr.K.sum())
-    log("config 5: sequential plain path")
+    log("serving trace: sequential plain path")
     seq_ctx = gq.Context(0, stream=side, arena_bytes=96 << 30)
     lat_seq = np.zeros(n)
     t0 = time.perf_counter()
@@ -412,7 +412,7 @@ def form_served(ctx, side, n_slots=6):
     span_seq = time.perf_counter() - t0
     del seq_ctx
     torch.cuda.empty_cache()
-    log("config 5: served")
+    log("serving trace: served")
     srv = gq.Server(0, n_slots=n_slots, arena_bytes=96 << 30)
     served = {"split32": _serve_trace(srv, tr, systems, cores, prevs, h1s, 1.0, gq.PREC_SPLIT32),
               "fp64": _serve_trace(srv, tr, systems, cores, prevs, h1s, 1.0, gq.PREC_FP64)}
@@ -420,14 +420,14 @@ def form_served(ctx, side, n_slots=6):
     for scale in (2.0, 4.0):
         r = _serve_trace(srv, tr, systems, cores, prevs, h1s, scale, gq.PREC_SPLIT32)
         capacity.append(r)
-        log(f"config 5: {r['rate_req_per_s']:.0f} req/s -> p99 {r['p99_ms']:.0f} ms, "
+        log(f"serving trace: {r['rate_req_per_s']:.0f} req/s -> p99 {r['p99_ms']:.0f} ms, "
             f"{r['solves_per_s']:.0f} solves/s")
         if r["p99_ms"] > 1000.0:
             break
     srv.close()
     sustained = max([served["split32"]] + capacity,
                     key=lambda r: r["rate_req_per_s"] if r["p99_ms"] <= 1000.0 else -1)
-    return {"workload": f"config 5: {n} requests, Poisson 20/s, {len(tr.pool)} seeded pool systems "
+    return {"workload": f"serving trace: {n} requests, Poisson 20/s, {len(tr.pool)} seeded pool systems "
                         f"of 500..20,000 atoms (log-uniform; water or chain-in-water), K = 1..8 "
                         f"({solves} solves), kT 0.01, paths of two at tau 0.07",
             "slots": n_slots, "served": served,
@@ -593,12 +593,12 @@ def form_large(ctx, side):
     return out
 
 
-def config2_step(ctx, side, steps):
+def water1000_step(ctx, side, steps):
     """The 1,000-water FP64 step (ground state + one perturbation)."""
     import torch
     from paper_2212_01997_amd import gq, inputs as I
     from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
-    s = I.config_system(2)
+    s = I.water1000_system()
     core = I.spatial_cores(s, 8)
     prev = bootstrap_prev(ctx, s, core, KT)
     graph = gq.Graph.for_system(s, core, TAU, prev, gq.PATHS2)
@@ -639,7 +639,7 @@ def main():
                     help="skip the served, batched and temperature forms and the 1,000-water step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 256 MiB (reference for byte counters)")
-    ap.add_argument("--only-form", choices=["large", "config2", "served"],
+    ap.add_argument("--only-form", choices=["large", "water1000", "served"],
                     help="run only this form (for profiling) and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -653,7 +653,7 @@ def main():
         ctx = gq.Context(0, stream=side)
         out = (form_large(ctx, side) if args.only_form == "large"
                else form_served(ctx, side) if args.only_form == "served"
-               else config2_step(ctx, side, args.steps))
+               else water1000_step(ctx, side, args.steps))
         print(json.dumps({"form": args.only_form, **out}), flush=True)
         return
 
@@ -663,7 +663,7 @@ def main():
     from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
 
     log("generating the 30,000-atom chain-in-water system")
-    system = I.config_system(3)
+    system = I.chain30000_system()
     core = I.spatial_cores(system, 8)
     h1_host = I.h1_diagonal(system, K_H1, seed=3002)
     side = torch.cuda.Stream()  # a stream of its own, so that steps can be captured
@@ -730,7 +730,7 @@ def main():
     errors = {"split32_vs_fp64_path": {"rho1": float((rho1_32 - rho1_64).abs().max()),
                                        "mu1": float(np.abs(mu1_32 - mu1_64).max()),
                                        "positions": int(K_H1 * info.nnz)}}
-    gold = _golden3()
+    gold = _golden_chain30000()
     gold_ok = gold is not None and all(
         gold["graph"][k] == _digest(ex[k]) for k in ("sub_orb_ptr", "sub_orbs", "rho_row_ptr", "rho_col"))
     if gold_ok:
@@ -875,7 +875,7 @@ def main():
         forms["large"] = form_large(ctx, side)
         torch.cuda.empty_cache()
         log("1,000-water FP64 step")
-        forms["config2_fp64_step"] = config2_step(ctx, side, args.steps)
+        forms["water1000_fp64_step"] = water1000_step(ctx, side, args.steps)
         torch.cuda.empty_cache()
         forms["served"] = form_served(ctx, side)
         line["forms"] = forms

@@ -534,23 +534,21 @@ def spatial_cores(system, core_size):
     return core
 
 
-# ------------------------------------------------------------ the configs
+# ------------------------------------------------------------ the benchmark systems
 
-def config_system(k, seed=None):
-    """The seeded systems of the benchmark configurations.
+def water32_system(seed=1001):
+    """32 waters in a 10 A box (96 atoms, 192 orbitals, N_e = 256)."""
+    return water_system(32, 10.0, seed, name="water32")
 
-    1: 32 waters in a 10 A box (96 atoms, 192 orbitals, N_e = 256)
-    2: 1,000 waters in a 31 A box (3,000 atoms, 6,000 orbitals)
-    3: 6,000-atom C/N/O/S chain in water, 30,000 atoms at 0.1 atoms / A^3
-    """
-    s = (1000 * k + 1) if seed is None else seed
-    if k == 1:
-        return water_system(32, 10.0, s, name="config1_water32")
-    if k == 2:
-        return water_system(1000, 31.0, s, name="config2_water1000")
-    if k == 3:
-        return chain_water_system(30000, 6000, s, name="config3_chain6000")
-    raise ValueError(f"unknown config {k}")
+
+def water1000_system(seed=2001):
+    """1,000 waters in a 31 A box (3,000 atoms, 6,000 orbitals)."""
+    return water_system(1000, 31.0, seed, name="water1000")
+
+
+def chain30000_system(seed=3001):
+    """A 6,000-atom C/N/O/S chain in water: 30,000 atoms at 0.1 atoms / A^3."""
+    return chain_water_system(30000, 6000, seed, name="chain30000")
 
 
 @dataclass

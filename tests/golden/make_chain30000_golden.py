@@ -1,4 +1,4 @@
-"""Writes config3_oracle.json: oracle values for the 30,000-atom chain-in-water
+"""Writes chain30000_oracle.json: oracle values for the 30,000-atom chain-in-water
 system (6,000-atom C/N/O/S chain in water at 0.1 atoms per cubic angstrom,
 72,000 orbitals, 8-atom Morton cores, graph = paths of two of the thresholded
 bootstrap density and Hamiltonian at tau = 0.07), six diagonal perturbations,
@@ -9,7 +9,7 @@ whole-system arrays are too large to store, so the file keeps mu, mu1 and the
 values at 4,096 seeded positions of rho and of each rho1, plus digests of the
 graph the values belong to.
 
-    python tests/golden/make_config3_golden.py      (about 15 minutes on 8 cores)
+    python tests/golden/make_chain30000_golden.py      (about 15 minutes on 8 cores)
 """
 import hashlib
 import json
@@ -45,14 +45,14 @@ def graph_digests(sub_orb_ptr, sub_orbs, n_core_orbs, rho_row_ptr, rho_col):
 
 def main():
     t0 = time.time()
-    s = I.config_system(3)
+    s = I.chain30000_system()
     core = I.spatial_cores(s, 8)
     prev = O.bootstrap_prev(s, core, 0.01, pool=True)
     print(f"bootstrap done {time.time() - t0:.0f} s", flush=True)
     g = O.graph_build(s, core, TAU, rho_prev=prev, flags=O.PATHS2)
     h1 = I.h1_diagonal(s, K, seed=3002)
     idx = np.sort(np.random.default_rng(3).choice(g.nnz, size=N_SAMPLE, replace=False))
-    out = {"system": "config 3: 30,000 atoms (6,000-atom chain in water), seed 3001; H1 seed 3002, K = 6; "
+    out = {"system": "30,000 atoms (6,000-atom chain in water), seed 3001; H1 seed 3002, K = 6; "
                      "8-atom Morton cores; bootstrap density at kT 0.01; paths of two, tau 0.07",
            "n_sub": int(g.n_sub), "nnz": int(g.nnz),
            "sizes_min": int(g.sizes().min()), "sizes_max": int(g.sizes().max()),
@@ -65,9 +65,9 @@ def main():
                                "rho": [float(r.rho[i]) for i in idx],
                                "rho1": [[float(r.rho1[q][i]) for i in idx] for q in range(K)]}
         print(f"kT {kT} done {time.time() - t0:.0f} s: mu {r.mu:.12f}", flush=True)
-    with open(os.path.join(HERE, "config3_oracle.json"), "w") as f:
+    with open(os.path.join(HERE, "chain30000_oracle.json"), "w") as f:
         json.dump(out, f)
-    print("wrote config3_oracle.json", flush=True)
+    print("wrote chain30000_oracle.json", flush=True)
 
 
 if __name__ == "__main__":

@@ -23,7 +23,7 @@ KT = 0.01
 
 
 def case(tau, flags):
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     prev = O.bootstrap_prev(s, core, KT)
     g = O.graph_build(s, core, tau, rho_prev=prev, flags=flags)
@@ -46,6 +46,6 @@ def case(tau, flags):
 if __name__ == "__main__":
     out = {"tau1e-5": case(1e-5, 0), "tau7e-2_paths2": case(7e-2, O.PATHS2),
            "complete": case(1e-5, O.COMPLETE)}
-    with open(os.path.join(HERE, "config1_oracle.json"), "w") as f:
+    with open(os.path.join(HERE, "water32_oracle.json"), "w") as f:
         json.dump(out, f, indent=1)
-    print("wrote config1_oracle.json")
+    print("wrote water32_oracle.json")

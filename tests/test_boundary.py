@@ -61,7 +61,7 @@ def _compare_graph(G, O, system, core, tau, prev=None, flags=0):
                                              (0.15, 1, 3), (0.3, 1, 1)])
 def test_graph_build_matches_oracle(gq, oracle_lib, tau, flags, cores):
     O = oracle_lib
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s) if cores == 1 else I.spatial_cores(s, cores)
     prev = O.bootstrap_prev(s, core, 0.01)
     _compare_graph(gq, O, s, core, tau, prev, flags)
@@ -79,9 +79,9 @@ def test_graph_build_matches_oracle_chain(gq, oracle_lib):
         _compare_graph(gq, O, s, core, tau, prev, 1)
 
 
-def test_graph_build_matches_oracle_config2(gq, oracle_lib):
+def test_graph_build_matches_oracle_water1000(gq, oracle_lib):
     O = oracle_lib
-    s = I.config_system(2)
+    s = I.water1000_system()
     core = I.spatial_cores(s, 8)
     g0 = O.graph_build(s, core, 0.0)
     # any previous density pattern exercises the threshold; use |H| scaled
@@ -90,7 +90,7 @@ def test_graph_build_matches_oracle_config2(gq, oracle_lib):
 
 
 def test_graph_build_errors(gq):
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     H = (s.h_row_ptr, s.h_col, s.h_val)
     with pytest.raises(gq.GQError, match="EINVAL.*tau"):
@@ -118,7 +118,7 @@ def test_graph_build_errors(gq):
 
 
 def test_footprint_counts_buffers(gq):
-    s = I.config_system(1)
+    s = I.water32_system()
     g = gq.Graph.for_system(s, I.single_atom_cores(s), 0.0, flags=gq.COMPLETE)
     i = g.info
     f1, f6 = g.footprint(1), g.footprint(6)

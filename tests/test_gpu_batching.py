@@ -50,7 +50,7 @@ def test_launch_variants_bit_identical(ctx):
     tile shape and grid of the X kernel gives the same bits, FP64 and split."""
     import torch
     from paper_2212_01997_amd.path import bootstrap_prev
-    s = I.config_system(2)
+    s = I.water1000_system()
     core = I.spatial_cores(s, 8)
     prev = bootstrap_prev(ctx, s, core, KT)
     K = 2

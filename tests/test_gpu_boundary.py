@@ -63,27 +63,27 @@ def _check_vs_oracle(O, s, core, tau, prev, flags, kT, mats, gpu, tol1):
 
 
 @pytest.mark.parametrize("precision,tol1", [(0, TOL), (1, TOL_MIXED)], ids=["fp64", "split32"])
-def test_csr_pattern_config1(ctx, oracle_lib, precision, tol1):
+def test_csr_pattern_water32(ctx, oracle_lib, precision, tol1):
     O = oracle_lib
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     prev = O.bootstrap_prev(s, core, KT)
     mats = I.h1_on_pattern(s, 2, seed=1003)
-    _say(f"csr pattern config1 precision={precision}")
+    _say(f"csr pattern water32 precision={precision}")
     gpu = _run_csr(ctx, s, core, 0.07, prev, 1, KT, mats, precision)
     err = _check_vs_oracle(O, s, core, 0.07, prev, 1, KT, mats, gpu, tol1)
     _say(f"  |dmu1| {err[0]:.2e} |drho1| {err[1]:.2e}")
 
 
 @pytest.mark.parametrize("precision,tol1", [(0, TOL), (1, TOL_MIXED)], ids=["fp64", "split32"])
-def test_csr_dense_config1_complete(ctx, oracle_lib, precision, tol1):
+def test_csr_dense_water32_complete(ctx, oracle_lib, precision, tol1):
     """Fully dense H1 on the complete graph (192-orbital subgraphs: three
     64-tiles and a ragged one)."""
     O = oracle_lib
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     mats = I.h1_dense(s, 1, seed=1004)
-    _say(f"csr dense config1 complete precision={precision}")
+    _say(f"csr dense water32 complete precision={precision}")
     gpu = _run_csr(ctx, s, core, 1e-5, None, 2, KT, mats, precision)
     err = _check_vs_oracle(O, s, core, 1e-5, None, 2, KT, mats, gpu, tol1)
     _say(f"  |dmu1| {err[0]:.2e} |drho1| {err[1]:.2e}")
@@ -127,7 +127,7 @@ def test_csr_needs_general_workspace(ctx):
     import torch
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
-    s = I.config_system(1)
+    s = I.water32_system()
     p = GraphPath(ctx, s, I.single_atom_cores(s), 1e-3, max_k=1)
     p.ground_state(KT)
     dm = _device_csrs(I.h1_on_pattern(s, 1, seed=5))

@@ -39,8 +39,8 @@ def K():
 
 
 def _case(name, O):
-    if name == "config1":
-        s = I.config_system(1)
+    if name == "water32":
+        s = I.water32_system()
         core = I.spatial_cores(s, 3)
     elif name == "water60":
         s = I.water_system(60, 12.2, seed=61)
@@ -66,7 +66,7 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("name", ["config1", "water60"])
+@pytest.mark.parametrize("name", ["water32", "water60"])
 def test_core_charges_and_response(ctx, oracle_lib, K, name):
     import torch
     O = oracle_lib
@@ -88,7 +88,7 @@ def test_core_charges_and_response(ctx, oracle_lib, K, name):
         assert np.abs(q1.sum(axis=1)).max() <= 1e-10  # no net charge moves
 
 
-@pytest.mark.parametrize("name", ["config1", "water60", "chain900"])
+@pytest.mark.parametrize("name", ["water32", "water60", "chain900"])
 def test_preconditioner(ctx, oracle_lib, K, name):
     O = oracle_lib
     s, core, prev, g, gamma = _case(name, O)
@@ -103,7 +103,7 @@ def test_preconditioner(ctx, oracle_lib, K, name):
     assert err <= 1e-9
 
 
-@pytest.mark.parametrize("name,m", [("config1", 3), ("water60", 6), ("chain900", 3)])
+@pytest.mark.parametrize("name,m", [("water32", 3), ("water60", 6), ("chain900", 3)])
 def test_krylov_kernel(ctx, oracle_lib, K, name, m):
     import torch
     O = oracle_lib
@@ -146,7 +146,7 @@ def test_charge_errors(ctx):
     import torch
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     p = GraphPath(ctx, s, core, 1e-3, max_k=1)
     gamma = I.coulomb_kernel(s)

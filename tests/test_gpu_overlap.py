@@ -39,8 +39,8 @@ def V():
 
 
 def _case(name, O):
-    if name == "config1":
-        s = I.config_system(1)
+    if name == "water32":
+        s = I.water32_system()
         core = I.spatial_cores(s, 3)
     elif name == "water60":
         s = I.water_system(60, 12.2, seed=61)
@@ -53,8 +53,8 @@ def _case(name, O):
     return s, core, prev, g
 
 
-@pytest.mark.parametrize("name,K,general", [("config1", 3, False), ("water60", 3, False),
-                                            ("config1", 2, True), ("chain900", 0, False)])
+@pytest.mark.parametrize("name,K,general", [("water32", 3, False), ("water60", 3, False),
+                                            ("water32", 2, True), ("chain900", 0, False)])
 def test_overlap_parity(ctx, oracle_lib, V, name, K, general):
     import torch
     from paper_2212_01997_amd import gq
@@ -85,7 +85,7 @@ def test_identity_overlap_matches_orthogonal_path(ctx, oracle_lib):
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
     O = oracle_lib
-    s, core, prev, g = _case("config1", O)
+    s, core, prev, g = _case("water32", O)
     n = s.n_orb
     eye = (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
     h1 = torch.as_tensor(I.h1_diagonal(s, 2, seed=78), device="cuda")
@@ -108,7 +108,7 @@ def test_overlap_static_response_matches(ctx, oracle_lib):
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
     O = oracle_lib
-    s, core, prev, g = _case("config1", O)
+    s, core, prev, g = _case("water32", O)
     h1 = torch.as_tensor(I.h1_diagonal(s, 3, seed=79), device="cuda")
     p = GraphPath(ctx, s, core, 0.07, prev, gq.PATHS2, max_k=3, S=I.overlap_matrix(s))
     p.ground_state(KT)
@@ -125,7 +125,7 @@ def test_overlap_errors(ctx, oracle_lib):
     import torch
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.spatial_cores(s, 3)
     S = I.overlap_matrix(s)
     Sd = gq.DeviceCsr(*S)

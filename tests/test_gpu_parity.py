@@ -69,8 +69,8 @@ def compare(gpu, g, r, tol=TOL, tol_mu=TOL_MU, tol1=None):
     return err1
 
 
-def case_config1(O, tau, flags, kT=KT, K=2):
-    s = I.config_system(1)
+def case_water32(O, tau, flags, kT=KT, K=2):
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     prev = O.bootstrap_prev(s, core, KT)
     return s, core, prev, I.h1_diagonal(s, K, seed=1002)
@@ -78,20 +78,20 @@ def case_config1(O, tau, flags, kT=KT, K=2):
 
 @pytest.mark.parametrize("tau,flags", [(1e-5, 0), (0.07, 1), (1e-5, 2)],
                          ids=["tau1e-5", "paths2_tau0.07", "complete"])
-def test_config1(ctx, oracle_lib, tau, flags):
+def test_water32(ctx, oracle_lib, tau, flags):
     O = oracle_lib
-    s, core, prev, h1 = case_config1(O, tau, flags)
-    _say(f"config1 tau={tau} flags={flags}")
+    s, core, prev, h1 = case_water32(O, tau, flags)
+    _say(f"water32 tau={tau} flags={flags}")
     g, r = run_oracle(O, s, core, tau, prev, flags, KT, h1)
     gpu = run_gpu(ctx, s, core, tau, prev, flags, KT, h1)
     compare(gpu, g, r)
 
 
 @pytest.mark.parametrize("kT", [0.003, 0.03])
-def test_config1_temperatures(ctx, oracle_lib, kT):
+def test_water32_temperatures(ctx, oracle_lib, kT):
     O = oracle_lib
-    s, core, prev, h1 = case_config1(O, 0.07, 1)
-    _say(f"config1 kT={kT}")
+    s, core, prev, h1 = case_water32(O, 0.07, 1)
+    _say(f"water32 kT={kT}")
     g, r = run_oracle(O, s, core, 0.07, prev, 1, kT, h1)
     gpu = run_gpu(ctx, s, core, 0.07, prev, 1, kT, h1)
     compare(gpu, g, r)
@@ -174,7 +174,7 @@ def test_tiny_subgraphs(ctx, oracle_lib):
 
 def test_deterministic(ctx, oracle_lib):
     O = oracle_lib
-    s, core, prev, h1 = case_config1(O, 0.07, 1)
+    s, core, prev, h1 = case_water32(O, 0.07, 1)
     a = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
     b = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
     assert a["mu"] == b["mu"]
@@ -183,31 +183,31 @@ def test_deterministic(ctx, oracle_lib):
 
 
 @pytest.fixture(scope="module")
-def config2(oracle_lib):
+def water1000(oracle_lib):
     """The benchmark workload: 1,000 waters, 8-atom cores, paths of two at
     tau = 0.07 on the bootstrap density; one perturbation."""
     O = oracle_lib
-    s = I.config_system(2)
+    s = I.water1000_system()
     core = I.spatial_cores(s, 8)
-    _say("config2 oracle bootstrap")
+    _say("water1000 oracle bootstrap")
     prev = O.bootstrap_prev(s, core, KT, pool=True)
     h1 = I.h1_diagonal(s, 1, seed=2002)
-    _say("config2 oracle solve")
+    _say("water1000 oracle solve")
     g, r = run_oracle(O, s, core, 0.07, prev, 1, KT, h1, pool=True)
     return s, core, prev, h1, g, r
 
 
-def test_config2_full_size(ctx, config2):
-    s, core, prev, h1, g, r = config2
-    _say(f"config2 gpu: sizes {g.sizes().min()}..{g.sizes().max()}")
+def test_water1000_full_size(ctx, water1000):
+    s, core, prev, h1, g, r = water1000
+    _say(f"water1000 gpu: sizes {g.sizes().min()}..{g.sizes().max()}")
     gpu = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1)
     compare(gpu, g, r)
 
 
-def test_config2_invariants(ctx, config2):
+def test_water1000_invariants(ctx, water1000):
     """Properties that hold at any size: Tr rho = N_e, Tr rho1 = 0, and
     H1 = I gives mu1 = 1 with rho1 = 0."""
-    s, core, prev, h1, g, r = config2
+    s, core, prev, h1, g, r = water1000
     h = np.vstack([h1, np.ones((1, s.n_orb))])
     gpu = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h)
     rows = np.repeat(np.arange(s.n_orb), np.diff(gpu["graph"]["rho_row_ptr"]))
@@ -249,11 +249,11 @@ def test_split32_chain_in_water(ctx, oracle_lib):
     _say(f"split32 chain900 kT=0.003: |dmu1| {err[0]:.2e} |drho1| {err[1]:.2e}")
 
 
-def test_split32_config2_full_size(ctx, config2):
-    s, core, prev, h1, g, r = config2
+def test_split32_water1000_full_size(ctx, water1000):
+    s, core, prev, h1, g, r = water1000
     gpu = run_gpu(ctx, s, core, 0.07, prev, 1, KT, h1, precision=1)
     err = compare(gpu, g, r, tol1=TOL_MIXED)
-    _say(f"split32 config2: |dmu1| {err[0]:.2e} |drho1| {err[1]:.2e}")
+    _say(f"split32 water1000: |dmu1| {err[0]:.2e} |drho1| {err[1]:.2e}")
 
 
 def test_split32_tile_edges(ctx, oracle_lib):
@@ -290,7 +290,7 @@ def test_error_paths(ctx):
     import torch
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
-    s = I.config_system(1)
+    s = I.water32_system()
     p = GraphPath(ctx, s, I.single_atom_cores(s), 1e-3, max_k=1)
     h1 = torch.zeros((1, s.n_orb), dtype=torch.float64, device="cuda")
     with pytest.raises(gq.GQError, match="call gq_density"):
@@ -311,7 +311,7 @@ def test_enoconv_from_iteration_cap(ctx):
     synchronising call returns GQ_ENOCONV; the default cap then succeeds."""
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
-    s = I.config_system(1)
+    s = I.water32_system()
     p = GraphPath(ctx, s, I.single_atom_cores(s), 1e-3, max_k=1)
     ctx.set_iteration_cap(0)
     try:
@@ -336,7 +336,7 @@ def test_size_limits_rejected(ctx):
     assert g.info.max_n == 2100
     with pytest.raises(gq.GQError, match="exceeds the limit 2048"):
         gq.Eigs(ctx, g, 1)
-    w = I.config_system(1)
+    w = I.water32_system()
     core = (np.arange(w.n_atoms) // 66).astype(np.int32)  # 22 waters: 132 core orbitals
     g2 = gq.Graph.for_system(w, core, 1e-3)
     assert g2.info.max_c > 128
@@ -390,21 +390,21 @@ def test_large_cores(ctx, oracle_lib, atoms_per_core):
     assert np.abs(po.rho1_view(2).cpu().numpy() - ov.rho1_ao).max() <= TOL
 
 
-# ------------------------------------------------ config 3 at full size
-def test_config3_full_size_sampled():
+# ------------------------------------------------ the 30,000-atom system at full size
+def test_chain30000_full_size_sampled():
     """The 30,000-atom chain-in-water system (3,750 subgraphs of 148..638
     orbitals, K = 6) at kT = 0.003, 0.01, 0.03: the graph bit-exact (digests of
     the oracle's maps), mu and mu1 against the oracle, rho and rho1 at 4,096
     sampled positions; FP64 within 1e-10, split-FP32 response within 1e-6.
-    The stored values come from tests/golden/make_config3_golden.py (oracle only)."""
+    The stored values come from tests/golden/make_chain30000_golden.py (oracle only)."""
     import hashlib
     import json
     import torch
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
-    with open(os.path.join(os.path.dirname(__file__), "golden", "config3_oracle.json")) as f:
+    with open(os.path.join(os.path.dirname(__file__), "golden", "chain30000_oracle.json")) as f:
         gold = json.load(f)
-    s = I.config_system(3)
+    s = I.chain30000_system()
     core = I.spatial_cores(s, 8)
     ctx = gq.Context(0)
     prev = bootstrap_prev(ctx, s, core, KT)
@@ -427,7 +427,7 @@ def test_config3_full_size_sampled():
             rho1 = p.rho1_view(K).cpu().numpy()[:, idx]
             err = (abs(mu - g["mu"]), np.abs(rho - np.array(g["rho"])).max(),
                    np.abs(mu1 - np.array(g["mu1"])).max(), np.abs(rho1 - np.array(g["rho1"])).max())
-            _say(f"config3 kT={kT} precision={precision}: |dmu| {err[0]:.1e} |drho| {err[1]:.1e} "
+            _say(f"chain30000 kT={kT} precision={precision}: |dmu| {err[0]:.1e} |drho| {err[1]:.1e} "
                  f"|dmu1| {err[2]:.1e} |drho1| {err[3]:.1e}")
             assert err[0] <= TOL_MU and err[1] <= TOL
             assert err[2] <= tol and err[3] <= tol

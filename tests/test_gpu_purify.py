@@ -43,8 +43,8 @@ def F():
 
 
 def _case(name, O):
-    if name == "config1":
-        s = I.config_system(1)
+    if name == "water32":
+        s = I.water32_system()
         core = I.spatial_cores(s, 3)
     elif name == "water60":
         s = I.water_system(60, 12.2, seed=61)
@@ -67,7 +67,7 @@ def _radius(O, s, g, mu):
     return R
 
 
-@pytest.mark.parametrize("name", ["config1", "water60", "chain900"])
+@pytest.mark.parametrize("name", ["water32", "water60", "chain900"])
 def test_purify_parity(ctx, oracle_lib, F, name):
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
@@ -97,7 +97,7 @@ def test_purify_eigenvalue_at_mu(ctx, oracle_lib):
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
     O = oracle_lib
-    s, core, prev, g, r = _case("config1", O)
+    s, core, prev, g, r = _case("water32", O)
     p = GraphPath(ctx, s, core, 0.07, prev, gq.PATHS2)
     mu = float(r.eps[np.argmin(np.abs(r.eps - r.mu))])
     with pytest.raises(gq.GQError, match="not converged"):
@@ -108,7 +108,7 @@ def test_purify_errors(ctx):
     import torch
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     p = GraphPath(ctx, s, core, 1e-3)
     rho = torch.empty(p.nnz, dtype=torch.float64, device="cuda")
@@ -124,9 +124,9 @@ def test_purify_errors(ctx):
         p.eigs.purify(H2, -0.2, rho)
 
 
-def test_config3_sampled(oracle_lib, F):
+def test_chain30000_sampled(oracle_lib, F):
     """The 30,000-atom chain-in-water system (3,750 subgraphs of 148..638
-    orbitals) at the oracle's kT = 0.01 mu (tests/golden/config3_oracle.json):
+    orbitals) at the oracle's kT = 0.01 mu (tests/golden/chain30000_oracle.json):
     the graph checked bit-exact against the oracle's digests, the purified
     core rows of eight sampled subgraphs (the smallest, the largest and six
     seeded picks) against the oracle's step rows, each within its own bar."""
@@ -136,10 +136,10 @@ def test_config3_sampled(oracle_lib, F):
     from paper_2212_01997_amd import gq
     from paper_2212_01997_amd.path import GraphPath, bootstrap_prev
     O = oracle_lib
-    with open(os.path.join(os.path.dirname(__file__), "golden", "config3_oracle.json")) as f:
+    with open(os.path.join(os.path.dirname(__file__), "golden", "chain30000_oracle.json")) as f:
         gold = json.load(f)
     mu = gold["kT"][repr(KT)]["mu"]
-    s = I.config_system(3)
+    s = I.chain30000_system()
     core = I.spatial_cores(s, 8)
     ctx = gq.Context(0)
     prev = bootstrap_prev(ctx, s, core, KT)
@@ -170,4 +170,4 @@ def test_config3_sampled(oracle_lib, F):
         bar = 64 * n * U * R / gap
         worst = max(worst, err / bar)
         assert err <= bar, (i, n, gap, err, bar)
-    _say(f"config3: {it} iterations, worst error / bar {worst:.2e} over {len(picks)} subgraphs")
+    _say(f"chain30000: {it} iterations, worst error / bar {worst:.2e} over {len(picks)} subgraphs")

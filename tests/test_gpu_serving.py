@@ -46,7 +46,7 @@ def ctx():
 def test_server_matches_oracle(oracle_lib):
     from paper_2212_01997_amd import gq
     O = oracle_lib
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     prev = O.bootstrap_prev(s, core, KT)
     h1 = I.h1_diagonal(s, 2, seed=1002)

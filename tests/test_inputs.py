@@ -14,7 +14,7 @@ def _min_image_pairs(pos, box, r):
     return p, np.sqrt((d * d).sum(axis=1))
 
 
-@pytest.mark.parametrize("make", [lambda: I.config_system(1), lambda: I.config_system(2),
+@pytest.mark.parametrize("make", [lambda: I.water32_system(), lambda: I.water1000_system(),
                                   lambda: I.chain_water_system(900, 180, seed=3001)])
 def test_geometry_constraints(make):
     s = make()
@@ -33,7 +33,7 @@ def test_geometry_constraints(make):
 
 
 def test_hamiltonian_shape():
-    s = I.config_system(1)
+    s = I.water32_system()
     H = s.dense_h()
     assert np.array_equal(H, H.T)
     assert s.n_orb == 192 and s.n_elec == 256
@@ -43,15 +43,15 @@ def test_hamiltonian_shape():
     assert set(np.round(np.diag(H), 2)) == {-0.87, -0.33, -0.24}
 
 
-def test_config3_shape():
-    s = I.config_system(3)
+def test_chain30000_shape():
+    s = I.chain30000_system()
     assert s.n_atoms == 30000 and s.n_orb == 72000
     assert abs(s.box - (30000 / 0.1) ** (1 / 3)) < 1e-9
     assert s.n_elec % 2 == 0
 
 
 def test_h1_per_atom_shift():
-    s = I.config_system(1)
+    s = I.water32_system()
     h1 = I.h1_diagonal(s, 3, seed=4)
     assert h1.shape == (3, s.n_orb)
     for I_ in range(s.n_atoms):

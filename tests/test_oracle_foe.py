@@ -83,7 +83,7 @@ def test_idempotent_and_commuting(F):
 @pytest.fixture(scope="module")
 def subgraph(oracle_lib):
     O = oracle_lib
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.spatial_cores(s, 3)
     g = O.graph_build(s, core, 0.07, rho_prev=O.bootstrap_prev(s, core, 0.01), flags=O.PATHS2)
     H = O.Csr(s.h_row_ptr, s.h_col, s.h_val)

@@ -18,11 +18,11 @@ KT = 0.01
 
 
 @pytest.mark.parametrize("key", ["tau1e-5", "tau7e-2_paths2", "complete"])
-def test_config1_golden(oracle_lib, key):
+def test_water32_golden(oracle_lib, key):
     O = oracle_lib
-    with open(os.path.join(HERE, "golden", "config1_oracle.json")) as f:
+    with open(os.path.join(HERE, "golden", "water32_oracle.json")) as f:
         ref = json.load(f)[key]
-    s = I.config_system(1)
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     prev = O.bootstrap_prev(s, core, KT)
     g = O.graph_build(s, core, ref["tau"], rho_prev=prev, flags=ref["flags"])

@@ -57,7 +57,7 @@ def check_equal(g, subs, rows):
 
 @pytest.fixture(scope="module")
 def cfg1():
-    return I.config_system(1)
+    return I.water32_system()
 
 
 @pytest.fixture(scope="module")
@@ -97,7 +97,7 @@ def test_graph_without_density(oracle_lib):
 
 
 def test_spatial_cores_are_dense_and_compact():
-    s = I.config_system(2)
+    s = I.water1000_system()
     core = I.spatial_cores(s, 8)
     counts = np.bincount(core)
     assert counts.min() == 8 and counts.max() == 8 and len(counts) == 375

@@ -132,7 +132,7 @@ def test_full_rank_krylov_is_the_newton_step(oracle_lib, K, small):
 
 def test_low_rank_vectors_orthonormal(oracle_lib, K):
     O = oracle_lib
-    s = I.config_system(1)
+    s = I.water32_system()
     gamma = I.coulomb_kernel(s)
     g = O.graph_build(s, I.single_atom_cores(s), 1e-3)
     r = O.solve(s, g, KT)

@@ -56,7 +56,7 @@ def line_system(species, spacing, box=12.0):
 
 @pytest.fixture(scope="module")
 def cfg1():
-    return I.config_system(1)
+    return I.water32_system()
 
 
 # ------------------------------------------------------- pin 1: complete graph

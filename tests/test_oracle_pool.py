@@ -25,8 +25,8 @@ def _same(a, b):
         assert np.array_equal(x, y), (name, float(np.abs(x - y).max()))
 
 
-def _config1(O, tau, flags):
-    s = I.config_system(1)
+def _water32(O, tau, flags):
+    s = I.water32_system()
     core = I.single_atom_cores(s)
     prev = O.bootstrap_prev(s, core, KT)
     g = O.graph_build(s, core, tau, rho_prev=prev, flags=flags)
@@ -35,9 +35,9 @@ def _config1(O, tau, flags):
 
 @pytest.mark.parametrize("tau,flags", [(1e-5, 0), (0.07, 1), (1e-5, 2)],
                          ids=["tau1e-5", "paths2_tau0.07", "complete"])
-def test_pool_equals_serial_config1(oracle_lib, tau, flags):
+def test_pool_equals_serial_water32(oracle_lib, tau, flags):
     O = oracle_lib
-    s, g, h1 = _config1(O, tau, flags)
+    s, g, h1 = _water32(O, tau, flags)
     ref = O.solve(s, g, KT, h1)
     for workers in (1, 3):
         _same(O.solve_pool(s, g, KT, h1, workers=workers), ref)
@@ -72,7 +72,7 @@ def test_pool_equals_serial_chain_in_water(oracle_lib):
 
 
 def test_pool_bootstrap_equals_serial(oracle_lib):
-    """The previous-step density the large tests and the stored config-3
+    """The previous-step density the large tests and the stored 30,000-atom
     values start from: pool and serial give the same array."""
     O = oracle_lib
     s = I.water_system(60, 12.2, seed=61)

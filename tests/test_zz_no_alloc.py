@@ -60,14 +60,14 @@ def test_two_calls_second_smaller(ctx, oracle_lib):
     _say("water60 K=3 fp64")
     ref, out, _ = _pair(ctx, s, core, 0.07, prev, 1, h1)
     _same(ref, out)
-    s1 = I.config_system(1)
+    s1 = I.water32_system()
     c1 = I.single_atom_cores(s1)
     prev1 = O.bootstrap_prev(s1, c1, KT)
     h1b = torch.as_tensor(I.h1_diagonal(s1, 1, seed=1002), device="cuda")
-    _say("config1 K=1 fp64 (smaller, after the larger)")
+    _say("water32 K=1 fp64 (smaller, after the larger)")
     ref, out, _ = _pair(ctx, s1, c1, 0.07, prev1, 1, h1b)
     _same(ref, out)
-    _say("config1 K=1 split32")
+    _say("water32 K=1 split32")
     ref, out, _ = _pair(ctx, s1, c1, 0.07, prev1, 1, h1b, precision=1)
     _same(ref, out)
 
@@ -84,16 +84,16 @@ def test_general_kind(ctx, oracle_lib):
     _same(ref, out)
 
 
-def test_chunked_config2(ctx):
+def test_chunked_water1000(ctx):
     """The 1,000-water system: one perturbation's buffers fill most of the
     scratch, so K = 2 runs as two chunks of one."""
     import torch
     from paper_2212_01997_amd.path import bootstrap_prev
-    s = I.config_system(2)
+    s = I.water1000_system()
     core = I.spatial_cores(s, 8)
     prev = bootstrap_prev(ctx, s, core, KT)
     h1 = torch.as_tensor(I.h1_diagonal(s, 2, seed=2002), device="cuda")
-    _say("config2 K=2 (chunked)")
+    _say("water1000 K=2 (chunked)")
     ref, out, _ = _pair(ctx, s, core, 0.07, prev, 1, h1)
     _same(ref, out)
 
