@@ -157,9 +157,13 @@ __device__ double tsum(double x, double* red) {
 // a time.
 // The thread with h = 0 also returns its row's entry in column c + 1 (first
 // chunk), which the next column of the panel starts from.
+// Rows from n0 on read their columns from n0 on (whole chunks: n0 is a
+// multiple of 16) from the LDS corner cor (column-major, leading dimension
+// ldc) instead of from A.
 __device__ __forceinline__ double symv_row(const double* __restrict__ row,
                                            const double* __restrict__ vl, int n, int c, int h,
-                                           int H, double& next_col) {
+                                           int H, double& next_col, const double* cor_row,
+                                           bool corner_row, int n0, int ldc) {
   double ac[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) ac[u] = 0.0;
@@ -169,8 +173,13 @@ __device__ __forceinline__ double symv_row(const double* __restrict__ row,
   for (int g = (c + 1) / kUnroll + h; g < g_end; g += H) {
     const int col = g * kUnroll;
     double x[kUnroll];
+    if (corner_row && col >= n0) {
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * min(col + u, n - 1)];
+      for (int u = 0; u < kUnroll; ++u) x[u] = cor_row[(size_t)ldc * (min(col + u, n - 1) - n0)];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) x[u] = row[(size_t)n * min(col + u, n - 1)];
+    }
     if (first) {
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
@@ -195,13 +204,20 @@ __device__ __forceinline__ double symv_row(const double* __restrict__ row,
 // + r]); larger ones read V from A's columns and W from the global scratch.
 constexpr int kLdsPanelN = 512;
 
+// The trailing matrix's bottom-right corner, rows and columns n0 .. n - 1
+// (m = n - n0 a multiple of 16, as large as the LDS left after the panel
+// allows), lives in LDS (cor, column-major, leading dimension m) for the whole
+// reduction: every column's symmetric product reads it there, the trailing
+// updates write it there, and A's copy of it is not read again.  The
+// reflectors are still stored in A for the back-transformation.
 template <bool LP>
 __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __restrict__ Wg,
                                              double* __restrict__ pan, int n, int b,
                                              double* __restrict__ D, double* __restrict__ E,
                                              double* __restrict__ TAU, double* vl, double* part,
                                              double* red, double (*yp)[2 * kPanel + 1],
-                                             double* yfin, double* rowc, double* alpha_sh) {
+                                             double* yfin, double* rowc, double* alpha_sh,
+                                             int lds_doubles) {
   const int tid = threadIdx.x;
   const int H = n <= 128 ? 8 : n <= 256 ? 4 : n <= 512 ? 2 : 1;
   const int P = kTdThreads / H;
@@ -209,6 +225,19 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
   const bool own = (h == 0) && (r < n);
   const int lane = tid & 63, wv = tid >> 6;
   if (tid < kUnroll) vl[n + tid] = 0.0;  // padding of the last chunk (the first barrier orders it)
+  double* cor = LP ? pan + 2 * kPanel * n : pan;
+  // n0 a multiple of 16, so that no chunk of the symmetric product and no
+  // 16x16 tile of a full panel's update straddles it; m^2 fits the LDS left
+  const int m_fit = min((int)sqrt((double)max(lds_doubles - (LP ? 2 * kPanel * n : 0), 0)), n);
+  const int n0 = min((n - m_fit + 15) & ~15, n);
+  const int m = n - n0;
+  for (int i = tid; i < m * m; i += kTdThreads)
+    cor[i] = A[(n0 + i % m) + (size_t)n * (n0 + i / m)];
+  __syncthreads();
+  auto At = [&](int row, int col) -> double {
+    return (row >= n0 && col >= n0) ? cor[(row - n0) + (size_t)m * (col - n0)]
+                                    : A[row + (size_t)n * col];
+  };
 
   for (int k0 = 0; k0 + 2 < n; k0 += kPanel) {
     const int nb = min(kPanel, n - 2 - k0);
@@ -238,7 +267,7 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
       __syncthreads();
       double a = 0.0;
       if (own && r >= c) {
-        a = have_next ? a_next : A[r + (size_t)n * c];
+        a = have_next ? a_next : At(r, c);
 #pragma unroll 4
         for (int q = 0; q < j; ++q) {
           const double vc = LP ? Vp(q, c) : rowc[q];
@@ -298,7 +327,8 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
       }
       // p = A22 v over the stale trailing matrix
       double acc = 0.0;
-      if (r >= c + 1 && r < n) acc = symv_row(A + r, vl, n, c, h, H, a_next);
+      if (r >= c + 1 && r < n)
+        acc = symv_row(A + r, vl, n, c, h, H, a_next, cor + max(r - n0, 0), r >= n0, n0, m);
       have_next = true;
       part[tid] = acc;
       __syncthreads();
@@ -344,7 +374,7 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
         const int rowc_ = min(row, n - 1), clc = min(cl, n - 1);
         double a4[4], wcv[kPanel / 4], vcv[kPanel / 4], vrv[kPanel / 4], wrv[kPanel / 4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a4[i] = A[rowc_ + (size_t)n * min(col0 + 4 * i + lk, n - 1)];
+        for (int i = 0; i < 4; ++i) a4[i] = At(rowc_, min(col0 + 4 * i + lk, n - 1));
 #pragma unroll
         for (int kq = 0; kq < kPanel / 4; ++kq) {
           const int qc = min(4 * kq + lk, nb - 1);
@@ -370,7 +400,10 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int col = col0 + 4 * i + lk;
-            if (col < n) A[row + (size_t)n * col] = acc[i];
+            if (col < n) {
+              if (row >= n0 && col >= n0) cor[(row - n0) + (size_t)m * (col - n0)] = acc[i];
+              else A[row + (size_t)n * col] = acc[i];
+            }
           }
         }
       }
@@ -379,10 +412,10 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
   }
   if (tid == 0) {
     if (n >= 2) {
-      D[b + n - 2] = A[(n - 2) + (size_t)n * (n - 2)];
-      E[b + n - 2] = A[(n - 1) + (size_t)n * (n - 2)];
+      D[b + n - 2] = At(n - 2, n - 2);
+      E[b + n - 2] = At(n - 1, n - 2);
     }
-    D[b + n - 1] = A[(size_t)(n - 1) * (n + 1)];
+    D[b + n - 1] = At(n - 1, n - 1);
     E[b + n - 1] = 0.0;
   }
 }
@@ -390,8 +423,8 @@ __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __r
 __global__ __launch_bounds__(kTdThreads) void k_tridiag(
     double* __restrict__ abuf, double* __restrict__ wsc, const int64_t* __restrict__ off2,
     const int32_t* __restrict__ sub_orb_ptr, const int32_t* __restrict__ order,
-    double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU) {
-  extern __shared__ double pan[];  // 2 kPanel min(max n, kLdsPanelN) doubles
+    double* __restrict__ D, double* __restrict__ E, double* __restrict__ TAU, int lds_doubles) {
+  extern __shared__ double pan[];  // the panel (n <= kLdsPanelN), then the corner
   __shared__ __align__(16) double vl[kTdMaxN + kUnroll];  // v, then kUnroll zeros
   __shared__ double part[kTdThreads];
   __shared__ double red[2 * (kTdThreads / 64)];  // the two sums of a column
@@ -405,9 +438,11 @@ __global__ __launch_bounds__(kTdThreads) void k_tridiag(
   double* A = abuf + off2[s];
   double* W = wsc + (size_t)b * kPanel;  // W[q * n + r]
   if (n <= kLdsPanelN)
-    tridiag_body<true>(A, W, pan, n, b, D, E, TAU, vl, part, red, yp, yfin, rowc, &alpha_sh);
+    tridiag_body<true>(A, W, pan, n, b, D, E, TAU, vl, part, red, yp, yfin, rowc, &alpha_sh,
+                       lds_doubles);
   else
-    tridiag_body<false>(A, W, pan, n, b, D, E, TAU, vl, part, red, yp, yfin, rowc, &alpha_sh);
+    tridiag_body<false>(A, W, pan, n, b, D, E, TAU, vl, part, red, yp, yfin, rowc, &alpha_sh,
+                        lds_doubles);
 }
 
 // ---------------------------------------------------------------------------
@@ -792,13 +827,13 @@ static void launch_tridiag_mwg(gq_ctx* ctx, const gq_graph* g, gq_eigs* e, hipSt
   prof_end(ctx);
 }
 
-static size_t tridiag_lds(int maxn) {
-  return (size_t)2 * kPanel * std::min(maxn, kLdsPanelN) * sizeof(double);
-}
+// Dynamic LDS of k_tridiag: the panel and the corner share what its 25.7 KB of
+// static LDS leave of the CU's 160 KB (one workgroup per CU either way).
+constexpr int kTdDynLds = 137216;
 
 void eig_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)tridiag_lds(kLdsPanelN));
+                            kTdDynLds);
 }
 
 void launch_gather(gq_ctx* ctx, const gq_graph* g, const gq_csr* H, double* A, int32_t* status,
@@ -824,11 +859,10 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
   if (nsmall > 0) {
     (void)hipEventRecord(ctx->ev_fork, st);
     (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-    const int n1 = g->sub_orb_ptr[g->order[nbig] + 1] - g->sub_orb_ptr[g->order[nbig]];
     prof_begin_on(ctx, "k_tridiag", ctx->side);
-    hipLaunchKernelGGL(k_tridiag, dim3(nsmall), dim3(kTdThreads), tridiag_lds(n1), ctx->side,
+    hipLaunchKernelGGL(k_tridiag, dim3(nsmall), dim3(kTdThreads), kTdDynLds, ctx->side,
                        e->A, e->wsc, dv.off2, dv.sub_orb_ptr, dv.order + nbig, e->dd, e->ee,
-                       e->tau);
+                       e->tau, kTdDynLds / 8);
     prof_end(ctx);
     launch_dc(ctx, g, e, 1, ctx->side);
   }
@@ -850,10 +884,10 @@ void launch_eigensolve(gq_ctx* ctx, const gq_graph* g, gq_eigs* e) {
       launch_tridiag_mwg(ctx, g, e, st, 0, nh, "k_tridiag_mwg");
     }
     if (nbig > nh) {
-      const int n0 = g->sub_orb_ptr[g->order[nh] + 1] - g->sub_orb_ptr[g->order[nh]];
       prof_begin(ctx, "k_tridiag");
-      hipLaunchKernelGGL(k_tridiag, dim3(nbig - nh), dim3(kTdThreads), tridiag_lds(n0), st, e->A,
-                         e->wsc, dv.off2, dv.sub_orb_ptr, dv.order + nh, e->dd, e->ee, e->tau);
+      hipLaunchKernelGGL(k_tridiag, dim3(nbig - nh), dim3(kTdThreads), kTdDynLds, st, e->A,
+                         e->wsc, dv.off2, dv.sub_orb_ptr, dv.order + nh, e->dd, e->ee, e->tau,
+                         kTdDynLds / 8);
       prof_end(ctx);
     }
     if (mwg_split) (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
