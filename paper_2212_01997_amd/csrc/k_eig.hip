@@ -205,11 +205,12 @@ __device__ __forceinline__ double symv_row(const double* __restrict__ row,
 constexpr int kLdsPanelN = 512;
 
 // The trailing matrix's bottom-right corner, rows and columns n0 .. n - 1
-// (m = n - n0 a multiple of 16, as large as the LDS left after the panel
-// allows), lives in LDS (cor, column-major, leading dimension m) for the whole
-// reduction: every column's symmetric product reads it there, the trailing
-// updates write it there, and A's copy of it is not read again.  The
-// reflectors are still stored in A for the back-transformation.
+// (n0 a multiple of 16, m = n - n0 as large as the LDS left after the panel
+// allows; the whole matrix when it fits), lives in LDS (cor, column-major,
+// leading dimension m) for the whole reduction: every column's symmetric
+// product reads it there, the trailing updates write it there, and A's copy
+// of it is not read again.  The reflectors are still stored in A for the
+// back-transformation.
 template <bool LP>
 __device__ __forceinline__ void tridiag_body(double* __restrict__ A, double* __restrict__ Wg,
                                              double* __restrict__ pan, int n, int b,
